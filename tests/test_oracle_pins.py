@@ -1,0 +1,596 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these tests calls the oracle to make its own expected value: the
+expected values are closed forms (geometric series of lattice sums, their
+derivatives, the paper's explicit trigonometric forms of the POLARIS, SANSPOL
+and unpolarized cross sections of Sec. 2.2-2.4), brute force on tiny inputs,
+exact identities, the worked-example tables of Sec. 4.1 and 4.2 (fixtures in
+tests/golden/), and finite differences.  Each test names the passage it pins.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2601_18444_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+BH = 2.91e8  # Sec. 2.1, magnetic scattering length b_H in A^-1 m^-1
+
+
+# ---------------------------------------------------------------------------
+# closed forms (independent of the oracle's arithmetic)
+# ---------------------------------------------------------------------------
+def dirichlet(t, n):
+    """sum_{m=0}^{n-1} exp(-i t m) by the geometric series."""
+    t = np.asarray(t, dtype=np.float64)
+    z = np.exp(-1j * t)
+    out = np.empty(t.shape, dtype=np.complex128)
+    small = np.abs(1 - z) < 1e-12
+    out[~small] = (1 - z[~small] ** n) / (1 - z[~small])
+    out[small] = n
+    return out
+
+
+def dirichlet_m(t, n):
+    """sum_{m=0}^{n-1} m exp(-i t m) = z (1 - n z^{n-1} + (n-1) z^n) / (1 - z)^2."""
+    t = np.asarray(t, dtype=np.float64)
+    z = np.exp(-1j * t)
+    out = np.empty(t.shape, dtype=np.complex128)
+    small = np.abs(1 - z) < 1e-9
+    zz = z[~small]
+    out[~small] = zz * (1 - n * zz ** (n - 1) + (n - 1) * zz ** n) / (1 - zz) ** 2
+    out[small] = n * (n - 1) / 2.0
+    return out
+
+
+def box_sums(qp, n, a, c):
+    """For the box c + (i a0, j a1, k a2): per axis D_d = sum exp(-i q_d x_d) and
+    X_d = sum x_d exp(-i q_d x_d) (q' = the phase vector in the box frame)."""
+    D, X = [], []
+    for d in range(3):
+        t = qp[:, d] * a[d]
+        e0 = np.exp(-1j * qp[:, d] * c[d])
+        Dd = e0 * dirichlet(t, n[d])
+        Xd = e0 * (c[d] * dirichlet(t, n[d]) + a[d] * dirichlet_m(t, n[d]))
+        D.append(Dd)
+        X.append(Xd)
+    return D, X
+
+
+def random_pixels(rng, n, qmax):
+    return rng.uniform(-qmax, qmax, n), rng.uniform(-qmax, qmax, n)
+
+
+def rel(a, b):
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+# ---------------------------------------------------------------------------
+# Sec. 3.3 DSFT and Sec. 3.2 rotation: box lattice, closed form
+# ---------------------------------------------------------------------------
+def test_box_lattice_closed_form_with_rotation(orc):
+    """S(q) of a rotated, off-centre, non-cubic box is a product of geometric
+    series in q' = R^T q (Sec. 3.2 position transform, Sec. 3.3 DSFT with the
+    exp(-i q.r) sign).  A transposed R, a flipped sign or a dropped offset
+    changes the value."""
+    n, a, c = (3, 5, 4), (0.7, 1.1, 0.9), (10.3, -7.1, 4.2)
+    pos = synth.box_lattice(n, a, c)
+    W = pos.shape[0]
+    R = synth.sample_rotation(37.0, -52.0) @ synth.rot_z(11.0).T
+    rng = np.random.default_rng(11)
+    qy, qz = random_pixels(rng, 200, 2.0)
+    m0 = np.array([0.3, -0.8, 0.5])
+    A = orc.amplitudes(pos, np.full(W, 1.7), np.tile(m0, (W, 1)), qy, qz, R=R)
+    q = np.stack([np.zeros_like(qy), qy, qz], axis=1)
+    qp = q @ R  # q' = R^T q
+    D, _ = box_sums(qp, n, a, c)
+    S = D[0] * D[1] * D[2]
+    assert rel(A[:, 0], 1.7 * S) < 1e-11
+    mr = R @ m0  # moments rotate with the sample (Sec. 3.1, alpha = 90 deg example)
+    for k in range(3):
+        assert rel(A[:, 1 + k], mr[k] * S) < 1e-11
+
+
+def test_linear_vortex_box_closed_form(orc):
+    """Linear vortex moments m = M1 (x e_y - y e_x) + M0 e_z (Sec. 4.2) on a box:
+    sum_j x_j exp(-i q.r_j) is the derivative of the geometric series, so the
+    imaginary parts and the sign of the phase are fixed exactly."""
+    n, a, c = (6, 4, 5), (1.0, 1.3, 0.8), (-2.6, 1.9, -1.7)
+    pos = synth.box_lattice(n, a, c)
+    M0, M1 = 1.3, 0.45
+    mag = np.stack([-M1 * pos[:, 1], M1 * pos[:, 0], np.full(pos.shape[0], M0)], axis=1)
+    R = synth.sample_rotation(23.0, 71.0)
+    rng = np.random.default_rng(12)
+    qy, qz = random_pixels(rng, 150, 1.5)
+    A = orc.amplitudes(pos, None, mag, qy, qz, R=R)
+    q = np.stack([np.zeros_like(qy), qy, qz], axis=1)
+    qp = q @ R
+    D, X = box_sums(qp, n, a, c)
+    S = D[0] * D[1] * D[2]
+    Sx = X[0] * D[1] * D[2]
+    Sy = D[0] * X[1] * D[2]
+    Mloc = np.stack([-M1 * Sy, M1 * Sx, M0 * S], axis=1)
+    Mlab = Mloc @ R.T
+    # the closed form divides by (1 - z)^2, which loses digits near z = 1
+    assert rel(A[:, 1:], Mlab) < 1e-8
+    assert np.all(A[:, 0] == 0)
+
+
+def test_tiny_inputs_brute_force(orc):
+    """One point: |S|^2 = w^2.  Two points: |S|^2 = w1^2 + w2^2 + 2 w1 w2 cos(q.(r1 - r2))."""
+    rng = np.random.default_rng(3)
+    qy, qz = random_pixels(rng, 50, 3.0)
+    p1 = rng.uniform(-5, 5, 3)
+    A = orc.amplitudes(p1[None, :], np.array([2.5]), None, qy, qz)
+    assert np.allclose(np.abs(A[:, 0]) ** 2, 6.25, rtol=1e-14)
+    p = rng.uniform(-5, 5, (2, 3))
+    w = np.array([1.3, -0.4])
+    A = orc.amplitudes(p, w, None, qy, qz)
+    d = p[0] - p[1]
+    expect = w[0] ** 2 + w[1] ** 2 + 2 * w[0] * w[1] * np.cos(qy * d[1] + qz * d[2])
+    assert np.allclose(np.abs(A[:, 0]) ** 2, expect, rtol=1e-12, atol=1e-14)
+
+
+def test_forward_sum_at_q0_is_total_weight(orc):
+    """S(0) = sum_j w_j exactly (spec pin F(0) = sum of moments)."""
+    cl = synth.random_cloud(300, 20.0, seed=5)
+    A = orc.amplitudes(cl["pos"], cl["nuc"], cl["mag"], np.zeros(1), np.zeros(1),
+                       R=synth.sample_rotation(40, 10))
+    assert abs(A[0, 0] - cl["nuc"].sum()) < 1e-11
+    mr = synth.sample_rotation(40, 10) @ cl["mag"].sum(axis=0)
+    assert np.allclose(A[0, 1:], mr, atol=1e-11)
+
+
+def test_bragg_artefact_at_two_pi_over_a(orc):
+    """A lattice sum is periodic: the artificial Bragg peak at q = 2 pi / a
+    repeats the q = 0 value (Sec. 3.1 Bragg/Nyquist guidance)."""
+    pos = synth.sphere_lattice(6.0, 2.0)
+    W = pos.shape[0]
+    qB = 2 * math.pi / 2.0
+    A = orc.amplitudes(pos, np.ones(W), None, np.array([0.0, qB, 0.0]), np.array([0.0, 0.0, qB]))
+    assert np.allclose(np.abs(A[:, 0]), W, rtol=1e-10)
+
+
+def test_translation_invariance_of_all_cross_sections(orc):
+    """|F|^2-type observables are invariant under r -> r + t (every observable is
+    a Hermitian form in the sums, and a translation multiplies all sums by one
+    phase)."""
+    cl = synth.random_cloud(200, 10.0, seed=6)
+    rng = np.random.default_rng(7)
+    qy, qz = random_pixels(rng, 64, 1.2)
+    qhat = orc.qhat_of(qy, qz)
+    R = synth.sample_rotation(15, 30)
+    A1 = orc.amplitudes(cl["pos"], cl["nuc"], cl["mag"], qy, qz, R=R)
+    A2 = orc.amplitudes(cl["pos"] + np.array([31.0, -7.5, 12.25]), cl["nuc"], cl["mag"], qy, qz, R=R)
+    o1 = orc.cross_sections(A1, qhat, P=(0.2, 0.6, 0.7745966692414834))
+    o2 = orc.cross_sections(A2, qhat, P=(0.2, 0.6, 0.7745966692414834))
+    for k in o1:
+        scale = np.max(np.abs(o1["UNPOL"]))
+        assert np.max(np.abs(o1[k] - o2[k])) < 1e-9 * scale, k
+
+
+# ---------------------------------------------------------------------------
+# Sec. 2: observables against the paper's explicit trigonometric forms
+# ---------------------------------------------------------------------------
+def _random_amplitudes(rng, n):
+    return rng.standard_normal((n, 4)) + 1j * rng.standard_normal((n, 4))
+
+
+def test_halpern_johnson_components_and_projection(orc):
+    """eq. HJdef1 components and |Q|^2 = |M|^2 - |qhat.M|^2 (so |Q| <= |M|)."""
+    rng = np.random.default_rng(8)
+    A = _random_amplitudes(rng, 40)
+    th = rng.uniform(0, 2 * np.pi, 40)
+    qhat = np.stack([np.zeros(40), np.sin(th), np.cos(th)], axis=1)
+    o = orc.cross_sections(A, qhat)
+    M = A[:, 1:]
+    qm = M[:, 1] * np.sin(th) + M[:, 2] * np.cos(th)
+    expect = np.sum(np.abs(M) ** 2, axis=1) - np.abs(qm) ** 2
+    assert np.allclose(o["M"], expect, rtol=1e-12)
+    assert np.all(o["M"] <= np.sum(np.abs(M) ** 2, axis=1) * (1 + 1e-12))
+    # B0 || e_x: dSigma_P = |Mx|^2 and chi = 0 (Sec. 2.1, Sec. 2.2)
+    ox = orc.cross_sections(A, qhat, P=(1.0, 0.0, 0.0))
+    assert np.allclose(ox["P"], np.abs(M[:, 0]) ** 2, rtol=1e-12)
+    assert np.max(np.abs(ox["CHI"])) < 1e-12 * np.max(ox["M"])
+
+
+def test_polaris_perpendicular_explicit_forms(orc):
+    """eqs. nsfperp, sfperp, sanspolperp and sigmasansperpunpol (B0 || e_z), with
+    bH = V = 1: the explicit forms fix the signs of NM and of the chiral term
+    (Q = qhat x (qhat x M) for every signed term)."""
+    rng = np.random.default_rng(9)
+    n = 60
+    A = _random_amplitudes(rng, n)
+    th = rng.uniform(0, 2 * np.pi, n)
+    s, c = np.sin(th), np.cos(th)
+    qhat = np.stack([np.zeros(n), s, c], axis=1)
+    bH = 0.7
+    o = orc.cross_sections(A, qhat, bH=bH, P=(0.0, 0.0, 1.0))
+    N, Mx, My, Mz = A[:, 0], A[:, 1], A[:, 2], A[:, 3]
+    ab2 = lambda z: np.abs(z) ** 2
+    re = lambda z: np.real(z)
+    yz = My * np.conj(Mz) + np.conj(My) * Mz
+    nz = N * np.conj(Mz) + np.conj(N) * Mz
+    ny = N * np.conj(My) + np.conj(N) * My
+    chi = (Mx * np.conj(My) - np.conj(Mx) * My) * c ** 2 - (Mx * np.conj(Mz) - np.conj(Mx) * Mz) * s * c
+    for sign, key in ((+1, "PP"), (-1, "MM")):
+        expect = bH ** 2 * re(ab2(N) / bH ** 2 + ab2(My) * s ** 2 * c ** 2 + ab2(Mz) * s ** 4
+                              - yz * s ** 3 * c - sign * nz * s ** 2 / bH + sign * ny * s * c / bH)
+        assert np.allclose(o[key], expect, rtol=1e-11, atol=1e-12), key
+    for sign, key in ((+1, "PM"), (-1, "MP")):
+        expect = bH ** 2 * re(ab2(Mx) + ab2(My) * c ** 4 + ab2(Mz) * s ** 2 * c ** 2
+                              - yz * s * c ** 3 - sign * 1j * chi)
+        assert np.allclose(o[key], expect, rtol=1e-11, atol=1e-12), key
+    for sign, key in ((+1, "PLUS"), (-1, "MINUS")):
+        expect = bH ** 2 * re(ab2(N) / bH ** 2 + ab2(Mx) + ab2(My) * c ** 2 + ab2(Mz) * s ** 2
+                              - yz * s * c - sign * nz * s ** 2 / bH + sign * ny * s * c / bH
+                              - sign * 1j * chi)
+        assert np.allclose(o[key], expect, rtol=1e-11, atol=1e-12), key
+    unpol = bH ** 2 * re(ab2(N) / bH ** 2 + ab2(Mx) + ab2(My) * c ** 2 + ab2(Mz) * s ** 2 - yz * s * c)
+    assert np.allclose(o["UNPOL"], unpol, rtol=1e-11)
+    # the B0 || e_z form of eq. PSANSdef
+    P = bH ** 2 * re(ab2(My) * s ** 2 * c ** 2 + ab2(Mz) * s ** 4 - yz * s ** 3 * c)
+    assert np.allclose(o["P"], P, rtol=1e-11, atol=1e-12)
+
+
+def test_polaris_parallel_explicit_forms(orc):
+    """eqs. nsfpara, sfpara, sanspolpara (B0 || e_x)."""
+    rng = np.random.default_rng(10)
+    n = 60
+    A = _random_amplitudes(rng, n)
+    th = rng.uniform(0, 2 * np.pi, n)
+    s, c = np.sin(th), np.cos(th)
+    qhat = np.stack([np.zeros(n), s, c], axis=1)
+    bH = 1.9
+    o = orc.cross_sections(A, qhat, bH=bH, V=2.0, scale=3.0, P=(1.0, 0.0, 0.0))
+    k = 3.0 / 2.0
+    N, Mx, My, Mz = A[:, 0], A[:, 1], A[:, 2], A[:, 3]
+    ab2 = lambda z: np.abs(z) ** 2
+    yz = np.real(My * np.conj(Mz) + np.conj(My) * Mz)
+    nx = np.real(N * np.conj(Mx) + np.conj(N) * Mx)
+    for sign, key in ((+1, "PP"), (-1, "MM")):
+        expect = k * bH ** 2 * (ab2(N) / bH ** 2 + ab2(Mx) - sign * nx / bH)
+        assert np.allclose(o[key], expect, rtol=1e-11), key
+    sf = k * bH ** 2 * (ab2(My) * c ** 2 + ab2(Mz) * s ** 2 - yz * s * c)
+    assert np.allclose(o["PM"], sf, rtol=1e-11, atol=1e-12)
+    assert np.allclose(o["MP"], sf, rtol=1e-11, atol=1e-12)
+    for sign, key in ((+1, "PLUS"), (-1, "MINUS")):
+        expect = k * bH ** 2 * (ab2(N) / bH ** 2 + ab2(Mx) + ab2(My) * c ** 2 + ab2(Mz) * s ** 2
+                                - yz * s * c - sign * nx / bH)
+        assert np.allclose(o[key], expect, rtol=1e-11, atol=1e-12), key
+
+
+def test_chi_vanishes_for_even_and_odd_fields(orc):
+    """chi = 0 for M(r) = M(-r) (real sums) and for odd M (imaginary sums), Sec. 2.2."""
+    rng = np.random.default_rng(13)
+    half = rng.uniform(-8, 8, (100, 3))
+    pos = np.concatenate([half, -half])
+    mh = rng.standard_normal((100, 3))
+    qy, qz = random_pixels(rng, 40, 1.0)
+    qhat = orc.qhat_of(qy, qz)
+    for mag in (np.concatenate([mh, mh]), np.concatenate([mh, -mh])):
+        A = orc.amplitudes(pos, None, mag, qy, qz)
+        o = orc.cross_sections(A, qhat, P=(0.0, 0.0, 1.0))
+        assert np.max(np.abs(o["CHI"])) < 1e-10 * np.max(o["M"])
+
+
+def test_uniform_magnetization_angular_forms(orc):
+    """For a uniformly magnetized object with N = 1 every sum is n S, so the
+    angular forms of the Sec. 4.1 cross sections hold exactly with 9 V^2 g^2
+    replaced by |S|^2: M ~ nx^2 + ny^2 c^2 + nz^2 s^2 - 2 ny nz s c,
+    NM ~ 2 (ny s c - nz s^2), P ~ ny^2 s^2 c^2 + nz^2 s^4 - 2 ny nz s^3 c, chi = 0."""
+    pos = synth.sphere_lattice(7.0, 1.0)
+    W = pos.shape[0]
+    nvec = np.array([0.36, -0.48, 0.8])
+    rng = np.random.default_rng(14)
+    qy, qz = random_pixels(rng, 80, 1.0)
+    qhat = orc.qhat_of(qy, qz)
+    A = orc.amplitudes(pos, np.ones(W), np.tile(nvec, (W, 1)), qy, qz)
+    o = orc.cross_sections(A, qhat, P=(0.0, 0.0, 1.0))
+    S2 = np.abs(A[:, 0]) ** 2
+    s, c = qhat[:, 1], qhat[:, 2]
+    nx, ny, nz = nvec
+    assert np.allclose(o["M"], S2 * (nx ** 2 + ny ** 2 * c ** 2 + nz ** 2 * s ** 2 - 2 * ny * nz * s * c), rtol=1e-9)
+    assert np.allclose(o["NM"], S2 * 2 * (ny * s * c - nz * s ** 2), rtol=1e-9, atol=1e-9 * S2.max())
+    assert np.allclose(o["P"], S2 * (ny ** 2 * s ** 2 * c ** 2 + nz ** 2 * s ** 4 - 2 * ny * nz * s ** 3 * c),
+                       rtol=1e-9, atol=1e-12 * S2.max())
+    assert np.max(np.abs(o["CHI"])) < 1e-9 * S2.max()
+
+
+# ---------------------------------------------------------------------------
+# Sec. 4.1 / 4.2 worked examples (golden tables)
+# ---------------------------------------------------------------------------
+def _read_table(name):
+    rows = {}
+    with open(os.path.join(GOLDEN, name)) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            parts = line.split()
+            rows[parts[0]] = [float(x) for x in parts[1:]]
+    return rows
+
+
+SPHERE_R_NM = 20.0
+VS = 4.0 / 3.0 * math.pi * (SPHERE_R_NM * 1e-9) ** 3  # m^3
+M0 = 1.7e6
+N0 = 8.0e14
+
+
+def _sphere_sample(a, vortex):
+    """Lattice sphere with weights normalised to the sphere volume, so the sums
+    approximate the continuum transforms (Sec. 3.1 micromagnetic scaling
+    mu_cell = M_s V_cell with V_cell = V_s / W)."""
+    pos = synth.sphere_lattice(SPHERE_R_NM, a)
+    W = pos.shape[0]
+    vcell = VS / W
+    nuc = np.full(W, N0 * vcell)
+    mag = np.zeros((W, 3))
+    mag[:, 2] = M0 * vcell
+    if vortex:
+        M1 = 5.0 * M0 / (SPHERE_R_NM * 1e-9)  # per metre
+        x, y = pos[:, 0] * 1e-9, pos[:, 1] * 1e-9
+        mag[:, 0] += -M1 * y * vcell
+        mag[:, 1] += M1 * x * vcell
+    return pos, nuc, mag
+
+
+def _polar_averages(orc, pos, nuc, mag, qvals, n_theta=32):
+    qq = np.repeat(qvals, n_theta)
+    th = np.tile(2 * np.pi * np.arange(n_theta) / n_theta, qvals.size)
+    qy, qz = qq * np.sin(th), qq * np.cos(th)
+    qhat = np.stack([np.zeros_like(th), np.sin(th), np.cos(th)], axis=1)
+    A = orc.amplitudes(pos, nuc, mag, qy, qz)
+    o = orc.cross_sections(A, qhat, V=VS, bH=BH, scale=1e-2, P=(0.0, 0.0, 1.0))
+    return {k: v.reshape(qvals.size, n_theta).mean(axis=1) for k, v in o.items()}
+
+
+def test_table1_sphere_intensities_at_q0(orc):
+    """Table I, I(q = 0) column (Sec. 4.1): absolute units (cm^-1), V = V_s,
+    bH of Sec. 2.1; the signed I_NM(0) = -1.326e5 fixes the sign of Q."""
+    tab = _read_table("table1_sphere.txt")
+    pos, nuc, mag = _sphere_sample(2.0, vortex=False)
+    av = _polar_averages(orc, pos, nuc, mag, np.array([1e-7]))
+    for key, (i0, _) in tab.items():
+        got = av[key][0]
+        if i0 == 0:
+            assert abs(got) < 1e-6 * tab["N"][0], key
+        else:
+            # printed to 4 significant digits
+            assert abs(got - i0) <= 0.5e-3 * abs(i0) + 0.0006e5, (key, got, i0)
+
+
+def test_table2_vortex_maxima(orc):
+    """Table II, I_max column (Sec. 4.2): the linear vortex adds M1^2 R^2 g'^2 to
+    the magnetic term (the printed 'M_1 R^2' of the 2D form must be squared, as
+    the averaged form has it).  Lattice a = 1 nm approximates the continuum to
+    ~0.2 %; maxima are printed to 4 digits."""
+    tab = _read_table("table2_vortex.txt")
+    pos, nuc, mag = _sphere_sample(1.0, vortex=True)
+    qvals = np.linspace(0.04, 0.16, 61)  # qR in [0.8, 3.2] brackets the maxima
+    av = _polar_averages(orc, pos, nuc, mag, qvals)
+    for key in ("M", "SF", "PM", "MP", "PLUS"):
+        got = av[key].max()
+        expect = tab[key][1]
+        assert abs(got - expect) <= 4e-3 * expect, (key, got, expect)
+    # the chiral term averages to zero (Sec. 2.5) even though it is nonzero in 2D
+    assert np.max(np.abs(av["CHI"])) < 1e-8 * tab["N"][0]
+
+
+def test_vortex_chiral_term_sign_and_magnitude(orc):
+    """dSigma_chi of the linear vortex, eq. below Sec. 4.2 differential cross
+    sections, with the missing factor R restored: 18 V_s bH^2 M0 M1 R g g'
+    sin^2(theta) cos(theta) (dimensionally required; checked here at one q)."""
+    pos, nuc, mag = _sphere_sample(1.0, vortex=True)
+    R = SPHERE_R_NM * 1e-9
+    M1 = 5.0 * M0 / R
+    q = 0.1  # nm^-1
+    th = np.array([0.3, 1.0, 2.2, 4.0])
+    qy, qz = q * np.sin(th), q * np.cos(th)
+    qhat = np.stack([np.zeros_like(th), np.sin(th), np.cos(th)], axis=1)
+    A = orc.amplitudes(pos, nuc, mag, qy, qz)
+    o = orc.cross_sections(A, qhat, V=VS, bH=BH, scale=1.0, P=(0.0, 0.0, 1.0))
+    v = q * SPHERE_R_NM
+    g = (math.sin(v) - v * math.cos(v)) / v ** 3
+    gp = ((v * v - 3) * math.sin(v) + 3 * v * math.cos(v)) / v ** 4
+    expect = 18 * VS * BH ** 2 * M0 * M1 * R * g * gp * np.sin(th) ** 2 * np.cos(th)
+    assert np.allclose(o["CHI"], expect, rtol=5e-3)
+
+
+# ---------------------------------------------------------------------------
+# Sec. 2.5 azimuthal average and angular spectrum
+# ---------------------------------------------------------------------------
+def test_azimuthal_average_polar_exact(orc):
+    """eq. iqazi by the trapezoidal rule on a periodic theta grid integrates
+    sin^2 -> 1/2, sin^4 -> 3/8, sin^2 cos^2 -> 1/8 exactly (n_theta >= 5)."""
+    nq, nt = 4, 12
+    qy, qz, qhat = orc.pixels(orc.POLAR, nq, nt, 1.0)
+    s, c = qhat[:, 1], qhat[:, 2]
+    f = np.stack([s ** 2, s ** 4, s ** 2 * c ** 2, np.full(s.size, 2.5)])
+    I, cnt = orc.azimuthal_average(orc.POLAR, nq, nt, 1.0, f, nq)
+    assert np.allclose(I[0], 0.5, atol=1e-15)
+    assert np.allclose(I[1], 3.0 / 8.0, atol=1e-15)
+    assert np.allclose(I[2], 1.0 / 8.0, atol=1e-15)
+    assert np.allclose(I[3], 2.5, atol=1e-15)
+    assert np.all(cnt == nt)
+
+
+def test_azimuthal_average_cartesian_annuli(orc):
+    """Cartesian annuli: a constant averages to itself in every non-empty bin,
+    empty bins are NaN with count 0, and the counts add up to the pixels with
+    |q| <= q_max_avg."""
+    n0 = n1 = 32
+    f = np.full((1, n0 * n1), 3.25)
+    I, cnt = orc.azimuthal_average(orc.CARTESIAN, n0, n1, 1.0, f, 40, qmax_avg=1.0)
+    ok = cnt > 0
+    assert np.allclose(I[0, ok], 3.25, rtol=1e-15)
+    assert np.all(np.isnan(I[0, ~ok]))
+    ax = synth_axis = -1.0 + np.arange(n0) * (2.0 / (n0 - 1))
+    qq = np.sqrt(synth_axis[:, None] ** 2 + ax[None, :] ** 2)
+    assert cnt.sum() == int(np.sum(qq <= 1.0))
+
+
+def test_rotation_about_beam_shifts_polar_pattern(orc):
+    """A sample rotation about the beam axis by one angular step rotates the
+    unpolarized 2D pattern by one column (positions AND moments rotate), so its
+    azimuthal average is unchanged (spec pin: averages of a rotated
+    sample)."""
+    cl = synth.random_cloud(150, 6.0, seed=15)
+    nq, nt = 5, 24
+    qy, qz, qhat = orc.pixels(orc.POLAR, nq, nt, 1.0)
+    step = 360.0 / nt
+    a = math.radians(step)
+    Rx = np.array([[1, 0, 0], [0, math.cos(a), -math.sin(a)], [0, math.sin(a), math.cos(a)]])
+    A0 = orc.amplitudes(cl["pos"], cl["nuc"], cl["mag"], qy, qz)
+    A1 = orc.amplitudes(cl["pos"], cl["nuc"], cl["mag"], qy, qz, R=Rx)
+    u0 = orc.cross_sections(A0, qhat)["UNPOL"].reshape(nq, nt)
+    u1 = orc.cross_sections(A1, qhat)["UNPOL"].reshape(nq, nt)
+    # rotating the sample by +a moves the pattern: u1(theta) = u0(theta + a)
+    assert rel(u1, np.roll(u0, -1, axis=1)) < 1e-11 or rel(u1, np.roll(u0, 1, axis=1)) < 1e-11
+    I0, _ = orc.azimuthal_average(orc.POLAR, nq, nt, 1.0, u0.reshape(1, -1), nq)
+    I1, _ = orc.azimuthal_average(orc.POLAR, nq, nt, 1.0, u1.reshape(1, -1), nq)
+    assert rel(I1, I0) < 1e-12
+
+
+def test_angular_spectrum_ratios(orc):
+    """Sec. 2.5: a sin^2 anisotropy gives A0c/A2c = -1 and sin^2 cos^2 gives
+    A0c/A4c = -1 (eqs. CosineSinceIntensities, ModalAmplitudes)."""
+    nq, nt = 3, 16
+    th = 2 * np.pi * np.arange(nt) / nt
+    f1 = np.tile(np.sin(th) ** 2, nq)
+    f2 = np.tile(np.sin(th) ** 2 * np.cos(th) ** 2, nq)
+    Is, Ic = orc.angular_spectrum(f1, nq, nt, 6)
+    assert np.allclose(Ic[:, 0] / Ic[:, 2], -1.0, atol=1e-12)
+    Is, Ic = orc.angular_spectrum(f2, nq, nt, 6)
+    assert np.allclose(Ic[:, 0] / Ic[:, 4], -1.0, atol=1e-12)
+    assert np.max(np.abs(Is)) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# Sec. 2.6 correlation functions
+# ---------------------------------------------------------------------------
+def _sphere_iq(q, Rn):
+    v = q * Rn
+    g = (np.sin(v) - v * np.cos(v)) / v ** 3
+    return g
+
+
+def test_correlation_of_uniform_sphere(orc):
+    """eq. crrad applied to I_N = 9 N0^2 V_s g(qR)^2 gives c(r) = N0^2 (1 - 3 xi/4
+    + xi^3/16) for xi = r/R <= 2 and 0 beyond (Sec. 3.1 r_max check); the
+    p_max of Table I is 2 pi^2 times r^2 c at xi_max = sqrt(105)/5 - 1 (the
+    Table's convention)."""
+    Rn = SPHERE_R_NM
+    q = np.linspace(1e-4, 30.0, 300001)  # nm^-1
+    vs_nm = 4.0 / 3.0 * math.pi * Rn ** 3
+    n0 = N0 * 1e-18  # nm^-2
+    I = 9 * n0 ** 2 * vs_nm * _sphere_iq(q, Rn) ** 2  # nm^-1
+    xi = np.array([0.0, 0.3, 0.9, 1.4, 1.9, 2.3, 3.0])
+    r = xi * Rn
+    c, p = orc.correlation(q, I[None, :], r)
+    expect = np.where(xi <= 2, n0 ** 2 * (1 - 0.75 * xi + xi ** 3 / 16), 0.0)
+    # at r = 0 the integrand decays only as q^-2: truncating at q_max leaves
+    # about 9 V_s / (4 pi^2 R^4 q_max) n0^2 = 1.6e-3 n0^2; for r > 0 j0 oscillates
+    assert abs(c[0, 0] - expect[0]) < 9 * vs_nm / (4 * math.pi ** 2 * Rn ** 4 * q[-1]) * 1.1 * n0 ** 2
+    assert np.allclose(c[0, 1:], expect[1:], atol=2e-4 * n0 ** 2)
+    xim = math.sqrt(105) / 5 - 1
+    c2, p2 = orc.correlation(q, I[None, :], np.array([xim * Rn]), scale=2 * math.pi ** 2)
+    tab = _read_table("table1_sphere.txt")
+    assert abs(p2[0, 0] - tab["N"][1]) < 0.01e-4
+    # f(xi_max) of Sec. 4.1
+    f = lambda x: 0.25 * x ** 2 * (x - 2) ** 2 * (x + 4)
+    assert abs(f(xim) - (144 / 5 - 336 * math.sqrt(105) / 125)) < 1e-12
+
+
+def test_correlation_trapezoid_rule_exact_for_linear(orc):
+    """The trapezoidal rule over (0, 0) and the samples is exact for an integrand
+    linear in q between nodes: I(q) q^2 j0(q r) at r = 0 with I = 1/q gives
+    int_0^qmax q dq = qmax^2/2 (Sec. 2.5 trapezoidal rule)."""
+    q = np.array([0.5, 1.0, 2.0, 3.5])
+    c, p = orc.correlation(q, (1.0 / q)[None, :], np.array([0.0, 1.0]))
+    assert abs(c[0, 0] - (3.5 ** 2 / 2) / (2 * math.pi ** 2)) < 1e-14
+    assert p[0, 0] == 0.0
+
+
+# ---------------------------------------------------------------------------
+# Sec. 3.3 objects: coherent / dilute / split
+# ---------------------------------------------------------------------------
+def test_objects_coherent_dilute_split(orc):
+    """Summation relation of Sec. 3.3: coherent total = sum_k exp(-i q.R r^k) F_k;
+    dilute spectral matrix = sum over single-object runs; with all r^k = 0 and
+    K objects the coherent total equals one merged object; a single object has
+    no interparticle interference."""
+    rng = np.random.default_rng(16)
+    sizes = [7, 12, 5]
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    pos = rng.uniform(-3, 3, (off[-1], 3))
+    nuc = rng.standard_normal(off[-1])
+    mag = rng.standard_normal((off[-1], 3))
+    rk = rng.uniform(-20, 20, (3, 3))
+    R = synth.sample_rotation(30, 60)
+    qy, qz = random_pixels(rng, 30, 1.0)
+    F = orc.amplitudes(pos, nuc, mag, qy, qz, R=R, obj_offsets=off, obj_pos=rk, per_object=True)
+    A = orc.amplitudes(pos, nuc, mag, qy, qz, R=R, obj_offsets=off, obj_pos=rk)
+    tot = np.zeros_like(A)
+    for k in range(3):
+        X = R @ rk[k]
+        ph = np.exp(-1j * (qy * X[1] + qz * X[2]))
+        tot += ph[:, None] * F[k]
+        single = orc.amplitudes(pos[off[k]:off[k + 1]], nuc[off[k]:off[k + 1]], mag[off[k]:off[k + 1]], qy, qz, R=R)
+        assert rel(F[k], single) < 1e-12
+    assert rel(A, tot) < 1e-11
+    merged = orc.amplitudes(pos, nuc, mag, qy, qz, R=R)
+    A0 = orc.amplitudes(pos, nuc, mag, qy, qz, R=R, obj_offsets=off, obj_pos=np.zeros((3, 3)))
+    assert rel(A0, merged) < 1e-12
+    G = orc.spectral(F)
+    Gs = sum(orc.spectral(F[k]) for k in range(3))
+    assert rel(G, Gs) < 1e-12
+    # spectral matrix entries are the products of Sec. 3.4 (G_ab = A_a conj(A_b))
+    assert np.allclose(G[:, 0], sum(np.abs(F[k][:, 0]) ** 2 for k in range(3)))
+    g12 = sum(F[k][:, 1] * np.conj(F[k][:, 2]) for k in range(3))
+    assert np.allclose(G[:, 10] + 1j * G[:, 11], g12)
+
+
+# ---------------------------------------------------------------------------
+# gradient: finite differences
+# ---------------------------------------------------------------------------
+def test_gradient_matches_richardson_finite_differences(orc):
+    """L is a quartic polynomial in any single weight, so the Richardson
+    combination of central differences at h and h/2 is exact up to rounding;
+    it must equal the oracle's chain-rule gradient for nuclear and magnetic
+    components, with a rotation (gradient w.r.t. the unrotated moment)."""
+    rng = np.random.default_rng(17)
+    W = 6
+    pos = rng.uniform(-3, 3, (W, 3))
+    nuc = rng.standard_normal(W)
+    mag = rng.standard_normal((W, 3))
+    qy, qz = random_pixels(rng, 15, 1.0)
+    qhat = orc.qhat_of(qy, qz)
+    T = rng.uniform(0, 5, 15)
+    w = rng.uniform(0.5, 2, 15)
+    R = synth.sample_rotation(25, -40)
+    kw = dict(V=1.3, bH=0.8, scale=1.1, R=R)
+    L, dn, dm = orc.loss_grad(pos, nuc, mag, qy, qz, qhat, T, w, **kw)
+
+    def loss(n_, m_):
+        return orc.loss_grad(pos, n_, m_, qy, qz, qhat, T, w, **kw)[0]
+
+    def fd(fun, h):
+        return (fun(h) - fun(-h)) / (2 * h)
+
+    h = 1e-2
+    for j in range(W):
+        def fn(e, j=j):
+            n2 = nuc.copy(); n2[j] += e
+            return loss(n2, mag)
+        rich = (4 * fd(fn, h / 2) - fd(fn, h)) / 3
+        assert abs(rich - dn[j]) < 1e-8 * (abs(dn[j]) + 1), (j, rich, dn[j])
+        for a in range(3):
+            def fm(e, j=j, a=a):
+                m2 = mag.copy(); m2[j, a] += e
+                return loss(nuc, m2)
+            rich = (4 * fd(fm, h / 2) - fd(fm, h)) / 3
+            assert abs(rich - dm[j, a]) < 1e-8 * (abs(dm[j, a]) + 1), (j, a, rich, dm[j, a])
