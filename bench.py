@@ -1,0 +1,191 @@
+"""Benchmark of the direct-Fourier-sum SANS path on one MI355X.
+
+A step is one pass of the whole hot path over the 64^3 vortex grid on a
+256 x 256 detector (|q_y|, |q_z| <= 2 nm^-1, 262,144 points, 65,536 pixels):
+  sample rotation/assembly, direct Fourier sums (FP64), the 13 cross sections,
+  the 128-bin azimuthal average, the correlation function (256 radii), the
+  regular-grid separable sums on the matrix cores (when built), and the loss
+  gradient through the adjoint sum.
+Every W x P point-pixel sum the step performs counts W*P terms; `value` is
+terms per second of the whole step (G terms/s).  Inputs are resident in HBM
+before timing starts.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP64_VALU = 256 * 2.4e9 * 64 * 2  # 78.6 TFLOP/s: 256 CUs x 64 FP64 FMA lanes x 2 flops x 2.4 GHz
+FLOPS_PER_TERM = 22  # one complex phasor product (6 flops) + 4 complex channel updates (16 flops)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-pixels", type=int, default=1536,
+                    help="pixels of the oracle's bounded sample")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(the multi-GPU layout is described in DESIGN.md)"}))
+        sys.exit(2)
+    import torch
+
+    from paper_2601_18444_amd import numag, synth
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    cfg = synth.vortex_c5()
+    g = cfg["grid"]
+    grid = numag.qgrid(g["kind"], g["n0"], g["n1"], g["qmax"])
+    W = cfg["pos"].shape[0]
+    P = grid.n_pixels
+    sample = numag.Sample(pos=cfg["pos"], nuc=cfg["nuc"], mag=cfg["mag"], device=dev)
+    regular = numag.Sample(nuc=cfg["nuc"], mag=cfg["mag"], regular=cfg["regular"], n_points=W, device=dev)
+    tf = cfg["target_field"]
+    tsample = numag.Sample(pos=tf["pos"], nuc=tf["nuc"], mag=tf["mag"], device=dev)
+    k = numag.consts(V=1.0, bH=1.0, scale=1.0, P=(0.0, 0.0, 1.0))
+    n_bins = cfg["n_bins"]
+
+    # target cross section and loss weights (input preparation, not timed)
+    tamp, _ = numag.amplitudes(tsample, grid)
+    T = numag.cross_section(grid, amp=tamp, c=k, obs=("UNPOL",))[0, 0].clone()
+    qax = -g["qmax"] + torch.arange(g["n0"], dtype=torch.float64, device=dev) * (2 * g["qmax"] / (g["n0"] - 1))
+    qn = torch.sqrt(qax[:, None] ** 2 + qax[None, :] ** 2).reshape(-1)
+    w = torch.where(qn <= g["qmax"], 1.0 / (T + 1e-3 * T.max()) ** 2, torch.zeros_like(T)).contiguous()
+    qb = torch.as_tensor((np.arange(n_bins) + 0.5) * (g["qmax"] / n_bins), device=dev)
+    rr = torch.linspace(0.0, 80.0, 256, dtype=torch.float64, device=dev)
+
+    amp = torch.empty((1, P, 4, 2), dtype=torch.float64, device=dev)
+    amp_sep = torch.empty_like(amp)
+    xs = torch.empty((1, 13, P), dtype=torch.float64, device=dev)
+    I = torch.empty((13, n_bins), dtype=torch.float64, device=dev)
+    cnt = torch.empty(n_bins, dtype=torch.int64, device=dev)
+    have_sep = True
+    try:
+        numag.amplitudes(regular, grid, path=numag.PATH_SEPARABLE_F64, out=amp_sep)
+    except numag.NumagError:
+        have_sep = False
+    torch.cuda.synchronize()
+
+    ev = {"direct": [], "adjoint": [], "separable": []}
+
+    def step(record):
+        def mark():
+            e = torch.cuda.Event(enable_timing=True)
+            e.record()
+            return e
+        e0 = mark() if record else None
+        numag.amplitudes(sample, grid, out=amp)                       # a1-a5
+        e1 = mark() if record else None
+        numag.cross_section(grid, amp=amp, c=k, obs=numag.OBSERVABLES, out=xs)  # a7
+        numag.azimuthal_average(grid, xs[0], n_bins, out=I, count_out=cnt)      # a8
+        numag.correlation(qb, I, rr)                                   # a9
+        e2 = mark() if record else None
+        if have_sep:
+            numag.amplitudes(regular, grid, path=numag.PATH_SEPARABLE_F64, out=amp_sep)  # a10
+        e3 = mark() if record else None
+        numag.grad(sample, grid, k, weight=w, target=T, amp=amp[0])   # a11
+        e4 = mark() if record else None
+        if record:
+            ev["direct"].append((e0, e1))
+            ev["separable"].append((e2, e3))
+            ev["adjoint"].append((e3, e4))
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+
+    def avg_ms(pairs):
+        return float(np.mean([a.elapsed_time(b) for a, b in pairs])) if pairs else float("nan")
+
+    t_direct = avg_ms(ev["direct"])
+    t_adj = avg_ms(ev["adjoint"])
+    t_sep = avg_ms(ev["separable"]) if have_sep else None
+    terms = W * P
+    sums_per_step = 2 + (1 if have_sep else 0)
+    value = sums_per_step * terms / (ms_per_step * 1e-3) / 1e9
+
+    achieved = FLOPS_PER_TERM * terms / (t_direct * 1e-3) / 1e12
+    out = {
+        "metric": "point*q-pixel terms/s (G/s), direct vs batched vs MFMA at rel err <= 1e-5",
+        "value": round(value, 3),
+        "unit": "Gterm/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "vortex grid 64^3 at 1 nm (262144 points), 256x256 detector |q|<=2 nm^-1: "
+                        "direct sums + 13 cross sections + azimuthal average + correlation"
+                        + (" + separable FP64-MFMA sums" if have_sep else "") + " + loss gradient (adjoint)",
+            "points": W, "pixels": P, "sums_per_step": sums_per_step,
+        },
+        "paths": {
+            "direct_Gterm_s": round(terms / (t_direct * 1e-3) / 1e9, 2),
+            "direct_ms": round(t_direct, 4),
+            "adjoint_Gterm_s": round(terms / (t_adj * 1e-3) / 1e9, 2),
+            "adjoint_ms": round(t_adj, 4),
+            "separable_f64_Gterm_s_effective": round(terms / (t_sep * 1e-3) / 1e9, 2) if have_sep else None,
+            "separable_ms": round(t_sep, 4) if have_sep else None,
+        },
+        "roofline": {
+            "kernel": "direct_cartesian_kernel (timed with prep + combine)",
+            "bound": "alu",
+            "achieved": round(achieved, 3),
+            "peak": round(PEAK_FP64_VALU / 1e12, 3),
+            "unit": "TFLOP/s",
+            "frac": round(achieved / (PEAK_FP64_VALU / 1e12), 4),
+            "traffic": None,
+        },
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        rng = np.random.default_rng(0)
+        qy, qz, _ = oracle.pixels(g["kind"], g["n0"], g["n1"], g["qmax"])
+        idx = rng.choice(P, args.cpu_pixels, replace=False)
+        t0 = time.perf_counter()
+        oracle.amplitudes(cfg["pos"], cfg["nuc"], cfg["mag"], qy[idx], qz[idx])
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": round(W * idx.size / dt / 1e9, 5),
+            "unit": "Gterm/s",
+            "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"FP64 oracle direct sums of the same 262144 points at {idx.size} random pixels "
+                      f"of the 256x256 detector ({W * idx.size:.3g} terms, {dt:.1f} s)",
+        }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,229 @@
+/*
+ * numag.h -- C ABI of the MI355X (gfx950) direct-Fourier-sum SANS library.
+ *
+ * The library computes the nuclear and magnetic small-angle neutron
+ * scattering observables of NuMagSANS (Adams & Michels, arXiv 2601.18444)
+ * from user-given point data: nuclear scattering lengths n_j and magnetic
+ * moments m_j at positions x_j of K objects with offsets r^k, after a sample
+ * rotation R, on a 2D detector in the y-z plane (beam along x).
+ *
+ * Conventions (each is the library's reading of the paper):
+ *   - Sums are raw:  S_c(q) = sum_j w_{j,c} exp(-i q . X_j),  c = N, Mx, My, Mz,
+ *     with X_j = R (x_j + r^{k(j)}) (Sec. 3.2 position transform),
+ *     w_{j,N} = n_j and (w_{j,Mx}, w_{j,My}, w_{j,Mz}) = R m_j (moments turn with
+ *     the sample, as the alpha = 90 deg example of Sec. 3.1 requires), and
+ *     q = (0, q_y, q_z) (Sec. 2.1 eq. qdef).  The DSFT prefactor (2 pi)^{-3/2}
+ *     and the 8 pi^3 of the cross sections cancel, and the (W Nbar)^{-1/2}
+ *     normalisation of Sec. 3.3 is undone by its absolute-unit rescale, so
+ *     every cross section is (scale / V) times a quadratic form in S.
+ *   - Halpern-Johnson vector Q = qhat x (qhat x M) (eq. HJdef) for every
+ *     signed term.
+ *   - Cartesian detector: q_i = -qmax + i * (2 qmax / (n - 1)) (FP64, one product
+ *     and one sum, no fused multiply-add); pixel p = i_y * n_z + i_z; the q = 0
+ *     pixel (odd n only) takes qhat = e_z.
+ *   - Polar detector (the paper's (q, theta) grid, Sec. 3.1/3.2):
+ *     q_i = i * qmax / (n_q - 1), theta_m = 2 pi m / n_theta,
+ *     q_y = q sin(theta), q_z = q cos(theta); pixel p = i_q * n_theta + m.
+ *   - Complex numbers are two doubles (re, im).
+ *
+ * Memory: every array argument is DEVICE memory owned by the caller unless the
+ * comment says "host".  The library never frees caller memory.  All work is
+ * enqueued on `stream` (a hipStream_t; NULL is the null stream) and returns
+ * before it completes.  Every entry point validates all arguments before any
+ * work is enqueued; an invalid call returns a negative status, enqueues
+ * nothing and leaves a message for numag_last_error() (per thread).
+ */
+#ifndef NUMAG_H
+#define NUMAG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define NUMAG_OK             0
+#define NUMAG_E_INVALID     -1  /* a bad argument; nothing was enqueued          */
+#define NUMAG_E_WORKSPACE   -2  /* workspace too small; nothing was enqueued     */
+#define NUMAG_E_HIP         -4  /* a HIP runtime call failed                     */
+#define NUMAG_E_UNSUPPORTED -5  /* valid request this build does not implement   */
+
+/* ---- detector kinds ----------------------------------------------------- */
+#define NUMAG_GRID_CARTESIAN 0
+#define NUMAG_GRID_POLAR     1
+
+/* ---- summation paths ---------------------------------------------------- */
+/* Direct sum over points (any point cloud, any rotation, Cartesian or polar
+   detector), FP64 accumulation; the general path. */
+#define NUMAG_PATH_DIRECT         0
+/* Regular-grid separable path: requires sample->regular, R = identity, one
+   object and a Cartesian detector.  The sum over x is a projection and the
+   rest is two dense complex contractions on the matrix cores. */
+#define NUMAG_PATH_SEPARABLE_F64  1  /* FP64 matrix-core contractions        */
+#define NUMAG_PATH_SEPARABLE_BF16X3 2 /* BF16 hi/lo split, 3 products, FP32 acc */
+
+/* ---- object modes (Sec. 3.3, summation relation and dilute limit) -------- */
+#define NUMAG_MODE_COHERENT 0  /* |sum_k exp(-i q.R r^k) F_k|^2                   */
+#define NUMAG_MODE_DILUTE   1  /* sum_k |F_k|^2  (no StructData: r^k unused)      */
+#define NUMAG_MODE_SPLIT    2  /* both: coherent total and the form-factor part   */
+
+/* ---- observables (bit index = order of output rows) ---------------------- */
+#define NUMAG_OBS_N      (1u << 0)   /* eq. NuclearSANS                            */
+#define NUMAG_OBS_M      (1u << 1)   /* eq. MagneticSANS                           */
+#define NUMAG_OBS_NM     (1u << 2)   /* eq. NMdef, nuclear-magnetic interference   */
+#define NUMAG_OBS_P      (1u << 3)   /* eq. PSANSdef                               */
+#define NUMAG_OBS_CHI    (1u << 4)   /* eq. ChiralSANS, the real dSigma_chi        */
+#define NUMAG_OBS_SF     (1u << 5)   /* eq. sfdef, spin-flip M - P                 */
+#define NUMAG_OBS_PP     (1u << 6)   /* ++ = N + NM + P           (Sec. 2.2)       */
+#define NUMAG_OBS_MM     (1u << 7)   /* -- = N - NM + P                            */
+#define NUMAG_OBS_PM     (1u << 8)   /* +- = SF + CHI                              */
+#define NUMAG_OBS_MP     (1u << 9)   /* -+ = SF - CHI                              */
+#define NUMAG_OBS_PLUS   (1u << 10)  /* SANSPOL + = ++ + +-       (Sec. 2.3)       */
+#define NUMAG_OBS_MINUS  (1u << 11)  /* SANSPOL - = -- + -+                        */
+#define NUMAG_OBS_UNPOL  (1u << 12)  /* unpolarized (++ + -- + +- + -+)/2 (Sec. 2.4) */
+#define NUMAG_OBS_ALL    0x1FFFu
+
+/* A regular grid of points (micromagnetic cells): point j = (ix * ny + iy) * nz + iz
+   sits at origin + (ix, iy, iz) * step.  Host struct. */
+typedef struct {
+    int32_t n[3];
+    int32_t reserved;
+    double origin[3];
+    double step[3];
+} numag_regular;
+
+/* Real-space input (Sec. 3.2: NucData, MagData, StructData). */
+typedef struct {
+    int64_t n_points;             /* W >= 0                                           */
+    const double *pos;            /* [W][3] local coordinates x^{kl} (nm); may be NULL
+                                     only when `regular` is given                      */
+    const double *nuc;            /* [W] nuclear scattering lengths, or NULL (channel off) */
+    const double *mag;            /* [W][3] magnetic moments, or NULL (channel off)    */
+    int64_t n_objects;            /* K >= 1                                           */
+    const int64_t *obj_offsets;   /* HOST [K+1] CSR offsets (obj k = points off[k] ..
+                                     off[k+1]-1, off[0] = 0, off[K] = W); NULL iff K = 1 */
+    const double *obj_pos;        /* [K][3] object positions r^k (nm), or NULL (= 0)    */
+    const numag_regular *regular; /* HOST, or NULL: points form this regular grid       */
+} numag_sample;
+
+/* Detector (Sec. 3.1: q_max and resolutions).  Host struct. */
+typedef struct {
+    int32_t kind;                 /* NUMAG_GRID_CARTESIAN or NUMAG_GRID_POLAR          */
+    int32_t n0;                   /* Cartesian: n_y (rows);  polar: n_q  (rows)       */
+    int32_t n1;                   /* Cartesian: n_z (cols);  polar: n_theta (cols)    */
+    int32_t reserved;
+    double qmax;                  /* nm^-1, > 0                                        */
+} numag_qgrid;
+
+/* Constants of the cross sections (Sec. 2.1, Sec. 3.3 absolute-unit rescale).
+   Every observable is (scale / V) times its quadratic form, with one factor bH
+   per magnetic amplitude.  Host struct. */
+typedef struct {
+    double V;                     /* scattering volume, > 0                             */
+    double bH;                    /* magnetic scattering length (2.91e8 A^-1 m^-1 in SI) */
+    double scale;                 /* unit factor (e.g. 1e-2 for m^-1 -> cm^-1)           */
+    double P[3];                  /* polarisation unit vector Phat                      */
+} numag_consts;
+
+/*
+ * Workspace bytes numag_amplitudes / numag_grad need for this request
+ * (0 when none).  Returns 0 and sets numag_last_error() on invalid input.
+ */
+size_t numag_workspace_size(const numag_sample *sample, int64_t n_rot, const numag_qgrid *grid,
+                            int32_t path, int32_t mode);
+
+/*
+ * Direct Fourier sums, Sec. 3.3 (DSFT and its cos/sin split), per object mode
+ * (Sec. 3.3 summation relation and dilute approximation), for n_rot sample
+ * rotations (Sec. 3.1; any R in SO(3)).
+ *   rot       HOST [n_rot][9] row-major rotation matrices, or NULL (identity;
+ *             then n_rot must be 1).  Each must be orthonormal with det +1
+ *             (|R R^T - I| <= 1e-9), else NUMAG_E_INVALID.
+ *   amp_out   [n_rot][P][4] complex (COHERENT, SPLIT): the coherent sums
+ *             S_c = sum_k exp(-i q.R r^k) F_k; NULL in DILUTE mode.
+ *   spec_out  [n_spec][P][16] (DILUTE, SPLIT): the spectral matrix
+ *             G_ab = (1/n_rot) sum_rot sum_k F_{k,a} conj(F_{k,b}) packed as
+ *             [G00 G11 G22 G33, Re G01, Im G01, Re G02, Im G02, Re G03, Im G03,
+ *              Re G12, Im G12, Re G13, Im G13, Re G23, Im G23]; n_spec = K when
+ *             spec_per_object != 0 (one matrix per object, averaged over the
+ *             rotations), else 1 (summed over objects).  NULL in COHERENT mode.
+ *   path      NUMAG_PATH_*; the separable paths need sample->regular, rot NULL,
+ *             K = 1, a Cartesian detector and COHERENT mode.
+ *   workspace device scratch of at least numag_workspace_size() bytes; its
+ *             contents are undefined after the call.
+ * Empty samples (W = 0) are valid and give zeros.
+ */
+int numag_amplitudes(const numag_sample *sample, int64_t n_rot, const double *rot,
+                     const numag_qgrid *grid, int32_t path, int32_t mode, int32_t spec_per_object,
+                     double *amp_out, double *spec_out, void *workspace, size_t ws_bytes,
+                     void *stream);
+
+/*
+ * Cross sections of Sec. 2 (eqs. NuclearSANS, MagneticSANS, HJdef, PSANSdef,
+ * sfdef, ChiralSANS, NMdef; the POLARIS, SANSPOL and unpolarized combinations
+ * of Sec. 2.2-2.4) from n_sets amplitude sets or spectral matrices.
+ *   amp       [n_sets][P][4] complex, or NULL
+ *   spec      [n_sets][P][16] packed spectral matrices (as numag_amplitudes
+ *             writes them), or NULL; exactly one of amp/spec is given.
+ *   obs_mask  NUMAG_OBS_* bits; rows of `out` follow increasing bit order.
+ *   out       [n_sets][popcount(obs_mask)][P] doubles.
+ */
+int numag_cross_section(const numag_qgrid *grid, int64_t n_sets, const double *amp,
+                        const double *spec, const numag_consts *consts, uint32_t obs_mask,
+                        double *out, void *stream);
+
+/*
+ * Azimuthal average, eq. iqazi, for n_f 2D data sets f [n_f][P].
+ * Cartesian detector: equal-width annuli of [0, qmax_avg] (bin b holds
+ *   b*dq <= |q| < (b+1)*dq with dq = qmax_avg / n_bins, |q| = qmax_avg in the last
+ *   bin, |q| > qmax_avg dropped); value = mean of the bin; empty bins are NaN.
+ *   Bin centres are (b + 1/2) dq.
+ * Polar detector: the periodic trapezoidal rule over theta of every q row;
+ *   n_bins must equal n_q and qmax_avg is ignored.
+ *   I_out     [n_f][n_bins];  count_out [n_bins] int64 or NULL.
+ */
+int numag_azimuthal_average(const numag_qgrid *grid, const double *f, int32_t n_f, int32_t n_bins,
+                            double qmax_avg, double *I_out, int64_t *count_out, void *stream);
+
+/*
+ * Correlation and pair-distance distribution functions, eqs. crrad and prrad:
+ *   c(r) = (scale / 2 pi^2) int I(q) j0(q r) q^2 dq,   p(r) = r^2 c(r),
+ * by the trapezoidal rule over the nodes (0, 0) and (q_b, I_b q_b^2 j0(q_b r));
+ * NaN samples of I are skipped.  scale = 1 is eq. crrad as printed; the
+ * p_max values of the paper's Tables I and II correspond to scale = 2 pi^2.
+ *   q [n_q] ascending, I [n_f][n_q], r [n_r];  c_out, p_out [n_f][n_r].
+ */
+int numag_correlation(const double *q, const double *I, int32_t n_q, int32_t n_f, const double *r,
+                      int32_t n_r, double scale, double *c_out, double *p_out, void *stream);
+
+/*
+ * Loss on the unpolarized cross section (Sec. 2.4) and its gradient with
+ * respect to every input weight (the adjoint, i.e. transposed, Fourier sum):
+ *   I_p = (scale/V)(|S_N|^2 + bH^2 |Q|^2),   L = sum_p w_p (I_p - T_p)^2,
+ *   dL/dn_j and dL/dm_j (the unrotated input moments: R^T dL/dm'_j).
+ * One rotation (rot HOST [9] or NULL), COHERENT mode, direct path.
+ *   amp_in    [P][4] complex sums of this sample (as numag_amplitudes writes
+ *             them), or NULL to compute them here.
+ *   target, weight  [P];  loss_out  [1] double (device).
+ *   target NULL: `weight` holds an upstream gradient dL/dI_p instead (the
+ *             backward of an autograd function) and loss_out may be NULL;
+ *   dnuc_out  [W] or NULL;  dmag_out [W][3] or NULL.
+ */
+int numag_grad(const numag_sample *sample, const double *rot, const numag_qgrid *grid,
+               const numag_consts *consts, const double *amp_in, const double *target,
+               const double *weight, double *loss_out, double *dnuc_out, double *dmag_out,
+               void *workspace, size_t ws_bytes, void *stream);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *numag_last_error(void);
+
+/* Library version string. */
+const char *numag_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NUMAG_H */

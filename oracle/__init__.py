@@ -68,12 +68,19 @@ def _load():
         lib.orc_correlation.argtypes = [i64, P, i64, P, i64, P, d, P, P]
         lib.orc_loss_grad.argtypes = [i64, P, P, P, i64, P, P, P, i64, P, P, P, d, d, d, P, P, P, P, P]
         lib.orc_angular_spectrum.argtypes = [i64, i64, P, i64, P, P]
+        lib.orc_threads.argtypes = []
+        lib.orc_threads.restype = ctypes.c_int
         for f in (lib.orc_amplitudes, lib.orc_spectral, lib.orc_cross_sections,
                   lib.orc_azimuthal_average, lib.orc_correlation, lib.orc_loss_grad,
                   lib.orc_angular_spectrum):
             f.restype = None
         _lib = lib
     return _lib
+
+
+def threads() -> int:
+    """OpenMP threads the oracle runs on."""
+    return int(_load().orc_threads())
 
 
 def _ptr(a):

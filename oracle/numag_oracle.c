@@ -38,6 +38,20 @@
 
 typedef double complex cplx;
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Number of OpenMP threads the oracle's parallel loops use. */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Geometry: Sec. 3.2, position transform with object offsets.               */
 /* R is row-major: R[3*a + b] = R_{a+1, b+1}.                                 */

@@ -1,0 +1,391 @@
+// C ABI of the numag library: argument validation, workspace layout and dispatch.
+// Host code only; every numerical step runs in the HIP kernels of this library.
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "numag_internal.h"
+
+namespace numag {
+
+static thread_local std::string g_error;
+
+void set_error(const std::string &msg) { g_error = msg; }
+void clear_error() { g_error.clear(); }
+
+}  // namespace numag
+
+using namespace numag;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t b) { return (b + kAlign - 1) & ~(kAlign - 1); }
+
+struct Carve {
+    char *base;
+    size_t used = 0;
+    explicit Carve(void *p) : base((char *)p) {}
+    void *take(size_t bytes)
+    {
+        void *r = base != nullptr ? base + used : nullptr;
+        used += align_up(bytes);
+        return r;
+    }
+};
+
+int invalid(const std::string &msg)
+{
+    set_error(msg);
+    return NUMAG_E_INVALID;
+}
+
+bool is_finite(double x) { return std::isfinite(x); }
+
+int check_grid(const numag_qgrid *g, const char *fn)
+{
+    if (g == nullptr) return invalid(std::string(fn) + ": grid is NULL");
+    if (g->kind != NUMAG_GRID_CARTESIAN && g->kind != NUMAG_GRID_POLAR)
+        return invalid(std::string(fn) + ": unknown detector kind");
+    if (g->n0 < 1 || g->n1 < 1) return invalid(std::string(fn) + ": detector sizes must be >= 1");
+    if ((int64_t)g->n0 * (int64_t)g->n1 > (int64_t)1 << 30)
+        return invalid(std::string(fn) + ": detector larger than 2^30 pixels");
+    if (!(g->qmax > 0.0) || !is_finite(g->qmax)) return invalid(std::string(fn) + ": qmax must be finite and > 0");
+    return NUMAG_OK;
+}
+
+int check_sample(const numag_sample *s, const char *fn)
+{
+    if (s == nullptr) return invalid(std::string(fn) + ": sample is NULL");
+    if (s->n_points < 0) return invalid(std::string(fn) + ": n_points < 0");
+    if (s->n_objects < 1) return invalid(std::string(fn) + ": n_objects must be >= 1");
+    if (s->regular != nullptr) {
+        const numag_regular &g = *s->regular;
+        if (g.n[0] < 1 || g.n[1] < 1 || g.n[2] < 1)
+            return invalid(std::string(fn) + ": regular grid sizes must be >= 1");
+        if ((int64_t)g.n[0] * g.n[1] * g.n[2] != s->n_points)
+            return invalid(std::string(fn) + ": regular grid size does not match n_points");
+        for (int a = 0; a < 3; ++a)
+            if (!is_finite(g.origin[a]) || !is_finite(g.step[a]))
+                return invalid(std::string(fn) + ": regular grid origin/step not finite");
+    } else if (s->n_points > 0 && s->pos == nullptr) {
+        return invalid(std::string(fn) + ": pos is NULL");
+    }
+    if (s->n_objects > 1) {
+        if (s->obj_offsets == nullptr) return invalid(std::string(fn) + ": obj_offsets required when K > 1");
+        const int64_t *o = s->obj_offsets;
+        if (o[0] != 0 || o[s->n_objects] != s->n_points)
+            return invalid(std::string(fn) + ": obj_offsets must start at 0 and end at n_points");
+        for (int64_t k = 0; k < s->n_objects; ++k)
+            if (o[k + 1] < o[k]) return invalid(std::string(fn) + ": obj_offsets not non-decreasing");
+    }
+    return NUMAG_OK;
+}
+
+int check_rotations(const double *rot, int64_t n_rot, const char *fn)
+{
+    if (n_rot < 1) return invalid(std::string(fn) + ": n_rot must be >= 1");
+    if (rot == nullptr) {
+        if (n_rot != 1) return invalid(std::string(fn) + ": rot NULL requires n_rot == 1");
+        return NUMAG_OK;
+    }
+    for (int64_t r = 0; r < n_rot; ++r) {
+        const double *R = rot + 9 * r;
+        for (int a = 0; a < 9; ++a)
+            if (!is_finite(R[a])) return invalid(std::string(fn) + ": rotation has non-finite entries");
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double dot = R[3 * a] * R[3 * b] + R[3 * a + 1] * R[3 * b + 1] + R[3 * a + 2] * R[3 * b + 2];
+                if (std::fabs(dot - (a == b ? 1.0 : 0.0)) > 1e-9)
+                    return invalid(std::string(fn) + ": rotation matrix is not orthonormal");
+            }
+        double det = R[0] * (R[4] * R[8] - R[5] * R[7]) - R[1] * (R[3] * R[8] - R[5] * R[6]) +
+                     R[2] * (R[3] * R[7] - R[4] * R[6]);
+        if (det < 0.0) return invalid(std::string(fn) + ": rotation matrix has det -1");
+    }
+    return NUMAG_OK;
+}
+
+Rot rot_of(const double *rot, int64_t r)
+{
+    Rot R{};
+    if (rot == nullptr) {
+        R.m[0] = R.m[4] = R.m[8] = 1.0;
+    } else {
+        std::memcpy(R.m, rot + 9 * r, sizeof(R.m));
+    }
+    return R;
+}
+
+bool rot_is_identity(const double *rot)
+{
+    if (rot == nullptr) return true;
+    for (int a = 0; a < 9; ++a)
+        if (rot[a] != ((a % 4) == 0 ? 1.0 : 0.0)) return false;
+    return true;
+}
+
+// Workspace of the coherent direct path for one rotation.
+struct DirectLayout {
+    size_t offsets, points, partial, total;
+};
+
+DirectLayout direct_layout(const numag_sample *s, const Detector &d)
+{
+    DirectLayout L{};
+    const bool need_off = s->n_objects > 1 && s->obj_pos != nullptr;
+    L.offsets = need_off ? align_up((size_t)(s->n_objects + 1) * sizeof(int64_t)) : 0;
+    L.points = align_up((size_t)std::max<int64_t>(s->n_points, 1) * sizeof(PointRec));
+    if (d.kind == NUMAG_GRID_CARTESIAN) {
+        DirectPlan p = plan_direct_cartesian(d, s->n_points);
+        L.partial = p.nsplit > 1 ? align_up(direct_partial_bytes(p, d)) : 0;
+    } else {
+        DirectPlan p = plan_direct_polar(d, s->n_points);
+        L.partial = align_up(direct_partial_bytes(p, d));
+    }
+    L.total = L.offsets + L.points + L.partial;
+    return L;
+}
+
+// Runs prep + direct sum + combine for one rotation into amp (P x 8 doubles).
+int run_direct(const numag_sample *s, const Rot &R, const Detector &d, double *amp, void *ws,
+               hipStream_t st)
+{
+    DirectLayout L = direct_layout(s, d);
+    Carve cv(ws);
+    int64_t *d_off = (int64_t *)cv.take(L.offsets);
+    PointRec *pts = (PointRec *)cv.take(L.points);
+    double *part = (double *)cv.take(L.partial);
+    const int64_t P = (int64_t)d.n0 * d.n1;
+    if (L.offsets != 0)
+        NUMAG_HIP_CHECK(hipMemcpyAsync(d_off, s->obj_offsets, (size_t)(s->n_objects + 1) * sizeof(int64_t),
+                                       hipMemcpyHostToDevice, st));
+    if (s->n_points == 0) {
+        return launch_fill(amp, P * 8, 0.0, st);
+    }
+    int rc = launch_prepare_points(s->pos, s->nuc, s->mag, s->n_points, s->regular,
+                                   L.offsets != 0 ? d_off : nullptr, s->n_objects, s->obj_pos, R, pts, st);
+    if (rc != NUMAG_OK) return rc;
+    if (d.kind == NUMAG_GRID_CARTESIAN) {
+        DirectPlan p = plan_direct_cartesian(d, s->n_points);
+        if (p.nsplit == 1) return launch_direct_cartesian(pts, s->n_points, d, p, amp, st);
+        rc = launch_direct_cartesian(pts, s->n_points, d, p, part, st);
+        if (rc != NUMAG_OK) return rc;
+        return launch_combine(part, p.nsplit, P, amp, 0, st);
+    }
+    DirectPlan p = plan_direct_polar(d, s->n_points);
+    rc = launch_direct_polar(pts, s->n_points, d, p, part, st);
+    if (rc != NUMAG_OK) return rc;
+    return launch_combine(part, p.nsplit, P, amp, 0, st);
+}
+
+size_t amplitudes_ws(const numag_sample *s, int64_t n_rot, const Detector &d, int32_t path, int32_t mode)
+{
+    (void)n_rot;
+    if (path == NUMAG_PATH_SEPARABLE_F64 || path == NUMAG_PATH_SEPARABLE_BF16X3)
+        return align_up(separable_workspace_bytes(*s->regular, d, path));
+    size_t b = 0;
+    if (mode == NUMAG_MODE_COHERENT || mode == NUMAG_MODE_SPLIT) b = direct_layout(s, d).total;
+    return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *numag_last_error(void) { return g_error.c_str(); }
+
+const char *numag_version(void) { return "numag 0.1 (gfx950)"; }
+
+size_t numag_workspace_size(const numag_sample *sample, int64_t n_rot, const numag_qgrid *grid,
+                            int32_t path, int32_t mode)
+{
+    clear_error();
+    if (check_sample(sample, "numag_workspace_size") != NUMAG_OK) return 0;
+    if (check_grid(grid, "numag_workspace_size") != NUMAG_OK) return 0;
+    if (mode < NUMAG_MODE_COHERENT || mode > NUMAG_MODE_SPLIT) {
+        set_error("numag_workspace_size: unknown mode");
+        return 0;
+    }
+    if (path < NUMAG_PATH_DIRECT || path > NUMAG_PATH_SEPARABLE_BF16X3) {
+        set_error("numag_workspace_size: unknown path");
+        return 0;
+    }
+    if (path != NUMAG_PATH_DIRECT && sample->regular == nullptr) {
+        set_error("numag_workspace_size: separable path needs a regular grid");
+        return 0;
+    }
+    Detector d = make_detector(*grid);
+    size_t amp = amplitudes_ws(sample, n_rot, d, path, mode);
+    size_t grad = 0;
+    if (path == NUMAG_PATH_DIRECT && mode == NUMAG_MODE_COHERENT && grid->kind == NUMAG_GRID_CARTESIAN) {
+        // numag_grad: points + amplitudes (when not given) + direct partials + adjoint scratch
+        const int64_t P = (int64_t)grid->n0 * grid->n1;
+        grad = direct_layout(sample, d).total + align_up((size_t)P * 8 * sizeof(double)) +
+               align_up(grad_workspace_bytes(d, sample->n_points));
+    }
+    return std::max(amp, grad);
+}
+
+int numag_amplitudes(const numag_sample *sample, int64_t n_rot, const double *rot, const numag_qgrid *grid,
+                     int32_t path, int32_t mode, int32_t spec_per_object, double *amp_out, double *spec_out,
+                     void *workspace, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    int rc;
+    if ((rc = check_sample(sample, "numag_amplitudes")) != NUMAG_OK) return rc;
+    if ((rc = check_grid(grid, "numag_amplitudes")) != NUMAG_OK) return rc;
+    if ((rc = check_rotations(rot, n_rot, "numag_amplitudes")) != NUMAG_OK) return rc;
+    if (mode < NUMAG_MODE_COHERENT || mode > NUMAG_MODE_SPLIT) return invalid("numag_amplitudes: unknown mode");
+    if (path < NUMAG_PATH_DIRECT || path > NUMAG_PATH_SEPARABLE_BF16X3)
+        return invalid("numag_amplitudes: unknown path");
+    if ((mode == NUMAG_MODE_COHERENT || mode == NUMAG_MODE_SPLIT) && amp_out == nullptr)
+        return invalid("numag_amplitudes: amp_out required in COHERENT/SPLIT mode");
+    if ((mode == NUMAG_MODE_DILUTE || mode == NUMAG_MODE_SPLIT) && spec_out == nullptr)
+        return invalid("numag_amplitudes: spec_out required in DILUTE/SPLIT mode");
+    if (path != NUMAG_PATH_DIRECT) {
+        if (sample->regular == nullptr) return invalid("numag_amplitudes: separable path needs sample->regular");
+        if (!rot_is_identity(rot) || n_rot != 1)
+            return invalid("numag_amplitudes: separable path needs the identity rotation");
+        if (sample->n_objects != 1) return invalid("numag_amplitudes: separable path needs one object");
+        if (grid->kind != NUMAG_GRID_CARTESIAN)
+            return invalid("numag_amplitudes: separable path needs a Cartesian detector");
+        if (mode != NUMAG_MODE_COHERENT) return invalid("numag_amplitudes: separable path is COHERENT only");
+    }
+    Detector d = make_detector(*grid);
+    const size_t need = amplitudes_ws(sample, n_rot, d, path, mode);
+    if (ws_bytes < need || (need > 0 && workspace == nullptr)) {
+        set_error("numag_amplitudes: workspace too small (need " + std::to_string(need) + " bytes)");
+        return NUMAG_E_WORKSPACE;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t P = (int64_t)grid->n0 * grid->n1;
+
+    if (path != NUMAG_PATH_DIRECT)
+        return launch_separable(sample->nuc, sample->mag, *sample->regular, d, path, amp_out, workspace,
+                                ws_bytes, st);
+
+    if (mode == NUMAG_MODE_COHERENT) {
+        for (int64_t r = 0; r < n_rot; ++r) {
+            rc = run_direct(sample, rot_of(rot, r), d, amp_out + r * P * 8, workspace, st);
+            if (rc != NUMAG_OK) return rc;
+        }
+        return NUMAG_OK;
+    }
+    (void)spec_per_object;
+    set_error("numag_amplitudes: DILUTE/SPLIT modes are not available in this build");
+    return NUMAG_E_UNSUPPORTED;
+}
+
+int numag_cross_section(const numag_qgrid *grid, int64_t n_sets, const double *amp, const double *spec,
+                        const numag_consts *consts, uint32_t obs_mask, double *out, void *stream)
+{
+    clear_error();
+    int rc;
+    if ((rc = check_grid(grid, "numag_cross_section")) != NUMAG_OK) return rc;
+    if (n_sets < 0) return invalid("numag_cross_section: n_sets < 0");
+    if ((amp == nullptr) == (spec == nullptr))
+        return invalid("numag_cross_section: give exactly one of amp and spec");
+    if (consts == nullptr) return invalid("numag_cross_section: consts is NULL");
+    if (!(consts->V > 0.0) || !is_finite(consts->V)) return invalid("numag_cross_section: V must be > 0");
+    if (!is_finite(consts->bH) || !is_finite(consts->scale)) return invalid("numag_cross_section: bH/scale not finite");
+    for (int a = 0; a < 3; ++a)
+        if (!is_finite(consts->P[a])) return invalid("numag_cross_section: P not finite");
+    if (obs_mask == 0 || (obs_mask & ~NUMAG_OBS_ALL) != 0)
+        return invalid("numag_cross_section: obs_mask empty or has unknown bits");
+    if (out == nullptr) return invalid("numag_cross_section: out is NULL");
+    return launch_cross_section(make_detector(*grid), n_sets, amp, spec, *consts, obs_mask, out,
+                                (hipStream_t)stream);
+}
+
+int numag_azimuthal_average(const numag_qgrid *grid, const double *f, int32_t n_f, int32_t n_bins,
+                            double qmax_avg, double *I_out, int64_t *count_out, void *stream)
+{
+    clear_error();
+    int rc;
+    if ((rc = check_grid(grid, "numag_azimuthal_average")) != NUMAG_OK) return rc;
+    if (n_f < 0 || n_bins < 1) return invalid("numag_azimuthal_average: need n_f >= 0 and n_bins >= 1");
+    if (n_f > 65535 || n_bins > (1 << 24)) return invalid("numag_azimuthal_average: n_f or n_bins too large");
+    if (f == nullptr && n_f > 0) return invalid("numag_azimuthal_average: f is NULL");
+    if (I_out == nullptr) return invalid("numag_azimuthal_average: I_out is NULL");
+    if (grid->kind == NUMAG_GRID_POLAR) {
+        if (n_bins != grid->n0) return invalid("numag_azimuthal_average: polar detector needs n_bins == n_q");
+    } else if (!(qmax_avg > 0.0) || !is_finite(qmax_avg)) {
+        return invalid("numag_azimuthal_average: qmax_avg must be > 0");
+    }
+    return launch_azimuthal(make_detector(*grid), f, n_f, n_bins, qmax_avg, I_out, count_out,
+                            (hipStream_t)stream);
+}
+
+int numag_correlation(const double *q, const double *I, int32_t n_q, int32_t n_f, const double *r, int32_t n_r,
+                      double scale, double *c_out, double *p_out, void *stream)
+{
+    clear_error();
+    if (n_q < 0 || n_f < 0 || n_r < 0) return invalid("numag_correlation: negative size");
+    if ((n_q > 0 && (q == nullptr || (n_f > 0 && I == nullptr))) || (n_r > 0 && r == nullptr))
+        return invalid("numag_correlation: NULL input");
+    if ((int64_t)n_f * n_r > 0 && (c_out == nullptr || p_out == nullptr))
+        return invalid("numag_correlation: NULL output");
+    if (!is_finite(scale)) return invalid("numag_correlation: scale not finite");
+    return launch_correlation(q, I, n_q, n_f, r, n_r, scale, c_out, p_out, (hipStream_t)stream);
+}
+
+int numag_grad(const numag_sample *sample, const double *rot, const numag_qgrid *grid,
+               const numag_consts *consts, const double *amp_in, const double *target, const double *weight,
+               double *loss_out, double *dnuc_out, double *dmag_out, void *workspace, size_t ws_bytes,
+               void *stream)
+{
+    clear_error();
+    int rc;
+    if ((rc = check_sample(sample, "numag_grad")) != NUMAG_OK) return rc;
+    if ((rc = check_grid(grid, "numag_grad")) != NUMAG_OK) return rc;
+    if ((rc = check_rotations(rot, 1, "numag_grad")) != NUMAG_OK) return rc;
+    if (grid->kind != NUMAG_GRID_CARTESIAN) {
+        set_error("numag_grad: only the Cartesian detector is available in this build");
+        return NUMAG_E_UNSUPPORTED;
+    }
+    if (consts == nullptr || !(consts->V > 0.0)) return invalid("numag_grad: consts missing or V <= 0");
+    if (weight == nullptr) return invalid("numag_grad: weight is required");
+    if (target != nullptr && loss_out == nullptr)
+        return invalid("numag_grad: loss_out is required when a target is given");
+    Detector d = make_detector(*grid);
+    const int64_t P = (int64_t)grid->n0 * grid->n1;
+    DirectLayout L = direct_layout(sample, d);
+    const size_t need = L.total + align_up((size_t)P * 8 * sizeof(double)) +
+                        align_up(grad_workspace_bytes(d, sample->n_points));
+    if (ws_bytes < need || workspace == nullptr) {
+        set_error("numag_grad: workspace too small (need " + std::to_string(need) + " bytes)");
+        return NUMAG_E_WORKSPACE;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    Carve cv(workspace);
+    char *direct_ws = (char *)cv.take(L.total);
+    double *amp = (double *)cv.take((size_t)P * 8 * sizeof(double));
+    void *gws = cv.take(grad_workspace_bytes(d, sample->n_points));
+    const Rot R = rot_of(rot, 0);
+    if (amp_in == nullptr) {
+        rc = run_direct(sample, R, d, amp, direct_ws, st);
+        if (rc != NUMAG_OK) return rc;
+        amp_in = amp;
+    } else {
+        // points only
+        Carve c2(direct_ws);
+        int64_t *d_off = (int64_t *)c2.take(L.offsets);
+        PointRec *pts = (PointRec *)c2.take(L.points);
+        if (L.offsets != 0)
+            NUMAG_HIP_CHECK(hipMemcpyAsync(d_off, sample->obj_offsets,
+                                           (size_t)(sample->n_objects + 1) * sizeof(int64_t),
+                                           hipMemcpyHostToDevice, st));
+        rc = launch_prepare_points(sample->pos, sample->nuc, sample->mag, sample->n_points, sample->regular,
+                                   L.offsets != 0 ? d_off : nullptr, sample->n_objects, sample->obj_pos, R, pts,
+                                   st);
+        if (rc != NUMAG_OK) return rc;
+    }
+    const PointRec *pts = (const PointRec *)(direct_ws + L.offsets);
+    return launch_grad(pts, sample->n_points, d, *consts, amp_in, target, weight, loss_out, dnuc_out, dmag_out,
+                       R, gws, grad_workspace_bytes(d, sample->n_points), st);
+}
+
+}  // extern "C"

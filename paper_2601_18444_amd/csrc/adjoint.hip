@@ -1,0 +1,273 @@
+// Gradient of a loss on the unpolarized cross section (Sec. 2.4) with respect
+// to every input weight: the adjoint (transposed) Fourier sum on gfx950.
+//
+//   I_p = (scale/V)(|S_N|^2 + bH^2 |Q|^2),  Q = -Pp S_M,  L = sum_p w_p (I_p - T_p)^2
+//   dL/dn_j   = Re sum_p a_N(p) exp(-i q_p . X_j),   a_N = 4 w r (scale/V) conj(S_N)
+//   dL/dm'_ja = Re sum_p a_a(p) exp(-i q_p . X_j),   a_a = 4 w r (scale/V) bH^2 conj((Pp S_M)_a)
+// with r = I_p - T_p and m' = R m (so dL/dm = R^T dL/dm').
+//
+// The adjoint sum swaps the roles of points and pixels: a lane owns a few
+// points and walks the detector, row by row; within a row the phasor of the
+// next column is one complex multiply by the point's column-step twiddle, and
+// the row-start phasor is a fresh FP64 sincos.  The residual weights of one
+// row are staged in LDS and read as wave-wide broadcasts.  Twelve FP64 VALU
+// operations per (point, pixel) term, as in the forward sum.
+#include "numag_internal.h"
+
+namespace numag {
+
+__device__ __forceinline__ double2 cmul_a(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+__device__ __forceinline__ double2 twiddle_a(double phi)
+{
+    double s, c;
+    sincos(phi, &s, &c);
+    return make_double2(c, -s);
+}
+
+__device__ __forceinline__ double axis_a(double origin, int i, double step)
+{
+#pragma clang fp contract(off)
+    double t = (double)i * step;
+    return origin + t;
+}
+
+constexpr int kResThreads = 256;
+
+// Residual weights a[p][4 complex] and per-block loss partials.
+__global__ __launch_bounds__(kResThreads) void residual_kernel(Detector d, numag_consts k,
+                                                               const double *__restrict__ amp,
+                                                               const double *__restrict__ target,
+                                                               const double *__restrict__ weight,
+                                                               double *__restrict__ a,
+                                                               double *__restrict__ loss_part)
+{
+    const int64_t P = (int64_t)d.n0 * d.n1;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double lp = 0.0;
+    if (p < P) {
+        const int row = (int)(p / d.n1), col = (int)(p % d.n1);
+        double s, c;
+        const double qy = axis_a(d.origin0, row, d.step0);
+        const double qz = axis_a(d.origin1, col, d.step1);
+        if (qy == 0.0 && qz == 0.0) {
+            s = 0.0;
+            c = 1.0;
+        } else {
+            double qn;
+            {
+#pragma clang fp contract(off)
+                double a2 = qy * qy;
+                double b2 = qz * qz;
+                qn = sqrt(a2 + b2);
+            }
+            s = qy / qn;
+            c = qz / qn;
+        }
+        const double qh[3] = {0.0, s, c};
+        const double *A = amp + p * 8;
+        double Vr[3], Vi[3];
+        for (int x = 0; x < 3; ++x) {
+            double dot_r = qh[0] * A[2] + qh[1] * A[4] + qh[2] * A[6];
+            double dot_i = qh[0] * A[3] + qh[1] * A[5] + qh[2] * A[7];
+            Vr[x] = A[2 + 2 * x] - qh[x] * dot_r;
+            Vi[x] = A[3 + 2 * x] - qh[x] * dot_i;
+        }
+        const double cf = k.scale / k.V;
+        const double b2 = k.bH * k.bH;
+        const double absV2 = Vr[0] * Vr[0] + Vi[0] * Vi[0] + Vr[1] * Vr[1] + Vi[1] * Vi[1] +
+                             Vr[2] * Vr[2] + Vi[2] * Vi[2];
+        const double I = cf * (A[0] * A[0] + A[1] * A[1] + b2 * absV2);
+        // dL/dI_p: 2 w (I - T) for the built-in loss, or the caller's upstream
+        // gradient (held in `weight`) when no target is given.
+        double dLdI;
+        if (target != nullptr) {
+            const double r = I - target[p];
+            const double w = weight[p];
+            lp = w * r * r;
+            dLdI = 2.0 * w * r;
+        } else {
+            dLdI = weight[p];
+        }
+        const double g = 2.0 * dLdI * cf;
+        double *o = a + p * 8;
+        o[0] = g * A[0];
+        o[1] = -g * A[1];
+        for (int x = 0; x < 3; ++x) {
+            o[2 + 2 * x] = g * b2 * Vr[x];
+            o[3 + 2 * x] = -g * b2 * Vi[x];
+        }
+    }
+    __shared__ double s_l[kResThreads];
+    s_l[threadIdx.x] = lp;
+    __syncthreads();
+    for (int w = kResThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s_l[threadIdx.x] += s_l[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss_part[blockIdx.x] = s_l[0];
+}
+
+__global__ void loss_sum_kernel(const double *__restrict__ part, int n, double *__restrict__ loss)
+{
+    __shared__ double s_l[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) acc += part[i];
+    s_l[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s_l[threadIdx.x] += s_l[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[0] = s_l[0];
+}
+
+constexpr int kAdjThreads = 256;
+constexpr int kAdjNPL = 4;      // points per lane
+constexpr int kAdjMaxCols = 512;  // columns staged per LDS pass
+
+// grid.x: point blocks of kAdjThreads * kAdjNPL; grid.y: row ranges.
+__global__ __launch_bounds__(kAdjThreads, 2) void adjoint_cartesian_kernel(
+    const PointRec *__restrict__ pts, int64_t W, Detector d, const double *__restrict__ a,
+    int rows_per_split, double *__restrict__ gpart)
+{
+    __shared__ double s_a[kAdjMaxCols * 8];
+    const int64_t jb = (int64_t)blockIdx.x * kAdjThreads * kAdjNPL + threadIdx.x;
+    const int r0 = blockIdx.y * rows_per_split;
+    const int r1 = min(d.n0, r0 + rows_per_split);
+
+    double Y[kAdjNPL], Z[kAdjNPL];
+    double2 ez0[kAdjNPL], dz[kAdjNPL];
+    double acc[kAdjNPL][4];
+    const double qz0 = axis_a(d.origin1, 0, d.step1);
+#pragma unroll
+    for (int u = 0; u < kAdjNPL; ++u) {
+        const int64_t j = jb + (int64_t)u * kAdjThreads;
+        const bool ok = j < W;
+        Y[u] = ok ? pts[j].Y : 0.0;
+        Z[u] = ok ? pts[j].Z : 0.0;
+        ez0[u] = twiddle_a(qz0 * Z[u]);
+        dz[u] = twiddle_a(d.step1 * Z[u]);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+    }
+
+    for (int row = r0; row < r1; ++row) {
+        const double qy = axis_a(d.origin0, row, d.step0);
+        double2 p[kAdjNPL];
+#pragma unroll
+        for (int u = 0; u < kAdjNPL; ++u) p[u] = cmul_a(twiddle_a(qy * Y[u]), ez0[u]);
+        for (int c0 = 0; c0 < d.n1; c0 += kAdjMaxCols) {
+            const int nc = min(kAdjMaxCols, d.n1 - c0);
+            __syncthreads();
+            const double *src = a + ((int64_t)row * d.n1 + c0) * 8;
+            for (int i = threadIdx.x; i < nc * 8; i += kAdjThreads) s_a[i] = src[i];
+            __syncthreads();
+#pragma unroll 2
+            for (int k = 0; k < nc; ++k) {
+                const double *ak = s_a + k * 8;
+                const double a0r = ak[0], a0i = ak[1], a1r = ak[2], a1i = ak[3];
+                const double a2r = ak[4], a2i = ak[5], a3r = ak[6], a3i = ak[7];
+#pragma unroll
+                for (int u = 0; u < kAdjNPL; ++u) {
+                    acc[u][0] += a0r * p[u].x - a0i * p[u].y;
+                    acc[u][1] += a1r * p[u].x - a1i * p[u].y;
+                    acc[u][2] += a2r * p[u].x - a2i * p[u].y;
+                    acc[u][3] += a3r * p[u].x - a3i * p[u].y;
+                    p[u] = cmul_a(p[u], dz[u]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kAdjNPL; ++u) {
+        const int64_t j = jb + (int64_t)u * kAdjThreads;
+        if (j < W) {
+            double *o = gpart + ((int64_t)blockIdx.y * W + j) * 4;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) o[v] = acc[u][v];
+        }
+    }
+}
+
+__global__ void grad_finalize_kernel(const double *__restrict__ gpart, int nsplit, int64_t W, Rot R,
+                                     double *__restrict__ dnuc, double *__restrict__ dmag)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= W) return;
+    double g[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int s = 0; s < nsplit; ++s)
+        for (int v = 0; v < 4; ++v) g[v] += gpart[((int64_t)s * W + j) * 4 + v];
+    if (dnuc != nullptr) dnuc[j] = g[0];
+    if (dmag != nullptr) {
+        for (int b = 0; b < 3; ++b)
+            dmag[3 * j + b] = R.m[0 * 3 + b] * g[1] + R.m[1 * 3 + b] * g[2] + R.m[2 * 3 + b] * g[3];
+    }
+}
+
+static int adjoint_row_splits(const Detector &d, int64_t W)
+{
+    int64_t pblocks = (W + kAdjThreads * kAdjNPL - 1) / (kAdjThreads * kAdjNPL);
+    if (pblocks < 1) pblocks = 1;
+    int64_t want = (2048 + pblocks - 1) / pblocks;
+    if (want > d.n0) want = d.n0;
+    if (want < 1) want = 1;
+    return (int)want;
+}
+
+size_t grad_workspace_bytes(const Detector &d, int64_t W)
+{
+    const int64_t P = (int64_t)d.n0 * d.n1;
+    const int64_t nres = (P + kResThreads - 1) / kResThreads;
+    const int splits = adjoint_row_splits(d, W);
+    size_t b = 0;
+    b += (size_t)P * 8 * sizeof(double);          // residual weights
+    b += (size_t)(nres + 1) * sizeof(double);      // loss partials
+    b += (size_t)splits * (size_t)W * 4 * sizeof(double);
+    return b + 3 * 256;
+}
+
+int launch_grad(const PointRec *pts, int64_t W, const Detector &d, const numag_consts &c,
+                const double *amp, const double *target, const double *weight, double *loss,
+                double *dnuc, double *dmag, const Rot &R, void *ws, size_t ws_bytes, hipStream_t s)
+{
+    const int64_t P = (int64_t)d.n0 * d.n1;
+    const int64_t nres = (P + kResThreads - 1) / kResThreads;
+    const int splits = adjoint_row_splits(d, W);
+    char *base = (char *)ws;
+    auto take = [&](size_t bytes) {
+        char *r = base;
+        base += (bytes + 255) & ~(size_t)255;
+        return r;
+    };
+    double *a = (double *)take((size_t)P * 8 * sizeof(double));
+    double *lpart = (double *)take((size_t)(nres + 1) * sizeof(double));
+    double *gpart = (double *)take((size_t)splits * (size_t)W * 4 * sizeof(double));
+    if ((size_t)(base - (char *)ws) > ws_bytes) {
+        set_error("numag_grad: workspace too small");
+        return NUMAG_E_WORKSPACE;
+    }
+    hipLaunchKernelGGL(residual_kernel, dim3((unsigned)nres), dim3(kResThreads), 0, s, d, c, amp, target,
+                       weight, a, lpart);
+    NUMAG_HIP_CHECK(hipGetLastError());
+    if (loss != nullptr) {
+        hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(256), 0, s, lpart, (int)nres, loss);
+        NUMAG_HIP_CHECK(hipGetLastError());
+    }
+    if (W <= 0) return NUMAG_OK;
+    const int rows_per = (d.n0 + splits - 1) / splits;
+    const int nsplit = (d.n0 + rows_per - 1) / rows_per;
+    const int64_t pblocks = (W + kAdjThreads * kAdjNPL - 1) / (kAdjThreads * kAdjNPL);
+    hipLaunchKernelGGL(adjoint_cartesian_kernel, dim3((unsigned)pblocks, nsplit), dim3(kAdjThreads), 0, s,
+                       pts, W, d, a, rows_per, gpart);
+    NUMAG_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(grad_finalize_kernel, dim3((unsigned)((W + 255) / 256)), dim3(256), 0, s, gpart,
+                       nsplit, W, R, dnuc, dmag);
+    NUMAG_HIP_CHECK(hipGetLastError());
+    return NUMAG_OK;
+}
+
+}  // namespace numag

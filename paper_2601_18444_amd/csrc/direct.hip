@@ -1,0 +1,478 @@
+// Direct Fourier sums on gfx950: the general (any point cloud, any rotation) path.
+//
+// Sums (Sec. 3.3, DSFT):  S_c(q_p) = sum_j w_{j,c} exp(-i q_p . X_j),  q = (0, q_y, q_z).
+//
+// Cartesian detector.  The phase separates in the lab frame,
+//   exp(-i (q_y Y + q_z Z)) = exp(-i q_y Y) * exp(-i q_z Z),
+// so a term costs one complex multiply for its phasor plus eight FMAs for the
+// four complex channel sums; there is no transcendental per term.  A wave owns
+// A detector rows x (64 lanes * B columns); per point a lane takes its row
+// twiddle exp(-i q_y Y) (wave-uniform, from LDS), its first-column twiddle
+// exp(-i q_z(k_lane) Z) (from LDS) and walks its B columns with the
+// column-step twiddle exp(-i dq_z Z).  Twiddles are generated per chunk of
+// points by the whole workgroup in FP64 (sincos plus short recurrences), and
+// everything is accumulated in FP64: on gfx950 an FP64 FMA issues at the same
+// rate as an unpacked FP32 FMA, so FP64 costs no throughput here and removes
+// the FP32 phase/accumulation error budget entirely.
+//
+// Polar detector (the paper's (q, theta) grid).  The phase q u_m(j) with
+// u_m = Y sin(theta_m) + Z cos(theta_m) is not separable; lanes own theta
+// columns and walk B consecutive q rows with the step twiddle exp(-i dq u).
+//
+// Work is split over point ranges (split-K); a fixed-order FP64 combine sums
+// the partial results, so results are bitwise reproducible.
+#include "numag_internal.h"
+
+namespace numag {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// exp(-i phi) = (cos phi, -sin phi)
+__device__ __forceinline__ double2 twiddle(double phi)
+{
+    double s, c;
+    sincos(phi, &s, &c);
+    return make_double2(c, -s);
+}
+
+// Detector axis value origin + i * step, as one rounded product and one rounded
+// sum (the detector definition; must not be fused).
+__device__ __forceinline__ double axis_value(double origin, int i, double step)
+{
+#pragma clang fp contract(off)
+    double t = (double)i * step;
+    return origin + t;
+}
+
+Detector make_detector(const numag_qgrid &g)
+{
+    Detector d{};
+    d.kind = g.kind;
+    d.n0 = g.n0;
+    d.n1 = g.n1;
+    d.qmax = g.qmax;
+    if (g.kind == NUMAG_GRID_CARTESIAN) {
+        d.step0 = g.n0 > 1 ? (2.0 * g.qmax) / (double)(g.n0 - 1) : 0.0;
+        d.step1 = g.n1 > 1 ? (2.0 * g.qmax) / (double)(g.n1 - 1) : 0.0;
+        d.origin0 = g.n0 > 1 ? -g.qmax : 0.0;
+        d.origin1 = g.n1 > 1 ? -g.qmax : 0.0;
+    } else {
+        d.step0 = g.n0 > 1 ? g.qmax / (double)(g.n0 - 1) : 0.0;
+        d.step1 = 0.0;  // theta_m = (2 pi m) / n_theta, computed as written
+        d.origin0 = 0.0;
+        d.origin1 = 0.0;
+    }
+    return d;
+}
+
+// ---------------------------------------------------------------------------
+// a1: sample assembly and rotation (Sec. 3.2): X = R (x + r^k), w' = (n, R m).
+// ---------------------------------------------------------------------------
+__global__ void prepare_points_kernel(const double *__restrict__ pos, const double *__restrict__ nuc,
+                                      const double *__restrict__ mag, int64_t W, int reg,
+                                      numag_regular g, const int64_t *__restrict__ off, int64_t K,
+                                      const double *__restrict__ obj_pos, Rot R,
+                                      PointRec *__restrict__ out)
+{
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= W) return;
+    double x[3];
+    if (reg) {
+        int64_t nyz = (int64_t)g.n[1] * g.n[2];
+        int64_t ix = j / nyz, rem = j % nyz;
+        int64_t iy = rem / g.n[2], iz = rem % g.n[2];
+        x[0] = g.origin[0] + (double)ix * g.step[0];
+        x[1] = g.origin[1] + (double)iy * g.step[1];
+        x[2] = g.origin[2] + (double)iz * g.step[2];
+    } else {
+        x[0] = pos[3 * j + 0];
+        x[1] = pos[3 * j + 1];
+        x[2] = pos[3 * j + 2];
+    }
+    if (obj_pos != nullptr) {
+        int64_t k = 0;
+        if (K > 1 && off != nullptr) {
+            int64_t lo = 0, hi = K - 1;  // largest k with off[k] <= j
+            while (lo < hi) {
+                int64_t mid = (lo + hi + 1) >> 1;
+                if (off[mid] <= j) lo = mid; else hi = mid - 1;
+            }
+            k = lo;
+        }
+        x[0] += obj_pos[3 * k + 0];
+        x[1] += obj_pos[3 * k + 1];
+        x[2] += obj_pos[3 * k + 2];
+    }
+    PointRec r;
+    r.X = R.m[0] * x[0] + R.m[1] * x[1] + R.m[2] * x[2];
+    r.Y = R.m[3] * x[0] + R.m[4] * x[1] + R.m[5] * x[2];
+    r.Z = R.m[6] * x[0] + R.m[7] * x[1] + R.m[8] * x[2];
+    r.w[0] = nuc != nullptr ? nuc[j] : 0.0;
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0;
+    if (mag != nullptr) {
+        m0 = mag[3 * j + 0];
+        m1 = mag[3 * j + 1];
+        m2 = mag[3 * j + 2];
+    }
+    r.w[1] = R.m[0] * m0 + R.m[1] * m1 + R.m[2] * m2;
+    r.w[2] = R.m[3] * m0 + R.m[4] * m1 + R.m[5] * m2;
+    r.w[3] = R.m[6] * m0 + R.m[7] * m1 + R.m[8] * m2;
+    r.pad = 0.0;
+    out[j] = r;
+}
+
+int launch_prepare_points(const double *pos, const double *nuc, const double *mag, int64_t W,
+                          const numag_regular *regular, const int64_t *d_offsets, int64_t K,
+                          const double *obj_pos, const Rot &R, PointRec *out, hipStream_t s)
+{
+    if (W <= 0) return NUMAG_OK;
+    numag_regular g{};
+    if (regular != nullptr) g = *regular;
+    const int tpb = 256;
+    int64_t blocks = (W + tpb - 1) / tpb;
+    hipLaunchKernelGGL(prepare_points_kernel, dim3((unsigned)blocks), dim3(tpb), 0, s, pos, nuc, mag, W,
+                       regular != nullptr ? 1 : 0, g, d_offsets, K, obj_pos, R, out);
+    NUMAG_HIP_CHECK(hipGetLastError());
+    return NUMAG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// a4: Cartesian direct sum.
+// ---------------------------------------------------------------------------
+constexpr int kChunk = 32;     // points staged per LDS chunk
+constexpr int kWaves = 4;      // waves per workgroup
+constexpr int kThreads = 64 * kWaves;
+
+template <int A, int B>
+__global__ __launch_bounds__(kThreads, 2) void direct_cartesian_kernel(
+    const PointRec *__restrict__ pts, int64_t W, int64_t per, Detector d, double *__restrict__ out)
+{
+    constexpr int ROWS = kWaves * A;
+    __shared__ double2 s_tz[kChunk][64];
+    __shared__ double2 s_ty[kChunk][ROWS];
+    __shared__ double2 s_dz[kChunk];
+    __shared__ double s_w[kChunk][4];
+
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int wave = t >> 6;
+    const int col0 = blockIdx.x * 64 * B;
+    const int row0 = blockIdx.y * ROWS;
+    const int64_t jbeg = (int64_t)blockIdx.z * per;
+    const int64_t jend = min(W, jbeg + per);
+
+    double acc[A][B][8];
+#pragma unroll
+    for (int r = 0; r < A; ++r)
+#pragma unroll
+        for (int c = 0; c < B; ++c)
+#pragma unroll
+            for (int v = 0; v < 8; ++v) acc[r][c][v] = 0.0;
+
+    const double bstep = (double)B * d.step1;  // exact: B is a power of two
+
+    for (int64_t j0 = jbeg; j0 < jend; j0 += kChunk) {
+        const int nk = (int)min((int64_t)kChunk, jend - j0);
+        __syncthreads();
+        // ---- twiddles of this chunk -------------------------------------------
+        {
+            // first-column twiddles of the 64 lanes: 8 segments of 8 lanes per point
+            const int jj = t >> 3, seg = t & 7;
+            const double z = jj < nk ? pts[j0 + jj].Z : 0.0;
+            const double qs = axis_value(d.origin1, col0 + seg * 8 * B, d.step1);
+            double2 e = twiddle(qs * z);
+            const double2 st = twiddle(bstep * z);
+#pragma unroll
+            for (int l = 0; l < 8; ++l) {
+                s_tz[jj][seg * 8 + l] = e;
+                e = cmul(e, st);
+            }
+        }
+        for (int it = t; it < kChunk * ROWS; it += kThreads) {
+            const int jj = it / ROWS, r = it % ROWS;
+            const double y = jj < nk ? pts[j0 + jj].Y : 0.0;
+            const double qy = axis_value(d.origin0, row0 + r, d.step0);
+            s_ty[jj][r] = twiddle(qy * y);
+        }
+        if (t < kChunk) {
+            const bool ok = t < nk;
+            const double z = ok ? pts[j0 + t].Z : 0.0;
+            s_dz[t] = twiddle(d.step1 * z);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) s_w[t][v] = ok ? pts[j0 + t].w[v] : 0.0;
+        }
+        __syncthreads();
+        // ---- accumulate -----------------------------------------------------
+#pragma unroll 2
+        for (int jj = 0; jj < nk; ++jj) {
+            const double2 ez = s_tz[jj][lane];
+            const double2 dz = s_dz[jj];
+            const double w0 = s_w[jj][0], w1 = s_w[jj][1], w2 = s_w[jj][2], w3 = s_w[jj][3];
+#pragma unroll
+            for (int r = 0; r < A; ++r) {
+                const double2 ey = s_ty[jj][wave * A + r];
+                double2 p = cmul(ey, ez);
+#pragma unroll
+                for (int c = 0; c < B; ++c) {
+                    acc[r][c][0] += w0 * p.x;
+                    acc[r][c][1] += w0 * p.y;
+                    acc[r][c][2] += w1 * p.x;
+                    acc[r][c][3] += w1 * p.y;
+                    acc[r][c][4] += w2 * p.x;
+                    acc[r][c][5] += w2 * p.y;
+                    acc[r][c][6] += w3 * p.x;
+                    acc[r][c][7] += w3 * p.y;
+                    if (c + 1 < B) p = cmul(p, dz);
+                }
+            }
+        }
+    }
+
+    const int64_t P = (int64_t)d.n0 * d.n1;
+    double *dst = out + (int64_t)blockIdx.z * P * 8;
+#pragma unroll
+    for (int r = 0; r < A; ++r) {
+        const int row = row0 + wave * A + r;
+#pragma unroll
+        for (int c = 0; c < B; ++c) {
+            const int col = col0 + lane * B + c;
+            if (row < d.n0 && col < d.n1) {
+                double *o = dst + ((int64_t)row * d.n1 + col) * 8;
+#pragma unroll
+                for (int v = 0; v < 8; ++v) o[v] = acc[r][c][v];
+            }
+        }
+    }
+}
+
+static int target_workgroups()
+{
+    static int cached = -1;
+    if (cached < 0) {
+        const char *e = getenv("NUMAG_TARGET_WGS");
+        cached = e != nullptr ? atoi(e) : 0;
+        if (cached <= 0) cached = 2048;
+    }
+    return cached;
+}
+
+DirectPlan plan_direct_cartesian(const Detector &d, int64_t W)
+{
+    DirectPlan p{};
+    int B = 1;
+    while (B < 8 && 64 * B < d.n1) B *= 2;
+    p.B = B;
+    p.A = 8 / B;
+    p.col_blocks = (d.n1 + 64 * B - 1) / (64 * B);
+    p.row_blocks = (d.n0 + kWaves * p.A - 1) / (kWaves * p.A);
+    int64_t blocks = (int64_t)p.col_blocks * p.row_blocks;
+    int64_t want = (target_workgroups() + blocks - 1) / blocks;
+    // each split should own a few chunks
+    int64_t max_split = (W + 4 * kChunk - 1) / (4 * kChunk);
+    if (max_split < 1) max_split = 1;
+    if (want > max_split) want = max_split;
+    if (want > 65535) want = 65535;
+    if (want < 1) want = 1;
+    int64_t per = (W + want - 1) / want;
+    per = ((per + kChunk - 1) / kChunk) * kChunk;
+    if (per < kChunk) per = kChunk;
+    p.per = per;
+    p.nsplit = (int)((W + per - 1) / per);
+    if (p.nsplit < 1) p.nsplit = 1;
+    return p;
+}
+
+size_t direct_partial_bytes(const DirectPlan &p, const Detector &d)
+{
+    return (size_t)p.nsplit * (size_t)d.n0 * (size_t)d.n1 * 8 * sizeof(double);
+}
+
+int launch_direct_cartesian(const PointRec *pts, int64_t W, const Detector &d, const DirectPlan &p,
+                            double *partial, hipStream_t s)
+{
+    dim3 grid(p.col_blocks, p.row_blocks, p.nsplit);
+    dim3 block(kThreads);
+#define NUMAG_LAUNCH_CART(AA, BB)                                                            \
+    hipLaunchKernelGGL((direct_cartesian_kernel<AA, BB>), grid, block, 0, s, pts, W, p.per, d, \
+                       partial)
+    switch (p.B) {
+        case 1: NUMAG_LAUNCH_CART(8, 1); break;
+        case 2: NUMAG_LAUNCH_CART(4, 2); break;
+        case 4: NUMAG_LAUNCH_CART(2, 4); break;
+        default: NUMAG_LAUNCH_CART(1, 8); break;
+    }
+#undef NUMAG_LAUNCH_CART
+    NUMAG_HIP_CHECK(hipGetLastError());
+    return NUMAG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Polar direct sum: lanes own theta columns, each walks B q rows.
+// ---------------------------------------------------------------------------
+constexpr int kPolarChunk = 8;
+constexpr int kPolarB = 8;
+
+__global__ __launch_bounds__(kThreads, 2) void direct_polar_kernel(const PointRec *__restrict__ pts,
+                                                                   int64_t W, int64_t per, Detector d,
+                                                                   double *__restrict__ out)
+{
+    constexpr int B = kPolarB;
+    constexpr int ROWS = kWaves * B;
+    __shared__ double2 s_start[kPolarChunk][kWaves][64];
+    __shared__ double2 s_step[kPolarChunk][64];
+    __shared__ double s_w[kPolarChunk][4];
+
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int wave = t >> 6;
+    const int col0 = blockIdx.x * 64;
+    const int row0 = blockIdx.y * ROWS;
+    const int64_t jbeg = (int64_t)blockIdx.z * per;
+    const int64_t jend = min(W, jbeg + per);
+
+    double acc[B][8];
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+        for (int v = 0; v < 8; ++v) acc[r][v] = 0.0;
+
+    // generation role: thread t handles column (t & 63) for points (t >> 6) + 4 i
+    const int gcol = col0 + lane;
+    const double theta = (2.0 * 3.141592653589793 * (double)gcol) / (double)d.n1;
+    double sth, cth;
+    sincos(theta, &sth, &cth);
+    const double q0 = axis_value(0.0, row0, d.step0);
+
+    for (int64_t j0 = jbeg; j0 < jend; j0 += kPolarChunk) {
+        const int nk = (int)min((int64_t)kPolarChunk, jend - j0);
+        __syncthreads();
+        for (int jj = wave; jj < kPolarChunk; jj += kWaves) {
+            const bool ok = jj < nk;
+            const double Y = ok ? pts[j0 + jj].Y : 0.0;
+            const double Z = ok ? pts[j0 + jj].Z : 0.0;
+            const double u = Y * sth + Z * cth;
+            const double2 step = twiddle(d.step0 * u);
+            double2 st = twiddle(q0 * u);
+            // step^B by squaring (B = 8)
+            double2 sb = cmul(step, step);
+            sb = cmul(sb, sb);
+            sb = cmul(sb, sb);
+            s_step[jj][lane] = step;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) {
+                s_start[jj][w][lane] = st;
+                st = cmul(st, sb);
+            }
+        }
+        if (t < kPolarChunk) {
+            const bool ok = t < nk;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) s_w[t][v] = ok ? pts[j0 + t].w[v] : 0.0;
+        }
+        __syncthreads();
+        for (int jj = 0; jj < nk; ++jj) {
+            double2 p = s_start[jj][wave][lane];
+            const double2 step = s_step[jj][lane];
+            const double w0 = s_w[jj][0], w1 = s_w[jj][1], w2 = s_w[jj][2], w3 = s_w[jj][3];
+#pragma unroll
+            for (int r = 0; r < B; ++r) {
+                acc[r][0] += w0 * p.x;
+                acc[r][1] += w0 * p.y;
+                acc[r][2] += w1 * p.x;
+                acc[r][3] += w1 * p.y;
+                acc[r][4] += w2 * p.x;
+                acc[r][5] += w2 * p.y;
+                acc[r][6] += w3 * p.x;
+                acc[r][7] += w3 * p.y;
+                if (r + 1 < B) p = cmul(p, step);
+            }
+        }
+    }
+    const int64_t P = (int64_t)d.n0 * d.n1;
+    double *dst = out + (int64_t)blockIdx.z * P * 8;
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+        const int row = row0 + wave * B + r;
+        if (row < d.n0 && gcol < d.n1) {
+            double *o = dst + ((int64_t)row * d.n1 + gcol) * 8;
+#pragma unroll
+            for (int v = 0; v < 8; ++v) o[v] = acc[r][v];
+        }
+    }
+}
+
+DirectPlan plan_direct_polar(const Detector &d, int64_t W)
+{
+    DirectPlan p{};
+    p.A = 1;
+    p.B = kPolarB;
+    p.col_blocks = (d.n1 + 63) / 64;
+    p.row_blocks = (d.n0 + kWaves * kPolarB - 1) / (kWaves * kPolarB);
+    int64_t blocks = (int64_t)p.col_blocks * p.row_blocks;
+    int64_t want = (target_workgroups() + blocks - 1) / blocks;
+    int64_t max_split = (W + 8 * kPolarChunk - 1) / (8 * kPolarChunk);
+    if (max_split < 1) max_split = 1;
+    if (want > max_split) want = max_split;
+    if (want > 65535) want = 65535;
+    if (want < 1) want = 1;
+    int64_t per = (W + want - 1) / want;
+    per = ((per + kPolarChunk - 1) / kPolarChunk) * kPolarChunk;
+    if (per < kPolarChunk) per = kPolarChunk;
+    p.per = per;
+    p.nsplit = (int)((W + per - 1) / per);
+    if (p.nsplit < 1) p.nsplit = 1;
+    return p;
+}
+
+int launch_direct_polar(const PointRec *pts, int64_t W, const Detector &d, const DirectPlan &p,
+                        double *partial, hipStream_t s)
+{
+    dim3 grid(p.col_blocks, p.row_blocks, p.nsplit);
+    hipLaunchKernelGGL(direct_polar_kernel, grid, dim3(kThreads), 0, s, pts, W, p.per, d, partial);
+    NUMAG_HIP_CHECK(hipGetLastError());
+    return NUMAG_OK;
+}
+
+__global__ void fill_kernel(double *__restrict__ out, int64_t n, double value)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = value;
+}
+
+int launch_fill(double *out, int64_t n, double value, hipStream_t s)
+{
+    if (n <= 0) return NUMAG_OK;
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, n, value);
+    NUMAG_HIP_CHECK(hipGetLastError());
+    return NUMAG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// a5: fixed-order FP64 combine of split partials.
+// ---------------------------------------------------------------------------
+__global__ void combine_kernel(const double *__restrict__ part, int nsplit, int64_t n,
+                               double *__restrict__ out, int accumulate)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = accumulate ? out[i] : 0.0;
+    for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * n + i];
+    out[i] = s;
+}
+
+int launch_combine(const double *part, int nsplit, int64_t P, double *out, int accumulate,
+                   hipStream_t s)
+{
+    int64_t n = P * 8;
+    if (n <= 0) return NUMAG_OK;
+    int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(combine_kernel, dim3((unsigned)blocks), dim3(256), 0, s, part, nsplit, n, out,
+                       accumulate);
+    NUMAG_HIP_CHECK(hipGetLastError());
+    return NUMAG_OK;
+}
+
+}  // namespace numag

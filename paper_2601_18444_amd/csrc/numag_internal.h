@@ -1,0 +1,132 @@
+// Internal declarations of the numag HIP library (gfx950).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/numag.h"
+
+namespace numag {
+
+// ---------------------------------------------------------------------------
+// Error reporting (thread-local message behind numag_last_error()).
+// ---------------------------------------------------------------------------
+void set_error(const std::string &msg);
+void clear_error();
+
+#define NUMAG_HIP_CHECK(expr)                                                        \
+    do {                                                                             \
+        hipError_t err_ = (expr);                                                    \
+        if (err_ != hipSuccess) {                                                    \
+            ::numag::set_error(std::string(#expr) + ": " + hipGetErrorString(err_)); \
+            return NUMAG_E_HIP;                                                      \
+        }                                                                            \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Detector descriptor passed by value to kernels.
+// q(i) = -qmax + i * step on both Cartesian axes (step = 2 qmax / (n - 1));
+// polar: q(i) = i * step with step = qmax / (n_q - 1), theta_m = m * dtheta.
+// ---------------------------------------------------------------------------
+struct Detector {
+    int kind;
+    int n0, n1;
+    double qmax;
+    double step0, step1;   // Cartesian: axis steps (rows, cols); polar: q step, theta step
+    double origin0, origin1;
+};
+
+Detector make_detector(const numag_qgrid &g);
+
+// Row-major 3x3 rotation as a kernel argument.
+struct Rot {
+    double m[9];
+};
+
+// Per-point record written by the preparation kernel: lab-frame position
+// (X, Y, Z) and lab-frame weights (n, m'x, m'y, m'z), padded to 64 bytes.
+struct alignas(64) PointRec {
+    double X, Y, Z;
+    double w[4];
+    double pad;
+};
+
+// ---------------------------------------------------------------------------
+// Launchers (each enqueues on `stream`, returns NUMAG_OK or NUMAG_E_HIP).
+// ---------------------------------------------------------------------------
+
+// a1: X_j = R (x_j + r^{k(j)}), w'_j = (n_j, R m_j).  obj_index maps point -> object
+// via device CSR offsets (nullptr when K == 1 or no object positions).
+int launch_prepare_points(const double *pos, const double *nuc, const double *mag, int64_t W,
+                          const numag_regular *regular, const int64_t *d_offsets, int64_t K,
+                          const double *obj_pos, const Rot &R, PointRec *out, hipStream_t s);
+
+// a4/a5: direct Cartesian sum.  Writes [nsplit][P][8] partial sums (or the final
+// [P][8] sums when nsplit == 1) for points [0, W).
+struct DirectPlan {
+    int A, B;        // rows per wave, columns per lane
+    int nsplit;      // point ranges summed by different workgroups
+    int64_t per;     // points per split (multiple of the chunk)
+    int col_blocks, row_blocks;
+};
+DirectPlan plan_direct_cartesian(const Detector &d, int64_t W);
+size_t direct_partial_bytes(const DirectPlan &p, const Detector &d);
+int launch_direct_cartesian(const PointRec *pts, int64_t W, const Detector &d, const DirectPlan &p,
+                            double *partial, hipStream_t s);
+
+// Polar detector direct sum: [nsplit][P][8] partials.
+DirectPlan plan_direct_polar(const Detector &d, int64_t W);
+int launch_direct_polar(const PointRec *pts, int64_t W, const Detector &d, const DirectPlan &p,
+                        double *partial, hipStream_t s);
+
+// out[i] = value for i < n (a kernel, so that callers may capture it in a graph).
+int launch_fill(double *out, int64_t n, double value, hipStream_t s);
+
+// Fixed-order sum of split partials: out[p][v] = sum_s part[s][p][v] (v < 8),
+// optionally added to `out` (accumulate != 0).
+int launch_combine(const double *part, int nsplit, int64_t P, double *out, int accumulate,
+                   hipStream_t s);
+
+// a6: one workgroup item per (object, pixel block, rotation group); sums are
+// complete per object and accumulated into exclusive slots:
+//   spec_slot[g][P][16] += F F^H  and (coherent part) amp_slot[g][P][8] += e^{-iq.R r^k} F.
+struct ObjectPlan {
+    int A, B;
+    int row_blocks, col_blocks;
+    int n_groups;          // slot groups (objects or rotations are split over them)
+    int64_t n_items;
+    int per_object_slots;  // slot index = object (spec per object) or group
+};
+int launch_objects(const double *pos, const double *nuc, const double *mag, int64_t W,
+                   const int64_t *d_offsets, const int64_t *h_offsets, int64_t K,
+                   const double *obj_pos, const double *d_rot, int64_t n_rot, const Detector &d,
+                   int mode, int spec_per_object, double *spec_slots, double *amp_slots,
+                   int n_groups, int *d_items, int *d_counter, hipStream_t s);
+
+// a7: cross sections from amplitudes ([n_sets][P][8]) or spectra ([n_sets][P][16]).
+int launch_cross_section(const Detector &d, int64_t n_sets, const double *amp, const double *spec,
+                         const numag_consts &c, uint32_t mask, double *out, hipStream_t s);
+
+// a8
+int launch_azimuthal(const Detector &d, const double *f, int n_f, int n_bins, double qmax_avg,
+                     double *I, int64_t *count, hipStream_t s);
+
+// a9
+int launch_correlation(const double *q, const double *I, int n_q, int n_f, const double *r, int n_r,
+                       double scale, double *c, double *p, hipStream_t s);
+
+// a11: residual weights, loss, adjoint sum.
+int launch_grad(const PointRec *pts, int64_t W, const Detector &d, const numag_consts &c,
+                const double *amp, const double *target, const double *weight, double *loss,
+                double *dnuc, double *dmag, const Rot &R, void *ws, size_t ws_bytes, hipStream_t s);
+size_t grad_workspace_bytes(const Detector &d, int64_t W);
+
+// a10: regular-grid separable path on the matrix cores.
+int launch_separable(const double *nuc, const double *mag, const numag_regular &g, const Detector &d,
+                     int path, double *amp, void *ws, size_t ws_bytes, hipStream_t s);
+size_t separable_workspace_bytes(const numag_regular &g, const Detector &d, int path);
+
+}  // namespace numag

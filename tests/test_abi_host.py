@@ -1,0 +1,117 @@
+"""Host-side tests of the C ABI: the library loads, exports every symbol the
+header declares, and rejects invalid arguments before any GPU work (so these
+run without a GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "numag.h")
+LIB = os.path.join(ROOT, "paper_2601_18444_amd", "libnumag.so")
+
+if not os.path.exists(LIB):  # pragma: no cover
+    pytest.skip("libnumag.so not built (run __graft_entry__.build())", allow_module_level=True)
+
+from paper_2601_18444_amd import numag  # noqa: E402
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(numag_[a-z_0-9]+)\s*\(", text, re.M)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert {"numag_amplitudes", "numag_cross_section", "numag_azimuthal_average", "numag_correlation",
+            "numag_grad", "numag_workspace_size", "numag_last_error", "numag_version"} <= set(names)
+    lib = ctypes.CDLL(LIB)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert "gfx950" in numag.version()
+
+
+def _cpu_sample(W=10, K=1, offsets=None):
+    s = numag.CSample()
+    s.n_points = W
+    s.pos = ctypes.c_void_p(0x1000) if W else None  # never dereferenced by validation
+    s.nuc = None
+    s.mag = None
+    s.n_objects = K
+    s.obj_offsets = offsets.ctypes.data_as(ctypes.c_void_p) if offsets is not None else None
+    s.obj_pos = None
+    s.regular = None
+    return s
+
+
+def _call_amp(sample, grid, rot=None, n_rot=1, mode=0, path=0, amp=0x2000, spec=None, ws=None, nws=0):
+    r = rot.ctypes.data_as(ctypes.c_void_p) if rot is not None else None
+    return numag._lib.numag_amplitudes(ctypes.byref(sample) if sample is not None else None, n_rot, r,
+                                       ctypes.byref(grid) if grid is not None else None, path, mode, 0,
+                                       ctypes.c_void_p(amp) if amp else None,
+                                       ctypes.c_void_p(spec) if spec else None,
+                                       ctypes.c_void_p(ws) if ws else None, nws, None)
+
+
+def test_invalid_arguments_are_rejected_without_gpu_work():
+    grid = numag.qgrid(0, 8, 8, 1.0)
+    s = _cpu_sample()
+    assert _call_amp(None, grid) == numag.E_INVALID
+    assert "sample is NULL" in numag.last_error()
+    assert _call_amp(s, None) == numag.E_INVALID
+    assert _call_amp(s, numag.qgrid(0, 0, 8, 1.0)) == numag.E_INVALID
+    assert _call_amp(s, numag.qgrid(0, 8, 8, -1.0)) == numag.E_INVALID
+    assert _call_amp(s, numag.qgrid(7, 8, 8, 1.0)) == numag.E_INVALID
+    bad = np.eye(3) * 1.01
+    assert _call_amp(s, grid, rot=bad) == numag.E_INVALID
+    assert "orthonormal" in numag.last_error()
+    refl = np.diag([1.0, 1.0, -1.0])
+    assert _call_amp(s, grid, rot=refl) == numag.E_INVALID
+    assert _call_amp(s, grid, n_rot=2) == numag.E_INVALID
+    assert _call_amp(s, grid, amp=None) == numag.E_INVALID  # amp_out required in COHERENT mode
+    assert _call_amp(s, grid, mode=1, amp=None, spec=None) == numag.E_INVALID
+    assert _call_amp(s, grid, mode=9) == numag.E_INVALID
+    assert _call_amp(s, grid, path=1) == numag.E_INVALID  # separable needs a regular grid
+    off = np.array([0, 4, 3, 10], dtype=np.int64)
+    assert _call_amp(_cpu_sample(10, 3, off), grid) == numag.E_INVALID
+    off = np.array([0, 4, 10], dtype=np.int64)
+    assert _call_amp(_cpu_sample(11, 2, off), grid) == numag.E_INVALID
+
+
+def test_workspace_size_and_too_small_workspace():
+    grid = numag.qgrid(0, 64, 64, 1.0)
+    s = _cpu_sample(W=100000)
+    n = numag._lib.numag_workspace_size(ctypes.byref(s), 1, ctypes.byref(grid), 0, 0)
+    assert n >= 100000 * 64
+    assert _call_amp(s, grid, ws=0x3000, nws=1000) == numag.E_WORKSPACE
+    assert "workspace too small" in numag.last_error()
+    # degenerate sizes plan without dividing by zero (empty sample, 1x1 detector, polar)
+    for W in (0, 1, 31, 33):
+        for g in (numag.qgrid(0, 1, 1, 1.0), numag.qgrid(0, 3, 700, 1.0), numag.qgrid(1, 5, 9, 1.0)):
+            e = _cpu_sample(W=W)
+            n = numag._lib.numag_workspace_size(ctypes.byref(e), 1, ctypes.byref(g), 0, 0)
+            assert n > 0, (W, g.kind)
+
+
+def test_other_entry_points_validate():
+    grid = numag.qgrid(0, 8, 8, 1.0)
+    c = numag.consts()
+    lib = numag._lib
+    assert lib.numag_cross_section(ctypes.byref(grid), 1, None, None, ctypes.byref(c), 1, ctypes.c_void_p(8),
+                                   None) == numag.E_INVALID
+    assert lib.numag_cross_section(ctypes.byref(grid), 1, ctypes.c_void_p(8), None, ctypes.byref(c), 0,
+                                   ctypes.c_void_p(8), None) == numag.E_INVALID
+    bad = numag.consts(V=0.0)
+    assert lib.numag_cross_section(ctypes.byref(grid), 1, ctypes.c_void_p(8), None, ctypes.byref(bad), 1,
+                                   ctypes.c_void_p(8), None) == numag.E_INVALID
+    assert lib.numag_azimuthal_average(ctypes.byref(grid), ctypes.c_void_p(8), 1, 0, 1.0, ctypes.c_void_p(8),
+                                       None, None) == numag.E_INVALID
+    pol = numag.qgrid(1, 8, 16, 1.0)
+    assert lib.numag_azimuthal_average(ctypes.byref(pol), ctypes.c_void_p(8), 1, 7, 1.0, ctypes.c_void_p(8),
+                                       None, None) == numag.E_INVALID
+    assert lib.numag_correlation(None, None, 3, 1, None, 2, 1.0, None, None, None) == numag.E_INVALID
+    s = _cpu_sample()
+    assert lib.numag_grad(ctypes.byref(s), None, ctypes.byref(grid), ctypes.byref(c), None, None, None, None,
+                          None, None, None, 0, None) == numag.E_INVALID
