@@ -62,14 +62,15 @@ static void mat_vec(const double *R, const double v[3], double out[3])
         out[a] = R[3 * a + 0] * v[0] + R[3 * a + 1] * v[1] + R[3 * a + 2] * v[2];
 }
 
-static int64_t object_of(int64_t K, const int64_t *off, int64_t j)
+/* Object index of every point from the CSR offsets (object k owns points
+   off[k] .. off[k+1]-1); all zero for a single object.  Caller frees. */
+static int64_t *object_index(int64_t W, int64_t K, const int64_t *off)
 {
-    /* CSR offsets: object k owns points off[k] .. off[k+1]-1.  Linear scan is
-       fine for an oracle. */
-    if (K <= 1 || off == NULL) return 0;
-    for (int64_t k = 0; k < K; ++k)
-        if (j >= off[k] && j < off[k + 1]) return k;
-    return K - 1;
+    int64_t *kidx = (int64_t *)calloc((size_t)(W > 0 ? W : 1), sizeof(int64_t));
+    if (K > 1 && off != NULL)
+        for (int64_t k = 0; k < K; ++k)
+            for (int64_t j = off[k]; j < off[k + 1]; ++j) kidx[j] = k;
+    return kidx;
 }
 
 /*
@@ -92,11 +93,12 @@ void orc_amplitudes(int64_t W, const double *pos, const double *nuc, const doubl
     cplx *out = (cplx *)out_ri;
     int64_t n_sets = per_object ? (K > 0 ? K : 1) : 1;
     memset(out_ri, 0, sizeof(cplx) * (size_t)(n_sets * n_pix * 4));
+    int64_t *kidx = object_index(W, K, off);
 
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t p = 0; p < n_pix; ++p) {
         for (int64_t j = 0; j < W; ++j) {
-            int64_t k = object_of(K, off, j);
+            int64_t k = kidx[j];
             double x[3] = {pos[3 * j + 0], pos[3 * j + 1], pos[3 * j + 2]};
             if (!per_object && obj_pos != NULL) {
                 x[0] += obj_pos[3 * k + 0];
@@ -123,6 +125,7 @@ void orc_amplitudes(int64_t W, const double *pos, const double *nuc, const doubl
             dst[3] += mr[2] * e;
         }
     }
+    free(kidx);
 }
 
 /*
@@ -397,10 +400,11 @@ void orc_loss_grad(int64_t W, const double *pos, const double *nuc, const double
         for (int a = 0; a < 3; ++a) Qp[3 * p + a] = Q[a];
     }
     *loss = L;
+    int64_t *kidx = object_index(W, K, off);
 
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t j = 0; j < W; ++j) {
-        int64_t k = object_of(K, off, j);
+        int64_t k = kidx[j];
         double x[3] = {pos[3 * j + 0], pos[3 * j + 1], pos[3 * j + 2]};
         if (obj_pos != NULL) {
             x[0] += obj_pos[3 * k + 0];
@@ -439,6 +443,7 @@ void orc_loss_grad(int64_t W, const double *pos, const double *nuc, const double
     free(A);
     free(g);
     free(Qp);
+    free(kidx);
 }
 
 /*

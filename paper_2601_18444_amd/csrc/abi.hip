@@ -181,14 +181,16 @@ int run_direct(const numag_sample *s, const Rot &R, const Detector &d, double *a
     return launch_combine(part, p.nsplit, P, amp, 0, st);
 }
 
-size_t amplitudes_ws(const numag_sample *s, int64_t n_rot, const Detector &d, int32_t path, int32_t mode)
+size_t amplitudes_ws(const numag_sample *s, int64_t n_rot, const Detector &d, int32_t path, int32_t mode,
+                     int32_t spec_per_object)
 {
-    (void)n_rot;
     if (path == NUMAG_PATH_SEPARABLE_F64 || path == NUMAG_PATH_SEPARABLE_BF16X3)
         return align_up(separable_workspace_bytes(*s->regular, d, path));
-    size_t b = 0;
-    if (mode == NUMAG_MODE_COHERENT || mode == NUMAG_MODE_SPLIT) b = direct_layout(s, d).total;
-    return b;
+    if (mode == NUMAG_MODE_COHERENT) return direct_layout(s, d).total;
+    std::vector<int64_t> off;
+    const int64_t K = s->n_objects;
+    const ObjectsPlan p = plan_objects(d, s->obj_offsets, K, n_rot, mode, spec_per_object);
+    return align_up(objects_workspace_bytes(p, d, K, n_rot, mode));
 }
 
 }  // namespace
@@ -217,8 +219,13 @@ size_t numag_workspace_size(const numag_sample *sample, int64_t n_rot, const num
         set_error("numag_workspace_size: separable path needs a regular grid");
         return 0;
     }
+    if (n_rot < 1) {
+        set_error("numag_workspace_size: n_rot must be >= 1");
+        return 0;
+    }
     Detector d = make_detector(*grid);
-    size_t amp = amplitudes_ws(sample, n_rot, d, path, mode);
+    // object modes: enough for both spectral layouts (per object or summed)
+    size_t amp = std::max(amplitudes_ws(sample, n_rot, d, path, mode, 0), amplitudes_ws(sample, n_rot, d, path, mode, 1));
     size_t grad = 0;
     if (path == NUMAG_PATH_DIRECT && mode == NUMAG_MODE_COHERENT && grid->kind == NUMAG_GRID_CARTESIAN) {
         // numag_grad: points + amplitudes (when not given) + direct partials + adjoint scratch
@@ -254,8 +261,20 @@ int numag_amplitudes(const numag_sample *sample, int64_t n_rot, const double *ro
             return invalid("numag_amplitudes: separable path needs a Cartesian detector");
         if (mode != NUMAG_MODE_COHERENT) return invalid("numag_amplitudes: separable path is COHERENT only");
     }
+    if (mode != NUMAG_MODE_COHERENT) {
+        if (mode == NUMAG_MODE_SPLIT && n_rot != 1) return invalid("numag_amplitudes: SPLIT mode takes one rotation");
+        if (grid->kind != NUMAG_GRID_CARTESIAN) {
+            set_error("numag_amplitudes: DILUTE/SPLIT modes need a Cartesian detector in this build");
+            return NUMAG_E_UNSUPPORTED;
+        }
+        if (sample->n_points > 0 && sample->pos == nullptr) {
+            set_error("numag_amplitudes: DILUTE/SPLIT modes need explicit positions");
+            return NUMAG_E_UNSUPPORTED;
+        }
+        if (n_rot > (int64_t)1 << 30) return invalid("numag_amplitudes: too many rotations");
+    }
     Detector d = make_detector(*grid);
-    const size_t need = amplitudes_ws(sample, n_rot, d, path, mode);
+    const size_t need = amplitudes_ws(sample, n_rot, d, path, mode, spec_per_object ? 1 : 0);
     if (ws_bytes < need || (need > 0 && workspace == nullptr)) {
         set_error("numag_amplitudes: workspace too small (need " + std::to_string(need) + " bytes)");
         return NUMAG_E_WORKSPACE;
@@ -263,20 +282,18 @@ int numag_amplitudes(const numag_sample *sample, int64_t n_rot, const double *ro
     hipStream_t st = (hipStream_t)stream;
     const int64_t P = (int64_t)grid->n0 * grid->n1;
 
+    if (mode != NUMAG_MODE_COHERENT)
+        return launch_objects(*sample, rot, n_rot, d, mode, spec_per_object ? 1 : 0, spec_out, amp_out, workspace,
+                              ws_bytes, st);
+    forget_workspace(workspace);
     if (path != NUMAG_PATH_DIRECT)
         return launch_separable(sample->nuc, sample->mag, *sample->regular, d, path, amp_out, workspace,
                                 ws_bytes, st);
-
-    if (mode == NUMAG_MODE_COHERENT) {
-        for (int64_t r = 0; r < n_rot; ++r) {
-            rc = run_direct(sample, rot_of(rot, r), d, amp_out + r * P * 8, workspace, st);
-            if (rc != NUMAG_OK) return rc;
-        }
-        return NUMAG_OK;
+    for (int64_t r = 0; r < n_rot; ++r) {
+        rc = run_direct(sample, rot_of(rot, r), d, amp_out + r * P * 8, workspace, st);
+        if (rc != NUMAG_OK) return rc;
     }
-    (void)spec_per_object;
-    set_error("numag_amplitudes: DILUTE/SPLIT modes are not available in this build");
-    return NUMAG_E_UNSUPPORTED;
+    return NUMAG_OK;
 }
 
 int numag_cross_section(const numag_qgrid *grid, int64_t n_sets, const double *amp, const double *spec,
@@ -360,6 +377,7 @@ int numag_grad(const numag_sample *sample, const double *rot, const numag_qgrid 
         return NUMAG_E_WORKSPACE;
     }
     hipStream_t st = (hipStream_t)stream;
+    forget_workspace(workspace);
     Carve cv(workspace);
     char *direct_ws = (char *)cv.take(L.total);
     double *amp = (double *)cv.take((size_t)P * 8 * sizeof(double));

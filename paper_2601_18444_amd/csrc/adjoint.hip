@@ -173,10 +173,11 @@ __global__ __launch_bounds__(kAdjThreads, 2) void adjoint_cartesian_kernel(
                 const double a2r = ak[4], a2i = ak[5], a3r = ak[6], a3i = ak[7];
 #pragma unroll
                 for (int u = 0; u < kAdjNPL; ++u) {
-                    acc[u][0] += a0r * p[u].x - a0i * p[u].y;
-                    acc[u][1] += a1r * p[u].x - a1i * p[u].y;
-                    acc[u][2] += a2r * p[u].x - a2i * p[u].y;
-                    acc[u][3] += a3r * p[u].x - a3i * p[u].y;
+                    // Re(a p) as two FMAs per channel
+                    acc[u][0] = fma(-a0i, p[u].y, fma(a0r, p[u].x, acc[u][0]));
+                    acc[u][1] = fma(-a1i, p[u].y, fma(a1r, p[u].x, acc[u][1]));
+                    acc[u][2] = fma(-a2i, p[u].y, fma(a2r, p[u].x, acc[u][2]));
+                    acc[u][3] = fma(-a3i, p[u].y, fma(a3r, p[u].x, acc[u][3]));
                     p[u] = cmul_a(p[u], dz[u]);
                 }
             }

@@ -21,7 +21,7 @@
 //
 // Work is split over point ranges (split-K); a fixed-order FP64 combine sums
 // the partial results, so results are bitwise reproducible.
-#include "numag_internal.h"
+#include "cartesian_sum.h"
 
 namespace numag {
 
@@ -142,95 +142,33 @@ int launch_prepare_points(const double *pos, const double *nuc, const double *ma
 // ---------------------------------------------------------------------------
 // a4: Cartesian direct sum.
 // ---------------------------------------------------------------------------
-constexpr int kChunk = 32;     // points staged per LDS chunk
-constexpr int kWaves = 4;      // waves per workgroup
-constexpr int kThreads = 64 * kWaves;
+constexpr int kWaves = cart::kWaves;
+constexpr int kThreads = cart::kThreads;
+constexpr int kChunk = cart::kChunk;
+
+struct PrepLoader {
+    const PointRec *pts;
+    __device__ __forceinline__ cart::PointPart load(int64_t j, int slot) const
+    {
+        const PointRec &r = pts[j];
+        return cart::PointPart{r.Y, r.Z, slot < 4 ? r.w[slot] : 0.0};
+    }
+};
 
 template <int A, int B>
 __global__ __launch_bounds__(kThreads, 2) void direct_cartesian_kernel(
     const PointRec *__restrict__ pts, int64_t W, int64_t per, Detector d, double *__restrict__ out)
 {
-    constexpr int ROWS = kWaves * A;
-    __shared__ double2 s_tz[kChunk][64];
-    __shared__ double2 s_ty[kChunk][ROWS];
-    __shared__ double2 s_dz[kChunk];
-    __shared__ double s_w[kChunk][4];
-
-    const int t = threadIdx.x;
-    const int lane = t & 63;
-    const int wave = t >> 6;
+    __shared__ cart::Smem<A> sm;
     const int col0 = blockIdx.x * 64 * B;
-    const int row0 = blockIdx.y * ROWS;
+    const int row0 = blockIdx.y * kWaves * A;
     const int64_t jbeg = (int64_t)blockIdx.z * per;
     const int64_t jend = min(W, jbeg + per);
-
     double acc[A][B][8];
-#pragma unroll
-    for (int r = 0; r < A; ++r)
-#pragma unroll
-        for (int c = 0; c < B; ++c)
-#pragma unroll
-            for (int v = 0; v < 8; ++v) acc[r][c][v] = 0.0;
+    cart::zero<A, B>(acc);
+    cart::accumulate<A, B>(PrepLoader{pts}, jbeg, jend, d, col0, row0, sm, acc);
 
-    const double bstep = (double)B * d.step1;  // exact: B is a power of two
-
-    for (int64_t j0 = jbeg; j0 < jend; j0 += kChunk) {
-        const int nk = (int)min((int64_t)kChunk, jend - j0);
-        __syncthreads();
-        // ---- twiddles of this chunk -------------------------------------------
-        {
-            // first-column twiddles of the 64 lanes: 8 segments of 8 lanes per point
-            const int jj = t >> 3, seg = t & 7;
-            const double z = jj < nk ? pts[j0 + jj].Z : 0.0;
-            const double qs = axis_value(d.origin1, col0 + seg * 8 * B, d.step1);
-            double2 e = twiddle(qs * z);
-            const double2 st = twiddle(bstep * z);
-#pragma unroll
-            for (int l = 0; l < 8; ++l) {
-                s_tz[jj][seg * 8 + l] = e;
-                e = cmul(e, st);
-            }
-        }
-        for (int it = t; it < kChunk * ROWS; it += kThreads) {
-            const int jj = it / ROWS, r = it % ROWS;
-            const double y = jj < nk ? pts[j0 + jj].Y : 0.0;
-            const double qy = axis_value(d.origin0, row0 + r, d.step0);
-            s_ty[jj][r] = twiddle(qy * y);
-        }
-        if (t < kChunk) {
-            const bool ok = t < nk;
-            const double z = ok ? pts[j0 + t].Z : 0.0;
-            s_dz[t] = twiddle(d.step1 * z);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) s_w[t][v] = ok ? pts[j0 + t].w[v] : 0.0;
-        }
-        __syncthreads();
-        // ---- accumulate -----------------------------------------------------
-#pragma unroll 2
-        for (int jj = 0; jj < nk; ++jj) {
-            const double2 ez = s_tz[jj][lane];
-            const double2 dz = s_dz[jj];
-            const double w0 = s_w[jj][0], w1 = s_w[jj][1], w2 = s_w[jj][2], w3 = s_w[jj][3];
-#pragma unroll
-            for (int r = 0; r < A; ++r) {
-                const double2 ey = s_ty[jj][wave * A + r];
-                double2 p = cmul(ey, ez);
-#pragma unroll
-                for (int c = 0; c < B; ++c) {
-                    acc[r][c][0] += w0 * p.x;
-                    acc[r][c][1] += w0 * p.y;
-                    acc[r][c][2] += w1 * p.x;
-                    acc[r][c][3] += w1 * p.y;
-                    acc[r][c][4] += w2 * p.x;
-                    acc[r][c][5] += w2 * p.y;
-                    acc[r][c][6] += w3 * p.x;
-                    acc[r][c][7] += w3 * p.y;
-                    if (c + 1 < B) p = cmul(p, dz);
-                }
-            }
-        }
-    }
-
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t P = (int64_t)d.n0 * d.n1;
     double *dst = out + (int64_t)blockIdx.z * P * 8;
 #pragma unroll

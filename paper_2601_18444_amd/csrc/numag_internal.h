@@ -90,21 +90,25 @@ int launch_fill(double *out, int64_t n, double value, hipStream_t s);
 int launch_combine(const double *part, int nsplit, int64_t P, double *out, int accumulate,
                    hipStream_t s);
 
-// a6: one workgroup item per (object, pixel block, rotation group); sums are
-// complete per object and accumulated into exclusive slots:
-//   spec_slot[g][P][16] += F F^H  and (coherent part) amp_slot[g][P][8] += e^{-iq.R r^k} F.
-struct ObjectPlan {
+// a6: work items (object slot, rotation group, pixel block); each sums complete
+// objects and adds F F^H (and, in split mode, exp(-i q.R r^k) F) into an
+// accumulator slot no other item touches; slots are reduced in a fixed order.
+struct ObjectsPlan {
     int A, B;
-    int row_blocks, col_blocks;
-    int n_groups;          // slot groups (objects or rotations are split over them)
+    int col_blocks, row_blocks;
+    int H;          // rotation groups
+    int n_kslots;   // object slots (one per object, or object groups)
     int64_t n_items;
-    int per_object_slots;  // slot index = object (spec per object) or group
 };
-int launch_objects(const double *pos, const double *nuc, const double *mag, int64_t W,
-                   const int64_t *d_offsets, const int64_t *h_offsets, int64_t K,
-                   const double *obj_pos, const double *d_rot, int64_t n_rot, const Detector &d,
-                   int mode, int spec_per_object, double *spec_slots, double *amp_slots,
-                   int n_groups, int *d_items, int *d_counter, hipStream_t s);
+ObjectsPlan plan_objects(const Detector &d, const int64_t *h_off, int64_t K, int64_t n_rot, int mode,
+                         int spec_per_object);
+size_t objects_workspace_bytes(const ObjectsPlan &p, const Detector &d, int64_t K, int64_t n_rot, int mode);
+int launch_objects(const numag_sample &s, const double *h_rot, int64_t n_rot, const Detector &d, int mode,
+                   int spec_per_object, double *spec_out, double *amp_out, void *ws, size_t ws_bytes,
+                   hipStream_t st);
+// Drops the record of tables uploaded into `ws` (any other use of a workspace
+// overwrites them).
+void forget_workspace(const void *ws);
 
 // a7: cross sections from amplitudes ([n_sets][P][8]) or spectra ([n_sets][P][16]).
 int launch_cross_section(const Detector &d, int64_t n_sets, const double *amp, const double *spec,

@@ -1,22 +1,317 @@
-// Regular-grid separable path (matrix cores).  Placeholder until the kernels land.
+// Regular-grid separable path on the gfx950 matrix cores.
+//
+// For points on a regular grid (micromagnetic cells) with no sample rotation,
+// the lab phase q.r = q_y y + q_z z does not involve x, so the DSFT of Sec. 3.3
+// factors exactly:
+//   S_c(y, z)   = sum_x w_c(x, y, z)                      (projection along the beam)
+//   T_c(y, k)   = sum_z S_c(y, z) exp(-i q_z(k) z)         (real x complex contraction)
+//   F_c(i, k)   = sum_y exp(-i q_y(i) y) T_c(y, k)         (complex x complex contraction)
+// The two contractions are dense GEMMs and run on MFMA:
+//   NUMAG_PATH_SEPARABLE_F64:    v_mfma_f64_16x16x4f64, FP64 operands and accumulation;
+//   NUMAG_PATH_SEPARABLE_BF16X3: v_mfma_f32_16x16x16bf16_1k with every operand split
+//                                into bf16 hi + lo and the three products hi*hi,
+//                                hi*lo, lo*hi accumulated in FP32.
+// Twiddles are generated in FP64 into the workspace; the projection is a
+// fixed-order FP64 sum.  One wave computes one 16 x 16 output tile.
 #include "numag_internal.h"
 
 namespace numag {
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double2 tw_s(double phi)
+{
+    double s, c;
+    sincos(phi, &s, &c);
+    return make_double2(c, -s);
+}
+
+__device__ __forceinline__ double axis_s(double origin, int i, double step)
+{
+#pragma clang fp contract(off)
+    double t = (double)i * step;
+    return origin + t;
+}
+
+struct SepLayout {
+    size_t ey, ez, s, t, total;
+};
+
+static size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static SepLayout sep_layout(const numag_regular &g, const Detector &d)
+{
+    const size_t ny = g.n[1], nz = g.n[2], n0 = d.n0, n1 = d.n1;
+    SepLayout L{};
+    L.ey = al(n0 * ny * sizeof(double2));
+    L.ez = al(nz * n1 * sizeof(double2));
+    L.s = al(4 * ny * nz * sizeof(double));
+    L.t = al(4 * ny * n1 * sizeof(double2));
+    L.total = L.ey + L.ez + L.s + L.t;
+    return L;
+}
+
 size_t separable_workspace_bytes(const numag_regular &g, const Detector &d, int path)
 {
-    (void)g;
-    (void)d;
     (void)path;
-    return 0;
+    return sep_layout(g, d).total;
+}
+
+// Ey[i][iy] = exp(-i q_y(i) y_iy),  Ez[iz][k] = exp(-i q_z(k) z_iz)
+__global__ void sep_twiddle_kernel(Detector d, numag_regular g, double2 *__restrict__ ey,
+                                   double2 *__restrict__ ez)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ny = g.n[1], nz = g.n[2];
+    const int64_t ne = (int64_t)d.n0 * ny;
+    if (idx < ne) {
+        const int i = (int)(idx / ny), iy = (int)(idx % ny);
+        const double y = g.origin[1] + (double)iy * g.step[1];
+        ey[idx] = tw_s(axis_s(d.origin0, i, d.step0) * y);
+    } else if (idx < ne + nz * d.n1) {
+        const int64_t r = idx - ne;
+        const int iz = (int)(r / d.n1), k = (int)(r % d.n1);
+        const double z = g.origin[2] + (double)iz * g.step[2];
+        ez[r] = tw_s(axis_s(d.origin1, k, d.step1) * z);
+    }
+}
+
+// S[c][iy][iz] = sum_ix w_c(ix, iy, iz), ix ascending
+__global__ void sep_project_kernel(const double *__restrict__ nuc, const double *__restrict__ mag,
+                                   numag_regular g, double *__restrict__ S)
+{
+    const int64_t nyz = (int64_t)g.n[1] * g.n[2];
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= 4 * nyz) return;
+    const int c = (int)(idx / nyz);
+    const int64_t rem = idx % nyz;
+    double s = 0.0;
+    if (c == 0) {
+        if (nuc != nullptr)
+            for (int ix = 0; ix < g.n[0]; ++ix) s += nuc[(int64_t)ix * nyz + rem];
+    } else if (mag != nullptr) {
+        for (int ix = 0; ix < g.n[0]; ++ix) s += mag[3 * ((int64_t)ix * nyz + rem) + (c - 1)];
+    }
+    S[idx] = s;
+}
+
+// ---- FP64 MFMA -------------------------------------------------------------
+// v_mfma_f64_16x16x4f64 lane layout: A[l % 16][l / 16], B[l / 16][l % 16],
+// D[4 r + l / 16][l % 16] for r < 4 (unlike the FP32-accumulating MFMAs below).
+
+// T[c][iy][k] = sum_iz S[c][iy][iz] Ez[iz][k]
+__global__ __launch_bounds__(256) void sep_contract1_f64(const double *__restrict__ S, const double2 *__restrict__ Ez,
+                                                         int ny, int nz, int n1, double2 *__restrict__ T)
+{
+    const int lane = threadIdx.x & 63;
+    const int tm = (ny + 15) / 16, tn = (n1 + 15) / 16;
+    const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (tile >= (int64_t)4 * tm * tn) return;
+    const int c = (int)(tile / (tm * tn));
+    const int rem = (int)(tile % (tm * tn));
+    const int m0 = (rem / tn) * 16, n0 = (rem % tn) * 16;
+    const int ai = m0 + (lane & 15), bj = n0 + (lane & 15), kq = lane >> 4;
+    const double *Sc = S + (int64_t)c * ny * nz;
+    v4d accR = {0.0, 0.0, 0.0, 0.0}, accI = {0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < nz; k += 4) {
+        const int kk = k + kq;
+        const double a = (ai < ny && kk < nz) ? Sc[(int64_t)ai * nz + kk] : 0.0;
+        const double2 b = (bj < n1 && kk < nz) ? Ez[(int64_t)kk * n1 + bj] : make_double2(0.0, 0.0);
+        accR = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b.x, accR, 0, 0, 0);
+        accI = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b.y, accI, 0, 0, 0);
+    }
+    double2 *Tc = T + (int64_t)c * ny * n1;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = m0 + 4 * r + kq;
+        if (i < ny && bj < n1) Tc[(int64_t)i * n1 + bj] = make_double2(accR[r], accI[r]);
+    }
+}
+
+// F[c][i][k] = sum_iy Ey[i][iy] T[c][iy][k]  ->  amp[(i n1 + k)][c]
+__global__ __launch_bounds__(256) void sep_contract2_f64(const double2 *__restrict__ Ey, const double2 *__restrict__ T,
+                                                         int n0, int ny, int n1, double *__restrict__ amp)
+{
+    const int lane = threadIdx.x & 63;
+    const int tm = (n0 + 15) / 16, tn = (n1 + 15) / 16;
+    const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (tile >= (int64_t)4 * tm * tn) return;
+    const int c = (int)(tile / (tm * tn));
+    const int rem = (int)(tile % (tm * tn));
+    const int m0 = (rem / tn) * 16, n0t = (rem % tn) * 16;
+    const int ai = m0 + (lane & 15), bj = n0t + (lane & 15), kq = lane >> 4;
+    const double2 *Tc = T + (int64_t)c * ny * n1;
+    v4d accR = {0.0, 0.0, 0.0, 0.0}, accI = {0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < ny; k += 4) {
+        const int kk = k + kq;
+        const double2 a = (ai < n0 && kk < ny) ? Ey[(int64_t)ai * ny + kk] : make_double2(0.0, 0.0);
+        const double2 b = (bj < n1 && kk < ny) ? Tc[(int64_t)kk * n1 + bj] : make_double2(0.0, 0.0);
+        accR = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, accR, 0, 0, 0);
+        accR = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, accR, 0, 0, 0);
+        accI = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, accI, 0, 0, 0);
+        accI = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, accI, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = m0 + 4 * r + kq;
+        if (i < n0 && bj < n1) {
+            double *o = amp + ((int64_t)i * n1 + bj) * 8 + 2 * c;
+            o[0] = accR[r];
+            o[1] = accI[r];
+        }
+    }
+}
+
+// ---- BF16 x 3 MFMA ---------------------------------------------------------
+// v_mfma_f32_16x16x16bf16_1k lane layout: A[l % 16][4 (l / 16) + v],
+// B[4 (l / 16) + v][l % 16] for v < 4, D[4 (l / 16) + r][l % 16].
+
+__device__ __forceinline__ short to_bf16(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+    return (short)(u >> 16);
+}
+
+__device__ __forceinline__ float from_bf16(short h) { return __uint_as_float(((uint32_t)(uint16_t)h) << 16); }
+
+struct Bf3 {
+    v4s hi, lo;
+};
+
+// element v of o: x = hi + lo, both bf16
+__device__ __forceinline__ void split_bf16(double x, Bf3 &o, int v)
+{
+    const short hi = to_bf16((float)x);
+    o.hi[v] = hi;
+    o.lo[v] = to_bf16((float)(x - (double)from_bf16(hi)));
+}
+
+__device__ __forceinline__ v4f mfma3(const Bf3 &a, const Bf3 &b, v4f acc)
+{
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.hi, b.hi, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.hi, b.lo, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.lo, b.hi, acc, 0, 0, 0);
+    return acc;
+}
+
+__global__ __launch_bounds__(256) void sep_contract1_bf16x3(const double *__restrict__ S,
+                                                            const double2 *__restrict__ Ez, int ny, int nz,
+                                                            int n1, double2 *__restrict__ T)
+{
+    const int lane = threadIdx.x & 63;
+    const int tm = (ny + 15) / 16, tn = (n1 + 15) / 16;
+    const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (tile >= (int64_t)4 * tm * tn) return;
+    const int c = (int)(tile / (tm * tn));
+    const int rem = (int)(tile % (tm * tn));
+    const int m0 = (rem / tn) * 16, n0 = (rem % tn) * 16;
+    const int ai = m0 + (lane & 15), bj = n0 + (lane & 15), kq = lane >> 4;
+    const double *Sc = S + (int64_t)c * ny * nz;
+    v4f accR = {0.f, 0.f, 0.f, 0.f}, accI = {0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < nz; k += 16) {
+        Bf3 a, br, bi;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int kk = k + 4 * kq + v;
+            const double av = (ai < ny && kk < nz) ? Sc[(int64_t)ai * nz + kk] : 0.0;
+            const double2 bv = (bj < n1 && kk < nz) ? Ez[(int64_t)kk * n1 + bj] : make_double2(0.0, 0.0);
+            split_bf16(av, a, v);
+            split_bf16(bv.x, br, v);
+            split_bf16(bv.y, bi, v);
+        }
+        accR = mfma3(a, br, accR);
+        accI = mfma3(a, bi, accI);
+    }
+    double2 *Tc = T + (int64_t)c * ny * n1;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = m0 + 4 * kq + r;
+        if (i < ny && bj < n1) Tc[(int64_t)i * n1 + bj] = make_double2((double)accR[r], (double)accI[r]);
+    }
+}
+
+__global__ __launch_bounds__(256) void sep_contract2_bf16x3(const double2 *__restrict__ Ey,
+                                                            const double2 *__restrict__ T, int n0, int ny,
+                                                            int n1, double *__restrict__ amp)
+{
+    const int lane = threadIdx.x & 63;
+    const int tm = (n0 + 15) / 16, tn = (n1 + 15) / 16;
+    const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (tile >= (int64_t)4 * tm * tn) return;
+    const int c = (int)(tile / (tm * tn));
+    const int rem = (int)(tile % (tm * tn));
+    const int m0 = (rem / tn) * 16, n0t = (rem % tn) * 16;
+    const int ai = m0 + (lane & 15), bj = n0t + (lane & 15), kq = lane >> 4;
+    const double2 *Tc = T + (int64_t)c * ny * n1;
+    v4f accR = {0.f, 0.f, 0.f, 0.f}, accI = {0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < ny; k += 16) {
+        Bf3 ar, ai_neg, aim, br, bi;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int kk = k + 4 * kq + v;
+            const double2 av = (ai < n0 && kk < ny) ? Ey[(int64_t)ai * ny + kk] : make_double2(0.0, 0.0);
+            const double2 bv = (bj < n1 && kk < ny) ? Tc[(int64_t)kk * n1 + bj] : make_double2(0.0, 0.0);
+            split_bf16(av.x, ar, v);
+            split_bf16(av.y, aim, v);
+            split_bf16(-av.y, ai_neg, v);
+            split_bf16(bv.x, br, v);
+            split_bf16(bv.y, bi, v);
+        }
+        accR = mfma3(ar, br, accR);
+        accR = mfma3(ai_neg, bi, accR);
+        accI = mfma3(ar, bi, accI);
+        accI = mfma3(aim, br, accI);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = m0 + 4 * kq + r;
+        if (i < n0 && bj < n1) {
+            double *o = amp + ((int64_t)i * n1 + bj) * 8 + 2 * c;
+            o[0] = (double)accR[r];
+            o[1] = (double)accI[r];
+        }
+    }
 }
 
 int launch_separable(const double *nuc, const double *mag, const numag_regular &g, const Detector &d, int path,
                      double *amp, void *ws, size_t ws_bytes, hipStream_t s)
 {
-    (void)nuc; (void)mag; (void)g; (void)d; (void)path; (void)amp; (void)ws; (void)ws_bytes; (void)s;
-    set_error("numag_amplitudes: separable path not available in this build");
-    return NUMAG_E_UNSUPPORTED;
+    const SepLayout L = sep_layout(g, d);
+    if (ws_bytes < L.total || ws == nullptr) {
+        set_error("numag_amplitudes: workspace too small for the separable path");
+        return NUMAG_E_WORKSPACE;
+    }
+    char *base = (char *)ws;
+    double2 *ey = (double2 *)base;
+    double2 *ez = (double2 *)(base + L.ey);
+    double *S = (double *)(base + L.ey + L.ez);
+    double2 *T = (double2 *)(base + L.ey + L.ez + L.s);
+    const int ny = g.n[1], nz = g.n[2];
+    const int64_t ntw = (int64_t)d.n0 * ny + (int64_t)nz * d.n1;
+    hipLaunchKernelGGL(sep_twiddle_kernel, dim3((unsigned)((ntw + 255) / 256)), dim3(256), 0, s, d, g, ey, ez);
+    NUMAG_HIP_CHECK(hipGetLastError());
+    const int64_t nproj = 4 * (int64_t)ny * nz;
+    hipLaunchKernelGGL(sep_project_kernel, dim3((unsigned)((nproj + 255) / 256)), dim3(256), 0, s, nuc, mag, g, S);
+    NUMAG_HIP_CHECK(hipGetLastError());
+    const int64_t t1 = 4LL * ((ny + 15) / 16) * ((d.n1 + 15) / 16);
+    const int64_t t2 = 4LL * ((d.n0 + 15) / 16) * ((d.n1 + 15) / 16);
+    if (path == NUMAG_PATH_SEPARABLE_F64) {
+        hipLaunchKernelGGL(sep_contract1_f64, dim3((unsigned)((t1 + 3) / 4)), dim3(256), 0, s, S, ez, ny, nz, d.n1, T);
+        NUMAG_HIP_CHECK(hipGetLastError());
+        hipLaunchKernelGGL(sep_contract2_f64, dim3((unsigned)((t2 + 3) / 4)), dim3(256), 0, s, ey, T, d.n0, ny, d.n1,
+                           amp);
+    } else {
+        hipLaunchKernelGGL(sep_contract1_bf16x3, dim3((unsigned)((t1 + 3) / 4)), dim3(256), 0, s, S, ez, ny, nz,
+                           d.n1, T);
+        NUMAG_HIP_CHECK(hipGetLastError());
+        hipLaunchKernelGGL(sep_contract2_bf16x3, dim3((unsigned)((t2 + 3) / 4)), dim3(256), 0, s, ey, T, d.n0, ny,
+                           d.n1, amp);
+    }
+    NUMAG_HIP_CHECK(hipGetLastError());
+    return NUMAG_OK;
 }
 
 }  // namespace numag

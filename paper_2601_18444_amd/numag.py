@@ -199,24 +199,63 @@ def workspace_size(sample: Sample, grid: QGrid, n_rot=1, path=PATH_DIRECT, mode=
 
 
 def amplitudes(sample: Sample, grid: QGrid, rot=None, path=PATH_DIRECT, mode=MODE_COHERENT,
-               spec_per_object=False, out=None, spec_out=None):
-    """numag_amplitudes.  Returns (amp [n_rot, P, 4, 2] or None, spec [n_spec, P, 16] or None)."""
+               spec_per_object=False, out=None, spec_out=None, ws: Optional[torch.Tensor] = None):
+    """numag_amplitudes.  Returns (amp [n_rot, P, 4, 2] or None, spec [n_spec, P, 16] or None).
+    In SPLIT mode amp has one rotation.  `ws` is an optional dedicated workspace."""
     r, n_rot = _rot_array(rot)
     dev = sample.device
     P = grid.n_pixels
     amp = spec = None
     if mode in (MODE_COHERENT, MODE_SPLIT):
-        amp = out if out is not None else torch.empty((n_rot, P, 4, 2), dtype=torch.float64, device=dev)
+        n_amp = n_rot if mode == MODE_COHERENT else 1
+        amp = out if out is not None else torch.empty((n_amp, P, 4, 2), dtype=torch.float64, device=dev)
     if mode in (MODE_DILUTE, MODE_SPLIT):
         n_spec = sample.n_objects if spec_per_object else 1
         spec = spec_out if spec_out is not None else torch.empty((n_spec, P, 16), dtype=torch.float64, device=dev)
-    nws = workspace_size(sample, grid, n_rot, path, mode)
-    ws = workspace(nws, dev)
+    if ws is None:
+        ws = workspace(workspace_size(sample, grid, n_rot, path, mode), dev)
     rc = _lib.numag_amplitudes(sample.c, n_rot, r.ctypes.data_as(ctypes.c_void_p) if r is not None else None,
                                ctypes.byref(grid), int(path), int(mode), int(bool(spec_per_object)),
                                _ptr(amp), _ptr(spec), _ptr(ws), ws.numel(), _stream())
     _check("numag_amplitudes", rc)
     return amp, spec
+
+
+class BatchedOrientations:
+    """Orientational average of a dilute sample (Sec. 3.3 dilute limit) over many
+    sample rotations: one persistent launch over (object, rotation group, pixel
+    block) work items, recorded once into a HIP graph and replayed.
+
+    The graph reads the sample's device arrays at replay time, so weights may
+    be updated in place between replays; rotations and object offsets are fixed
+    at construction.  The dedicated workspace must not be shared."""
+
+    def __init__(self, sample: Sample, grid: QGrid, rotations, spec_per_object: bool = True):
+        self.sample, self.grid = sample, grid
+        self.rot = np.ascontiguousarray(np.asarray(rotations, dtype=np.float64).reshape(-1, 9))
+        self.spec_per_object = spec_per_object
+        dev = sample.device
+        n_spec = sample.n_objects if spec_per_object else 1
+        self.spec = torch.empty((n_spec, grid.n_pixels, 16), dtype=torch.float64, device=dev)
+        nws = workspace_size(sample, grid, self.rot.shape[0], PATH_DIRECT, MODE_DILUTE)
+        self.ws = torch.empty(max(nws, 256), dtype=torch.uint8, device=dev)
+        self._call()  # uploads the work tables into the dedicated workspace
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._call()
+
+    def _call(self):
+        amplitudes(self.sample, self.grid, rot=self.rot, mode=MODE_DILUTE, spec_per_object=self.spec_per_object,
+                   spec_out=self.spec, ws=self.ws)
+
+    def eager(self) -> torch.Tensor:
+        self._call()
+        return self.spec
+
+    def replay(self) -> torch.Tensor:
+        self.graph.replay()
+        return self.spec
 
 
 def obs_mask(obs: Iterable[str]) -> int:
