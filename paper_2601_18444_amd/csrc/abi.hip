@@ -166,7 +166,8 @@ int run_direct(const numag_sample *s, const Rot &R, const Detector &d, double *a
         return launch_fill(amp, P * 8, 0.0, st);
     }
     int rc = launch_prepare_points(s->pos, s->nuc, s->mag, s->n_points, s->regular,
-                                   L.offsets != 0 ? d_off : nullptr, s->n_objects, s->obj_pos, R, pts, st);
+                                   L.offsets != 0 ? d_off : nullptr, s->n_objects, s->obj_pos, R,
+                                   d.kind == NUMAG_GRID_CARTESIAN ? d.step1 : 0.0, pts, st);
     if (rc != NUMAG_OK) return rc;
     if (d.kind == NUMAG_GRID_CARTESIAN) {
         DirectPlan p = plan_direct_cartesian(d, s->n_points);
@@ -187,10 +188,8 @@ size_t amplitudes_ws(const numag_sample *s, int64_t n_rot, const Detector &d, in
     if (path == NUMAG_PATH_SEPARABLE_F64 || path == NUMAG_PATH_SEPARABLE_BF16X3)
         return align_up(separable_workspace_bytes(*s->regular, d, path));
     if (mode == NUMAG_MODE_COHERENT) return direct_layout(s, d).total;
-    std::vector<int64_t> off;
-    const int64_t K = s->n_objects;
-    const ObjectsPlan p = plan_objects(d, s->obj_offsets, K, n_rot, mode, spec_per_object);
-    return align_up(objects_workspace_bytes(p, d, K, n_rot, mode));
+    return align_up(objects_workspace_bytes(d, s->obj_offsets, s->n_objects, s->n_points, n_rot, mode,
+                                            spec_per_object));
 }
 
 }  // namespace
@@ -397,8 +396,8 @@ int numag_grad(const numag_sample *sample, const double *rot, const numag_qgrid 
                                            (size_t)(sample->n_objects + 1) * sizeof(int64_t),
                                            hipMemcpyHostToDevice, st));
         rc = launch_prepare_points(sample->pos, sample->nuc, sample->mag, sample->n_points, sample->regular,
-                                   L.offsets != 0 ? d_off : nullptr, sample->n_objects, sample->obj_pos, R, pts,
-                                   st);
+                                   L.offsets != 0 ? d_off : nullptr, sample->n_objects, sample->obj_pos, R, 0.0,
+                                   pts, st);
         if (rc != NUMAG_OK) return rc;
     }
     const PointRec *pts = (const PointRec *)(direct_ws + L.offsets);

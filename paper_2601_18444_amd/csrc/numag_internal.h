@@ -46,12 +46,13 @@ struct Rot {
     double m[9];
 };
 
-// Per-point record written by the preparation kernel: lab-frame position
-// (X, Y, Z) and lab-frame weights (n, m'x, m'y, m'z), padded to 64 bytes.
+// Per-point record written by the preparation kernel: lab-frame Y, Z (q has
+// no x component), lab-frame weights (n, m'x, m'y, m'z) and the column-step
+// twiddle exp(-i dq_z Z) of the Cartesian detector (zero when not needed).
 struct alignas(64) PointRec {
-    double X, Y, Z;
+    double Y, Z;
     double w[4];
-    double pad;
+    double dzr, dzi;
 };
 
 // ---------------------------------------------------------------------------
@@ -60,9 +61,10 @@ struct alignas(64) PointRec {
 
 // a1: X_j = R (x_j + r^{k(j)}), w'_j = (n_j, R m_j).  obj_index maps point -> object
 // via device CSR offsets (nullptr when K == 1 or no object positions).
+// dq_z is the Cartesian column step (0 for a polar detector).
 int launch_prepare_points(const double *pos, const double *nuc, const double *mag, int64_t W,
                           const numag_regular *regular, const int64_t *d_offsets, int64_t K,
-                          const double *obj_pos, const Rot &R, PointRec *out, hipStream_t s);
+                          const double *obj_pos, const Rot &R, double dq_z, PointRec *out, hipStream_t s);
 
 // a4/a5: direct Cartesian sum.  Writes [nsplit][P][8] partial sums (or the final
 // [P][8] sums when nsplit == 1) for points [0, W).
@@ -96,13 +98,12 @@ int launch_combine(const double *part, int nsplit, int64_t P, double *out, int a
 struct ObjectsPlan {
     int A, B;
     int col_blocks, row_blocks;
-    int H;          // rotation groups
-    int n_kslots;   // object slots (one per object, or object groups)
+    int n_slots;    // accumulator slots (object set x rotation range)
+    int n_out;      // spectral matrices written (K per object, or 1)
     int64_t n_items;
 };
-ObjectsPlan plan_objects(const Detector &d, const int64_t *h_off, int64_t K, int64_t n_rot, int mode,
-                         int spec_per_object);
-size_t objects_workspace_bytes(const ObjectsPlan &p, const Detector &d, int64_t K, int64_t n_rot, int mode);
+size_t objects_workspace_bytes(const Detector &d, const int64_t *h_off, int64_t K, int64_t W, int64_t n_rot,
+                               int mode, int spec_per_object);
 int launch_objects(const numag_sample &s, const double *h_rot, int64_t n_rot, const Detector &d, int mode,
                    int spec_per_object, double *spec_out, double *amp_out, void *ws, size_t ws_bytes,
                    hipStream_t st);

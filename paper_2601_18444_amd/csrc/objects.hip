@@ -3,19 +3,23 @@
 //
 // Dilute and split modes need each object's amplitude F_k complete before its
 // outer product F_k F_k^H is formed, so sums are not split over point ranges
-// here.  A work item is (object slot, rotation group, pixel block): the
-// workgroup sums every point of its objects for every rotation of its group
-// with the Cartesian building block (FP64), then adds F F^H (and, in split
-// mode, exp(-i q.R r^k) F for the coherent total) into a slot of FP64
-// accumulators that no other item touches.  Items are sorted by cost and
-// handed out by a persistent kernel through an atomic counter, so particles of
-// very uneven size balance across the chip; slot contents are summed in a
-// fixed order at the end, so results are reproducible bit for bit.
+// here.  The work is cut into accumulator slots: a slot is a set of objects
+// (one object, or a contiguous group of roughly equal point count) and a range
+// of rotations, sized so that every slot costs about the same; a large particle
+// gets many rotation ranges, a small one a single range.  A work item is
+// (slot, pixel block): the workgroup sums every point of the slot's objects for
+// every rotation of its range with the Cartesian building block (FP64), then
+// adds F F^H (and, in split mode, exp(-i q.R r^k) F for the coherent total)
+// into the slot's FP64 accumulators, which no other item touches.  Items are
+// sorted by cost and handed out by a persistent kernel through an atomic
+// counter; slots are reduced in a fixed order, so results are reproducible
+// bit for bit.
 //
 // Rotations are applied on the fly (X = R x, w' = (n, R m)) while a chunk's
 // twiddles are generated, so the point data is read once per chunk and never
 // rewritten per orientation.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <mutex>
 #include <unordered_map>
@@ -30,8 +34,10 @@ namespace {
 constexpr int kTarget = 2048;  // work items aimed for
 
 struct RawLoader {
+    static constexpr bool kHasRec = false;
     const double *pos, *nuc, *mag;
     const double *R;  // row-major 3x3, wave-uniform
+    __device__ __forceinline__ const PointRec *rec(int64_t) const { return nullptr; }
     __device__ __forceinline__ cart::PointPart load(int64_t j, int slot) const
     {
         const double x0 = pos[3 * j], x1 = pos[3 * j + 1], x2 = pos[3 * j + 2];
@@ -54,13 +60,12 @@ struct ObjArgs {
     const int64_t *off;      // [K+1]
     const double *obj_pos;   // [K][3] or null
     const double *rot;       // [n_rot][9]
-    const int4 *items;       // (kslot, h, block, -)
-    const int2 *kslot_range; // object range of a slot
-    const int2 *rot_range;   // rotation range of a group
-    int n_items, n_kslots, col_blocks;
+    const int2 *items;       // (slot, pixel block), sorted by cost
+    const int4 *slots;       // (object lo, object hi, rotation lo, rotation hi)
+    int n_items, col_blocks;
     int *counter;
-    double *spec;            // [H][n_kslots][P][16]
-    double *amp;             // [n_kslots][P][8] or null (split mode)
+    double *spec;            // [n_slots][P][16]
+    double *amp;             // [n_slots][P][8] or null (split mode)
 };
 
 template <int A, int B>
@@ -76,16 +81,15 @@ __global__ __launch_bounds__(cart::kThreads, 2) void objects_kernel(ObjArgs a, D
         const int it = s_item;
         __syncthreads();
         if (it >= a.n_items) break;
-        const int4 item = a.items[it];
-        const int ks = item.x, h = item.y, blk = item.z;
+        const int2 item = a.items[it];
+        const int slot = item.x, blk = item.y;
         const int col0 = (blk % a.col_blocks) * 64 * B;
         const int row0 = (blk / a.col_blocks) * cart::kWaves * A;
-        const int2 kr = a.kslot_range[ks];
-        const int2 rr = a.rot_range[h];
-        double *G = a.spec + ((int64_t)h * a.n_kslots + ks) * P * 16;
-        for (int r = rr.x; r < rr.y; ++r) {
+        const int4 sr = a.slots[slot];
+        double *G = a.spec + (int64_t)slot * P * 16;
+        for (int r = sr.z; r < sr.w; ++r) {
             const double *R = a.rot + 9 * (int64_t)r;
-            for (int k = kr.x; k < kr.y; ++k) {
+            for (int k = sr.x; k < sr.y; ++k) {
                 double acc[A][B][8];
                 cart::zero<A, B>(acc);
                 cart::accumulate<A, B>(RawLoader{a.pos, a.nuc, a.mag, R}, a.off[k], a.off[k + 1], d, col0, row0,
@@ -98,14 +102,14 @@ __global__ __launch_bounds__(cart::kThreads, 2) void objects_kernel(ObjArgs a, D
                     XZ = R[6] * o[0] + R[7] * o[1] + R[8] * o[2];
                 }
 #pragma unroll
-                for (int rr2 = 0; rr2 < A; ++rr2) {
-                    const int row = row0 + wave * A + rr2;
+                for (int rr = 0; rr < A; ++rr) {
+                    const int row = row0 + wave * A + rr;
 #pragma unroll
                     for (int c = 0; c < B; ++c) {
                         const int col = col0 + lane * B + c;
                         if (row >= d.n0 || col >= d.n1) continue;
                         const int64_t p = (int64_t)row * d.n1 + col;
-                        const double *F = acc[rr2][c];
+                        const double *F = acc[rr][c];
                         double *g = G + p * 16;
                         // G_ab += F_a conj(F_b): diagonal, then the upper triangle
                         g[0] += F[0] * F[0] + F[1] * F[1];
@@ -125,7 +129,7 @@ __global__ __launch_bounds__(cart::kThreads, 2) void objects_kernel(ObjArgs a, D
                             const double qy = cart::axis_value(d.origin0, row, d.step0);
                             const double qz = cart::axis_value(d.origin1, col, d.step1);
                             const double2 ph = cart::twiddle(qy * XY + qz * XZ);
-                            double *o = a.amp + ((int64_t)ks * P + p) * 8;
+                            double *o = a.amp + ((int64_t)slot * P + p) * 8;
 #pragma unroll
                             for (int v = 0; v < 4; ++v) {
                                 o[2 * v] += ph.x * F[2 * v] - ph.y * F[2 * v + 1];
@@ -145,32 +149,26 @@ __global__ void fill_i32_kernel(int *p, int n, int v)
     if (i < n) p[i] = v;
 }
 
-// spec_out[s][p][v] = scale * sum over (h, kslot) mapped to s
-__global__ void spec_reduce_kernel(const double *__restrict__ slots, int H, int n_kslots, int per_object,
+// out[s][p][v] = scale * sum of the slots of output s (slot_off CSR, ascending)
+__global__ void spec_reduce_kernel(const double *__restrict__ slots, const int *__restrict__ slot_off, int n_out,
                                    int64_t P, double scale, double *__restrict__ out)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t n_out = (per_object ? n_kslots : 1) * P * 16;
-    if (idx >= n_out) return;
+    if (idx >= (int64_t)n_out * P * 16) return;
+    const int s = (int)(idx / (P * 16));
     const int64_t pv = idx % (P * 16);
-    double s = 0.0;
-    if (per_object) {
-        const int ks = (int)(idx / (P * 16));
-        for (int h = 0; h < H; ++h) s += slots[((int64_t)h * n_kslots + ks) * P * 16 + pv];
-    } else {
-        for (int h = 0; h < H; ++h)
-            for (int ks = 0; ks < n_kslots; ++ks) s += slots[((int64_t)h * n_kslots + ks) * P * 16 + pv];
-    }
-    out[idx] = scale * s;
+    double acc = 0.0;
+    for (int sl = slot_off[s]; sl < slot_off[s + 1]; ++sl) acc += slots[(int64_t)sl * P * 16 + pv];
+    out[idx] = scale * acc;
 }
 
-__global__ void amp_reduce_kernel(const double *__restrict__ slots, int n_kslots, int64_t P,
+__global__ void amp_reduce_kernel(const double *__restrict__ slots, int n_slots, int64_t P,
                                   double *__restrict__ out)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= P * 8) return;
     double s = 0.0;
-    for (int ks = 0; ks < n_kslots; ++ks) s += slots[(int64_t)ks * P * 8 + idx];
+    for (int sl = 0; sl < n_slots; ++sl) s += slots[(int64_t)sl * P * 8 + idx];
     out[idx] = s;
 }
 
@@ -194,6 +192,81 @@ struct Upload {
 std::mutex g_upload_mu;
 std::unordered_map<const void *, Upload> g_uploads;
 
+// The full host-side plan: object groups, slots and sorted items.
+struct Tables {
+    ObjectsPlan p;
+    std::vector<int64_t> off;     // [K+1]
+    std::vector<int4> slots;      // (object lo, hi, rotation lo, hi)
+    std::vector<int> slot_off;    // outputs -> slots (CSR)
+    std::vector<int2> items;      // (slot, block), by decreasing cost
+};
+
+Tables make_tables(const Detector &d, const int64_t *h_off, int64_t K, int64_t W, int64_t n_rot, int mode,
+                   int spec_per_object)
+{
+    Tables T;
+    ObjectsPlan &p = T.p;
+    cart::choose_shape(d.n1, p.A, p.B);
+    p.col_blocks = (d.n1 + 64 * p.B - 1) / (64 * p.B);
+    p.row_blocks = (d.n0 + cart::kWaves * p.A - 1) / (cart::kWaves * p.A);
+    const int64_t nblocks = (int64_t)p.col_blocks * p.row_blocks;
+    T.off.resize(K + 1);
+    if (K == 1 || h_off == nullptr) {
+        T.off[0] = 0;
+        T.off[1] = W;
+    } else {
+        std::memcpy(T.off.data(), h_off, sizeof(int64_t) * (K + 1));
+    }
+    const std::vector<int64_t> &off = T.off;
+    // slot groups wanted (each spans all pixel blocks)
+    const int64_t want = std::max<int64_t>(1, (kTarget + nblocks - 1) / nblocks);
+    // object groups: single objects, or contiguous groups of roughly equal point counts
+    std::vector<int2> groups;
+    if (spec_per_object) {
+        for (int64_t k = 0; k < K; ++k) groups.push_back(make_int2((int)k, (int)k + 1));
+    } else {
+        const int64_t G = std::max<int64_t>(1, std::min<int64_t>(want, K));
+        int64_t k = 0;
+        for (int64_t g = 0; g < G && k < K; ++g) {
+            const int64_t target = (W * (g + 1)) / G;
+            const int64_t k0 = k;
+            while (k < K && (off[k + 1] <= target || k == k0)) ++k;
+            if (g == G - 1) k = K;
+            groups.push_back(make_int2((int)k0, (int)k));
+        }
+    }
+    // rotation ranges per group, proportional to the group's cost
+    const double total = (double)std::max<int64_t>(W, 1) * (double)n_rot;
+    const double per_slot = total / (double)std::max<int64_t>(want, (int64_t)groups.size());
+    T.slot_off.push_back(0);
+    for (const int2 &g : groups) {
+        const double cost = (double)(off[g.y] - off[g.x] + 1) * (double)n_rot;
+        int64_t H = (int64_t)std::ceil(cost / per_slot);
+        H = std::max<int64_t>(1, std::min<int64_t>(H, n_rot));
+        if (mode == NUMAG_MODE_SPLIT) H = 1;
+        for (int64_t h = 0; h < H; ++h)
+            T.slots.push_back(make_int4(g.x, g.y, (int)(n_rot * h / H), (int)(n_rot * (h + 1) / H)));
+        if (spec_per_object) T.slot_off.push_back((int)T.slots.size());
+    }
+    if (!spec_per_object) T.slot_off.push_back((int)T.slots.size());
+    p.n_slots = (int)T.slots.size();
+    p.n_out = spec_per_object ? (int)K : 1;
+    // items, most expensive first
+    std::vector<std::pair<int64_t, int2>> it;
+    it.reserve((size_t)p.n_slots * nblocks);
+    for (int s = 0; s < p.n_slots; ++s) {
+        const int4 sl = T.slots[s];
+        const int64_t cost = (off[sl.y] - off[sl.x] + 1) * (int64_t)(sl.w - sl.z);
+        for (int64_t b = 0; b < nblocks; ++b) it.push_back({cost, make_int2(s, (int)b)});
+    }
+    std::stable_sort(it.begin(), it.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+    for (auto &x : it) T.items.push_back(x.second);
+    p.n_items = (int64_t)T.items.size();
+    return T;
+}
+
+size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
+
 }  // namespace
 
 void forget_workspace(const void *ws)
@@ -202,42 +275,20 @@ void forget_workspace(const void *ws)
     g_uploads.erase(ws);
 }
 
-ObjectsPlan plan_objects(const Detector &d, const int64_t *h_off, int64_t K, int64_t n_rot, int mode,
-                         int spec_per_object)
+size_t objects_workspace_bytes(const Detector &d, const int64_t *h_off, int64_t K, int64_t W, int64_t n_rot,
+                               int mode, int spec_per_object)
 {
-    ObjectsPlan p{};
-    cart::choose_shape(d.n1, p.A, p.B);
-    p.col_blocks = (d.n1 + 64 * p.B - 1) / (64 * p.B);
-    p.row_blocks = (d.n0 + cart::kWaves * p.A - 1) / (cart::kWaves * p.A);
-    const int64_t nblocks = (int64_t)p.col_blocks * p.row_blocks;
-    int64_t H = (kTarget + K * nblocks - 1) / (K * nblocks);
-    H = std::max<int64_t>(1, std::min<int64_t>(H, n_rot));
-    if (mode == NUMAG_MODE_SPLIT) H = 1;
-    p.H = (int)H;
-    if (spec_per_object) {
-        p.n_kslots = (int)K;
-    } else {
-        int64_t G = (kTarget + H * nblocks - 1) / (H * nblocks);
-        p.n_kslots = (int)std::max<int64_t>(1, std::min<int64_t>(G, K));
-    }
-    p.n_items = (int64_t)p.n_kslots * p.H * nblocks;
-    (void)h_off;
-    return p;
-}
-
-size_t objects_workspace_bytes(const ObjectsPlan &p, const Detector &d, int64_t K, int64_t n_rot, int mode)
-{
-    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const Tables T = make_tables(d, h_off, K, W, n_rot, mode, spec_per_object);
     const size_t P = (size_t)d.n0 * d.n1;
     size_t b = 0;
     b += al((size_t)(K + 1) * sizeof(int64_t));
     b += al((size_t)n_rot * 9 * sizeof(double));
-    b += al((size_t)p.n_items * sizeof(int4));
-    b += al((size_t)p.n_kslots * sizeof(int2));
-    b += al((size_t)p.H * sizeof(int2));
+    b += al(T.items.size() * sizeof(int2));
+    b += al(T.slots.size() * sizeof(int4));
+    b += al(T.slot_off.size() * sizeof(int));
     b += al(sizeof(int) * 64);
-    b += al((size_t)p.H * p.n_kslots * P * 16 * sizeof(double));
-    if (mode == NUMAG_MODE_SPLIT) b += al((size_t)p.n_kslots * P * 8 * sizeof(double));
+    b += al((size_t)T.p.n_slots * P * 16 * sizeof(double));
+    if (mode == NUMAG_MODE_SPLIT) b += al((size_t)T.p.n_slots * P * 8 * sizeof(double));
     return b;
 }
 
@@ -246,69 +297,28 @@ int launch_objects(const numag_sample &s, const double *h_rot, int64_t n_rot, co
                    hipStream_t st)
 {
     const int64_t K = s.n_objects;
-    const int64_t W = s.n_points;
-    std::vector<int64_t> off(K + 1);
-    if (K == 1 || s.obj_offsets == nullptr) {
-        off[0] = 0;
-        off[1] = W;
-    } else {
-        std::memcpy(off.data(), s.obj_offsets, sizeof(int64_t) * (K + 1));
-    }
-    const ObjectsPlan p = plan_objects(d, off.data(), K, n_rot, mode, spec_per_object);
-    const int64_t nblocks = (int64_t)p.col_blocks * p.row_blocks;
     const int64_t P = (int64_t)d.n0 * d.n1;
-
-    // object ranges of the slots: single objects, or contiguous groups of
-    // roughly equal point counts
-    std::vector<int2> ksr(p.n_kslots);
-    if (spec_per_object || p.n_kslots == K) {
-        for (int64_t k = 0; k < p.n_kslots; ++k) ksr[k] = make_int2((int)k, (int)k + 1);
-    } else {
-        int64_t k = 0;
-        for (int g = 0; g < p.n_kslots; ++g) {
-            const int64_t target = (W * (g + 1)) / p.n_kslots;
-            const int64_t k0 = k;
-            while (k < K && (off[k + 1] <= target || k == k0)) ++k;
-            if (g == p.n_kslots - 1) k = K;
-            ksr[g] = make_int2((int)k0, (int)k);
-        }
-    }
-    std::vector<int2> rr(p.H);
-    for (int h = 0; h < p.H; ++h) rr[h] = make_int2((int)(n_rot * h / p.H), (int)(n_rot * (h + 1) / p.H));
-    std::vector<int4> items;
-    std::vector<int64_t> cost;
-    items.reserve(p.n_items);
-    for (int ks = 0; ks < p.n_kslots; ++ks)
-        for (int h = 0; h < p.H; ++h)
-            for (int64_t b = 0; b < nblocks; ++b) items.push_back(make_int4(ks, h, (int)b, 0));
-    std::vector<int64_t> idx(items.size());
-    for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int64_t)i;
-    auto item_cost = [&](const int4 &it) {
-        return (off[ksr[it.x].y] - off[ksr[it.x].x] + 1) * (int64_t)(rr[it.y].y - rr[it.y].x);
-    };
-    std::stable_sort(idx.begin(), idx.end(),
-                     [&](int64_t a, int64_t b) { return item_cost(items[a]) > item_cost(items[b]); });
-    std::vector<int4> sorted(items.size());
-    for (size_t i = 0; i < idx.size(); ++i) sorted[i] = items[idx[i]];
+    const Tables T = make_tables(d, s.obj_offsets, K, s.n_points, n_rot, mode, spec_per_object);
+    const ObjectsPlan &p = T.p;
 
     // workspace layout
     char *base = (char *)ws;
     size_t used = 0;
     auto take = [&](size_t bytes) {
         char *r = base + used;
-        used += (bytes + 255) & ~(size_t)255;
+        used += al(bytes);
         return r;
     };
     char *tables = base;
     int64_t *d_off = (int64_t *)take(sizeof(int64_t) * (K + 1));
     double *d_rot = (double *)take(sizeof(double) * 9 * n_rot);
-    int4 *d_items = (int4 *)take(sizeof(int4) * sorted.size());
-    int2 *d_ksr = (int2 *)take(sizeof(int2) * ksr.size());
-    int2 *d_rr = (int2 *)take(sizeof(int2) * rr.size());
+    int2 *d_items = (int2 *)take(sizeof(int2) * T.items.size());
+    int4 *d_slots = (int4 *)take(sizeof(int4) * T.slots.size());
+    int *d_slot_off = (int *)take(sizeof(int) * T.slot_off.size());
     const size_t table_bytes = used;
     int *d_counter = (int *)take(sizeof(int) * 64);
-    double *d_spec = (double *)take(sizeof(double) * 16 * (size_t)p.H * p.n_kslots * P);
-    double *d_amp = mode == NUMAG_MODE_SPLIT ? (double *)take(sizeof(double) * 8 * (size_t)p.n_kslots * P) : nullptr;
+    double *d_spec = (double *)take(sizeof(double) * 16 * (size_t)p.n_slots * P);
+    double *d_amp = mode == NUMAG_MODE_SPLIT ? (double *)take(sizeof(double) * 8 * (size_t)p.n_slots * P) : nullptr;
     if (used > ws_bytes) {
         set_error("numag_amplitudes: workspace too small for the object path");
         return NUMAG_E_WORKSPACE;
@@ -319,16 +329,16 @@ int launch_objects(const numag_sample &s, const double *h_rot, int64_t n_rot, co
     auto put = [&](const void *dst, const void *src, size_t n) {
         std::memcpy(img.data() + ((const char *)dst - tables), src, n);
     };
-    put(d_off, off.data(), sizeof(int64_t) * (K + 1));
+    put(d_off, T.off.data(), sizeof(int64_t) * (K + 1));
     if (h_rot != nullptr) {
         put(d_rot, h_rot, sizeof(double) * 9 * n_rot);
     } else {
         const double I3[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
         put(d_rot, I3, sizeof(I3));
     }
-    put(d_items, sorted.data(), sizeof(int4) * sorted.size());
-    put(d_ksr, ksr.data(), sizeof(int2) * ksr.size());
-    put(d_rr, rr.data(), sizeof(int2) * rr.size());
+    put(d_items, T.items.data(), sizeof(int2) * T.items.size());
+    put(d_slots, T.slots.data(), sizeof(int4) * T.slots.size());
+    put(d_slot_off, T.slot_off.data(), sizeof(int) * T.slot_off.size());
     bool upload = true;
     {
         std::lock_guard<std::mutex> lk(g_upload_mu);
@@ -343,9 +353,9 @@ int launch_objects(const numag_sample &s, const double *h_rot, int64_t n_rot, co
     }
 
     // zero the accumulators and the counter (kernels, so the sequence can be captured)
-    int rc = launch_fill(d_spec, 16 * (int64_t)p.H * p.n_kslots * P, 0.0, st);
+    int rc = launch_fill(d_spec, 16 * (int64_t)p.n_slots * P, 0.0, st);
     if (rc != NUMAG_OK) return rc;
-    if (d_amp != nullptr && (rc = launch_fill(d_amp, 8 * (int64_t)p.n_kslots * P, 0.0, st)) != NUMAG_OK) return rc;
+    if (d_amp != nullptr && (rc = launch_fill(d_amp, 8 * (int64_t)p.n_slots * P, 0.0, st)) != NUMAG_OK) return rc;
     hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, st, d_counter, 64, 0);
     NUMAG_HIP_CHECK(hipGetLastError());
 
@@ -357,10 +367,8 @@ int launch_objects(const numag_sample &s, const double *h_rot, int64_t n_rot, co
     args.obj_pos = s.obj_pos;
     args.rot = d_rot;
     args.items = d_items;
-    args.kslot_range = d_ksr;
-    args.rot_range = d_rr;
+    args.slots = d_slots;
     args.n_items = (int)p.n_items;
-    args.n_kslots = p.n_kslots;
     args.col_blocks = p.col_blocks;
     args.counter = d_counter;
     args.spec = d_spec;
@@ -374,13 +382,13 @@ int launch_objects(const numag_sample &s, const double *h_rot, int64_t n_rot, co
     }
     NUMAG_HIP_CHECK(hipGetLastError());
 
-    const int64_t n_spec = (spec_per_object ? p.n_kslots : 1) * P * 16;
-    hipLaunchKernelGGL(spec_reduce_kernel, dim3((unsigned)((n_spec + 255) / 256)), dim3(256), 0, st, d_spec, p.H,
-                       p.n_kslots, spec_per_object, P, 1.0 / (double)n_rot, spec_out);
+    const int64_t n_spec = (int64_t)p.n_out * P * 16;
+    hipLaunchKernelGGL(spec_reduce_kernel, dim3((unsigned)((n_spec + 255) / 256)), dim3(256), 0, st, d_spec, d_slot_off,
+                       p.n_out, P, 1.0 / (double)n_rot, spec_out);
     NUMAG_HIP_CHECK(hipGetLastError());
     if (d_amp != nullptr) {
         hipLaunchKernelGGL(amp_reduce_kernel, dim3((unsigned)((P * 8 + 255) / 256)), dim3(256), 0, st, d_amp,
-                           p.n_kslots, P, amp_out);
+                           p.n_slots, P, amp_out);
         NUMAG_HIP_CHECK(hipGetLastError());
     }
     return NUMAG_OK;
