@@ -35,7 +35,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-pixels", type=int, default=24576,
+    ap.add_argument("--cpu-pixels", type=int, default=49152,
                     help="pixels of the oracle's bounded sample")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the separate orientation-batch measurement")

@@ -216,6 +216,33 @@ int numag_grad(const numag_sample *sample, const double *rot, const numag_qgrid 
                const double *weight, double *loss_out, double *dnuc_out, double *dmag_out,
                void *workspace, size_t ws_bytes, void *stream);
 
+/*
+ * Two-dimensional correlation function, eq. crav2d,
+ *   C(rho, alpha) = int int f(q, theta) exp(i q rho cos(theta - alpha)) q dq dtheta,
+ * evaluated as the trapezoidal quadrature over the detector `grid` (polar:
+ * weights h_i q_i dtheta with h_i = dq halved at q = 0 and q_max; Cartesian:
+ * dq_y dq_z with halved edge rows/columns) at the points of the real-space grid
+ * `rgrid` (same descriptor; its qmax is r_max in nm: Cartesian r on [-r_max, r_max]^2,
+ * polar rho_a = a r_max / (n_rho - 1), alpha_b = 2 pi b / n_alpha with
+ * r = rho (sin alpha, cos alpha)).
+ *   f       [n_f][P] data sets on `grid`
+ *   C_out   [n_f][R][2] complex (R = rgrid pixels)
+ *   workspace of at least numag_correlation_2d_workspace_size() bytes.
+ */
+size_t numag_correlation_2d_workspace_size(const numag_qgrid *grid, const numag_qgrid *rgrid);
+int numag_correlation_2d(const numag_qgrid *grid, const double *f, int32_t n_f, const numag_qgrid *rgrid,
+                         double *C_out, void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * Angular spectrum, eqs. CosineSinceIntensities and ModalAmplitudes, on a polar
+ * detector (periodic trapezoidal rule over theta):
+ *   I_k^{s,c}(q_i) = (2 - delta_k0)/(2 pi) int f(q_i, theta) {sin, cos}(k theta) dtheta,
+ *   a_k = sum_i I_k(q_i),  A_k = a_k / sum_j sqrt(a_j^s^2 + a_j^c^2),  0 <= k <= k_max.
+ *   Is_out, Ic_out [n_f][n_q][k_max+1];  As_out, Ac_out [n_f][k_max+1] or NULL.
+ */
+int numag_angular_spectrum(const numag_qgrid *grid, const double *f, int32_t n_f, int32_t k_max, double *Is_out,
+                           double *Ic_out, double *As_out, double *Ac_out, void *stream);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *numag_last_error(void);
 

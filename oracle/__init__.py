@@ -68,6 +68,8 @@ def _load():
         lib.orc_correlation.argtypes = [i64, P, i64, P, i64, P, d, P, P]
         lib.orc_loss_grad.argtypes = [i64, P, P, P, i64, P, P, P, i64, P, P, P, d, d, d, P, P, P, P, P]
         lib.orc_angular_spectrum.argtypes = [i64, i64, P, i64, P, P]
+        lib.orc_correlation_2d.argtypes = [i64, P, P, P, i64, P, i64, P, P, P]
+        lib.orc_correlation_2d.restype = None
         lib.orc_threads.argtypes = []
         lib.orc_threads.restype = ctypes.c_int
         for f in (lib.orc_amplitudes, lib.orc_spectral, lib.orc_cross_sections,
@@ -260,6 +262,58 @@ def loss_grad(pos, nuc, mag, qy, qz, qhat, target, weight, V=1.0, bH=1.0, scale=
                       qy.size, _ptr(qy), _ptr(qz), _ptr(qhat), float(V), float(bH), float(scale),
                       _ptr(T), _ptr(w), _ptr(loss), _ptr(dn), _ptr(dm))
     return float(loss[0]), dn, dm
+
+
+def quadrature_weights(kind, n0, n1, qmax):
+    """Trapezoidal weights of int d^2q over a detector (Sec. 2.5 trapezoidal rule).
+    Polar: q dq dtheta with weight h_i q_i dtheta, h_i = dq (1/2 at q = 0 and q_max),
+    periodic in theta.  Cartesian: dq_y dq_z with 1/2 on edge rows and columns."""
+    if kind == POLAR:
+        dq = qmax / (n0 - 1) if n0 > 1 else 0.0
+        q = np.arange(n0, dtype=np.float64) * dq
+        h = np.full(n0, dq)
+        h[0] *= 0.5
+        h[-1] *= 0.5
+        dth = 2.0 * np.pi / n1
+        return np.repeat(h * q * dth, n1)
+    cy = np.ones(n0)
+    cz = np.ones(n1)
+    cy[[0, -1]] = 0.5
+    cz[[0, -1]] = 0.5
+    dqy = 2.0 * qmax / (n0 - 1) if n0 > 1 else 1.0
+    dqz = 2.0 * qmax / (n1 - 1) if n1 > 1 else 1.0
+    return (np.outer(cy, cz) * dqy * dqz).reshape(-1)
+
+
+def real_space_points(kind, n0, n1, rmax):
+    """Output points of the 2D correlation: Cartesian r on [-rmax, rmax]^2 like the
+    detector axes, or polar rho_a = a rmax/(n0 - 1), alpha_b = 2 pi b / n1 with
+    r = rho (sin alpha, cos alpha)."""
+    qy, qz, _ = pixels(kind, n0, n1, rmax)
+    return qy, qz
+
+
+def correlation_2d(kind, n0, n1, qmax, f, rkind, r0, r1, rmax):
+    """eq. crav2d: C on the real-space grid (rkind, r0, r1, rmax) from data sets f
+    [n_f, P] on the detector (kind, n0, n1, qmax).  Returns complex [n_f, R]."""
+    lib = _load()
+    f = np.ascontiguousarray(np.atleast_2d(f), dtype=np.float64)
+    qy, qz, _ = pixels(kind, n0, n1, qmax)
+    wq = np.ascontiguousarray(quadrature_weights(kind, n0, n1, qmax))
+    ry, rz = real_space_points(rkind, r0, r1, rmax)
+    ry, rz = np.ascontiguousarray(ry), np.ascontiguousarray(rz)
+    out = np.zeros((f.shape[0], ry.size), dtype=np.complex128)
+    lib.orc_correlation_2d(qy.size, _ptr(qy), _ptr(qz), _ptr(wq), f.shape[0], _ptr(f), ry.size, _ptr(ry),
+                           _ptr(rz), _ptr(out))
+    return out
+
+
+def modal_amplitudes(Is, Ic):
+    """eq. ModalAmplitudes: a_k = sum_i I_k(q_i), A_k = a_k / sum_j sqrt(a_j^s^2 + a_j^c^2)."""
+    a_s = np.sum(Is, axis=0)
+    a_c = np.sum(Ic, axis=0)
+    norm = np.sum(np.sqrt(a_s ** 2 + a_c ** 2))
+    return a_s / norm, a_c / norm
 
 
 def angular_spectrum(f_polar, n_q, n_theta, k_max):

@@ -447,6 +447,31 @@ void orc_loss_grad(int64_t W, const double *pos, const double *nuc, const double
 }
 
 /*
+ * Two-dimensional correlation function, eq. crav2d:
+ *   C(r) = int int dSigma(q, theta) exp(i q rho cos(theta - alpha)) q dq dtheta,
+ * with q rho cos(theta - alpha) = q . r for q = q (sin theta, cos theta) and
+ * r = rho (sin alpha, cos alpha) in the detector plane.  The integral is the
+ * quadrature sum_p wq[p] f[p] exp(i (qy[p] ry + qz[p] rz)); the trapezoidal
+ * weights wq (which include the Jacobian q on a polar detector) are given by
+ * the caller.  f is [n_f][n_pix]; out is [n_f][n_r] complex.
+ */
+void orc_correlation_2d(int64_t n_pix, const double *qy, const double *qz, const double *wq, int64_t n_f,
+                        const double *f, int64_t n_r, const double *ry, const double *rz, double *out_ri)
+{
+    cplx *out = (cplx *)out_ri;
+#pragma omp parallel for collapse(2) schedule(dynamic, 16)
+    for (int64_t s = 0; s < n_f; ++s)
+        for (int64_t t = 0; t < n_r; ++t) {
+            cplx acc = 0.0;
+            for (int64_t p = 0; p < n_pix; ++p) {
+                double phi = qy[p] * ry[t] + qz[p] * rz[t];
+                acc += wq[p] * f[s * n_pix + p] * (cos(phi) + I * sin(phi));
+            }
+            out[s * n_r + t] = acc;
+        }
+}
+
+/*
  * Modal (angular Fourier) intensities, eq. CosineSinceIntensities, on a polar
  * detector (rows q_i, columns theta_m = 2 pi m / n_theta) by the trapezoidal
  * rule over one period:

@@ -167,7 +167,7 @@ int run_direct(const numag_sample *s, const Rot &R, const Detector &d, double *a
     }
     int rc = launch_prepare_points(s->pos, s->nuc, s->mag, s->n_points, s->regular,
                                    L.offsets != 0 ? d_off : nullptr, s->n_objects, s->obj_pos, R,
-                                   d.kind == NUMAG_GRID_CARTESIAN ? d.step1 : 0.0, pts, st);
+                                   pts, st);
     if (rc != NUMAG_OK) return rc;
     if (d.kind == NUMAG_GRID_CARTESIAN) {
         DirectPlan p = plan_direct_cartesian(d, s->n_points);
@@ -195,6 +195,51 @@ size_t amplitudes_ws(const numag_sample *s, int64_t n_rot, const Detector &d, in
 }  // namespace
 
 extern "C" {
+
+size_t numag_correlation_2d_workspace_size(const numag_qgrid *grid, const numag_qgrid *rgrid)
+{
+    clear_error();
+    if (check_grid(grid, "numag_correlation_2d_workspace_size") != NUMAG_OK) return 0;
+    if (check_grid(rgrid, "numag_correlation_2d_workspace_size") != NUMAG_OK) return 0;
+    return correlation_2d_workspace_bytes(make_detector(*grid), make_detector(*rgrid));
+}
+
+int numag_correlation_2d(const numag_qgrid *grid, const double *f, int32_t n_f, const numag_qgrid *rgrid,
+                         double *C_out, void *workspace, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    int rc;
+    if ((rc = check_grid(grid, "numag_correlation_2d")) != NUMAG_OK) return rc;
+    if ((rc = check_grid(rgrid, "numag_correlation_2d")) != NUMAG_OK) return rc;
+    if (n_f < 0) return invalid("numag_correlation_2d: n_f < 0");
+    if (n_f > 0 && (f == nullptr || C_out == nullptr)) return invalid("numag_correlation_2d: NULL data or output");
+    const Detector d = make_detector(*grid), rd = make_detector(*rgrid);
+    const size_t need = correlation_2d_workspace_bytes(d, rd);
+    if (ws_bytes < need || workspace == nullptr) {
+        set_error("numag_correlation_2d: workspace too small (need " + std::to_string(need) + " bytes)");
+        return NUMAG_E_WORKSPACE;
+    }
+    if (n_f == 0) return NUMAG_OK;
+    forget_workspace(workspace);
+    return launch_correlation_2d(d, f, n_f, rd, C_out, workspace, ws_bytes, (hipStream_t)stream);
+}
+
+int numag_angular_spectrum(const numag_qgrid *grid, const double *f, int32_t n_f, int32_t k_max, double *Is_out,
+                           double *Ic_out, double *As_out, double *Ac_out, void *stream)
+{
+    clear_error();
+    int rc;
+    if ((rc = check_grid(grid, "numag_angular_spectrum")) != NUMAG_OK) return rc;
+    if (grid->kind != NUMAG_GRID_POLAR) return invalid("numag_angular_spectrum: needs a polar detector");
+    if (n_f < 0 || k_max < 0) return invalid("numag_angular_spectrum: n_f and k_max must be >= 0");
+    if (n_f > 65535) return invalid("numag_angular_spectrum: too many data sets");
+    if (n_f > 0 && (f == nullptr || Is_out == nullptr || Ic_out == nullptr))
+        return invalid("numag_angular_spectrum: NULL data or output");
+    if ((As_out == nullptr) != (Ac_out == nullptr))
+        return invalid("numag_angular_spectrum: give both or none of As_out, Ac_out");
+    return launch_angular_spectrum(make_detector(*grid), f, n_f, k_max, Is_out, Ic_out, As_out, Ac_out,
+                                   (hipStream_t)stream);
+}
 
 const char *numag_last_error(void) { return g_error.c_str(); }
 
@@ -396,7 +441,7 @@ int numag_grad(const numag_sample *sample, const double *rot, const numag_qgrid 
                                            (size_t)(sample->n_objects + 1) * sizeof(int64_t),
                                            hipMemcpyHostToDevice, st));
         rc = launch_prepare_points(sample->pos, sample->nuc, sample->mag, sample->n_points, sample->regular,
-                                   L.offsets != 0 ? d_off : nullptr, sample->n_objects, sample->obj_pos, R, 0.0,
+                                   L.offsets != 0 ? d_off : nullptr, sample->n_objects, sample->obj_pos, R,
                                    pts, st);
         if (rc != NUMAG_OK) return rc;
     }

@@ -74,7 +74,7 @@ Detector make_detector(const numag_qgrid &g)
 __global__ void prepare_points_kernel(const double *__restrict__ pos, const double *__restrict__ nuc,
                                       const double *__restrict__ mag, int64_t W, int reg,
                                       numag_regular g, const int64_t *__restrict__ off, int64_t K,
-                                      const double *__restrict__ obj_pos, Rot R, double dq_z,
+                                      const double *__restrict__ obj_pos, Rot R,
                                       PointRec *__restrict__ out)
 {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -119,20 +119,13 @@ __global__ void prepare_points_kernel(const double *__restrict__ pos, const doub
     r.w[1] = R.m[0] * m0 + R.m[1] * m1 + R.m[2] * m2;
     r.w[2] = R.m[3] * m0 + R.m[4] * m1 + R.m[5] * m2;
     r.w[3] = R.m[6] * m0 + R.m[7] * m1 + R.m[8] * m2;
-    if (dq_z != 0.0) {
-        const double2 dz = twiddle(dq_z * r.Z);
-        r.dzr = dz.x;
-        r.dzi = dz.y;
-    } else {
-        r.dzr = 1.0;
-        r.dzi = 0.0;
-    }
+    r.pad[0] = r.pad[1] = 0.0;
     out[j] = r;
 }
 
 int launch_prepare_points(const double *pos, const double *nuc, const double *mag, int64_t W,
                           const numag_regular *regular, const int64_t *d_offsets, int64_t K,
-                          const double *obj_pos, const Rot &R, double dq_z, PointRec *out, hipStream_t s)
+                          const double *obj_pos, const Rot &R, PointRec *out, hipStream_t s)
 {
     if (W <= 0) return NUMAG_OK;
     numag_regular g{};
@@ -140,7 +133,7 @@ int launch_prepare_points(const double *pos, const double *nuc, const double *ma
     const int tpb = 256;
     int64_t blocks = (W + tpb - 1) / tpb;
     hipLaunchKernelGGL(prepare_points_kernel, dim3((unsigned)blocks), dim3(tpb), 0, s, pos, nuc, mag, W,
-                       regular != nullptr ? 1 : 0, g, d_offsets, K, obj_pos, R, dq_z, out);
+                       regular != nullptr ? 1 : 0, g, d_offsets, K, obj_pos, R, out);
     NUMAG_HIP_CHECK(hipGetLastError());
     return NUMAG_OK;
 }
@@ -153,14 +146,12 @@ constexpr int kThreads = cart::kThreads;
 constexpr int kChunk = cart::kChunk;
 
 struct PrepLoader {
-    static constexpr bool kHasRec = true;
     const PointRec *__restrict__ pts;
     __device__ __forceinline__ cart::PointPart load(int64_t j, int slot) const
     {
         const PointRec &r = pts[j];
         return cart::PointPart{r.Y, r.Z, slot < 4 ? r.w[slot] : 0.0};
     }
-    __device__ __forceinline__ const PointRec *rec(int64_t j) const { return pts + j; }
 };
 
 template <int A, int B>

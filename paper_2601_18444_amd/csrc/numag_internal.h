@@ -47,12 +47,11 @@ struct Rot {
 };
 
 // Per-point record written by the preparation kernel: lab-frame Y, Z (q has
-// no x component), lab-frame weights (n, m'x, m'y, m'z) and the column-step
-// twiddle exp(-i dq_z Z) of the Cartesian detector (zero when not needed).
+// no x component) and lab-frame weights (n, m'x, m'y, m'z), padded to 64 bytes.
 struct alignas(64) PointRec {
     double Y, Z;
     double w[4];
-    double dzr, dzi;
+    double pad[2];
 };
 
 // ---------------------------------------------------------------------------
@@ -61,10 +60,9 @@ struct alignas(64) PointRec {
 
 // a1: X_j = R (x_j + r^{k(j)}), w'_j = (n_j, R m_j).  obj_index maps point -> object
 // via device CSR offsets (nullptr when K == 1 or no object positions).
-// dq_z is the Cartesian column step (0 for a polar detector).
 int launch_prepare_points(const double *pos, const double *nuc, const double *mag, int64_t W,
                           const numag_regular *regular, const int64_t *d_offsets, int64_t K,
-                          const double *obj_pos, const Rot &R, double dq_z, PointRec *out, hipStream_t s);
+                          const double *obj_pos, const Rot &R, PointRec *out, hipStream_t s);
 
 // a4/a5: direct Cartesian sum.  Writes [nsplit][P][8] partial sums (or the final
 // [P][8] sums when nsplit == 1) for points [0, W).
@@ -128,6 +126,15 @@ int launch_grad(const PointRec *pts, int64_t W, const Detector &d, const numag_c
                 const double *amp, const double *target, const double *weight, double *loss,
                 double *dnuc, double *dmag, const Rot &R, void *ws, size_t ws_bytes, hipStream_t s);
 size_t grad_workspace_bytes(const Detector &d, int64_t W);
+
+// 2D correlation function (eq. crav2d) from data on detector d onto real-space grid rd.
+size_t correlation_2d_workspace_bytes(const Detector &d, const Detector &rd);
+int launch_correlation_2d(const Detector &d, const double *f, int n_f, const Detector &rd, double *C, void *ws,
+                          size_t ws_bytes, hipStream_t s);
+
+// Angular spectrum (eqs. CosineSinceIntensities, ModalAmplitudes) on a polar detector.
+int launch_angular_spectrum(const Detector &d, const double *f, int n_f, int k_max, double *Is, double *Ic,
+                            double *As, double *Ac, hipStream_t s);
 
 // a10: regular-grid separable path on the matrix cores.
 int launch_separable(const double *nuc, const double *mag, const numag_regular &g, const Detector &d,

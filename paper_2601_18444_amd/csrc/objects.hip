@@ -34,10 +34,8 @@ namespace {
 constexpr int kTarget = 2048;  // work items aimed for
 
 struct RawLoader {
-    static constexpr bool kHasRec = false;
     const double *pos, *nuc, *mag;
     const double *R;  // row-major 3x3, wave-uniform
-    __device__ __forceinline__ const PointRec *rec(int64_t) const { return nullptr; }
     __device__ __forceinline__ cart::PointPart load(int64_t j, int slot) const
     {
         const double x0 = pos[3 * j], x1 = pos[3 * j + 1], x2 = pos[3 * j + 2];

@@ -59,11 +59,48 @@ size_t separable_workspace_bytes(const numag_regular &g, const Detector &d, int 
     return sep_layout(g, d).total;
 }
 
-// Ey[i][iy] = exp(-i q_y(i) y_iy),  Ez[iz][k] = exp(-i q_z(k) z_iz)
-__global__ void sep_twiddle_kernel(Detector d, numag_regular g, double2 *__restrict__ ey,
-                                   double2 *__restrict__ ez)
+constexpr int kProjCells = 64;   // (y, z) cells per projection workgroup
+constexpr int kProjSlices = 4;   // x slices per cell (one thread each)
+
+// One launch for the operands of both contractions.
+// Workgroups [0, n_proj): projection S[c][iy][iz] = sum_x w_c(x, iy, iz) for 64
+// cells, x split into 4 slices summed by 4 threads, slices added in a fixed
+// order through LDS.  Workgroups [n_proj, ...): twiddles
+// Ey[i][iy] = exp(-i q_y(i) y_iy) and Ez[iz][k] = exp(-i q_z(k) z_iz).
+__global__ __launch_bounds__(256) void sep_prepare_kernel(Detector d, numag_regular g, const double *__restrict__ nuc,
+                                                          const double *__restrict__ mag, int n_proj,
+                                                          double *__restrict__ S, double2 *__restrict__ ey,
+                                                          double2 *__restrict__ ez)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nyz = (int64_t)g.n[1] * g.n[2];
+    if ((int)blockIdx.x < n_proj) {
+        __shared__ double part[kProjSlices][4][kProjCells];
+        const int cell = threadIdx.x % kProjCells, slice = threadIdx.x / kProjCells;
+        const int64_t rem = (int64_t)blockIdx.x * kProjCells + cell;
+        double s[4] = {0.0, 0.0, 0.0, 0.0};
+        if (rem < nyz) {
+            for (int ix = slice; ix < g.n[0]; ix += kProjSlices) {
+                const int64_t j = (int64_t)ix * nyz + rem;
+                if (nuc != nullptr) s[0] += nuc[j];
+                if (mag != nullptr) {
+                    s[1] += mag[3 * j];
+                    s[2] += mag[3 * j + 1];
+                    s[3] += mag[3 * j + 2];
+                }
+            }
+        }
+        for (int c = 0; c < 4; ++c) part[slice][c][cell] = s[c];
+        __syncthreads();
+        // thread (c, cell) adds the slices in order
+        const int c = threadIdx.x / kProjCells;
+        if (rem < nyz) {
+            double t = 0.0;
+            for (int sl = 0; sl < kProjSlices; ++sl) t += part[sl][c][cell];
+            S[c * nyz + rem] = t;
+        }
+        return;
+    }
+    const int64_t idx = (int64_t)(blockIdx.x - n_proj) * blockDim.x + threadIdx.x;
     const int64_t ny = g.n[1], nz = g.n[2];
     const int64_t ne = (int64_t)d.n0 * ny;
     if (idx < ne) {
@@ -76,25 +113,6 @@ __global__ void sep_twiddle_kernel(Detector d, numag_regular g, double2 *__restr
         const double z = g.origin[2] + (double)iz * g.step[2];
         ez[r] = tw_s(axis_s(d.origin1, k, d.step1) * z);
     }
-}
-
-// S[c][iy][iz] = sum_ix w_c(ix, iy, iz), ix ascending
-__global__ void sep_project_kernel(const double *__restrict__ nuc, const double *__restrict__ mag,
-                                   numag_regular g, double *__restrict__ S)
-{
-    const int64_t nyz = (int64_t)g.n[1] * g.n[2];
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= 4 * nyz) return;
-    const int c = (int)(idx / nyz);
-    const int64_t rem = idx % nyz;
-    double s = 0.0;
-    if (c == 0) {
-        if (nuc != nullptr)
-            for (int ix = 0; ix < g.n[0]; ++ix) s += nuc[(int64_t)ix * nyz + rem];
-    } else if (mag != nullptr) {
-        for (int ix = 0; ix < g.n[0]; ++ix) s += mag[3 * ((int64_t)ix * nyz + rem) + (c - 1)];
-    }
-    S[idx] = s;
 }
 
 // ---- FP64 MFMA -------------------------------------------------------------
@@ -115,6 +133,7 @@ __global__ __launch_bounds__(256) void sep_contract1_f64(const double *__restric
     const int ai = m0 + (lane & 15), bj = n0 + (lane & 15), kq = lane >> 4;
     const double *Sc = S + (int64_t)c * ny * nz;
     v4d accR = {0.0, 0.0, 0.0, 0.0}, accI = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
     for (int k = 0; k < nz; k += 4) {
         const int kk = k + kq;
         const double a = (ai < ny && kk < nz) ? Sc[(int64_t)ai * nz + kk] : 0.0;
@@ -144,6 +163,7 @@ __global__ __launch_bounds__(256) void sep_contract2_f64(const double2 *__restri
     const int ai = m0 + (lane & 15), bj = n0t + (lane & 15), kq = lane >> 4;
     const double2 *Tc = T + (int64_t)c * ny * n1;
     v4d accR = {0.0, 0.0, 0.0, 0.0}, accI = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
     for (int k = 0; k < ny; k += 4) {
         const int kk = k + kq;
         const double2 a = (ai < n0 && kk < ny) ? Ey[(int64_t)ai * ny + kk] : make_double2(0.0, 0.0);
@@ -291,10 +311,10 @@ int launch_separable(const double *nuc, const double *mag, const numag_regular &
     double2 *T = (double2 *)(base + L.ey + L.ez + L.s);
     const int ny = g.n[1], nz = g.n[2];
     const int64_t ntw = (int64_t)d.n0 * ny + (int64_t)nz * d.n1;
-    hipLaunchKernelGGL(sep_twiddle_kernel, dim3((unsigned)((ntw + 255) / 256)), dim3(256), 0, s, d, g, ey, ez);
-    NUMAG_HIP_CHECK(hipGetLastError());
-    const int64_t nproj = 4 * (int64_t)ny * nz;
-    hipLaunchKernelGGL(sep_project_kernel, dim3((unsigned)((nproj + 255) / 256)), dim3(256), 0, s, nuc, mag, g, S);
+    const int64_t n_proj = ((int64_t)ny * nz + kProjCells - 1) / kProjCells;
+    const int64_t n_tw = (ntw + 255) / 256;
+    hipLaunchKernelGGL(sep_prepare_kernel, dim3((unsigned)(n_proj + n_tw)), dim3(256), 0, s, d, g, nuc, mag,
+                       (int)n_proj, S, ey, ez);
     NUMAG_HIP_CHECK(hipGetLastError());
     const int64_t t1 = 4LL * ((ny + 15) / 16) * ((d.n1 + 15) / 16);
     const int64_t t2 = 4LL * ((d.n0 + 15) / 16) * ((d.n1 + 15) / 16);

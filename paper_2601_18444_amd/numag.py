@@ -69,6 +69,9 @@ def _load():
         "numag_azimuthal_average": (ctypes.c_int, [P, P, i32, i32, d, P, P, P]),
         "numag_correlation": (ctypes.c_int, [P, P, i32, i32, P, i32, d, P, P, P]),
         "numag_grad": (ctypes.c_int, [P, P, P, P, P, P, P, P, P, P, P, sz, P]),
+        "numag_correlation_2d_workspace_size": (sz, [P, P]),
+        "numag_correlation_2d": (ctypes.c_int, [P, P, i32, P, P, P, sz, P]),
+        "numag_angular_spectrum": (ctypes.c_int, [P, P, i32, i32, P, P, P, P, P]),
         "numag_last_error": (ctypes.c_char_p, []),
         "numag_version": (ctypes.c_char_p, []),
     }
@@ -312,6 +315,38 @@ def correlation(q: torch.Tensor, I: torch.Tensor, r: torch.Tensor, scale: float 
                                 _ptr(p), _stream())
     _check("numag_correlation", rc)
     return c, p
+
+
+def correlation_2d(grid: QGrid, f: torch.Tensor, rgrid: QGrid, out=None):
+    """numag_correlation_2d (eq. crav2d).  f is [n_f, P] on `grid`; returns complex
+    [n_f, R, 2] on the real-space grid `rgrid` (its qmax is r_max)."""
+    f2 = f.reshape(-1, grid.n_pixels).contiguous()
+    n_f = f2.shape[0]
+    C = out if out is not None else torch.empty((n_f, rgrid.n_pixels, 2), dtype=torch.float64, device=f.device)
+    nws = _lib.numag_correlation_2d_workspace_size(ctypes.byref(grid), ctypes.byref(rgrid))
+    if nws == 0:
+        raise NumagError("numag_correlation_2d_workspace_size", E_INVALID, last_error())
+    ws = workspace(nws, f.device)
+    rc = _lib.numag_correlation_2d(ctypes.byref(grid), _ptr(f2), n_f, ctypes.byref(rgrid), _ptr(C), _ptr(ws),
+                                   ws.numel(), _stream())
+    _check("numag_correlation_2d", rc)
+    return C
+
+
+def angular_spectrum(grid: QGrid, f: torch.Tensor, k_max: int, amplitudes: bool = True):
+    """numag_angular_spectrum on a polar detector.  Returns (Is, Ic [n_f, n_q, k_max+1],
+    As, Ac [n_f, k_max+1] or None)."""
+    f2 = f.reshape(-1, grid.n_pixels).contiguous()
+    n_f = f2.shape[0]
+    dev = f.device
+    Is = torch.empty((n_f, grid.n0, k_max + 1), dtype=torch.float64, device=dev)
+    Ic = torch.empty_like(Is)
+    As = torch.empty((n_f, k_max + 1), dtype=torch.float64, device=dev) if amplitudes else None
+    Ac = torch.empty_like(As) if amplitudes else None
+    rc = _lib.numag_angular_spectrum(ctypes.byref(grid), _ptr(f2), n_f, int(k_max), _ptr(Is), _ptr(Ic), _ptr(As),
+                                     _ptr(Ac), _stream())
+    _check("numag_angular_spectrum", rc)
+    return Is, Ic, As, Ac
 
 
 def grad(sample: Sample, grid: QGrid, c: Consts, weight: torch.Tensor, target: Optional[torch.Tensor] = None,
