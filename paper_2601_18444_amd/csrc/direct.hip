@@ -69,7 +69,7 @@ Detector make_detector(const numag_qgrid &g)
 }
 
 // ---------------------------------------------------------------------------
-// a1: sample assembly and rotation (Sec. 3.2): X = R (x + r^k), w' = (n, R m).
+// sample assembly and rotation (Sec. 3.2): X = R (x + r^k), w' = (n, R m).
 // ---------------------------------------------------------------------------
 __global__ void prepare_points_kernel(const double *__restrict__ pos, const double *__restrict__ nuc,
                                       const double *__restrict__ mag, int64_t W, int reg,
@@ -139,7 +139,7 @@ int launch_prepare_points(const double *pos, const double *nuc, const double *ma
 }
 
 // ---------------------------------------------------------------------------
-// a4: Cartesian direct sum.
+// Cartesian direct sum.
 // ---------------------------------------------------------------------------
 constexpr int kWaves = cart::kWaves;
 constexpr int kThreads = cart::kThreads;
@@ -154,33 +154,32 @@ struct PrepLoader {
     }
 };
 
-template <int A, int B>
+template <int LR>
 __global__ __launch_bounds__(kThreads, 2) void direct_cartesian_kernel(
     const PointRec *__restrict__ pts, int64_t W, int64_t per, Detector d, double *__restrict__ out)
 {
-    __shared__ cart::Smem<A> sm;
-    const int col0 = blockIdx.x * 64 * B;
-    const int row0 = blockIdx.y * kWaves * A;
+    using T = cart::Tile<LR>;
+    __shared__ cart::Smem<LR> sm;
+    const int col0 = blockIdx.x * T::COLS;
+    const int row0 = blockIdx.y * T::ROWS;
     const int64_t jbeg = (int64_t)blockIdx.z * per;
     const int64_t jend = min(W, jbeg + per);
-    double acc[A][B][8];
-    cart::zero<A, B>(acc);
-    cart::accumulate<A, B>(PrepLoader{pts}, jbeg, jend, d, col0, row0, sm, acc);
+    double acc[cart::kB][8];
+    cart::zero(acc);
+    cart::accumulate<LR>(PrepLoader{pts}, jbeg, jend, d, col0, row0, sm, acc);
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t P = (int64_t)d.n0 * d.n1;
     double *dst = out + (int64_t)blockIdx.z * P * 8;
+    const int row = T::row(row0, lane, wave);
+    if (row >= d.n0) return;
 #pragma unroll
-    for (int r = 0; r < A; ++r) {
-        const int row = row0 + wave * A + r;
+    for (int c = 0; c < cart::kB; ++c) {
+        const int col = T::col(col0, lane, c);
+        if (col < d.n1) {
+            double *o = dst + ((int64_t)row * d.n1 + col) * 8;
 #pragma unroll
-        for (int c = 0; c < B; ++c) {
-            const int col = col0 + lane * B + c;
-            if (row < d.n0 && col < d.n1) {
-                double *o = dst + ((int64_t)row * d.n1 + col) * 8;
-#pragma unroll
-                for (int v = 0; v < 8; ++v) o[v] = acc[r][c][v];
-            }
+            for (int v = 0; v < 8; ++v) o[v] = acc[c][v];
         }
     }
 }
@@ -199,12 +198,10 @@ static int target_workgroups()
 DirectPlan plan_direct_cartesian(const Detector &d, int64_t W)
 {
     DirectPlan p{};
-    int B = 1;
-    while (B < 8 && 64 * B < d.n1) B *= 2;
-    p.B = B;
-    p.A = 8 / B;
-    p.col_blocks = (d.n1 + 64 * B - 1) / (64 * B);
-    p.row_blocks = (d.n0 + kWaves * p.A - 1) / (kWaves * p.A);
+    p.lanes = cart::choose_lanes(d.n1);
+    const int cols = p.lanes * cart::kB, rows = kThreads / p.lanes;
+    p.col_blocks = (d.n1 + cols - 1) / cols;
+    p.row_blocks = (d.n0 + rows - 1) / rows;
     int64_t blocks = (int64_t)p.col_blocks * p.row_blocks;
     int64_t want = (target_workgroups() + blocks - 1) / blocks;
     // each split should own a few chunks
@@ -232,14 +229,13 @@ int launch_direct_cartesian(const PointRec *pts, int64_t W, const Detector &d, c
 {
     dim3 grid(p.col_blocks, p.row_blocks, p.nsplit);
     dim3 block(kThreads);
-#define NUMAG_LAUNCH_CART(AA, BB)                                                            \
-    hipLaunchKernelGGL((direct_cartesian_kernel<AA, BB>), grid, block, 0, s, pts, W, p.per, d, \
-                       partial)
-    switch (p.B) {
-        case 1: NUMAG_LAUNCH_CART(8, 1); break;
-        case 2: NUMAG_LAUNCH_CART(4, 2); break;
-        case 4: NUMAG_LAUNCH_CART(2, 4); break;
-        default: NUMAG_LAUNCH_CART(1, 8); break;
+#define NUMAG_LAUNCH_CART(LR) \
+    hipLaunchKernelGGL((direct_cartesian_kernel<LR>), grid, block, 0, s, pts, W, p.per, d, partial)
+    switch (p.lanes) {
+        case 8: NUMAG_LAUNCH_CART(8); break;
+        case 16: NUMAG_LAUNCH_CART(16); break;
+        case 32: NUMAG_LAUNCH_CART(32); break;
+        default: NUMAG_LAUNCH_CART(64); break;
     }
 #undef NUMAG_LAUNCH_CART
     NUMAG_HIP_CHECK(hipGetLastError());
@@ -260,6 +256,7 @@ __global__ __launch_bounds__(kThreads, 2) void direct_polar_kernel(const PointRe
     constexpr int ROWS = kWaves * B;
     __shared__ double2 s_start[kPolarChunk][kWaves][64];
     __shared__ double2 s_step[kPolarChunk][64];
+    __shared__ double s_k[kPolarChunk][64];
     __shared__ double s_w[kPolarChunk][4];
 
     const int t = threadIdx.x;
@@ -298,6 +295,7 @@ __global__ __launch_bounds__(kThreads, 2) void direct_polar_kernel(const PointRe
             sb = cmul(sb, sb);
             sb = cmul(sb, sb);
             s_step[jj][lane] = step;
+            s_k[jj][lane] = step.x + step.x;
 #pragma unroll
             for (int w = 0; w < kWaves; ++w) {
                 s_start[jj][w][lane] = st;
@@ -311,20 +309,23 @@ __global__ __launch_bounds__(kThreads, 2) void direct_polar_kernel(const PointRe
         }
         __syncthreads();
         for (int jj = 0; jj < nk; ++jj) {
-            double2 p = s_start[jj][wave][lane];
+            cart::Operands o;
             const double2 step = s_step[jj][lane];
-            const double w0 = s_w[jj][0], w1 = s_w[jj][1], w2 = s_w[jj][2], w3 = s_w[jj][3];
+            o.k = s_k[jj][lane];
 #pragma unroll
-            for (int r = 0; r < B; ++r) {
-                acc[r][0] += w0 * p.x;
-                acc[r][1] += w0 * p.y;
-                acc[r][2] += w1 * p.x;
-                acc[r][3] += w1 * p.y;
-                acc[r][4] += w2 * p.x;
-                acc[r][5] += w2 * p.y;
-                acc[r][6] += w3 * p.x;
-                acc[r][7] += w3 * p.y;
-                if (r + 1 < B) p = cmul(p, step);
+            for (int v = 0; v < 4; ++v) o.w[v] = s_w[jj][v];
+            // rows 0 and 1 by the start and one step, further rows by the
+            // two-term recurrence p_{r+1} = 2 cos(dq u) p_r - p_{r-1}
+            double2 pm = s_start[jj][wave][lane];
+            double2 pc = cmul(pm, step);
+            cart::add_weighted(o, pm, acc[0]);
+            cart::add_weighted(o, pc, acc[1]);
+#pragma unroll
+            for (int r = 2; r < B; ++r) {
+                const double2 pn = make_double2(fma(o.k, pc.x, -pm.x), fma(o.k, pc.y, -pm.y));
+                cart::add_weighted(o, pn, acc[r]);
+                pm = pc;
+                pc = pn;
             }
         }
     }
@@ -344,8 +345,7 @@ __global__ __launch_bounds__(kThreads, 2) void direct_polar_kernel(const PointRe
 DirectPlan plan_direct_polar(const Detector &d, int64_t W)
 {
     DirectPlan p{};
-    p.A = 1;
-    p.B = kPolarB;
+    p.lanes = 64;
     p.col_blocks = (d.n1 + 63) / 64;
     p.row_blocks = (d.n0 + kWaves * kPolarB - 1) / (kWaves * kPolarB);
     int64_t blocks = (int64_t)p.col_blocks * p.row_blocks;
@@ -388,7 +388,7 @@ int launch_fill(double *out, int64_t n, double value, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------
-// a5: fixed-order FP64 combine of split partials.
+// fixed-order FP64 combine of split partials.
 // ---------------------------------------------------------------------------
 __global__ void combine_kernel(const double *__restrict__ part, int nsplit, int64_t n,
                                double *__restrict__ out, int accumulate)

@@ -58,16 +58,16 @@ struct alignas(64) PointRec {
 // Launchers (each enqueues on `stream`, returns NUMAG_OK or NUMAG_E_HIP).
 // ---------------------------------------------------------------------------
 
-// a1: X_j = R (x_j + r^{k(j)}), w'_j = (n_j, R m_j).  obj_index maps point -> object
+// X_j = R (x_j + r^{k(j)}), w'_j = (n_j, R m_j).  obj_index maps point -> object
 // via device CSR offsets (nullptr when K == 1 or no object positions).
 int launch_prepare_points(const double *pos, const double *nuc, const double *mag, int64_t W,
                           const numag_regular *regular, const int64_t *d_offsets, int64_t K,
                           const double *obj_pos, const Rot &R, PointRec *out, hipStream_t s);
 
-// a4/a5: direct Cartesian sum.  Writes [nsplit][P][8] partial sums (or the final
+// direct Cartesian sum.  Writes [nsplit][P][8] partial sums (or the final
 // [P][8] sums when nsplit == 1) for points [0, W).
 struct DirectPlan {
-    int A, B;        // rows per wave, columns per lane
+    int lanes;       // lanes per detector row (Cartesian) or 64 (polar)
     int nsplit;      // point ranges summed by different workgroups
     int64_t per;     // points per split (multiple of the chunk)
     int col_blocks, row_blocks;
@@ -90,11 +90,11 @@ int launch_fill(double *out, int64_t n, double value, hipStream_t s);
 int launch_combine(const double *part, int nsplit, int64_t P, double *out, int accumulate,
                    hipStream_t s);
 
-// a6: work items (object slot, rotation group, pixel block); each sums complete
+// work items (object slot, rotation group, pixel block); each sums complete
 // objects and adds F F^H (and, in split mode, exp(-i q.R r^k) F) into an
 // accumulator slot no other item touches; slots are reduced in a fixed order.
 struct ObjectsPlan {
-    int A, B;
+    int lanes;      // lanes per detector row
     int col_blocks, row_blocks;
     int n_slots;    // accumulator slots (object set x rotation range)
     int n_out;      // spectral matrices written (K per object, or 1)
@@ -109,7 +109,7 @@ int launch_objects(const numag_sample &s, const double *h_rot, int64_t n_rot, co
 // overwrites them).
 void forget_workspace(const void *ws);
 
-// a7: cross sections from amplitudes ([n_sets][P][8]) or spectra ([n_sets][P][16]).
+// cross sections from amplitudes ([n_sets][P][8]) or spectra ([n_sets][P][16]).
 int launch_cross_section(const Detector &d, int64_t n_sets, const double *amp, const double *spec,
                          const numag_consts &c, uint32_t mask, double *out, hipStream_t s);
 
@@ -121,7 +121,7 @@ int launch_azimuthal(const Detector &d, const double *f, int n_f, int n_bins, do
 int launch_correlation(const double *q, const double *I, int n_q, int n_f, const double *r, int n_r,
                        double scale, double *c, double *p, hipStream_t s);
 
-// a11: residual weights, loss, adjoint sum.
+// residual weights, loss, adjoint sum.
 int launch_grad(const PointRec *pts, int64_t W, const Detector &d, const numag_consts &c,
                 const double *amp, const double *target, const double *weight, double *loss,
                 double *dnuc, double *dmag, const Rot &R, void *ws, size_t ws_bytes, hipStream_t s);
@@ -136,7 +136,7 @@ int launch_correlation_2d(const Detector &d, const double *f, int n_f, const Det
 int launch_angular_spectrum(const Detector &d, const double *f, int n_f, int k_max, double *Is, double *Ic,
                             double *As, double *Ac, hipStream_t s);
 
-// a10: regular-grid separable path on the matrix cores.
+// regular-grid separable path on the matrix cores.
 int launch_separable(const double *nuc, const double *mag, const numag_regular &g, const Detector &d,
                      int path, double *amp, void *ws, size_t ws_bytes, hipStream_t s);
 size_t separable_workspace_bytes(const numag_regular &g, const Detector &d, int path);

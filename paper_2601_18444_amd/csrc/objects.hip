@@ -66,10 +66,11 @@ struct ObjArgs {
     double *amp;             // [n_slots][P][8] or null (split mode)
 };
 
-template <int A, int B>
+template <int LR>
 __global__ __launch_bounds__(cart::kThreads, 2) void objects_kernel(ObjArgs a, Detector d)
 {
-    __shared__ cart::Smem<A> sm;
+    using T = cart::Tile<LR>;
+    __shared__ cart::Smem<LR> sm;
     __shared__ int s_item;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t P = (int64_t)d.n0 * d.n1;
@@ -81,17 +82,18 @@ __global__ __launch_bounds__(cart::kThreads, 2) void objects_kernel(ObjArgs a, D
         if (it >= a.n_items) break;
         const int2 item = a.items[it];
         const int slot = item.x, blk = item.y;
-        const int col0 = (blk % a.col_blocks) * 64 * B;
-        const int row0 = (blk / a.col_blocks) * cart::kWaves * A;
+        const int col0 = (blk % a.col_blocks) * T::COLS;
+        const int row0 = (blk / a.col_blocks) * T::ROWS;
+        const int row = T::row(row0, lane, wave);
         const int4 sr = a.slots[slot];
         double *G = a.spec + (int64_t)slot * P * 16;
         for (int r = sr.z; r < sr.w; ++r) {
             const double *R = a.rot + 9 * (int64_t)r;
             for (int k = sr.x; k < sr.y; ++k) {
-                double acc[A][B][8];
-                cart::zero<A, B>(acc);
-                cart::accumulate<A, B>(RawLoader{a.pos, a.nuc, a.mag, R}, a.off[k], a.off[k + 1], d, col0, row0,
-                                       sm, acc);
+                double acc[cart::kB][8];
+                cart::zero(acc);
+                cart::accumulate<LR>(RawLoader{a.pos, a.nuc, a.mag, R}, a.off[k], a.off[k + 1], d, col0, row0, sm,
+                                     acc);
                 // lab position of the object (split mode)
                 double XY = 0.0, XZ = 0.0;
                 if (a.amp != nullptr && a.obj_pos != nullptr) {
@@ -99,15 +101,13 @@ __global__ __launch_bounds__(cart::kThreads, 2) void objects_kernel(ObjArgs a, D
                     XY = R[3] * o[0] + R[4] * o[1] + R[5] * o[2];
                     XZ = R[6] * o[0] + R[7] * o[1] + R[8] * o[2];
                 }
+                {
 #pragma unroll
-                for (int rr = 0; rr < A; ++rr) {
-                    const int row = row0 + wave * A + rr;
-#pragma unroll
-                    for (int c = 0; c < B; ++c) {
-                        const int col = col0 + lane * B + c;
+                    for (int c = 0; c < cart::kB; ++c) {
+                        const int col = T::col(col0, lane, c);
                         if (row >= d.n0 || col >= d.n1) continue;
                         const int64_t p = (int64_t)row * d.n1 + col;
-                        const double *F = acc[rr][c];
+                        const double *F = acc[c];
                         double *g = G + p * 16;
                         // G_ab += F_a conj(F_b): diagonal, then the upper triangle
                         g[0] += F[0] * F[0] + F[1] * F[1];
@@ -204,9 +204,10 @@ Tables make_tables(const Detector &d, const int64_t *h_off, int64_t K, int64_t W
 {
     Tables T;
     ObjectsPlan &p = T.p;
-    cart::choose_shape(d.n1, p.A, p.B);
-    p.col_blocks = (d.n1 + 64 * p.B - 1) / (64 * p.B);
-    p.row_blocks = (d.n0 + cart::kWaves * p.A - 1) / (cart::kWaves * p.A);
+    p.lanes = cart::choose_lanes(d.n1);
+    const int cols = p.lanes * cart::kB, rows = cart::kThreads / p.lanes;
+    p.col_blocks = (d.n1 + cols - 1) / cols;
+    p.row_blocks = (d.n0 + rows - 1) / rows;
     const int64_t nblocks = (int64_t)p.col_blocks * p.row_blocks;
     T.off.resize(K + 1);
     if (K == 1 || h_off == nullptr) {
@@ -372,11 +373,11 @@ int launch_objects(const numag_sample &s, const double *h_rot, int64_t n_rot, co
     args.spec = d_spec;
     args.amp = d_amp;
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(p.n_items, 2LL * device_cus()));
-    switch (p.B) {
-        case 1: hipLaunchKernelGGL((objects_kernel<8, 1>), dim3((unsigned)grid), dim3(cart::kThreads), 0, st, args, d); break;
-        case 2: hipLaunchKernelGGL((objects_kernel<4, 2>), dim3((unsigned)grid), dim3(cart::kThreads), 0, st, args, d); break;
-        case 4: hipLaunchKernelGGL((objects_kernel<2, 4>), dim3((unsigned)grid), dim3(cart::kThreads), 0, st, args, d); break;
-        default: hipLaunchKernelGGL((objects_kernel<1, 8>), dim3((unsigned)grid), dim3(cart::kThreads), 0, st, args, d); break;
+    switch (p.lanes) {
+        case 8: hipLaunchKernelGGL((objects_kernel<8>), dim3((unsigned)grid), dim3(cart::kThreads), 0, st, args, d); break;
+        case 16: hipLaunchKernelGGL((objects_kernel<16>), dim3((unsigned)grid), dim3(cart::kThreads), 0, st, args, d); break;
+        case 32: hipLaunchKernelGGL((objects_kernel<32>), dim3((unsigned)grid), dim3(cart::kThreads), 0, st, args, d); break;
+        default: hipLaunchKernelGGL((objects_kernel<64>), dim3((unsigned)grid), dim3(cart::kThreads), 0, st, args, d); break;
     }
     NUMAG_HIP_CHECK(hipGetLastError());
 

@@ -60,7 +60,7 @@ __device__ __forceinline__ void pixel_qhat(const Detector &d, int64_t p, double 
 }
 
 // ---------------------------------------------------------------------------
-// a7: cross sections
+// cross sections
 // ---------------------------------------------------------------------------
 __global__ void cross_section_kernel(Detector d, int64_t n_sets, const double *__restrict__ amp,
                                      const double *__restrict__ spec, numag_consts k, uint32_t mask,
@@ -172,7 +172,7 @@ int launch_cross_section(const Detector &d, int64_t n_sets, const double *amp, c
 }
 
 // ---------------------------------------------------------------------------
-// a8: azimuthal average
+// azimuthal average
 // ---------------------------------------------------------------------------
 // Bin of a Cartesian pixel: floor(|q| / dq) with |q| = sqrt(qy*qy + qz*qz)
 // (no fused operations), |q| == qmax_avg into the last bin, -1 if outside.
@@ -308,7 +308,7 @@ int launch_azimuthal(const Detector &d, const double *f, int n_f, int n_bins, do
 }
 
 // ---------------------------------------------------------------------------
-// a9: correlation functions (trapezoid in the order of the samples)
+// correlation functions (trapezoid in the order of the samples)
 // ---------------------------------------------------------------------------
 __global__ void correlation_kernel(const double *__restrict__ q, const double *__restrict__ Iq, int n_q,
                                    int n_f, const double *__restrict__ r, int n_r, double scale,
