@@ -13,9 +13,11 @@ before timing starts.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -26,7 +28,18 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP64_VALU = 256 * 2.4e9 * 64 * 2  # 78.6 TFLOP/s: 256 CUs x 64 FP64 FMA lanes x 2 flops x 2.4 GHz
-FLOPS_PER_TERM = 22  # one complex phasor product (6 flops) + 4 complex channel updates (16 flops)
+# algorithmic work of one (point, pixel) term: the phase q.X (2 FMA) and the
+# four channel sums, real and imaginary parts (8 FMA); the sine and cosine are
+# not counted
+FLOPS_PER_TERM = 20
+PROFILES = os.path.join(ROOT, "profiles")
+# kernel -> (library timer id, sources that define it, file holding its HBM counters)
+KERNELS = {
+    "direct_cartesian_kernel": (0, ["cartesian_sum.h", "direct.hip", "numag_internal.h"],
+                                "direct_cartesian_kernel_vortex64_256x256_pmc.md"),
+    "adjoint_cartesian_kernel": (1, ["adjoint.hip", "numag_internal.h"],
+                                 "adjoint_cartesian_kernel_vortex64_256x256_pmc.md"),
+}
 
 
 def parse():
@@ -37,6 +50,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=49152,
                     help="pixels of the oracle's bounded sample")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run one plain 1 GiB device-to-device copy (reference for HBM counters)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the separate orientation-batch measurement")
     return ap.parse_args()
@@ -89,6 +104,44 @@ def measure_batched(torch, numag, synth):
     }
 
 
+def sources_sha256(names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2601_18444_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_per_launch(kernel):
+    """HBM bytes per launch of `kernel` from its committed counter summary, or None
+    when there is none or the kernel's sources changed since it was taken."""
+    _, srcs, name = KERNELS[kernel]
+    path = os.path.join(PROFILES, name)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        m = re.match(r"^\s*-?\s*`?([a-z_0-9]+)`?\s*:\s*`?([0-9a-f.e+]+)`?\s*$", line.strip())
+        if m:
+            vals[m.group(1)] = m.group(2)
+    if vals.get("sources_sha256") != sources_sha256(srcs):
+        return None
+    try:
+        return int(float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"]))
+    except KeyError:
+        return None
+
+
+def calibrate_copy(torch):
+    n = 1 << 27  # 1 GiB of float64
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8}))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -96,6 +149,10 @@ def main():
                                    "(the multi-GPU layout is described in DESIGN.md)"}))
         sys.exit(2)
     import torch
+
+    if args.calibrate_copy:
+        calibrate_copy(torch)
+        return
 
     from paper_2601_18444_amd import numag, synth
 
@@ -161,12 +218,20 @@ def main():
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
+    # per-launch kernel durations: HIP events the library records on the
+    # stream the kernels run on
+    numag.kernel_timer(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step(True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = 1e3 * elapsed / args.steps
+    numag.kernel_timer(False)
+    kernel_ms = {}
+    for name, (kid, _, _) in KERNELS.items():
+        tot, n = numag.kernel_timer_read(kid)
+        kernel_ms[name] = tot / n if n else float("nan")
 
     def avg_ms(pairs):
         return float(np.mean([a.elapsed_time(b) for a, b in pairs])) if pairs else float("nan")
@@ -192,7 +257,10 @@ def main():
     sums_per_step = 2 + (1 if have_sep else 0)
     value = sums_per_step * terms / (ms_per_step * 1e-3) / 1e9
 
-    achieved = FLOPS_PER_TERM * terms / (t_direct * 1e-3) / 1e12
+    dominant = max(kernel_ms, key=lambda k: kernel_ms[k])
+    t_kernel = kernel_ms[dominant]
+    achieved = FLOPS_PER_TERM * terms / (t_kernel * 1e-3) / 1e12
+    traffic = traffic_per_launch(dominant)
     out = {
         "metric": "point*q-pixel terms/s (G/s), direct vs batched vs MFMA at rel err <= 1e-5",
         "value": round(value, 3),
@@ -215,20 +283,24 @@ def main():
         "paths": {
             "direct_Gterm_s": round(terms / (t_direct * 1e-3) / 1e9, 2),
             "direct_ms": round(t_direct, 4),
+            "direct_kernel_ms": round(kernel_ms["direct_cartesian_kernel"], 4),
             "adjoint_Gterm_s": round(terms / (t_adj * 1e-3) / 1e9, 2),
             "adjoint_ms": round(t_adj, 4),
+            "adjoint_kernel_ms": round(kernel_ms["adjoint_cartesian_kernel"], 4),
             "separable_f64_Gterm_s_effective": round(terms / (t_sep * 1e-3) / 1e9, 2) if have_sep else None,
             "separable_ms": round(t_sep, 4) if have_sep else None,
             "separable_bf16x3_Gterm_s_effective": round(terms / (t_bf16 * 1e-3) / 1e9, 2) if t_bf16 else None,
         },
         "roofline": {
-            "kernel": "direct_cartesian_kernel (timed with prep + combine)",
+            "kernel": dominant,
             "bound": "alu",
             "achieved": round(achieved, 3),
             "peak": round(PEAK_FP64_VALU / 1e12, 3),
             "unit": "TFLOP/s",
             "frac": round(achieved / (PEAK_FP64_VALU / 1e12), 4),
-            "traffic": None,
+            "traffic": traffic,
+            "launch_ms": round(t_kernel, 4),
+            "flops_per_launch": FLOPS_PER_TERM * terms,
         },
     }
 

@@ -243,6 +243,25 @@ int numag_correlation_2d(const numag_qgrid *grid, const double *f, int32_t n_f, 
 int numag_angular_spectrum(const numag_qgrid *grid, const double *f, int32_t n_f, int32_t k_max, double *Is_out,
                            double *Ic_out, double *As_out, double *Ac_out, void *stream);
 
+/*
+ * Kernel timer, for measurement harnesses.  While enabled, the library records
+ * a HIP event pair on the caller's stream around every launch of its sum
+ * kernels (the events are enqueued like the kernels: nothing blocks).  Leave
+ * it disabled while a stream is being captured into a graph.
+ *   numag_kernel_timer(1) enables and clears, numag_kernel_timer(0) disables
+ *   (the recorded launches stay readable).
+ *   numag_kernel_timer_read waits for the recorded launches of `kernel`
+ *   (NUMAG_KERNEL_*), writes their summed duration in milliseconds and their
+ *   count (either pointer may be NULL) and forgets them.
+ * Returns NUMAG_OK, NUMAG_E_INVALID for an unknown kernel id, or NUMAG_E_HIP.
+ */
+#define NUMAG_KERNEL_DIRECT   0  /* Cartesian or polar direct sum kernel   */
+#define NUMAG_KERNEL_ADJOINT  1  /* adjoint (gradient) sum kernel          */
+#define NUMAG_KERNEL_OBJECTS  2  /* object/orientation work-queue kernel   */
+#define NUMAG_KERNEL_COUNT    3
+int numag_kernel_timer(int32_t enable);
+int numag_kernel_timer_read(int32_t kernel, double *total_ms, int64_t *launches);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *numag_last_error(void);
 

@@ -7,11 +7,13 @@
 // with r = I_p - T_p and m' = R m (so dL/dm = R^T dL/dm').
 //
 // The adjoint sum swaps the roles of points and pixels: a lane owns a few
-// points and walks the detector, row by row; within a row the phasor of the
-// next column is one complex multiply by the point's column-step twiddle, and
-// the row-start phasor is a fresh FP64 sincos.  The residual weights of one
-// row are staged in LDS and read as wave-wide broadcasts.  Twelve FP64 VALU
-// operations per (point, pixel) term, as in the forward sum.
+// points and walks the detector, row by row.  The row-start phasor is a fresh
+// FP64 sincos; along the row the phasors follow the two-term recurrence
+//     p_{c+1} = 2 cos(dq_z Z) p_c - p_{c-1}
+// (two FMAs per column; an error made at column k reaches column c multiplied
+// by at most c - k + 1, so a 256-column row keeps about 38 of the 53 bits in
+// the worst case).  The residual weights of one row are staged in LDS and read
+// as wave-wide broadcasts.  Ten FP64 VALU operations per (point, pixel) term.
 #include "numag_internal.h"
 
 namespace numag {
@@ -139,8 +141,8 @@ __global__ __launch_bounds__(kAdjThreads, 2) void adjoint_cartesian_kernel(
     const int r0 = blockIdx.y * rows_per_split;
     const int r1 = min(d.n0, r0 + rows_per_split);
 
-    double Y[kAdjNPL], Z[kAdjNPL];
-    double2 ez0[kAdjNPL], dz[kAdjNPL];
+    double Y[kAdjNPL], Z[kAdjNPL], kz[kAdjNPL];
+    double2 ez0[kAdjNPL], dzc[kAdjNPL];
     double acc[kAdjNPL][4];
     const double qz0 = axis_a(d.origin1, 0, d.step1);
 #pragma unroll
@@ -150,16 +152,22 @@ __global__ __launch_bounds__(kAdjThreads, 2) void adjoint_cartesian_kernel(
         Y[u] = ok ? pts[j].Y : 0.0;
         Z[u] = ok ? pts[j].Z : 0.0;
         ez0[u] = twiddle_a(qz0 * Z[u]);
-        dz[u] = twiddle_a(d.step1 * Z[u]);
+        const double2 dz = twiddle_a(d.step1 * Z[u]);
+        dzc[u] = make_double2(dz.x, -dz.y);  // inverse column step
+        kz[u] = dz.x + dz.x;
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
     }
 
     for (int row = r0; row < r1; ++row) {
         const double qy = axis_a(d.origin0, row, d.step0);
-        double2 p[kAdjNPL];
+        // pc: phasor of the current column, pm: of the column before it
+        double2 pc[kAdjNPL], pm[kAdjNPL];
 #pragma unroll
-        for (int u = 0; u < kAdjNPL; ++u) p[u] = cmul_a(twiddle_a(qy * Y[u]), ez0[u]);
+        for (int u = 0; u < kAdjNPL; ++u) {
+            pc[u] = cmul_a(twiddle_a(qy * Y[u]), ez0[u]);
+            pm[u] = cmul_a(pc[u], dzc[u]);
+        }
         for (int c0 = 0; c0 < d.n1; c0 += kAdjMaxCols) {
             const int nc = min(kAdjMaxCols, d.n1 - c0);
             __syncthreads();
@@ -174,11 +182,13 @@ __global__ __launch_bounds__(kAdjThreads, 2) void adjoint_cartesian_kernel(
 #pragma unroll
                 for (int u = 0; u < kAdjNPL; ++u) {
                     // Re(a p) as two FMAs per channel
-                    acc[u][0] = fma(-a0i, p[u].y, fma(a0r, p[u].x, acc[u][0]));
-                    acc[u][1] = fma(-a1i, p[u].y, fma(a1r, p[u].x, acc[u][1]));
-                    acc[u][2] = fma(-a2i, p[u].y, fma(a2r, p[u].x, acc[u][2]));
-                    acc[u][3] = fma(-a3i, p[u].y, fma(a3r, p[u].x, acc[u][3]));
-                    p[u] = cmul_a(p[u], dz[u]);
+                    const double2 p = pc[u];
+                    acc[u][0] = fma(-a0i, p.y, fma(a0r, p.x, acc[u][0]));
+                    acc[u][1] = fma(-a1i, p.y, fma(a1r, p.x, acc[u][1]));
+                    acc[u][2] = fma(-a2i, p.y, fma(a2r, p.x, acc[u][2]));
+                    acc[u][3] = fma(-a3i, p.y, fma(a3r, p.x, acc[u][3]));
+                    pc[u] = make_double2(fma(kz[u], p.x, -pm[u].x), fma(kz[u], p.y, -pm[u].y));
+                    pm[u] = p;
                 }
             }
         }
@@ -262,8 +272,11 @@ int launch_grad(const PointRec *pts, int64_t W, const Detector &d, const numag_c
     const int rows_per = (d.n0 + splits - 1) / splits;
     const int nsplit = (d.n0 + rows_per - 1) / rows_per;
     const int64_t pblocks = (W + kAdjThreads * kAdjNPL - 1) / (kAdjThreads * kAdjNPL);
-    hipLaunchKernelGGL(adjoint_cartesian_kernel, dim3((unsigned)pblocks, nsplit), dim3(kAdjThreads), 0, s,
-                       pts, W, d, a, rows_per, gpart);
+    {
+        TimedLaunch timed(NUMAG_KERNEL_ADJOINT, s);
+        hipLaunchKernelGGL(adjoint_cartesian_kernel, dim3((unsigned)pblocks, nsplit), dim3(kAdjThreads), 0, s,
+                           pts, W, d, a, rows_per, gpart);
+    }
     NUMAG_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(grad_finalize_kernel, dim3((unsigned)((W + 255) / 256)), dim3(256), 0, s, gpart,
                        nsplit, W, R, dnuc, dmag);

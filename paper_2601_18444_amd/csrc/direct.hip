@@ -229,6 +229,7 @@ int launch_direct_cartesian(const PointRec *pts, int64_t W, const Detector &d, c
 {
     dim3 grid(p.col_blocks, p.row_blocks, p.nsplit);
     dim3 block(kThreads);
+    TimedLaunch timed(NUMAG_KERNEL_DIRECT, s);
 #define NUMAG_LAUNCH_CART(LR) \
     hipLaunchKernelGGL((direct_cartesian_kernel<LR>), grid, block, 0, s, pts, W, p.per, d, partial)
     switch (p.lanes) {
@@ -368,6 +369,7 @@ int launch_direct_polar(const PointRec *pts, int64_t W, const Detector &d, const
                         double *partial, hipStream_t s)
 {
     dim3 grid(p.col_blocks, p.row_blocks, p.nsplit);
+    TimedLaunch timed(NUMAG_KERNEL_DIRECT, s);
     hipLaunchKernelGGL(direct_polar_kernel, grid, dim3(kThreads), 0, s, pts, W, p.per, d, partial);
     NUMAG_HIP_CHECK(hipGetLastError());
     return NUMAG_OK;

@@ -27,6 +27,24 @@ void clear_error();
     } while (0)
 
 // ---------------------------------------------------------------------------
+// Kernel timer: TimedLaunch brackets one kernel launch with a HIP event pair
+// on its stream while numag_kernel_timer is enabled.
+// ---------------------------------------------------------------------------
+bool timer_enabled();
+int timer_begin(int kernel, hipStream_t s);   // returns a record id, or -1
+void timer_end(int id, hipStream_t s);
+
+struct TimedLaunch {
+    int id;
+    hipStream_t s;
+    TimedLaunch(int kernel, hipStream_t st) : id(timer_enabled() ? timer_begin(kernel, st) : -1), s(st) {}
+    ~TimedLaunch()
+    {
+        if (id >= 0) timer_end(id, s);
+    }
+};
+
+// ---------------------------------------------------------------------------
 // Detector descriptor passed by value to kernels.
 // q(i) = -qmax + i * step on both Cartesian axes (step = 2 qmax / (n - 1));
 // polar: q(i) = i * step with step = qmax / (n_q - 1), theta_m = m * dtheta.

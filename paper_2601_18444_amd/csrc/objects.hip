@@ -373,11 +373,14 @@ int launch_objects(const numag_sample &s, const double *h_rot, int64_t n_rot, co
     args.spec = d_spec;
     args.amp = d_amp;
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(p.n_items, 2LL * device_cus()));
-    switch (p.lanes) {
-        case 8: hipLaunchKernelGGL((objects_kernel<8>), dim3((unsigned)grid), dim3(cart::kThreads), 0, st, args, d); break;
-        case 16: hipLaunchKernelGGL((objects_kernel<16>), dim3((unsigned)grid), dim3(cart::kThreads), 0, st, args, d); break;
-        case 32: hipLaunchKernelGGL((objects_kernel<32>), dim3((unsigned)grid), dim3(cart::kThreads), 0, st, args, d); break;
-        default: hipLaunchKernelGGL((objects_kernel<64>), dim3((unsigned)grid), dim3(cart::kThreads), 0, st, args, d); break;
+    {
+        TimedLaunch timed(NUMAG_KERNEL_OBJECTS, st);
+        switch (p.lanes) {
+            case 8: hipLaunchKernelGGL((objects_kernel<8>), dim3((unsigned)grid), dim3(cart::kThreads), 0, st, args, d); break;
+            case 16: hipLaunchKernelGGL((objects_kernel<16>), dim3((unsigned)grid), dim3(cart::kThreads), 0, st, args, d); break;
+            case 32: hipLaunchKernelGGL((objects_kernel<32>), dim3((unsigned)grid), dim3(cart::kThreads), 0, st, args, d); break;
+            default: hipLaunchKernelGGL((objects_kernel<64>), dim3((unsigned)grid), dim3(cart::kThreads), 0, st, args, d); break;
+        }
     }
     NUMAG_HIP_CHECK(hipGetLastError());
 

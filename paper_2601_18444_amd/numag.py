@@ -72,6 +72,8 @@ def _load():
         "numag_correlation_2d_workspace_size": (sz, [P, P]),
         "numag_correlation_2d": (ctypes.c_int, [P, P, i32, P, P, P, sz, P]),
         "numag_angular_spectrum": (ctypes.c_int, [P, P, i32, i32, P, P, P, P, P]),
+        "numag_kernel_timer": (ctypes.c_int, [i32]),
+        "numag_kernel_timer_read": (ctypes.c_int, [i32, P, P]),
         "numag_last_error": (ctypes.c_char_p, []),
         "numag_version": (ctypes.c_char_p, []),
     }
@@ -96,6 +98,22 @@ def version() -> str:
 def _check(fn, rc):
     if rc != OK:
         raise NumagError(fn, rc, last_error())
+
+
+KERNEL_DIRECT, KERNEL_ADJOINT, KERNEL_OBJECTS = 0, 1, 2
+
+
+def kernel_timer(enable: bool) -> None:
+    """Enable (and clear) or disable the library's per-launch kernel timer."""
+    _check("numag_kernel_timer", _lib.numag_kernel_timer(1 if enable else 0))
+
+
+def kernel_timer_read(kernel: int):
+    """(summed milliseconds, launches) of the recorded launches of `kernel`; waits for them."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _check("numag_kernel_timer_read", _lib.numag_kernel_timer_read(kernel, ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
 
 
 def _stream():

@@ -115,3 +115,14 @@ def test_other_entry_points_validate():
     s = _cpu_sample()
     assert lib.numag_grad(ctypes.byref(s), None, ctypes.byref(grid), ctypes.byref(c), None, None, None, None,
                           None, None, None, 0, None) == numag.E_INVALID
+
+
+def test_kernel_timer_without_launches():
+    numag.kernel_timer(True)
+    assert numag.kernel_timer_read(numag.KERNEL_DIRECT) == (0.0, 0)
+    assert numag.kernel_timer_read(numag.KERNEL_OBJECTS) == (0.0, 0)
+    numag.kernel_timer(False)
+    assert numag._lib.numag_kernel_timer_read(3, None, None) == numag.E_INVALID
+    assert numag._lib.numag_kernel_timer_read(-1, None, None) == numag.E_INVALID
+    assert "unknown kernel" in numag.last_error()
+    assert numag._lib.numag_kernel_timer_read(numag.KERNEL_ADJOINT, None, None) == numag.OK

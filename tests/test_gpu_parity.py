@@ -287,3 +287,31 @@ def test_separable_paths_c2_full_size(orc):
     errs = [gated_rel_err(xbf[i], x64[i]) for i in range(3)]
     print(f"BF16x3 separable gated rel err N/M/unpol: {errs}")
     assert max(errs) < 5e-2
+
+
+@pytest.mark.parametrize("n0,n1", [(13, 50), (11, 100), (9, 200), (7, 300), (5, 700)])
+def test_detector_widths_every_lane_layout(orc, n0, n1):
+    """Detector widths that select each lanes-per-row layout (8, 16, 32, 64 and two
+    column blocks), with ragged rows and columns and a ragged point count."""
+    cl = synth.random_cloud(3001, 15.0, seed=27)
+    grid = numag.qgrid(0, n0, n1, 1.3)
+    amp, _ = numag.amplitudes(_sample(cl), grid)
+    qy, qz, _ = orc.pixels(0, n0, n1, 1.3)
+    _check_amp(amp_to_complex(amp[0]), _oracle_amp(orc, cl, qy, qz))
+
+
+def test_kernel_timer_counts_launches():
+    """The library's kernel timer records one event pair per sum-kernel launch."""
+    cl = synth.random_cloud(2000, 10.0, seed=28)
+    grid = numag.qgrid(0, 32, 32, 1.0)
+    s = _sample(cl)
+    numag.amplitudes(s, grid)
+    numag.kernel_timer(True)
+    for _ in range(3):
+        numag.amplitudes(s, grid)
+    numag.kernel_timer(False)
+    numag.amplitudes(s, grid)  # not recorded
+    ms, n = numag.kernel_timer_read(numag.KERNEL_DIRECT)
+    assert n == 3 and ms > 0.0
+    assert numag.kernel_timer_read(numag.KERNEL_DIRECT) == (0.0, 0)
+    assert numag.kernel_timer_read(numag.KERNEL_ADJOINT) == (0.0, 0)

@@ -51,3 +51,17 @@ def test_modal_amplitudes_normalisation(orc):
     As, Ac = orc.modal_amplitudes(Is, Ic)
     assert abs(Ac[0] - 0.5) < 1e-12 and abs(Ac[2] + 0.5) < 1e-12
     assert abs(np.sum(np.sqrt(As ** 2 + Ac ** 2)) - 1.0) < 1e-12
+
+
+def test_modal_amplitudes_sin2cos2(orc):
+    """sin^2 cos^2 = (1 - cos 4 theta)/8: I0 = 1/8, I4c = -1/8, every other mode 0, so
+    A0c/A4c = -1 (the ratio the paper quotes for this pattern)."""
+    nq, nt = 4, 32
+    th = 2 * np.pi * np.arange(nt) / nt
+    f = np.tile(np.sin(th) ** 2 * np.cos(th) ** 2, nq)
+    Is, Ic = orc.angular_spectrum(f, nq, nt, 8)
+    assert np.allclose(Ic[:, 0], 0.125, atol=1e-13) and np.allclose(Ic[:, 4], -0.125, atol=1e-13)
+    others = [k for k in range(9) if k not in (0, 4)]
+    assert np.max(np.abs(Ic[:, others])) < 1e-13 and np.max(np.abs(Is)) < 1e-13
+    As, Ac = orc.modal_amplitudes(Is, Ic)
+    assert abs(Ac[0] / Ac[4] + 1.0) < 1e-12
