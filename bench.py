@@ -104,6 +104,50 @@ def measure_batched(torch, numag, synth):
     }
 
 
+def measure_snapshots(torch, numag, synth, n_snap=64):
+    """Loop mode: n_snap field-sweep snapshots of the 64^3 vortex grid on the 256 x 256
+    detector in one batched FP64 separable call, next to n_snap single calls."""
+    dev = "cuda:0"
+    nuc, mags, reg, _ = synth.vortex_field_sweep(n_snap)
+    W = nuc.size
+    nucs = torch.as_tensor(np.ascontiguousarray(np.broadcast_to(nuc, (n_snap, W))), device=dev)
+    mt = torch.as_tensor(mags, device=dev)
+    grid = numag.qgrid(0, 256, 256, 2.0)
+    points = numag.regular_grid(reg["n"], reg["origin"], reg["step"])
+    out = torch.empty((n_snap, grid.n_pixels, 4, 2), dtype=torch.float64, device=dev)
+    numag.amplitudes_snapshots(points, grid, nuc=nucs, mag=mt, out=out, device=dev)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record()
+    for _ in range(reps):
+        numag.amplitudes_snapshots(points, grid, nuc=nucs, mag=mt, out=out, device=dev)
+    e1.record()
+    torch.cuda.synchronize()
+    t_batch = e0.elapsed_time(e1) * 1e-3 / reps
+    single = numag.Sample(nuc=nuc, mag=mags[0], regular=reg, n_points=W, device=dev)
+    smp = [single.with_weights(nuc=nucs[b], mag=mt[b]) for b in range(n_snap)]
+    amp1 = torch.empty((1, grid.n_pixels, 4, 2), dtype=torch.float64, device=dev)
+    numag.amplitudes(smp[0], grid, path=numag.PATH_SEPARABLE_F64, out=amp1)
+    torch.cuda.synchronize()
+    e0.record()
+    for b in range(n_snap):
+        numag.amplitudes(smp[b], grid, path=numag.PATH_SEPARABLE_F64, out=amp1)
+    e1.record()
+    torch.cuda.synchronize()
+    t_single = e0.elapsed_time(e1) * 1e-3
+    flops = n_snap * 4 * (64 * 64 * 256 * 4 + 256 * 64 * 256 * 8)  # both contractions, four channels
+    return {
+        "workload": f"{n_snap} field-sweep snapshots of the 64^3 vortex grid, 256x256 detector, FP64 MFMA separable "
+                    "path, one batched call",
+        "batched_ms": round(t_batch * 1e3, 4),
+        "per_snapshot_us": round(t_batch / n_snap * 1e6, 2),
+        "batched_Gterm_s_effective": round(n_snap * W * grid.n_pixels / t_batch / 1e9, 1),
+        "batched_mfma_TFLOP_s": round(flops / t_batch / 1e12, 3),
+        "single_calls_per_snapshot_us": round(t_single / n_snap * 1e6, 2),
+    }
+
+
 def sources_sha256(names):
     h = hashlib.sha256()
     for n in names:
@@ -306,6 +350,7 @@ def main():
 
     if not args.no_batched:
         out["paths"]["batched"] = measure_batched(torch, numag, synth)
+        out["paths"]["snapshots"] = measure_snapshots(torch, numag, synth)
 
     if not args.no_cpu_baseline:
         import oracle

@@ -161,6 +161,26 @@ int numag_amplitudes(const numag_sample *sample, int64_t n_rot, const double *ro
                      void *stream);
 
 /*
+ * Loop mode (Sec. 3.1 loop modes; Sec. 3.2: one real-space data set per field,
+ * temperature or time value): the raw sums of n_snap weight snapshots given on
+ * one regular grid, unrotated, one object, on a Cartesian detector, by a
+ * separable path (NUMAG_PATH_SEPARABLE_F64 or _BF16X3) in one batched call.
+ *   points    HOST regular grid of the W = n[0] n[1] n[2] points (as numag_sample.regular)
+ *   nuc       [n_snap][W] or NULL (channel off);  mag [n_snap][W][3] or NULL
+ *   amp_out   [n_snap][P][4] complex: snapshot b equals numag_amplitudes of
+ *             snapshot b alone on the same path.
+ *   workspace at least numag_snapshots_workspace_size() bytes (it grows with
+ *             n_snap: 4 n_snap (ny nz + 2 ny n1) doubles plus the twiddles).
+ * Returns NUMAG_E_INVALID for n_snap < 1, a non-separable path, a polar
+ * detector or a bad grid; numag_snapshots_workspace_size returns 0 then.
+ */
+size_t numag_snapshots_workspace_size(const numag_regular *points, int64_t n_snap, const numag_qgrid *grid,
+                                      int32_t path);
+int numag_amplitudes_snapshots(const numag_regular *points, int64_t n_snap, const double *nuc, const double *mag,
+                               const numag_qgrid *grid, int32_t path, double *amp_out, void *workspace,
+                               size_t ws_bytes, void *stream);
+
+/*
  * Cross sections of Sec. 2 (eqs. NuclearSANS, MagneticSANS, HJdef, PSANSdef,
  * sfdef, ChiralSANS, NMdef; the POLARIS, SANSPOL and unpolarized combinations
  * of Sec. 2.2-2.4) from n_sets amplitude sets or spectral matrices.
@@ -173,6 +193,18 @@ int numag_amplitudes(const numag_sample *sample, int64_t n_rot, const double *ro
 int numag_cross_section(const numag_qgrid *grid, int64_t n_sets, const double *amp,
                         const double *spec, const numag_consts *consts, uint32_t obs_mask,
                         double *out, void *stream);
+
+/*
+ * Export of the Fourier cross-correlation functions (Sec. 3.4: G^R_ab = Re,
+ * G^I_ab = Im of M_a conj(M_b)), extended by the nuclear channel: for every
+ * amplitude set and pixel, G_ab = A_a conj(A_b) over a, b in (N, Mx, My, Mz),
+ * packed as numag_amplitudes packs spectral matrices (16 reals: the four
+ * diagonal entries, then Re/Im of the upper entries 01 02 03 12 13 23).  Any
+ * detector kind.  No unit factors are applied.
+ *   amp       [n_sets][P][4] complex (device);  spec_out [n_sets][P][16] (device)
+ */
+int numag_spectral_matrix(const numag_qgrid *grid, int64_t n_sets, const double *amp, double *spec_out,
+                          void *stream);
 
 /*
  * Azimuthal average, eq. iqazi, for n_f 2D data sets f [n_f][P].

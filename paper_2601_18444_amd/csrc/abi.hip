@@ -186,7 +186,7 @@ size_t amplitudes_ws(const numag_sample *s, int64_t n_rot, const Detector &d, in
                      int32_t spec_per_object)
 {
     if (path == NUMAG_PATH_SEPARABLE_F64 || path == NUMAG_PATH_SEPARABLE_BF16X3)
-        return align_up(separable_workspace_bytes(*s->regular, d, path));
+        return align_up(separable_workspace_bytes(*s->regular, d, path, 1));
     if (mode == NUMAG_MODE_COHERENT) return direct_layout(s, d).total;
     return align_up(objects_workspace_bytes(d, s->obj_offsets, s->n_objects, s->n_points, n_rot, mode,
                                             spec_per_object));
@@ -331,13 +331,72 @@ int numag_amplitudes(const numag_sample *sample, int64_t n_rot, const double *ro
                               ws_bytes, st);
     forget_workspace(workspace);
     if (path != NUMAG_PATH_DIRECT)
-        return launch_separable(sample->nuc, sample->mag, *sample->regular, d, path, amp_out, workspace,
+        return launch_separable(sample->nuc, sample->mag, *sample->regular, d, path, 1, amp_out, workspace,
                                 ws_bytes, st);
     for (int64_t r = 0; r < n_rot; ++r) {
         rc = run_direct(sample, rot_of(rot, r), d, amp_out + r * P * 8, workspace, st);
         if (rc != NUMAG_OK) return rc;
     }
     return NUMAG_OK;
+}
+
+static int check_snapshots(const numag_regular *points, int64_t n_snap, const numag_qgrid *grid, int32_t path,
+                           const char *fn)
+{
+    int rc;
+    if (points == nullptr) return invalid(std::string(fn) + ": points is NULL");
+    if (n_snap < 1) return invalid(std::string(fn) + ": n_snap must be >= 1");
+    if ((rc = check_grid(grid, fn)) != NUMAG_OK) return rc;
+    if (path != NUMAG_PATH_SEPARABLE_F64 && path != NUMAG_PATH_SEPARABLE_BF16X3)
+        return invalid(std::string(fn) + ": snapshots run on the separable paths");
+    if (grid->kind != NUMAG_GRID_CARTESIAN) return invalid(std::string(fn) + ": separable path needs a Cartesian detector");
+    numag_sample smp{};
+    smp.n_points = (int64_t)points->n[0] * points->n[1] * points->n[2];
+    smp.n_objects = 1;
+    smp.regular = points;
+    if ((rc = check_sample(&smp, fn)) != NUMAG_OK) return rc;
+    // 4 n_snap channel sets index the contraction tiles as int
+    const int64_t tiles = 4 * n_snap * (((int64_t)grid->n0 + 15) / 16) * (((int64_t)grid->n1 + 15) / 16);
+    if (tiles > ((int64_t)1 << 31) - 4) return invalid(std::string(fn) + ": too many snapshots for one call");
+    return NUMAG_OK;
+}
+
+size_t numag_snapshots_workspace_size(const numag_regular *points, int64_t n_snap, const numag_qgrid *grid,
+                                      int32_t path)
+{
+    clear_error();
+    if (check_snapshots(points, n_snap, grid, path, "numag_snapshots_workspace_size") != NUMAG_OK) return 0;
+    return align_up(separable_workspace_bytes(*points, make_detector(*grid), path, n_snap));
+}
+
+int numag_amplitudes_snapshots(const numag_regular *points, int64_t n_snap, const double *nuc, const double *mag,
+                               const numag_qgrid *grid, int32_t path, double *amp_out, void *workspace,
+                               size_t ws_bytes, void *stream)
+{
+    clear_error();
+    int rc;
+    if ((rc = check_snapshots(points, n_snap, grid, path, "numag_amplitudes_snapshots")) != NUMAG_OK) return rc;
+    if (amp_out == nullptr) return invalid("numag_amplitudes_snapshots: amp_out is NULL");
+    const Detector d = make_detector(*grid);
+    const size_t need = align_up(separable_workspace_bytes(*points, d, path, n_snap));
+    if (ws_bytes < need || workspace == nullptr) {
+        set_error("numag_amplitudes_snapshots: workspace too small (need " + std::to_string(need) + " bytes)");
+        return NUMAG_E_WORKSPACE;
+    }
+    forget_workspace(workspace);
+    return launch_separable(nuc, mag, *points, d, path, n_snap, amp_out, workspace, ws_bytes, (hipStream_t)stream);
+}
+
+int numag_spectral_matrix(const numag_qgrid *grid, int64_t n_sets, const double *amp, double *spec_out,
+                          void *stream)
+{
+    clear_error();
+    int rc;
+    if ((rc = check_grid(grid, "numag_spectral_matrix")) != NUMAG_OK) return rc;
+    if (n_sets < 0) return invalid("numag_spectral_matrix: n_sets < 0");
+    if (n_sets > 0 && (amp == nullptr || spec_out == nullptr))
+        return invalid("numag_spectral_matrix: amp and spec_out are required");
+    return launch_spectral_matrix(n_sets, (int64_t)grid->n0 * grid->n1, amp, spec_out, (hipStream_t)stream);
 }
 
 int numag_cross_section(const numag_qgrid *grid, int64_t n_sets, const double *amp, const double *spec,

@@ -244,18 +244,39 @@ int launch_direct_cartesian(const PointRec *pts, int64_t W, const Detector &d, c
 }
 
 // ---------------------------------------------------------------------------
-// Polar direct sum: lanes own theta columns, each walks B q rows.
+// Polar direct sum.  The phase q_i u_m with u_m = Y sin(theta_m) + Z cos(theta_m)
+// does not separate, but along q it is a geometric sequence: lanes own theta
+// columns and each walks 8 q rows, the first by the row-group start, the second
+// by one step exp(-i dq u), the rest by the two-term recurrence
+// p_{r+1} = 2 cos(dq u) p_r - p_{r-1}.  A workgroup of WV waves covers 8 WV rows,
+// so the per-(point, column) generation (u, one sincos for the step, the block
+// start step^row0 by squaring, the wave starts by powers of step^8) is shared
+// by 8 WV rows.
 // ---------------------------------------------------------------------------
 constexpr int kPolarChunk = 8;
 constexpr int kPolarB = 8;
 
-__global__ __launch_bounds__(kThreads, 2) void direct_polar_kernel(const PointRec *__restrict__ pts,
-                                                                   int64_t W, int64_t per, Detector d,
-                                                                   double *__restrict__ out)
+// z^e for e >= 0 by binary powering (|z| = 1; relative error about e ulp).
+__device__ __forceinline__ double2 cpow_int(double2 z, int e)
+{
+    double2 r = make_double2(1.0, 0.0);
+    while (e > 0) {
+        if (e & 1) r = cart::cmul(r, z);
+        z = cart::cmul(z, z);
+        e >>= 1;
+    }
+    return r;
+}
+
+template <int WV>
+__global__ __launch_bounds__(64 * WV, 8 / WV) void direct_polar_kernel(const PointRec *__restrict__ pts, int64_t W,
+                                                                      int64_t per, Detector d,
+                                                                      double *__restrict__ out)
 {
     constexpr int B = kPolarB;
-    constexpr int ROWS = kWaves * B;
-    __shared__ double2 s_start[kPolarChunk][kWaves][64];
+    constexpr int ROWS = WV * B;
+    static_assert(kPolarChunk % WV == 0 || WV % kPolarChunk == 0, "chunk and waves");
+    __shared__ double2 s_start[kPolarChunk][WV][64];
     __shared__ double2 s_step[kPolarChunk][64];
     __shared__ double s_k[kPolarChunk][64];
     __shared__ double s_w[kPolarChunk][4];
@@ -274,33 +295,32 @@ __global__ __launch_bounds__(kThreads, 2) void direct_polar_kernel(const PointRe
 #pragma unroll
         for (int v = 0; v < 8; ++v) acc[r][v] = 0.0;
 
-    // generation role: thread t handles column (t & 63) for points (t >> 6) + 4 i
+    // generation role: thread t handles column (t & 63) for points wave, wave + WV, ...
     const int gcol = col0 + lane;
     const double theta = (2.0 * 3.141592653589793 * (double)gcol) / (double)d.n1;
     double sth, cth;
     sincos(theta, &sth, &cth);
-    const double q0 = axis_value(0.0, row0, d.step0);
 
     for (int64_t j0 = jbeg; j0 < jend; j0 += kPolarChunk) {
         const int nk = (int)min((int64_t)kPolarChunk, jend - j0);
         __syncthreads();
-        for (int jj = wave; jj < kPolarChunk; jj += kWaves) {
+        for (int jj = wave; jj < kPolarChunk; jj += WV) {
             const bool ok = jj < nk;
             const double Y = ok ? pts[j0 + jj].Y : 0.0;
             const double Z = ok ? pts[j0 + jj].Z : 0.0;
             const double u = Y * sth + Z * cth;
             const double2 step = twiddle(d.step0 * u);
-            double2 st = twiddle(q0 * u);
-            // step^B by squaring (B = 8)
-            double2 sb = cmul(step, step);
-            sb = cmul(sb, sb);
-            sb = cmul(sb, sb);
+            double2 sb = cart::cmul(step, step);  // step^8: from one wave's rows to the next
+            sb = cart::cmul(sb, sb);
+            sb = cart::cmul(sb, sb);
+            // start of the block: q(row0) = row0 dq, so exp(-i q(row0) u) = step^row0
+            double2 st = cpow_int(sb, row0 / B);
             s_step[jj][lane] = step;
             s_k[jj][lane] = step.x + step.x;
 #pragma unroll
-            for (int w = 0; w < kWaves; ++w) {
+            for (int w = 0; w < WV; ++w) {
                 s_start[jj][w][lane] = st;
-                st = cmul(st, sb);
+                st = cart::cmul(st, sb);
             }
         }
         if (t < kPolarChunk) {
@@ -315,10 +335,8 @@ __global__ __launch_bounds__(kThreads, 2) void direct_polar_kernel(const PointRe
             o.k = s_k[jj][lane];
 #pragma unroll
             for (int v = 0; v < 4; ++v) o.w[v] = s_w[jj][v];
-            // rows 0 and 1 by the start and one step, further rows by the
-            // two-term recurrence p_{r+1} = 2 cos(dq u) p_r - p_{r-1}
             double2 pm = s_start[jj][wave][lane];
-            double2 pc = cmul(pm, step);
+            double2 pc = cart::cmul(pm, step);
             cart::add_weighted(o, pm, acc[0]);
             cart::add_weighted(o, pc, acc[1]);
 #pragma unroll
@@ -343,14 +361,19 @@ __global__ __launch_bounds__(kThreads, 2) void direct_polar_kernel(const PointRe
     }
 }
 
+// Waves per workgroup of the polar kernel: 8 (64 rows) unless the detector has
+// at most 32 q rows.
+static int polar_waves(const Detector &d) { return d.n0 > 4 * kPolarB ? 8 : 4; }
+
 DirectPlan plan_direct_polar(const Detector &d, int64_t W)
 {
     DirectPlan p{};
     p.lanes = 64;
+    const int rows = polar_waves(d) * kPolarB;
     p.col_blocks = (d.n1 + 63) / 64;
-    p.row_blocks = (d.n0 + kWaves * kPolarB - 1) / (kWaves * kPolarB);
+    p.row_blocks = (d.n0 + rows - 1) / rows;
     int64_t blocks = (int64_t)p.col_blocks * p.row_blocks;
-    int64_t want = (target_workgroups() + blocks - 1) / blocks;
+    int64_t want = (target_workgroups() * 4 / polar_waves(d) + blocks - 1) / blocks;
     int64_t max_split = (W + 8 * kPolarChunk - 1) / (8 * kPolarChunk);
     if (max_split < 1) max_split = 1;
     if (want > max_split) want = max_split;
@@ -370,7 +393,10 @@ int launch_direct_polar(const PointRec *pts, int64_t W, const Detector &d, const
 {
     dim3 grid(p.col_blocks, p.row_blocks, p.nsplit);
     TimedLaunch timed(NUMAG_KERNEL_DIRECT, s);
-    hipLaunchKernelGGL(direct_polar_kernel, grid, dim3(kThreads), 0, s, pts, W, p.per, d, partial);
+    if (polar_waves(d) == 8)
+        hipLaunchKernelGGL(direct_polar_kernel<8>, grid, dim3(512), 0, s, pts, W, p.per, d, partial);
+    else
+        hipLaunchKernelGGL(direct_polar_kernel<4>, grid, dim3(256), 0, s, pts, W, p.per, d, partial);
     NUMAG_HIP_CHECK(hipGetLastError());
     return NUMAG_OK;
 }

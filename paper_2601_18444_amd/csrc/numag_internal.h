@@ -130,6 +130,7 @@ void forget_workspace(const void *ws);
 // cross sections from amplitudes ([n_sets][P][8]) or spectra ([n_sets][P][16]).
 int launch_cross_section(const Detector &d, int64_t n_sets, const double *amp, const double *spec,
                          const numag_consts &c, uint32_t mask, double *out, hipStream_t s);
+int launch_spectral_matrix(int64_t n_sets, int64_t P, const double *amp, double *spec, hipStream_t s);
 
 // a8
 int launch_azimuthal(const Detector &d, const double *f, int n_f, int n_bins, double qmax_avg,
@@ -154,9 +155,10 @@ int launch_correlation_2d(const Detector &d, const double *f, int n_f, const Det
 int launch_angular_spectrum(const Detector &d, const double *f, int n_f, int k_max, double *Is, double *Ic,
                             double *As, double *Ac, hipStream_t s);
 
-// regular-grid separable path on the matrix cores.
+// regular-grid separable path on the matrix cores, for n_snap weight snapshots
+// (nuc [n_snap][W], mag [n_snap][W][3]; amp [n_snap][P][8]).
 int launch_separable(const double *nuc, const double *mag, const numag_regular &g, const Detector &d,
-                     int path, double *amp, void *ws, size_t ws_bytes, hipStream_t s);
-size_t separable_workspace_bytes(const numag_regular &g, const Detector &d, int path);
+                     int path, int64_t n_snap, double *amp, void *ws, size_t ws_bytes, hipStream_t s);
+size_t separable_workspace_bytes(const numag_regular &g, const Detector &d, int path, int64_t n_snap);
 
 }  // namespace numag

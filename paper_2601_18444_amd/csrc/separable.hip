@@ -13,6 +13,11 @@
 //                                hi*lo, lo*hi accumulated in FP32.
 // Twiddles are generated in FP64 into the workspace; the projection is a
 // fixed-order FP64 sum.  One wave computes one 16 x 16 output tile.
+//
+// Loop mode (Sec. 3.1 loop modes, Sec. 3.2 data sets m_1 ... m_B): B weight
+// snapshots on the same grid share the twiddles and run as 4 B channel sets
+// through the same launches, so the contractions see B times the work per
+// launch.  A snapshot's result does not depend on the others in the batch.
 #include "numag_internal.h"
 
 namespace numag {
@@ -41,42 +46,47 @@ struct SepLayout {
 
 static size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
 
-static SepLayout sep_layout(const numag_regular &g, const Detector &d)
+static SepLayout sep_layout(const numag_regular &g, const Detector &d, int64_t n_snap)
 {
-    const size_t ny = g.n[1], nz = g.n[2], n0 = d.n0, n1 = d.n1;
+    const size_t ny = g.n[1], nz = g.n[2], n0 = d.n0, n1 = d.n1, sets = 4 * (size_t)n_snap;
     SepLayout L{};
     L.ey = al(n0 * ny * sizeof(double2));
     L.ez = al(nz * n1 * sizeof(double2));
-    L.s = al(4 * ny * nz * sizeof(double));
-    L.t = al(4 * ny * n1 * sizeof(double2));
+    L.s = al(sets * ny * nz * sizeof(double));
+    L.t = al(sets * ny * n1 * sizeof(double2));
     L.total = L.ey + L.ez + L.s + L.t;
     return L;
 }
 
-size_t separable_workspace_bytes(const numag_regular &g, const Detector &d, int path)
+size_t separable_workspace_bytes(const numag_regular &g, const Detector &d, int path, int64_t n_snap)
 {
     (void)path;
-    return sep_layout(g, d).total;
+    return sep_layout(g, d, n_snap).total;
 }
 
 constexpr int kProjCells = 64;   // (y, z) cells per projection workgroup
 constexpr int kProjSlices = 4;   // x slices per cell (one thread each)
 
 // One launch for the operands of both contractions.
-// Workgroups [0, n_proj): projection S[c][iy][iz] = sum_x w_c(x, iy, iz) for 64
-// cells, x split into 4 slices summed by 4 threads, slices added in a fixed
-// order through LDS.  Workgroups [n_proj, ...): twiddles
+// Workgroups [0, n_proj * n_snap): projection S[b][c][iy][iz] = sum_x w_c(x, iy, iz)
+// of snapshot b for 64 cells, x split into 4 slices summed by 4 threads, slices
+// added in a fixed order through LDS.  The remaining workgroups: twiddles
 // Ey[i][iy] = exp(-i q_y(i) y_iy) and Ez[iz][k] = exp(-i q_z(k) z_iz).
 __global__ __launch_bounds__(256) void sep_prepare_kernel(Detector d, numag_regular g, const double *__restrict__ nuc,
-                                                          const double *__restrict__ mag, int n_proj,
+                                                          const double *__restrict__ mag, int n_proj, int n_snap,
                                                           double *__restrict__ S, double2 *__restrict__ ey,
                                                           double2 *__restrict__ ez)
 {
     const int64_t nyz = (int64_t)g.n[1] * g.n[2];
-    if ((int)blockIdx.x < n_proj) {
+    const int64_t W = (int64_t)g.n[0] * nyz;
+    if ((int64_t)blockIdx.x < (int64_t)n_proj * n_snap) {
         __shared__ double part[kProjSlices][4][kProjCells];
+        const int b = (int)(blockIdx.x / n_proj);
+        if (nuc != nullptr) nuc += (int64_t)b * W;
+        if (mag != nullptr) mag += (int64_t)b * W * 3;
+        S += (int64_t)b * 4 * nyz;
         const int cell = threadIdx.x % kProjCells, slice = threadIdx.x / kProjCells;
-        const int64_t rem = (int64_t)blockIdx.x * kProjCells + cell;
+        const int64_t rem = (int64_t)(blockIdx.x % n_proj) * kProjCells + cell;
         double s[4] = {0.0, 0.0, 0.0, 0.0};
         if (rem < nyz) {
             for (int ix = slice; ix < g.n[0]; ix += kProjSlices) {
@@ -100,7 +110,7 @@ __global__ __launch_bounds__(256) void sep_prepare_kernel(Detector d, numag_regu
         }
         return;
     }
-    const int64_t idx = (int64_t)(blockIdx.x - n_proj) * blockDim.x + threadIdx.x;
+    const int64_t idx = ((int64_t)blockIdx.x - (int64_t)n_proj * n_snap) * blockDim.x + threadIdx.x;
     const int64_t ny = g.n[1], nz = g.n[2];
     const int64_t ne = (int64_t)d.n0 * ny;
     if (idx < ne) {
@@ -121,12 +131,12 @@ __global__ __launch_bounds__(256) void sep_prepare_kernel(Detector d, numag_regu
 
 // T[c][iy][k] = sum_iz S[c][iy][iz] Ez[iz][k]
 __global__ __launch_bounds__(256) void sep_contract1_f64(const double *__restrict__ S, const double2 *__restrict__ Ez,
-                                                         int ny, int nz, int n1, double2 *__restrict__ T)
+                                                         int ny, int nz, int n1, int n_sets, double2 *__restrict__ T)
 {
     const int lane = threadIdx.x & 63;
     const int tm = (ny + 15) / 16, tn = (n1 + 15) / 16;
     const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (tile >= (int64_t)4 * tm * tn) return;
+    if (tile >= (int64_t)n_sets * tm * tn) return;
     const int c = (int)(tile / (tm * tn));
     const int rem = (int)(tile % (tm * tn));
     const int m0 = (rem / tn) * 16, n0 = (rem % tn) * 16;
@@ -151,12 +161,12 @@ __global__ __launch_bounds__(256) void sep_contract1_f64(const double *__restric
 
 // F[c][i][k] = sum_iy Ey[i][iy] T[c][iy][k]  ->  amp[(i n1 + k)][c]
 __global__ __launch_bounds__(256) void sep_contract2_f64(const double2 *__restrict__ Ey, const double2 *__restrict__ T,
-                                                         int n0, int ny, int n1, double *__restrict__ amp)
+                                                         int n0, int ny, int n1, int n_sets, double *__restrict__ amp)
 {
     const int lane = threadIdx.x & 63;
     const int tm = (n0 + 15) / 16, tn = (n1 + 15) / 16;
     const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (tile >= (int64_t)4 * tm * tn) return;
+    if (tile >= (int64_t)n_sets * tm * tn) return;
     const int c = (int)(tile / (tm * tn));
     const int rem = (int)(tile % (tm * tn));
     const int m0 = (rem / tn) * 16, n0t = (rem % tn) * 16;
@@ -177,7 +187,7 @@ __global__ __launch_bounds__(256) void sep_contract2_f64(const double2 *__restri
     for (int r = 0; r < 4; ++r) {
         const int i = m0 + 4 * r + kq;
         if (i < n0 && bj < n1) {
-            double *o = amp + ((int64_t)i * n1 + bj) * 8 + 2 * c;
+            double *o = amp + (((int64_t)(c >> 2) * n0 + i) * n1 + bj) * 8 + 2 * (c & 3);
             o[0] = accR[r];
             o[1] = accI[r];
         }
@@ -219,12 +229,12 @@ __device__ __forceinline__ v4f mfma3(const Bf3 &a, const Bf3 &b, v4f acc)
 
 __global__ __launch_bounds__(256) void sep_contract1_bf16x3(const double *__restrict__ S,
                                                             const double2 *__restrict__ Ez, int ny, int nz,
-                                                            int n1, double2 *__restrict__ T)
+                                                            int n1, int n_sets, double2 *__restrict__ T)
 {
     const int lane = threadIdx.x & 63;
     const int tm = (ny + 15) / 16, tn = (n1 + 15) / 16;
     const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (tile >= (int64_t)4 * tm * tn) return;
+    if (tile >= (int64_t)n_sets * tm * tn) return;
     const int c = (int)(tile / (tm * tn));
     const int rem = (int)(tile % (tm * tn));
     const int m0 = (rem / tn) * 16, n0 = (rem % tn) * 16;
@@ -255,12 +265,12 @@ __global__ __launch_bounds__(256) void sep_contract1_bf16x3(const double *__rest
 
 __global__ __launch_bounds__(256) void sep_contract2_bf16x3(const double2 *__restrict__ Ey,
                                                             const double2 *__restrict__ T, int n0, int ny,
-                                                            int n1, double *__restrict__ amp)
+                                                            int n1, int n_sets, double *__restrict__ amp)
 {
     const int lane = threadIdx.x & 63;
     const int tm = (n0 + 15) / 16, tn = (n1 + 15) / 16;
     const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (tile >= (int64_t)4 * tm * tn) return;
+    if (tile >= (int64_t)n_sets * tm * tn) return;
     const int c = (int)(tile / (tm * tn));
     const int rem = (int)(tile % (tm * tn));
     const int m0 = (rem / tn) * 16, n0t = (rem % tn) * 16;
@@ -289,7 +299,7 @@ __global__ __launch_bounds__(256) void sep_contract2_bf16x3(const double2 *__res
     for (int r = 0; r < 4; ++r) {
         const int i = m0 + 4 * kq + r;
         if (i < n0 && bj < n1) {
-            double *o = amp + ((int64_t)i * n1 + bj) * 8 + 2 * c;
+            double *o = amp + (((int64_t)(c >> 2) * n0 + i) * n1 + bj) * 8 + 2 * (c & 3);
             o[0] = (double)accR[r];
             o[1] = (double)accI[r];
         }
@@ -297,9 +307,9 @@ __global__ __launch_bounds__(256) void sep_contract2_bf16x3(const double2 *__res
 }
 
 int launch_separable(const double *nuc, const double *mag, const numag_regular &g, const Detector &d, int path,
-                     double *amp, void *ws, size_t ws_bytes, hipStream_t s)
+                     int64_t n_snap, double *amp, void *ws, size_t ws_bytes, hipStream_t s)
 {
-    const SepLayout L = sep_layout(g, d);
+    const SepLayout L = sep_layout(g, d, n_snap);
     if (ws_bytes < L.total || ws == nullptr) {
         set_error("numag_amplitudes: workspace too small for the separable path");
         return NUMAG_E_WORKSPACE;
@@ -310,25 +320,27 @@ int launch_separable(const double *nuc, const double *mag, const numag_regular &
     double *S = (double *)(base + L.ey + L.ez);
     double2 *T = (double2 *)(base + L.ey + L.ez + L.s);
     const int ny = g.n[1], nz = g.n[2];
+    const int sets = (int)(4 * n_snap);
     const int64_t ntw = (int64_t)d.n0 * ny + (int64_t)nz * d.n1;
     const int64_t n_proj = ((int64_t)ny * nz + kProjCells - 1) / kProjCells;
     const int64_t n_tw = (ntw + 255) / 256;
-    hipLaunchKernelGGL(sep_prepare_kernel, dim3((unsigned)(n_proj + n_tw)), dim3(256), 0, s, d, g, nuc, mag,
-                       (int)n_proj, S, ey, ez);
+    hipLaunchKernelGGL(sep_prepare_kernel, dim3((unsigned)(n_proj * n_snap + n_tw)), dim3(256), 0, s, d, g, nuc, mag,
+                       (int)n_proj, (int)n_snap, S, ey, ez);
     NUMAG_HIP_CHECK(hipGetLastError());
-    const int64_t t1 = 4LL * ((ny + 15) / 16) * ((d.n1 + 15) / 16);
-    const int64_t t2 = 4LL * ((d.n0 + 15) / 16) * ((d.n1 + 15) / 16);
+    const int64_t t1 = (int64_t)sets * ((ny + 15) / 16) * ((d.n1 + 15) / 16);
+    const int64_t t2 = (int64_t)sets * ((d.n0 + 15) / 16) * ((d.n1 + 15) / 16);
     if (path == NUMAG_PATH_SEPARABLE_F64) {
-        hipLaunchKernelGGL(sep_contract1_f64, dim3((unsigned)((t1 + 3) / 4)), dim3(256), 0, s, S, ez, ny, nz, d.n1, T);
+        hipLaunchKernelGGL(sep_contract1_f64, dim3((unsigned)((t1 + 3) / 4)), dim3(256), 0, s, S, ez, ny, nz, d.n1,
+                           sets, T);
         NUMAG_HIP_CHECK(hipGetLastError());
         hipLaunchKernelGGL(sep_contract2_f64, dim3((unsigned)((t2 + 3) / 4)), dim3(256), 0, s, ey, T, d.n0, ny, d.n1,
-                           amp);
+                           sets, amp);
     } else {
         hipLaunchKernelGGL(sep_contract1_bf16x3, dim3((unsigned)((t1 + 3) / 4)), dim3(256), 0, s, S, ez, ny, nz,
-                           d.n1, T);
+                           d.n1, sets, T);
         NUMAG_HIP_CHECK(hipGetLastError());
         hipLaunchKernelGGL(sep_contract2_bf16x3, dim3((unsigned)((t2 + 3) / 4)), dim3(256), 0, s, ey, T, d.n0, ny,
-                           d.n1, amp);
+                           d.n1, sets, amp);
     }
     NUMAG_HIP_CHECK(hipGetLastError());
     return NUMAG_OK;

@@ -72,6 +72,9 @@ def _load():
         "numag_correlation_2d_workspace_size": (sz, [P, P]),
         "numag_correlation_2d": (ctypes.c_int, [P, P, i32, P, P, P, sz, P]),
         "numag_angular_spectrum": (ctypes.c_int, [P, P, i32, i32, P, P, P, P, P]),
+        "numag_spectral_matrix": (ctypes.c_int, [P, i64, P, P, P]),
+        "numag_snapshots_workspace_size": (sz, [P, i64, P, i32]),
+        "numag_amplitudes_snapshots": (ctypes.c_int, [P, i64, P, P, P, i32, P, P, sz, P]),
         "numag_kernel_timer": (ctypes.c_int, [i32]),
         "numag_kernel_timer_read": (ctypes.c_int, [i32, P, P]),
         "numag_last_error": (ctypes.c_char_p, []),
@@ -242,6 +245,36 @@ def amplitudes(sample: Sample, grid: QGrid, rot=None, path=PATH_DIRECT, mode=MOD
     return amp, spec
 
 
+def regular_grid(n, origin, step) -> Regular:
+    """A numag_regular descriptor (point j = (ix n1 + iy) n2 + iz at origin + i * step)."""
+    return Regular((ctypes.c_int32 * 3)(*[int(v) for v in n]), 0, (ctypes.c_double * 3)(*[float(v) for v in origin]),
+                   (ctypes.c_double * 3)(*[float(v) for v in step]))
+
+
+def amplitudes_snapshots(points: Regular, grid: QGrid, nuc=None, mag=None, path=PATH_SEPARABLE_F64, out=None,
+                         device="cuda"):
+    """numag_amplitudes_snapshots (loop mode): nuc [B, W] and/or mag [B, W, 3] on the
+    regular grid `points`; returns amp [B, P, 4, 2]."""
+    dev = torch.device(device)
+    W = int(points.n[0]) * int(points.n[1]) * int(points.n[2])
+    nt = _dev(nuc, dev, (-1, W)) if nuc is not None else None
+    mt = _dev(mag, dev, (-1, W, 3)) if mag is not None else None
+    if nt is None and mt is None:
+        raise ValueError("amplitudes_snapshots: nuc or mag is required")
+    B = (nt if nt is not None else mt).shape[0]
+    if nt is not None and mt is not None and nt.shape[0] != mt.shape[0]:
+        raise ValueError("amplitudes_snapshots: nuc and mag hold different snapshot counts")
+    amp = out if out is not None else torch.empty((B, grid.n_pixels, 4, 2), dtype=torch.float64, device=dev)
+    nbytes = _lib.numag_snapshots_workspace_size(ctypes.byref(points), B, ctypes.byref(grid), int(path))
+    if nbytes == 0:
+        raise NumagError("numag_snapshots_workspace_size", E_INVALID, last_error())
+    ws = workspace(nbytes, dev)
+    rc = _lib.numag_amplitudes_snapshots(ctypes.byref(points), B, _ptr(nt), _ptr(mt), ctypes.byref(grid), int(path),
+                                         _ptr(amp), _ptr(ws), ws.numel(), _stream())
+    _check("numag_amplitudes_snapshots", rc)
+    return amp
+
+
 class BatchedOrientations:
     """Orientational average of a dilute sample (Sec. 3.3 dilute limit) over many
     sample rotations: one persistent launch over (object, rotation group, pixel
@@ -299,6 +332,18 @@ def cross_section(grid: QGrid, amp=None, spec=None, c: Optional[Consts] = None, 
                                   _ptr(res), _stream())
     _check("numag_cross_section", rc)
     return res
+
+
+def spectral_matrix(grid: QGrid, amp: torch.Tensor, out=None):
+    """numag_spectral_matrix: G = A A^H per amplitude set, [n_sets, P, 16] packed."""
+    a = amp.reshape(-1, grid.n_pixels, 4, 2)
+    if not a.is_contiguous():
+        raise ValueError("spectral_matrix: amp must be contiguous")
+    G = out if out is not None else torch.empty((a.shape[0], grid.n_pixels, 16), dtype=torch.float64,
+                                                device=a.device)
+    _check("numag_spectral_matrix", _lib.numag_spectral_matrix(ctypes.byref(grid), a.shape[0], _ptr(a), _ptr(G),
+                                                                _stream()))
+    return G
 
 
 def ordered(obs: Iterable[str]):

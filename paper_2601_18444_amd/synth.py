@@ -173,6 +173,26 @@ def vortex_c5(n: int = 64, det: int = 256, qmax: float = 2.0, seed: int = 2, shi
     return base
 
 
+def vortex_field_sweep(n_snap: int, n: int = 64, seed: int = 2, h_max: float = 1.0):
+    """Loop-mode stand-in (a field sweep): the vortex field of ``vortex_field`` with a
+    uniform field-like component h_b e_z added and the moments renormalised, for
+    h_b evenly spaced in [-h_max, h_max] (b < n_snap).  Returns (nuc [W],
+    mag [n_snap, W, 3], regular-grid descriptor, h)."""
+    pos, nuc, m = vortex_field(n=n, seed=seed)
+    inside = nuc > 0
+    h = np.linspace(-h_max, h_max, n_snap) if n_snap > 1 else np.zeros(1)
+    mags = np.empty((n_snap,) + m.shape)
+    for b in range(n_snap):
+        mb = m + h[b] * np.array([0.0, 0.0, 1.0])
+        nrm = np.linalg.norm(mb, axis=1, keepdims=True)
+        mb = np.where(nrm > 0, mb / np.where(nrm > 0, nrm, 1.0), 0.0)
+        mb[~inside] = 0.0
+        mags[b] = mb
+    c0 = -(n - 1) / 2.0
+    regular = {"n": (n, n, n), "origin": (c0, c0, c0), "step": (1.0, 1.0, 1.0)}
+    return nuc, mags, regular, h
+
+
 def tilted_moment(e: np.ndarray, tilt_deg: float) -> np.ndarray:
     """Rotate the unit vector e toward +z by tilt_deg inside span(e, z), stopping at z."""
     z = np.array([0.0, 0.0, 1.0])

@@ -126,3 +126,38 @@ def test_kernel_timer_without_launches():
     assert numag._lib.numag_kernel_timer_read(-1, None, None) == numag.E_INVALID
     assert "unknown kernel" in numag.last_error()
     assert numag._lib.numag_kernel_timer_read(numag.KERNEL_ADJOINT, None, None) == numag.OK
+
+
+def test_snapshots_validate_without_gpu_work():
+    lib = numag._lib
+    pts = numag.regular_grid((4, 5, 6), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0))
+    grid = numag.qgrid(0, 8, 8, 1.0)
+    pol = numag.qgrid(1, 8, 8, 1.0)
+    F64 = numag.PATH_SEPARABLE_F64
+    assert lib.numag_snapshots_workspace_size(ctypes.byref(pts), 2, ctypes.byref(grid), F64) > 0
+    assert lib.numag_snapshots_workspace_size(ctypes.byref(pts), 0, ctypes.byref(grid), F64) == 0
+    assert lib.numag_snapshots_workspace_size(ctypes.byref(pts), 2, ctypes.byref(grid), numag.PATH_DIRECT) == 0
+    assert lib.numag_snapshots_workspace_size(ctypes.byref(pts), 2, ctypes.byref(pol), F64) == 0
+    assert lib.numag_snapshots_workspace_size(None, 2, ctypes.byref(grid), F64) == 0
+    one = lib.numag_snapshots_workspace_size(ctypes.byref(pts), 1, ctypes.byref(grid), F64)
+    two = lib.numag_snapshots_workspace_size(ctypes.byref(pts), 2, ctypes.byref(grid), F64)
+    assert two > one
+    bad = numag.regular_grid((0, 5, 6), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0))
+    assert lib.numag_snapshots_workspace_size(ctypes.byref(bad), 1, ctypes.byref(grid), F64) == 0
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    assert lib.numag_amplitudes_snapshots(ctypes.byref(pts), 0, fake, None, ctypes.byref(grid), F64, fake, fake,
+                                          1 << 20, None) == numag.E_INVALID
+    assert lib.numag_amplitudes_snapshots(ctypes.byref(pts), 2, fake, None, ctypes.byref(grid), F64, None, fake,
+                                          1 << 20, None) == numag.E_INVALID
+    assert lib.numag_amplitudes_snapshots(ctypes.byref(pts), 2, fake, None, ctypes.byref(grid), F64, fake, fake,
+                                          16, None) == numag.E_WORKSPACE
+    assert "workspace too small" in numag.last_error()
+
+
+def test_spectral_matrix_validates():
+    lib = numag._lib
+    grid = numag.qgrid(0, 8, 8, 1.0)
+    assert lib.numag_spectral_matrix(ctypes.byref(grid), -1, None, None, None) == numag.E_INVALID
+    assert lib.numag_spectral_matrix(ctypes.byref(grid), 2, None, ctypes.c_void_p(8), None) == numag.E_INVALID
+    assert lib.numag_spectral_matrix(None, 1, ctypes.c_void_p(8), ctypes.c_void_p(8), None) == numag.E_INVALID
+    assert lib.numag_spectral_matrix(ctypes.byref(grid), 0, None, None, None) == numag.OK

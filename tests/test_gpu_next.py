@@ -64,3 +64,22 @@ def test_angular_spectrum_vs_oracle(orc):
         Asr, Acr = orc.modal_amplitudes(Isr, Icr)
         assert max_norm_err(As[s].cpu().numpy(), Asr) <= 1e-12
         assert max_norm_err(Ac[s].cpu().numpy(), Acr) <= 1e-12
+
+
+@pytest.mark.parametrize("kind,n0,n1", [(0, 33, 41), (1, 25, 48)])
+def test_spectral_matrix_export(orc, kind, n0, n1):
+    """Sec. 3.4 export G_ab = A_a conj(A_b) on both detector kinds: against the
+    oracle's spectral matrix of the oracle's sums, and the identity with the
+    cross sections (computed from G or from the amplitudes, the same numbers)."""
+    cl = synth.random_cloud(1800, 9.0, seed=61)
+    grid = numag.qgrid(kind, n0, n1, 1.3)
+    s = numag.Sample(pos=cl["pos"], nuc=cl["nuc"], mag=cl["mag"], device=DEV)
+    R = synth.sample_rotation(20, 75)
+    amp, _ = numag.amplitudes(s, grid, rot=R)
+    G = numag.spectral_matrix(grid, amp)
+    qy, qz, _ = orc.pixels(kind, n0, n1, 1.3)
+    Gref = orc.spectral(orc.amplitudes(cl["pos"], cl["nuc"], cl["mag"], qy, qz, R=R))
+    assert max_norm_err(G[0].cpu().numpy(), Gref) <= 1e-9
+    xa = numag.cross_section(grid, amp=amp, obs=numag.OBSERVABLES)
+    xg = numag.cross_section(grid, spec=G, obs=numag.OBSERVABLES)
+    assert max_norm_err(xg.cpu().numpy(), xa.cpu().numpy()) <= 1e-12

@@ -136,6 +136,18 @@ def test_polar_detector(orc):
     assert max_norm_err(I.cpu().numpy(), Iref) <= 1e-12
 
 
+@pytest.mark.parametrize("nq,nt", [(150, 70), (20, 130)])
+def test_polar_detector_row_blocks(orc, nq, nt):
+    """Polar detectors with several q-row blocks (block starts by powers of the
+    step) and a ragged theta block, and a short one (the four-wave layout)."""
+    cl = synth.random_cloud(2001, 12.0, seed=29)
+    grid = numag.qgrid(1, nq, nt, 1.7)
+    R = synth.sample_rotation(35, -50)
+    amp, _ = numag.amplitudes(_sample(cl), grid, rot=R)
+    qy, qz, _ = orc.pixels(1, nq, nt, 1.7)
+    _check_amp(amp_to_complex(amp[0]), _oracle_amp(orc, cl, qy, qz, R=R))
+
+
 def test_edge_cases_empty_single_pixel_zero_q(orc):
     """W = 0 gives zeros; a 1x1 detector is the q = 0 pixel; odd n includes q = 0."""
     grid = numag.qgrid(0, 16, 16, 1.0)

@@ -1,0 +1,87 @@
+"""Loop-mode snapshots (Sec. 3.1 loop modes): a batch of weight snapshots on one
+regular grid through the separable matrix-core path.  Each snapshot must equal
+the single-snapshot call bit for bit (same kernels, same operand order) and the
+FP64 oracle within the 1e-5 gate."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2601_18444_amd import numag, synth  # noqa: E402
+from tests.helpers import amp_to_complex, gated_rel_err  # noqa: E402
+
+TOL = 1e-5
+DEV = "cuda:0"
+
+
+def _check(gpu, ref):
+    for c in range(4):
+        e = gated_rel_err(gpu[:, c], ref[:, c])
+        assert e <= TOL, f"channel {c}: gated rel err {e:.3e}"
+
+
+def test_snapshots_ragged_grid_vs_single_calls_and_oracle(orc):
+    n, a, origin = (5, 7, 9), (1.1, 0.9, 1.3), (-2.0, -3.0, -5.0)
+    pos = synth.box_lattice(n, a, origin)
+    W = pos.shape[0]
+    B = 3
+    rng = np.random.default_rng(40)
+    nuc = rng.standard_normal((B, W))
+    mag = rng.standard_normal((B, W, 3))
+    grid = numag.qgrid(0, 19, 37, 1.2)
+    points = numag.regular_grid(n, origin, a)
+    amp = numag.amplitudes_snapshots(points, grid, nuc=nuc, mag=mag, device=DEV)
+    assert amp.shape == (B, 19 * 37, 4, 2)
+    qy, qz, _ = orc.pixels(0, 19, 37, 1.2)
+    reg = {"n": n, "origin": origin, "step": a}
+    for b in range(B):
+        s = numag.Sample(nuc=nuc[b], mag=mag[b], regular=reg, n_points=W, device=DEV)
+        single, _ = numag.amplitudes(s, grid, path=numag.PATH_SEPARABLE_F64)
+        assert torch.equal(amp[b], single[0]), f"snapshot {b} differs from its single call"
+        _check(amp_to_complex(amp[b]), orc.amplitudes(pos, nuc[b], mag[b], qy, qz))
+
+
+def test_snapshots_channel_off_and_bf16_batch():
+    """mag only (nuclear channel off gives zeros) and the BF16x3 mode batch equal
+    their single calls."""
+    n, a, origin = (4, 6, 10), (1.0, 1.0, 1.0), (-1.5, -2.5, -4.5)
+    W = 4 * 6 * 10
+    rng = np.random.default_rng(41)
+    mag = rng.standard_normal((2, W, 3))
+    grid = numag.qgrid(0, 16, 24, 1.0)
+    points = numag.regular_grid(n, origin, a)
+    reg = {"n": n, "origin": origin, "step": a}
+    for path in (numag.PATH_SEPARABLE_F64, numag.PATH_SEPARABLE_BF16X3):
+        amp = numag.amplitudes_snapshots(points, grid, mag=mag, path=path, device=DEV)
+        assert torch.count_nonzero(amp[:, :, 0, :]).item() == 0
+        for b in range(2):
+            s = numag.Sample(mag=mag[b], regular=reg, n_points=W, device=DEV)
+            single, _ = numag.amplitudes(s, grid, path=path)
+            assert torch.equal(amp[b], single[0])
+
+
+def test_snapshots_vortex_sweep_full_size(orc):
+    """Eight snapshots of a field sweep on the 64^3 vortex grid, 256 x 256 detector:
+    every snapshot equals its single call; two are checked against the oracle on
+    sampled pixels."""
+    B = 8
+    nuc, mags, reg, _ = synth.vortex_field_sweep(B)
+    W = nuc.size
+    nucs = np.broadcast_to(nuc, (B, W))
+    grid = numag.qgrid(0, 256, 256, 2.0)
+    points = numag.regular_grid(reg["n"], reg["origin"], reg["step"])
+    amp = numag.amplitudes_snapshots(points, grid, nuc=nucs, mag=mags, device=DEV)
+    qy, qz, _ = orc.pixels(0, 256, 256, 2.0)
+    idx = np.sort(np.random.default_rng(42).choice(qy.size, 64, replace=False))
+    pos = synth.box_lattice(reg["n"], reg["step"], reg["origin"])
+    for b in range(B):
+        s = numag.Sample(nuc=nuc, mag=mags[b], regular=reg, n_points=W, device=DEV)
+        single, _ = numag.amplitudes(s, grid, path=numag.PATH_SEPARABLE_F64)
+        assert torch.equal(amp[b], single[0])
+    for b in (0, B - 1):
+        ref = orc.amplitudes(pos, nuc, mags[b], qy[idx], qz[idx])
+        _check(amp_to_complex(amp[b])[idx], ref)
