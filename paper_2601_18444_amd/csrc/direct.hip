@@ -268,6 +268,40 @@ __device__ __forceinline__ double2 cpow_int(double2 z, int e)
     return r;
 }
 
+// Operands of point jj for this lane: ez = the wave's start phasor, dz = the q step.
+template <int WV>
+__device__ __forceinline__ cart::Operands polar_operands(const double2 (&s_start)[kPolarChunk + 1][WV][64],
+                                                         const double2 (&s_step)[kPolarChunk + 1][64],
+                                                         const double (&s_k)[kPolarChunk + 1][64],
+                                                         const double (&s_w)[kPolarChunk + 1][4], int jj, int lane,
+                                                         int wave)
+{
+    cart::Operands o;
+    o.ez = s_start[jj][wave][lane];
+    o.dz = s_step[jj][lane];
+    o.k = s_k[jj][lane];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) o.w[v] = s_w[jj][v];
+    return o;
+}
+
+// Adds one point to the lane's B q rows: start, one step, then the recurrence.
+template <int B>
+__device__ __forceinline__ void polar_point(const cart::Operands &o, double (&acc)[B][8])
+{
+    double2 pm = o.ez;
+    double2 pc = cart::cmul(pm, o.dz);
+    cart::add_weighted(o, pm, acc[0]);
+    cart::add_weighted(o, pc, acc[1]);
+#pragma unroll
+    for (int r = 2; r < B; ++r) {
+        const double2 pn = make_double2(fma(o.k, pc.x, -pm.x), fma(o.k, pc.y, -pm.y));
+        cart::add_weighted(o, pn, acc[r]);
+        pm = pc;
+        pc = pn;
+    }
+}
+
 template <int WV>
 __global__ __launch_bounds__(64 * WV, 8 / WV) void direct_polar_kernel(const PointRec *__restrict__ pts, int64_t W,
                                                                       int64_t per, Detector d,
@@ -276,10 +310,11 @@ __global__ __launch_bounds__(64 * WV, 8 / WV) void direct_polar_kernel(const Poi
     constexpr int B = kPolarB;
     constexpr int ROWS = WV * B;
     static_assert(kPolarChunk % WV == 0 || WV % kPolarChunk == 0, "chunk and waves");
-    __shared__ double2 s_start[kPolarChunk][WV][64];
-    __shared__ double2 s_step[kPolarChunk][64];
-    __shared__ double s_k[kPolarChunk][64];
-    __shared__ double s_w[kPolarChunk][4];
+    // one row per point of a chunk plus one the pipelined loop may read past the end
+    __shared__ double2 s_start[kPolarChunk + 1][WV][64];
+    __shared__ double2 s_step[kPolarChunk + 1][64];
+    __shared__ double s_k[kPolarChunk + 1][64];
+    __shared__ double s_w[kPolarChunk + 1][4];
 
     const int t = threadIdx.x;
     const int lane = t & 63;
@@ -329,24 +364,21 @@ __global__ __launch_bounds__(64 * WV, 8 / WV) void direct_polar_kernel(const Poi
             for (int v = 0; v < 4; ++v) s_w[t][v] = ok ? pts[j0 + t].w[v] : 0.0;
         }
         __syncthreads();
-        for (int jj = 0; jj < nk; ++jj) {
-            cart::Operands o;
-            const double2 step = s_step[jj][lane];
-            o.k = s_k[jj][lane];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) o.w[v] = s_w[jj][v];
-            double2 pm = s_start[jj][wave][lane];
-            double2 pc = cart::cmul(pm, step);
-            cart::add_weighted(o, pm, acc[0]);
-            cart::add_weighted(o, pc, acc[1]);
-#pragma unroll
-            for (int r = 2; r < B; ++r) {
-                const double2 pn = make_double2(fma(o.k, pc.x, -pm.x), fma(o.k, pc.y, -pm.y));
-                cart::add_weighted(o, pn, acc[r]);
-                pm = pc;
-                pc = pn;
-            }
+        // operands of the next point are requested before the current point is
+        // accumulated (as in the Cartesian loop)
+        cart::Operands opa = polar_operands<WV>(s_start, s_step, s_k, s_w, 0, lane, wave);
+        int jj = 0;
+        for (; jj + 1 < nk; jj += 2) {
+            const cart::Operands opb = polar_operands<WV>(s_start, s_step, s_k, s_w, jj + 1, lane, wave);
+            __builtin_amdgcn_sched_barrier(0);
+            polar_point<B>(opa, acc);
+            __builtin_amdgcn_sched_barrier(0);
+            opa = polar_operands<WV>(s_start, s_step, s_k, s_w, jj + 2, lane, wave);  // row kPolarChunk at most
+            __builtin_amdgcn_sched_barrier(0);
+            polar_point<B>(opb, acc);
+            __builtin_amdgcn_sched_barrier(0);
         }
+        if (jj < nk) polar_point<B>(opa, acc);
     }
     const int64_t P = (int64_t)d.n0 * d.n1;
     double *dst = out + (int64_t)blockIdx.z * P * 8;
