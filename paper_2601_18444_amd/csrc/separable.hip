@@ -44,16 +44,25 @@ struct SepLayout {
     size_t ey, ez, s, t, total;
 };
 
+// Output tile of one wave in the second contraction (rows i, columns k).
+constexpr int kC2M = 32, kC2N = 64;
+
+// The operands of the second contraction are zero-padded so that its loads need
+// no bounds checks: E_y is [n0p][nyp], T is [sets][nyp][n1p] with n0p, nyp, n1p
+// the detector rows, grid y cells and detector columns rounded up to 32, 4, 64.
+__host__ __device__ static inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
 static size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
 
 static SepLayout sep_layout(const numag_regular &g, const Detector &d, int64_t n_snap)
 {
-    const size_t ny = g.n[1], nz = g.n[2], n0 = d.n0, n1 = d.n1, sets = 4 * (size_t)n_snap;
+    const size_t ny = g.n[1], nz = g.n[2], n1 = d.n1, sets = 4 * (size_t)n_snap;
+    const size_t n0p = round_up(d.n0, kC2M), nyp = round_up(g.n[1], 4), n1p = round_up(d.n1, kC2N);
     SepLayout L{};
-    L.ey = al(n0 * ny * sizeof(double2));
+    L.ey = al(n0p * nyp * sizeof(double2));
     L.ez = al(nz * n1 * sizeof(double2));
     L.s = al(sets * ny * nz * sizeof(double));
-    L.t = al(sets * ny * n1 * sizeof(double2));
+    L.t = al(sets * nyp * n1p * sizeof(double2));
     L.total = L.ey + L.ez + L.s + L.t;
     return L;
 }
@@ -112,11 +121,12 @@ __global__ __launch_bounds__(256) void sep_prepare_kernel(Detector d, numag_regu
     }
     const int64_t idx = ((int64_t)blockIdx.x - (int64_t)n_proj * n_snap) * blockDim.x + threadIdx.x;
     const int64_t ny = g.n[1], nz = g.n[2];
-    const int64_t ne = (int64_t)d.n0 * ny;
+    const int64_t nyp = round_up(g.n[1], 4);
+    const int64_t ne = (int64_t)round_up(d.n0, kC2M) * nyp;
     if (idx < ne) {
-        const int i = (int)(idx / ny), iy = (int)(idx % ny);
+        const int i = (int)(idx / nyp), iy = (int)(idx % nyp);
         const double y = g.origin[1] + (double)iy * g.step[1];
-        ey[idx] = tw_s(axis_s(d.origin0, i, d.step0) * y);
+        ey[idx] = (i < d.n0 && iy < ny) ? tw_s(axis_s(d.origin0, i, d.step0) * y) : make_double2(0.0, 0.0);
     } else if (idx < ne + nz * d.n1) {
         const int64_t r = idx - ne;
         const int iz = (int)(r / d.n1), k = (int)(r % d.n1);
@@ -131,10 +141,11 @@ __global__ __launch_bounds__(256) void sep_prepare_kernel(Detector d, numag_regu
 
 // T[c][iy][k] = sum_iz S[c][iy][iz] Ez[iz][k]
 __global__ __launch_bounds__(256) void sep_contract1_f64(const double *__restrict__ S, const double2 *__restrict__ Ez,
-                                                         int ny, int nz, int n1, int n_sets, double2 *__restrict__ T)
+                                                         int ny, int nz, int n1, int nyp, int n1p, int n_sets,
+                                                         double2 *__restrict__ T)
 {
     const int lane = threadIdx.x & 63;
-    const int tm = (ny + 15) / 16, tn = (n1 + 15) / 16;
+    const int tm = (nyp + 15) / 16, tn = (n1p + 15) / 16;
     const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (tile >= (int64_t)n_sets * tm * tn) return;
     const int c = (int)(tile / (tm * tn));
@@ -151,45 +162,91 @@ __global__ __launch_bounds__(256) void sep_contract1_f64(const double *__restric
         accR = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b.x, accR, 0, 0, 0);
         accI = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b.y, accI, 0, 0, 0);
     }
-    double2 *Tc = T + (int64_t)c * ny * n1;
+    double2 *Tc = T + (int64_t)c * nyp * n1p;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int i = m0 + 4 * r + kq;
-        if (i < ny && bj < n1) Tc[(int64_t)i * n1 + bj] = make_double2(accR[r], accI[r]);
+        if (i < nyp && bj < n1p) Tc[(int64_t)i * n1p + bj] = make_double2(accR[r], accI[r]);
     }
 }
 
-// F[c][i][k] = sum_iy Ey[i][iy] T[c][iy][k]  ->  amp[(i n1 + k)][c]
+// F[c][i][k] = sum_iy Ey[i][iy] T[c][iy][k]  ->  amp[c / 4][(i n1 + k)][c % 4]
+//
+// This contraction carries nine tenths of the flops, so it runs on
+// v_mfma_f64_4x4x4f64 (four 4 x 4 x 4 blocks per instruction), which issues its
+// flops faster on gfx950 than the 16 x 16 x 4 form.  Lane layout (one-hot probe):
+// block g = (l / 4) % 4, A[g][l % 4][l / 16], B[g][l / 16][l % 4], D[g][l / 16][l % 4].
+// A wave owns a (16 MG) x (4 NG) output tile: per K step of 4 it holds MG A
+// fragments (rows i0 + 16 mg + 4 g + m) and NG B fragments (columns k0 + 4 ng + n,
+// the same for every block) and issues MG x NG x 4 instructions (the complex
+// product as four real ones).  Every output element sees the same instruction
+// sequence whatever the tile shape, so the shape (chosen by the amount of work)
+// does not change the result.
+template <int MG, int NG>
 __global__ __launch_bounds__(256) void sep_contract2_f64(const double2 *__restrict__ Ey, const double2 *__restrict__ T,
-                                                         int n0, int ny, int n1, int n_sets, double *__restrict__ amp)
+                                                         int n0, int n1, int nyp, int n1p, int n_sets,
+                                                         double *__restrict__ amp)
 {
+    constexpr int TM = 16 * MG, TN = 4 * NG;
+    static_assert(kC2M % TM == 0 && kC2N % TN == 0, "tile inside the padding");
     const int lane = threadIdx.x & 63;
-    const int tm = (n0 + 15) / 16, tn = (n1 + 15) / 16;
+    const int tm = (n0 + TM - 1) / TM, tn = (n1 + TN - 1) / TN;
     const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (tile >= (int64_t)n_sets * tm * tn) return;
-    const int c = (int)(tile / (tm * tn));
-    const int rem = (int)(tile % (tm * tn));
-    const int m0 = (rem / tn) * 16, n0t = (rem % tn) * 16;
-    const int ai = m0 + (lane & 15), bj = n0t + (lane & 15), kq = lane >> 4;
-    const double2 *Tc = T + (int64_t)c * ny * n1;
-    v4d accR = {0.0, 0.0, 0.0, 0.0}, accI = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 8
-    for (int k = 0; k < ny; k += 4) {
-        const int kk = k + kq;
-        const double2 a = (ai < n0 && kk < ny) ? Ey[(int64_t)ai * ny + kk] : make_double2(0.0, 0.0);
-        const double2 b = (bj < n1 && kk < ny) ? Tc[(int64_t)kk * n1 + bj] : make_double2(0.0, 0.0);
-        accR = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, accR, 0, 0, 0);
-        accR = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, accR, 0, 0, 0);
-        accI = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, accI, 0, 0, 0);
-        accI = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, accI, 0, 0, 0);
-    }
+    const int c = (int)(tile / ((int64_t)tm * tn));
+    const int rem = (int)(tile % ((int64_t)tm * tn));
+    const int i0 = (rem / tn) * TM, k0 = (rem % tn) * TN;
+    const int g = (lane >> 2) & 3, e = lane & 3, kq = lane >> 4;
+    // this lane's operand streams (every index stays inside the padded arrays)
+    const double2 *pa = Ey + (int64_t)(i0 + 4 * g + e) * nyp + kq;               // + 16 mg nyp + y0
+    const double2 *pb = T + (int64_t)c * nyp * n1p + (int64_t)kq * n1p + k0 + e;  // + y0 n1p + 4 ng
+    double accR[MG][NG], accI[MG][NG];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int i = m0 + 4 * r + kq;
-        if (i < n0 && bj < n1) {
-            double *o = amp + (((int64_t)(c >> 2) * n0 + i) * n1 + bj) * 8 + 2 * (c & 3);
-            o[0] = accR[r];
-            o[1] = accI[r];
+    for (int mg = 0; mg < MG; ++mg)
+#pragma unroll
+        for (int ng = 0; ng < NG; ++ng) accR[mg][ng] = accI[mg][ng] = 0.0;
+
+    auto load = [&](int y0, double2 (&a)[MG], double2 (&b)[NG]) {
+#pragma unroll
+        for (int mg = 0; mg < MG; ++mg) a[mg] = pa[(int64_t)16 * mg * nyp + y0];
+#pragma unroll
+        for (int ng = 0; ng < NG; ++ng) b[ng] = pb[(int64_t)y0 * n1p + 4 * ng];
+    };
+    auto mma = [&](const double2 (&a)[MG], const double2 (&b)[NG]) {
+#pragma unroll
+        for (int ng = 0; ng < NG; ++ng)
+#pragma unroll
+            for (int mg = 0; mg < MG; ++mg) {
+                accR[mg][ng] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[mg].x, b[ng].x, accR[mg][ng], 0, 0, 0);
+                accR[mg][ng] = __builtin_amdgcn_mfma_f64_4x4x4f64(-a[mg].y, b[ng].y, accR[mg][ng], 0, 0, 0);
+                accI[mg][ng] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[mg].x, b[ng].y, accI[mg][ng], 0, 0, 0);
+                accI[mg][ng] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[mg].y, b[ng].x, accI[mg][ng], 0, 0, 0);
+            }
+    };
+    // two register buffers: the next K step's fragments load while this one's MFMAs run
+    double2 a0[MG], b0[NG], a1[MG], b1[NG];
+    load(0, a0, b0);
+    for (int y0 = 0; y0 < nyp; y0 += 8) {
+        const bool more = y0 + 4 < nyp;
+        if (more) load(y0 + 4, a1, b1);
+        mma(a0, b0);
+        if (!more) break;
+        if (y0 + 8 < nyp) load(y0 + 8, a0, b0);
+        mma(a1, b1);
+    }
+    double *dst = amp + (int64_t)(c >> 2) * n0 * n1 * 8 + 2 * (c & 3);
+#pragma unroll
+    for (int mg = 0; mg < MG; ++mg) {
+        const int row = i0 + 16 * mg + 4 * g + kq;
+        if (row >= n0) continue;
+#pragma unroll
+        for (int ng = 0; ng < NG; ++ng) {
+            const int col = k0 + 4 * ng + e;
+            if (col < n1) {
+                double *o = dst + ((int64_t)row * n1 + col) * 8;
+                o[0] = accR[mg][ng];
+                o[1] = accI[mg][ng];
+            }
         }
     }
 }
@@ -229,10 +286,11 @@ __device__ __forceinline__ v4f mfma3(const Bf3 &a, const Bf3 &b, v4f acc)
 
 __global__ __launch_bounds__(256) void sep_contract1_bf16x3(const double *__restrict__ S,
                                                             const double2 *__restrict__ Ez, int ny, int nz,
-                                                            int n1, int n_sets, double2 *__restrict__ T)
+                                                            int n1, int nyp, int n1p, int n_sets,
+                                                            double2 *__restrict__ T)
 {
     const int lane = threadIdx.x & 63;
-    const int tm = (ny + 15) / 16, tn = (n1 + 15) / 16;
+    const int tm = (nyp + 15) / 16, tn = (n1p + 15) / 16;
     const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (tile >= (int64_t)n_sets * tm * tn) return;
     const int c = (int)(tile / (tm * tn));
@@ -255,17 +313,18 @@ __global__ __launch_bounds__(256) void sep_contract1_bf16x3(const double *__rest
         accR = mfma3(a, br, accR);
         accI = mfma3(a, bi, accI);
     }
-    double2 *Tc = T + (int64_t)c * ny * n1;
+    double2 *Tc = T + (int64_t)c * nyp * n1p;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int i = m0 + 4 * kq + r;
-        if (i < ny && bj < n1) Tc[(int64_t)i * n1 + bj] = make_double2((double)accR[r], (double)accI[r]);
+        if (i < nyp && bj < n1p) Tc[(int64_t)i * n1p + bj] = make_double2((double)accR[r], (double)accI[r]);
     }
 }
 
 __global__ __launch_bounds__(256) void sep_contract2_bf16x3(const double2 *__restrict__ Ey,
                                                             const double2 *__restrict__ T, int n0, int ny,
-                                                            int n1, int n_sets, double *__restrict__ amp)
+                                                            int n1, int nyp, int n1p, int n_sets,
+                                                            double *__restrict__ amp)
 {
     const int lane = threadIdx.x & 63;
     const int tm = (n0 + 15) / 16, tn = (n1 + 15) / 16;
@@ -275,15 +334,15 @@ __global__ __launch_bounds__(256) void sep_contract2_bf16x3(const double2 *__res
     const int rem = (int)(tile % (tm * tn));
     const int m0 = (rem / tn) * 16, n0t = (rem % tn) * 16;
     const int ai = m0 + (lane & 15), bj = n0t + (lane & 15), kq = lane >> 4;
-    const double2 *Tc = T + (int64_t)c * ny * n1;
+    const double2 *Tc = T + (int64_t)c * nyp * n1p;
     v4f accR = {0.f, 0.f, 0.f, 0.f}, accI = {0.f, 0.f, 0.f, 0.f};
     for (int k = 0; k < ny; k += 16) {
         Bf3 ar, ai_neg, aim, br, bi;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int kk = k + 4 * kq + v;
-            const double2 av = (ai < n0 && kk < ny) ? Ey[(int64_t)ai * ny + kk] : make_double2(0.0, 0.0);
-            const double2 bv = (bj < n1 && kk < ny) ? Tc[(int64_t)kk * n1 + bj] : make_double2(0.0, 0.0);
+            const double2 av = (ai < n0 && kk < ny) ? Ey[(int64_t)ai * nyp + kk] : make_double2(0.0, 0.0);
+            const double2 bv = (bj < n1 && kk < ny) ? Tc[(int64_t)kk * n1p + bj] : make_double2(0.0, 0.0);
             split_bf16(av.x, ar, v);
             split_bf16(av.y, aim, v);
             split_bf16(-av.y, ai_neg, v);
@@ -320,27 +379,36 @@ int launch_separable(const double *nuc, const double *mag, const numag_regular &
     double *S = (double *)(base + L.ey + L.ez);
     double2 *T = (double2 *)(base + L.ey + L.ez + L.s);
     const int ny = g.n[1], nz = g.n[2];
+    const int nyp = round_up(ny, 4), n1p = round_up(d.n1, kC2N), n0p = round_up(d.n0, kC2M);
     const int sets = (int)(4 * n_snap);
-    const int64_t ntw = (int64_t)d.n0 * ny + (int64_t)nz * d.n1;
+    const int64_t ntw = (int64_t)n0p * nyp + (int64_t)nz * d.n1;
     const int64_t n_proj = ((int64_t)ny * nz + kProjCells - 1) / kProjCells;
     const int64_t n_tw = (ntw + 255) / 256;
     hipLaunchKernelGGL(sep_prepare_kernel, dim3((unsigned)(n_proj * n_snap + n_tw)), dim3(256), 0, s, d, g, nuc, mag,
                        (int)n_proj, (int)n_snap, S, ey, ez);
     NUMAG_HIP_CHECK(hipGetLastError());
-    const int64_t t1 = (int64_t)sets * ((ny + 15) / 16) * ((d.n1 + 15) / 16);
+    const int64_t t1 = (int64_t)sets * ((nyp + 15) / 16) * ((n1p + 15) / 16);
     const int64_t t2 = (int64_t)sets * ((d.n0 + 15) / 16) * ((d.n1 + 15) / 16);
+    // 32 x 32 tiles when they give every SIMD a few waves, else 16 x 16
+    const int64_t t2big = (int64_t)sets * ((d.n0 + 31) / 32) * ((d.n1 + 31) / 32);
+    const bool big = t2big >= 4096;
+    const int64_t t2f = big ? t2big : (int64_t)sets * ((d.n0 + 15) / 16) * ((d.n1 + 15) / 16);
     if (path == NUMAG_PATH_SEPARABLE_F64) {
         hipLaunchKernelGGL(sep_contract1_f64, dim3((unsigned)((t1 + 3) / 4)), dim3(256), 0, s, S, ez, ny, nz, d.n1,
-                           sets, T);
+                           nyp, n1p, sets, T);
         NUMAG_HIP_CHECK(hipGetLastError());
-        hipLaunchKernelGGL(sep_contract2_f64, dim3((unsigned)((t2 + 3) / 4)), dim3(256), 0, s, ey, T, d.n0, ny, d.n1,
-                           sets, amp);
+        if (big)
+            hipLaunchKernelGGL((sep_contract2_f64<2, 8>), dim3((unsigned)((t2f + 3) / 4)), dim3(256), 0, s, ey, T,
+                               d.n0, d.n1, nyp, n1p, sets, amp);
+        else
+            hipLaunchKernelGGL((sep_contract2_f64<1, 4>), dim3((unsigned)((t2f + 3) / 4)), dim3(256), 0, s, ey, T,
+                               d.n0, d.n1, nyp, n1p, sets, amp);
     } else {
         hipLaunchKernelGGL(sep_contract1_bf16x3, dim3((unsigned)((t1 + 3) / 4)), dim3(256), 0, s, S, ez, ny, nz,
-                           d.n1, sets, T);
+                           d.n1, nyp, n1p, sets, T);
         NUMAG_HIP_CHECK(hipGetLastError());
         hipLaunchKernelGGL(sep_contract2_bf16x3, dim3((unsigned)((t2 + 3) / 4)), dim3(256), 0, s, ey, T, d.n0, ny,
-                           d.n1, sets, amp);
+                           d.n1, nyp, n1p, sets, amp);
     }
     NUMAG_HIP_CHECK(hipGetLastError());
     return NUMAG_OK;
