@@ -15,27 +15,9 @@
 // the worst case).  The residual weights of one row are staged in LDS and read
 // as wave-wide broadcasts.  Ten FP64 VALU operations per (point, pixel) term.
 #include "numag_internal.h"
+#include "phasor.h"
 
 namespace numag {
-
-__device__ __forceinline__ double2 cmul_a(double2 a, double2 b)
-{
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-
-__device__ __forceinline__ double2 twiddle_a(double phi)
-{
-    double s, c;
-    sincos(phi, &s, &c);
-    return make_double2(c, -s);
-}
-
-__device__ __forceinline__ double axis_a(double origin, int i, double step)
-{
-#pragma clang fp contract(off)
-    double t = (double)i * step;
-    return origin + t;
-}
 
 constexpr int kResThreads = 256;
 
@@ -53,8 +35,8 @@ __global__ __launch_bounds__(kResThreads) void residual_kernel(Detector d, numag
     if (p < P) {
         const int row = (int)(p / d.n1), col = (int)(p % d.n1);
         double s, c;
-        const double qy = axis_a(d.origin0, row, d.step0);
-        const double qz = axis_a(d.origin1, col, d.step1);
+        const double qy = axis_value(d.origin0, row, d.step0);
+        const double qz = axis_value(d.origin1, col, d.step1);
         if (qy == 0.0 && qz == 0.0) {
             s = 0.0;
             c = 1.0;
@@ -144,15 +126,15 @@ __global__ __launch_bounds__(kAdjThreads, 2) void adjoint_cartesian_kernel(
     double Y[kAdjNPL], Z[kAdjNPL], kz[kAdjNPL];
     double2 ez0[kAdjNPL], dzc[kAdjNPL];
     double acc[kAdjNPL][4];
-    const double qz0 = axis_a(d.origin1, 0, d.step1);
+    const double qz0 = axis_value(d.origin1, 0, d.step1);
 #pragma unroll
     for (int u = 0; u < kAdjNPL; ++u) {
         const int64_t j = jb + (int64_t)u * kAdjThreads;
         const bool ok = j < W;
         Y[u] = ok ? pts[j].Y : 0.0;
         Z[u] = ok ? pts[j].Z : 0.0;
-        ez0[u] = twiddle_a(qz0 * Z[u]);
-        const double2 dz = twiddle_a(d.step1 * Z[u]);
+        ez0[u] = twiddle(qz0 * Z[u]);
+        const double2 dz = twiddle(d.step1 * Z[u]);
         dzc[u] = make_double2(dz.x, -dz.y);  // inverse column step
         kz[u] = dz.x + dz.x;
 #pragma unroll
@@ -160,13 +142,13 @@ __global__ __launch_bounds__(kAdjThreads, 2) void adjoint_cartesian_kernel(
     }
 
     for (int row = r0; row < r1; ++row) {
-        const double qy = axis_a(d.origin0, row, d.step0);
+        const double qy = axis_value(d.origin0, row, d.step0);
         // pc: phasor of the current column, pm: of the column before it
         double2 pc[kAdjNPL], pm[kAdjNPL];
 #pragma unroll
         for (int u = 0; u < kAdjNPL; ++u) {
-            pc[u] = cmul_a(twiddle_a(qy * Y[u]), ez0[u]);
-            pm[u] = cmul_a(pc[u], dzc[u]);
+            pc[u] = cmul(twiddle(qy * Y[u]), ez0[u]);
+            pm[u] = cmul(pc[u], dzc[u]);
         }
         for (int c0 = 0; c0 < d.n1; c0 += kAdjMaxCols) {
             const int nc = min(kAdjMaxCols, d.n1 - c0);

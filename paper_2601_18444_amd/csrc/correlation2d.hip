@@ -12,15 +12,10 @@
 // the detector.  It therefore runs on the same Cartesian / polar direct-sum
 // kernels, and the four weight channels carry four data sets at once.
 #include "numag_internal.h"
+#include "phasor.h"
 
 namespace numag {
 
-__device__ __forceinline__ double axis_c2(double origin, int i, double step)
-{
-#pragma clang fp contract(off)
-    double t = (double)i * step;
-    return origin + t;
-}
 
 // Pixels of detector d as points: Y = -q_y, Z = -q_z, weights wq * f_(set0 + c).
 __global__ void corr2d_points_kernel(Detector d, const double *__restrict__ f, int n_f, int set0,
@@ -32,14 +27,14 @@ __global__ void corr2d_points_kernel(Detector d, const double *__restrict__ f, i
     const int row = (int)(p / d.n1), col = (int)(p % d.n1);
     double qy, qz, wq;
     if (d.kind == NUMAG_GRID_CARTESIAN) {
-        qy = axis_c2(d.origin0, row, d.step0);
-        qz = axis_c2(d.origin1, col, d.step1);
+        qy = axis_value(d.origin0, row, d.step0);
+        qz = axis_value(d.origin1, col, d.step1);
         const double cy = (row == 0 || row == d.n0 - 1) ? 0.5 : 1.0;
         const double cz = (col == 0 || col == d.n1 - 1) ? 0.5 : 1.0;
         const double dy = d.n0 > 1 ? d.step0 : 1.0, dz = d.n1 > 1 ? d.step1 : 1.0;
         wq = cy * cz * dy * dz;
     } else {
-        const double q = axis_c2(0.0, row, d.step0);
+        const double q = axis_value(0.0, row, d.step0);
         const double th = (2.0 * 3.141592653589793 * (double)col) / (double)d.n1;
         double s, c;
         sincos(th, &s, &c);

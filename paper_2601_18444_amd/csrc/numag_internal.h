@@ -8,6 +8,7 @@
 #include <string>
 
 #include "../../include/numag.h"
+#include "types.h"
 
 namespace numag {
 
@@ -44,33 +45,7 @@ struct TimedLaunch {
     }
 };
 
-// ---------------------------------------------------------------------------
-// Detector descriptor passed by value to kernels.
-// q(i) = -qmax + i * step on both Cartesian axes (step = 2 qmax / (n - 1));
-// polar: q(i) = i * step with step = qmax / (n_q - 1), theta_m = m * dtheta.
-// ---------------------------------------------------------------------------
-struct Detector {
-    int kind;
-    int n0, n1;
-    double qmax;
-    double step0, step1;   // Cartesian: axis steps (rows, cols); polar: q step, theta step
-    double origin0, origin1;
-};
-
 Detector make_detector(const numag_qgrid &g);
-
-// Row-major 3x3 rotation as a kernel argument.
-struct Rot {
-    double m[9];
-};
-
-// Per-point record written by the preparation kernel: lab-frame Y, Z (q has
-// no x component) and lab-frame weights (n, m'x, m'y, m'z), padded to 64 bytes.
-struct alignas(64) PointRec {
-    double Y, Z;
-    double w[4];
-    double pad[2];
-};
 
 // ---------------------------------------------------------------------------
 // Launchers (each enqueues on `stream`, returns NUMAG_OK or NUMAG_E_HIP).
@@ -90,6 +65,8 @@ struct DirectPlan {
     int64_t per;     // points per split (multiple of the chunk)
     int col_blocks, row_blocks;
 };
+// Workgroups a direct-sum launch aims for (split-K included).
+int target_workgroups();
 DirectPlan plan_direct_cartesian(const Detector &d, int64_t W);
 size_t direct_partial_bytes(const DirectPlan &p, const Detector &d);
 int launch_direct_cartesian(const PointRec *pts, int64_t W, const Detector &d, const DirectPlan &p,

@@ -124,9 +124,9 @@ __global__ __launch_bounds__(cart::kThreads, 2) void objects_kernel(ObjArgs a, D
                             g[5 + 2 * t] += ai * br - ar * bi;
                         }
                         if (a.amp != nullptr) {
-                            const double qy = cart::axis_value(d.origin0, row, d.step0);
-                            const double qz = cart::axis_value(d.origin1, col, d.step1);
-                            const double2 ph = cart::twiddle(qy * XY + qz * XZ);
+                            const double qy = axis_value(d.origin0, row, d.step0);
+                            const double qz = axis_value(d.origin1, col, d.step1);
+                            const double2 ph = twiddle(qy * XY + qz * XZ);
                             double *o = a.amp + ((int64_t)slot * P + p) * 8;
 #pragma unroll
                             for (int v = 0; v < 4; ++v) {

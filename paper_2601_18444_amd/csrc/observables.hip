@@ -13,6 +13,7 @@
 //   chiral term  = 2 [Px Im H_yz + Py Im H_zx + Pz Im H_xy]
 // (the last from -i Phat.(Q x Q*) with Q_b conj(Q_c) = H_bc).
 #include "numag_internal.h"
+#include "phasor.h"
 
 namespace numag {
 
@@ -25,20 +26,14 @@ __device__ __forceinline__ C cconj(C a) { return C{a.re, -a.im}; }
 __device__ __forceinline__ C cadd(C a, C b) { return C{a.re + b.re, a.im + b.im}; }
 __device__ __forceinline__ C cscale(double s, C a) { return C{s * a.re, s * a.im}; }
 
-__device__ __forceinline__ double axis_value_nc(double origin, int i, double step)
-{
-#pragma clang fp contract(off)
-    double t = (double)i * step;
-    return origin + t;
-}
 
 // Unit vector of pixel p (Cartesian: q / |q|, q = 0 -> e_z; polar: column angle).
 __device__ __forceinline__ void pixel_qhat(const Detector &d, int64_t p, double &s, double &c)
 {
     const int row = (int)(p / d.n1), col = (int)(p % d.n1);
     if (d.kind == NUMAG_GRID_CARTESIAN) {
-        const double qy = axis_value_nc(d.origin0, row, d.step0);
-        const double qz = axis_value_nc(d.origin1, col, d.step1);
+        const double qy = axis_value(d.origin0, row, d.step0);
+        const double qz = axis_value(d.origin1, col, d.step1);
         if (qy == 0.0 && qz == 0.0) {
             s = 0.0;
             c = 1.0;
@@ -254,7 +249,7 @@ __global__ __launch_bounds__(kAzThreads) void azimuthal_cartesian_kernel(
     const int i_lo = idx_lo(-r_out, d.origin0, d.step0, d.n0);
     const int i_hi = idx_hi(r_out, d.origin0, d.step0, d.n0);
     for (int i = i_lo + (int)threadIdx.x; i <= i_hi; i += kAzThreads) {
-        const double qy = axis_value_nc(d.origin0, i, d.step0);
+        const double qy = axis_value(d.origin0, i, d.step0);
         const double y2 = qy * qy;
         const double c_out = sqrt(fmax(0.0, r_out * r_out - y2));
         const double c_in = (r_in * r_in > y2) ? sqrt(r_in * r_in - y2) : 0.0;
@@ -270,7 +265,7 @@ __global__ __launch_bounds__(kAzThreads) void azimuthal_cartesian_kernel(
                 if (k_hi >= r_lo) k_hi = r_lo - 1;
             }
             for (int k = k_lo; k <= k_hi; ++k) {
-                const double qz = axis_value_nc(d.origin1, k, d.step1);
+                const double qz = axis_value(d.origin1, k, d.step1);
                 if (cart_bin(qy, qz, dq, qmax_avg, n_bins) == b) {
                     sum += fs[(int64_t)i * d.n1 + k];
                     ++cnt;

@@ -19,26 +19,13 @@
 // through the same launches, so the contractions see B times the work per
 // launch.  A snapshot's result does not depend on the others in the batch.
 #include "numag_internal.h"
+#include "phasor.h"
 
 namespace numag {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef short v4s __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ double2 tw_s(double phi)
-{
-    double s, c;
-    sincos(phi, &s, &c);
-    return make_double2(c, -s);
-}
-
-__device__ __forceinline__ double axis_s(double origin, int i, double step)
-{
-#pragma clang fp contract(off)
-    double t = (double)i * step;
-    return origin + t;
-}
 
 struct SepLayout {
     size_t ey, ez, s, t, total;
@@ -126,12 +113,12 @@ __global__ __launch_bounds__(256) void sep_prepare_kernel(Detector d, numag_regu
     if (idx < ne) {
         const int i = (int)(idx / nyp), iy = (int)(idx % nyp);
         const double y = g.origin[1] + (double)iy * g.step[1];
-        ey[idx] = (i < d.n0 && iy < ny) ? tw_s(axis_s(d.origin0, i, d.step0) * y) : make_double2(0.0, 0.0);
+        ey[idx] = (i < d.n0 && iy < ny) ? twiddle(axis_value(d.origin0, i, d.step0) * y) : make_double2(0.0, 0.0);
     } else if (idx < ne + nz * d.n1) {
         const int64_t r = idx - ne;
         const int iz = (int)(r / d.n1), k = (int)(r % d.n1);
         const double z = g.origin[2] + (double)iz * g.step[2];
-        ez[r] = tw_s(axis_s(d.origin1, k, d.step1) * z);
+        ez[r] = twiddle(axis_value(d.origin1, k, d.step1) * z);
     }
 }
 

@@ -327,3 +327,18 @@ def test_kernel_timer_counts_launches():
     assert n == 3 and ms > 0.0
     assert numag.kernel_timer_read(numag.KERNEL_DIRECT) == (0.0, 0)
     assert numag.kernel_timer_read(numag.KERNEL_ADJOINT) == (0.0, 0)
+
+
+@pytest.mark.parametrize("kind,n0,n1", [(0, 1001, 1001), (1, 1000, 1000)])
+def test_paper_size_detectors_sampled(orc, kind, n0, n1):
+    """The paper's largest detector (1000 x 1000, its ensemble example's (q, theta)
+    grid) and a Cartesian 1001 x 1001 one (two column blocks of the widest lane
+    layout, ragged): 20001 points, checked on 256 sampled pixels."""
+    cl = synth.random_cloud(20001, 40.0, seed=33)
+    grid = numag.qgrid(kind, n0, n1, 1.5)
+    R = synth.sample_rotation(-15, 140)
+    amp, _ = numag.amplitudes(_sample(cl), grid, rot=R)
+    qy, qz, _ = orc.pixels(kind, n0, n1, 1.5)
+    idx = np.sort(np.random.default_rng(34).choice(qy.size, 256, replace=False))
+    ref = _oracle_amp(orc, cl, qy[idx], qz[idx], R=R)
+    _check_amp(amp_to_complex(amp[0])[idx], ref)
