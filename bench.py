@@ -329,6 +329,20 @@ def main():
         torch.cuda.synchronize()
         t_bf16 = avg_ms(pairs)
 
+    # the Hermitian half-detector form of the direct sum, timed outside the step
+    amp_h = torch.empty_like(amp)
+    numag.amplitudes(sample, grid, path=numag.PATH_DIRECT_HERMITIAN, out=amp_h)
+    pairs = []
+    for _ in range(10):
+        a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a0.record()
+        numag.amplitudes(sample, grid, path=numag.PATH_DIRECT_HERMITIAN, out=amp_h)
+        a1.record()
+        pairs.append((a0, a1))
+    torch.cuda.synchronize()
+    t_herm = avg_ms(pairs)
+    herm_err = float((amp_h - amp).abs().max() / amp.abs().max())
+
     t_direct = avg_ms(ev["direct"])
     t_adj = avg_ms(ev["adjoint"])
     t_sep = avg_ms(ev["separable"]) if have_sep else None
@@ -363,6 +377,9 @@ def main():
             "direct_Gterm_s": round(terms / (t_direct * 1e-3) / 1e9, 2),
             "direct_ms": round(t_direct, 4),
             "direct_kernel_ms": round(kernel_ms["direct_cartesian_kernel"], 4),
+            "direct_hermitian_ms": round(t_herm, 4),
+            "direct_hermitian_Gterm_s_effective": round(terms / (t_herm * 1e-3) / 1e9, 2),
+            "direct_hermitian_max_diff_vs_direct": herm_err,
             "adjoint_Gterm_s": round(terms / (t_adj * 1e-3) / 1e9, 2),
             "adjoint_ms": round(t_adj, 4),
             "adjoint_kernel_ms": round(kernel_ms["adjoint_cartesian_kernel"], 4),

@@ -63,6 +63,13 @@ extern "C" {
    rest is two dense complex contractions on the matrix cores. */
 #define NUMAG_PATH_SEPARABLE_F64  1  /* FP64 matrix-core contractions        */
 #define NUMAG_PATH_SEPARABLE_BF16X3 2 /* BF16 hi/lo split, 3 products, FP32 acc */
+/* Direct path on half of a detector that is symmetric about q = 0 (every
+   Cartesian detector; a polar one with an even n_theta), the other half filled
+   by S(-q) = conj S(q), which holds because the weights are real: half the
+   work, the same sums up to rounding (the mirrored pixel takes the conjugate
+   of its partner's sum instead of a sum over its own q, which differs from -q
+   by at most an ulp).  COHERENT mode only. */
+#define NUMAG_PATH_DIRECT_HERMITIAN 3
 
 /* ---- object modes (Sec. 3.3, summation relation and dilute limit) -------- */
 #define NUMAG_MODE_COHERENT 0  /* |sum_k exp(-i q.R r^k) F_k|^2                   */

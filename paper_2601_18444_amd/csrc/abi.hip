@@ -2,6 +2,7 @@
 // Host code only; every numerical step runs in the HIP kernels of this library.
 #include <cmath>
 #include <cstring>
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -138,20 +139,26 @@ DirectLayout direct_layout(const numag_sample *s, const Detector &d)
     const bool need_off = s->n_objects > 1 && s->obj_pos != nullptr;
     L.offsets = need_off ? align_up((size_t)(s->n_objects + 1) * sizeof(int64_t)) : 0;
     L.points = align_up((size_t)std::max<int64_t>(s->n_points, 1) * sizeof(PointRec));
+    // partial sums of the full detector or of its Hermitian half, whichever is larger
+    Detector dh = d;
     if (d.kind == NUMAG_GRID_CARTESIAN) {
-        DirectPlan p = plan_direct_cartesian(d, s->n_points);
-        L.partial = p.nsplit > 1 ? align_up(direct_partial_bytes(p, d)) : 0;
+        dh.n0 = (d.n0 + 1) / 2;
+        const DirectPlan p = plan_direct_cartesian(d, s->n_points), ph = plan_direct_cartesian(dh, s->n_points);
+        L.partial = std::max(p.nsplit > 1 ? align_up(direct_partial_bytes(p, d)) : 0,
+                             ph.nsplit > 1 ? align_up(direct_partial_bytes(ph, dh)) : 0);
     } else {
-        DirectPlan p = plan_direct_polar(d, s->n_points);
-        L.partial = align_up(direct_partial_bytes(p, d));
+        dh.n1 = std::max(1, d.n1 / 2);
+        const DirectPlan p = plan_direct_polar(d, s->n_points), ph = plan_direct_polar(dh, s->n_points);
+        L.partial = std::max(align_up(direct_partial_bytes(p, d)), align_up(direct_partial_bytes(ph, dh)));
     }
     L.total = L.offsets + L.points + L.partial;
     return L;
 }
 
-// Runs prep + direct sum + combine for one rotation into amp (P x 8 doubles).
+// Direct sums of one rotation: prep + sum + combine into amp (P x 8 doubles).  hermitian: evaluate half of the (centro-
+// symmetric) detector and complete it by S(-q) = conj S(q) (real weights).
 int run_direct(const numag_sample *s, const Rot &R, const Detector &d, double *amp, void *ws,
-               hipStream_t st)
+               hipStream_t st, bool hermitian = false)
 {
     DirectLayout L = direct_layout(s, d);
     Carve cv(ws);
@@ -170,11 +177,26 @@ int run_direct(const numag_sample *s, const Rot &R, const Detector &d, double *a
                                    pts, st);
     if (rc != NUMAG_OK) return rc;
     if (d.kind == NUMAG_GRID_CARTESIAN) {
-        DirectPlan p = plan_direct_cartesian(d, s->n_points);
-        if (p.nsplit == 1) return launch_direct_cartesian(pts, s->n_points, d, p, amp, st);
-        rc = launch_direct_cartesian(pts, s->n_points, d, p, part, st);
+        Detector dh = d;
+        if (hermitian) dh.n0 = (d.n0 + 1) / 2;  // rows [0, h): the first h n1 pixels of the output
+        const int64_t Ph = (int64_t)dh.n0 * d.n1;
+        DirectPlan p = plan_direct_cartesian(dh, s->n_points);
+        if (p.nsplit == 1) {
+            rc = launch_direct_cartesian(pts, s->n_points, dh, p, amp, st);
+        } else {
+            rc = launch_direct_cartesian(pts, s->n_points, dh, p, part, st);
+            if (rc == NUMAG_OK) rc = launch_combine(part, p.nsplit, Ph, amp, 0, st);
+        }
+        if (rc != NUMAG_OK || !hermitian) return rc;
+        return launch_mirror_cartesian(amp, P, Ph, st);
+    }
+    if (hermitian) {
+        Detector dh = d;
+        dh.n1 = d.n1 / 2;  // columns [0, n_theta / 2); their mirrors are m + n_theta / 2
+        DirectPlan p = plan_direct_polar(dh, s->n_points);
+        rc = launch_direct_polar(pts, s->n_points, dh, p, part, st);
         if (rc != NUMAG_OK) return rc;
-        return launch_combine(part, p.nsplit, P, amp, 0, st);
+        return launch_combine_polar_half(part, p.nsplit, d.n0, dh.n1, amp, st);
     }
     DirectPlan p = plan_direct_polar(d, s->n_points);
     rc = launch_direct_polar(pts, s->n_points, d, p, part, st);
@@ -255,11 +277,11 @@ size_t numag_workspace_size(const numag_sample *sample, int64_t n_rot, const num
         set_error("numag_workspace_size: unknown mode");
         return 0;
     }
-    if (path < NUMAG_PATH_DIRECT || path > NUMAG_PATH_SEPARABLE_BF16X3) {
+    if (path < NUMAG_PATH_DIRECT || path > NUMAG_PATH_DIRECT_HERMITIAN) {
         set_error("numag_workspace_size: unknown path");
         return 0;
     }
-    if (path != NUMAG_PATH_DIRECT && sample->regular == nullptr) {
+    if ((path == NUMAG_PATH_SEPARABLE_F64 || path == NUMAG_PATH_SEPARABLE_BF16X3) && sample->regular == nullptr) {
         set_error("numag_workspace_size: separable path needs a regular grid");
         return 0;
     }
@@ -290,13 +312,18 @@ int numag_amplitudes(const numag_sample *sample, int64_t n_rot, const double *ro
     if ((rc = check_grid(grid, "numag_amplitudes")) != NUMAG_OK) return rc;
     if ((rc = check_rotations(rot, n_rot, "numag_amplitudes")) != NUMAG_OK) return rc;
     if (mode < NUMAG_MODE_COHERENT || mode > NUMAG_MODE_SPLIT) return invalid("numag_amplitudes: unknown mode");
-    if (path < NUMAG_PATH_DIRECT || path > NUMAG_PATH_SEPARABLE_BF16X3)
+    if (path < NUMAG_PATH_DIRECT || path > NUMAG_PATH_DIRECT_HERMITIAN)
         return invalid("numag_amplitudes: unknown path");
+    if (path == NUMAG_PATH_DIRECT_HERMITIAN) {
+        if (mode != NUMAG_MODE_COHERENT) return invalid("numag_amplitudes: the Hermitian path is COHERENT only");
+        if (grid->kind == NUMAG_GRID_POLAR && grid->n1 % 2 != 0)
+            return invalid("numag_amplitudes: the Hermitian path needs an even n_theta on a polar detector");
+    }
     if ((mode == NUMAG_MODE_COHERENT || mode == NUMAG_MODE_SPLIT) && amp_out == nullptr)
         return invalid("numag_amplitudes: amp_out required in COHERENT/SPLIT mode");
     if ((mode == NUMAG_MODE_DILUTE || mode == NUMAG_MODE_SPLIT) && spec_out == nullptr)
         return invalid("numag_amplitudes: spec_out required in DILUTE/SPLIT mode");
-    if (path != NUMAG_PATH_DIRECT) {
+    if (path == NUMAG_PATH_SEPARABLE_F64 || path == NUMAG_PATH_SEPARABLE_BF16X3) {
         if (sample->regular == nullptr) return invalid("numag_amplitudes: separable path needs sample->regular");
         if (!rot_is_identity(rot) || n_rot != 1)
             return invalid("numag_amplitudes: separable path needs the identity rotation");
@@ -330,11 +357,12 @@ int numag_amplitudes(const numag_sample *sample, int64_t n_rot, const double *ro
         return launch_objects(*sample, rot, n_rot, d, mode, spec_per_object ? 1 : 0, spec_out, amp_out, workspace,
                               ws_bytes, st);
     forget_workspace(workspace);
-    if (path != NUMAG_PATH_DIRECT)
+    if (path == NUMAG_PATH_SEPARABLE_F64 || path == NUMAG_PATH_SEPARABLE_BF16X3)
         return launch_separable(sample->nuc, sample->mag, *sample->regular, d, path, 1, amp_out, workspace,
                                 ws_bytes, st);
     for (int64_t r = 0; r < n_rot; ++r) {
-        rc = run_direct(sample, rot_of(rot, r), d, amp_out + r * P * 8, workspace, st);
+        rc = run_direct(sample, rot_of(rot, r), d, amp_out + r * P * 8, workspace, st,
+                        path == NUMAG_PATH_DIRECT_HERMITIAN);
         if (rc != NUMAG_OK) return rc;
     }
     return NUMAG_OK;

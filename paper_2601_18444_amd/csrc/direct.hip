@@ -24,6 +24,7 @@ Detector make_detector(const numag_qgrid &g)
     d.kind = g.kind;
     d.n0 = g.n0;
     d.n1 = g.n1;
+    d.n_theta = g.n1;
     d.qmax = g.qmax;
     if (g.kind == NUMAG_GRID_CARTESIAN) {
         d.step0 = g.n0 > 1 ? (2.0 * g.qmax) / (double)(g.n0 - 1) : 0.0;
@@ -249,6 +250,57 @@ int launch_combine(const double *part, int nsplit, int64_t P, double *out, int a
     int64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(combine_kernel, dim3((unsigned)blocks), dim3(256), 0, s, part, nsplit, n, out,
                        accumulate);
+    NUMAG_HIP_CHECK(hipGetLastError());
+    return NUMAG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Hermitian completion: for real weights S(-q) = conj S(q).  Cartesian: rows
+// [0, h) of the row-major output are computed, pixel p mirrors to P - 1 - p.
+// Polar (even n_theta): columns [0, n_theta / 2) are computed into a
+// [n0][n_theta / 2] block, column m mirrors to m + n_theta / 2.
+// ---------------------------------------------------------------------------
+__global__ void mirror_cartesian_kernel(double *__restrict__ amp, int64_t P, int64_t Ph)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Ph * 8) return;
+    const int64_t p = i >> 3;
+    const int v = (int)(i & 7);
+    const int64_t q = P - 1 - p;
+    if (q >= Ph) amp[q * 8 + v] = (v & 1) ? -amp[i] : amp[i];
+}
+
+int launch_mirror_cartesian(double *amp, int64_t P, int64_t Ph, hipStream_t s)
+{
+    if (Ph <= 0) return NUMAG_OK;
+    hipLaunchKernelGGL(mirror_cartesian_kernel, dim3((unsigned)((Ph * 8 + 255) / 256)), dim3(256), 0, s, amp, P, Ph);
+    NUMAG_HIP_CHECK(hipGetLastError());
+    return NUMAG_OK;
+}
+
+// out[i][m] = sum of the splits of part[.][i][m], out[i][m + nh] = its conjugate
+__global__ void combine_polar_half_kernel(const double *__restrict__ part, int nsplit, int n0, int nh,
+                                          double *__restrict__ out)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t Ph = (int64_t)n0 * nh;
+    if (idx >= Ph * 8) return;
+    const int64_t p = idx >> 3;
+    const int v = (int)(idx & 7);
+    double s = 0.0;
+    for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * Ph * 8 + idx];
+    const int64_t i = p / nh, m = p % nh;
+    const int64_t full = i * 2 * nh + m;
+    out[full * 8 + v] = s;
+    out[(full + nh) * 8 + v] = (v & 1) ? -s : s;
+}
+
+int launch_combine_polar_half(const double *part, int nsplit, int n0, int nh, double *out, hipStream_t s)
+{
+    const int64_t n = (int64_t)n0 * nh * 8;
+    if (n <= 0) return NUMAG_OK;
+    hipLaunchKernelGGL(combine_polar_half_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, nsplit,
+                       n0, nh, out);
     NUMAG_HIP_CHECK(hipGetLastError());
     return NUMAG_OK;
 }

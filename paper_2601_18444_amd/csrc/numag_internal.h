@@ -65,6 +65,10 @@ struct DirectPlan {
     int64_t per;     // points per split (multiple of the chunk)
     int col_blocks, row_blocks;
 };
+// Hermitian completion of a half-detector sum (see direct.hip).
+int launch_mirror_cartesian(double *amp, int64_t P, int64_t Ph, hipStream_t s);
+int launch_combine_polar_half(const double *part, int nsplit, int n0, int nh, double *out, hipStream_t s);
+
 // Workgroups a direct-sum launch aims for (split-K included).
 int target_workgroups();
 DirectPlan plan_direct_cartesian(const Detector &d, int64_t W);

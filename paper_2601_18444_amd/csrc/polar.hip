@@ -94,7 +94,7 @@ __global__ __launch_bounds__(64 * WV, 8 / WV) void direct_polar_kernel(const Poi
 
     // generation role: thread t handles column (t & 63) for points wave, wave + WV, ...
     const int gcol = col0 + lane;
-    const double theta = (2.0 * 3.141592653589793 * (double)gcol) / (double)d.n1;
+    const double theta = (2.0 * 3.141592653589793 * (double)gcol) / (double)d.n_theta;
     double sth, cth;
     sincos(theta, &sth, &cth);
 

@@ -13,7 +13,8 @@ namespace numag {
 // ---------------------------------------------------------------------------
 struct Detector {
     int kind;
-    int n0, n1;
+    int n0, n1;            // rows and columns evaluated
+    int n_theta;           // polar: columns of the full detector (theta_m = 2 pi m / n_theta)
     double qmax;
     double step0, step1;   // Cartesian: axis steps (rows, cols); polar: q step, theta step
     double origin0, origin1;

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libnumag.so")
 
 OBSERVABLES = ("N", "M", "NM", "P", "CHI", "SF", "PP", "MM", "PM", "MP", "PLUS", "MINUS", "UNPOL")
 GRID_CARTESIAN, GRID_POLAR = 0, 1
-PATH_DIRECT, PATH_SEPARABLE_F64, PATH_SEPARABLE_BF16X3 = 0, 1, 2
+PATH_DIRECT, PATH_SEPARABLE_F64, PATH_SEPARABLE_BF16X3, PATH_DIRECT_HERMITIAN = 0, 1, 2, 3
 MODE_COHERENT, MODE_DILUTE, MODE_SPLIT = 0, 1, 2
 OK, E_INVALID, E_WORKSPACE, E_HIP, E_UNSUPPORTED = 0, -1, -2, -4, -5
 

@@ -161,3 +161,16 @@ def test_spectral_matrix_validates():
     assert lib.numag_spectral_matrix(ctypes.byref(grid), 2, None, ctypes.c_void_p(8), None) == numag.E_INVALID
     assert lib.numag_spectral_matrix(None, 1, ctypes.c_void_p(8), ctypes.c_void_p(8), None) == numag.E_INVALID
     assert lib.numag_spectral_matrix(ctypes.byref(grid), 0, None, None, None) == numag.OK
+
+
+def test_hermitian_path_validates():
+    s = _cpu_sample()
+    pol_odd = numag.qgrid(1, 8, 9, 1.0)
+    H = numag.PATH_DIRECT_HERMITIAN
+    assert _call_amp(s, pol_odd, path=H, ws=0x3000, nws=1 << 30) == numag.E_INVALID
+    assert "even n_theta" in numag.last_error()
+    grid = numag.qgrid(0, 8, 8, 1.0)
+    assert _call_amp(s, grid, path=H, mode=numag.MODE_DILUTE, amp=None, spec=0x4000, ws=0x3000,
+                     nws=1 << 30) == numag.E_INVALID
+    assert _call_amp(s, grid, path=4, ws=0x3000, nws=1 << 30) == numag.E_INVALID
+    assert numag._lib.numag_workspace_size(ctypes.byref(s), 1, ctypes.byref(grid), H, 0) > 0
