@@ -67,14 +67,32 @@ __global__ void corr2d_scatter_kernel(const double *__restrict__ amp, int64_t R,
 
 static size_t al2(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// The real-space grid to evaluate: C(-r) = conj C(r) for real data, so only half
+// of a grid symmetric about r = 0 is summed (Cartesian: rows [0, ceil(n0/2));
+// polar with an even n_alpha: columns [0, n_alpha/2)) and the rest is mirrored.
+static Detector half_grid(const Detector &rd)
+{
+    Detector rh = rd;
+    if (rd.kind == NUMAG_GRID_CARTESIAN)
+        rh.n0 = (rd.n0 + 1) / 2;
+    else if (rd.n1 % 2 == 0)
+        rh.n1 = rd.n1 / 2;
+    return rh;
+}
+
+static DirectPlan corr2d_plan(const Detector &rh, int64_t P)
+{
+    return rh.kind == NUMAG_GRID_CARTESIAN ? plan_direct_cartesian(rh, P) : plan_direct_polar(rh, P);
+}
+
 size_t correlation_2d_workspace_bytes(const Detector &d, const Detector &rd)
 {
     const int64_t P = (int64_t)d.n0 * d.n1;
     const int64_t R = (int64_t)rd.n0 * rd.n1;
-    const DirectPlan p = rd.kind == NUMAG_GRID_CARTESIAN ? plan_direct_cartesian(rd, P) : plan_direct_polar(rd, P);
-    return al2((size_t)P * sizeof(PointRec)) + al2(direct_partial_bytes(p, rd)) + al2((size_t)R * 8 * sizeof(double));
+    const Detector rh = half_grid(rd);
+    return al2((size_t)P * sizeof(PointRec)) + al2(direct_partial_bytes(corr2d_plan(rh, P), rh)) +
+           al2((size_t)R * 8 * sizeof(double));
 }
-
 int launch_correlation_2d(const Detector &d, const double *f, int n_f, const Detector &rd, double *C, void *ws,
                           size_t ws_bytes, hipStream_t s)
 {
@@ -84,25 +102,29 @@ int launch_correlation_2d(const Detector &d, const double *f, int n_f, const Det
         set_error("numag_correlation_2d: workspace too small");
         return NUMAG_E_WORKSPACE;
     }
-    const DirectPlan plan = rd.kind == NUMAG_GRID_CARTESIAN ? plan_direct_cartesian(rd, P) : plan_direct_polar(rd, P);
+    const Detector rh = half_grid(rd);
+    const int64_t Rh = (int64_t)rh.n0 * rh.n1;
+    const DirectPlan plan = corr2d_plan(rh, P);
     char *base = (char *)ws;
     PointRec *pts = (PointRec *)base;
     double *part = (double *)(base + al2((size_t)P * sizeof(PointRec)));
-    double *amp = (double *)(base + al2((size_t)P * sizeof(PointRec)) + al2(direct_partial_bytes(plan, rd)));
+    double *amp = (double *)(base + al2((size_t)P * sizeof(PointRec)) + al2(direct_partial_bytes(plan, rh)));
     for (int set0 = 0; set0 < n_f; set0 += 4) {
         hipLaunchKernelGGL(corr2d_points_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, d, f, n_f, set0,
                            pts);
         NUMAG_HIP_CHECK(hipGetLastError());
         int rc;
-        if (rd.kind == NUMAG_GRID_CARTESIAN)
-            rc = launch_direct_cartesian(pts, P, rd, plan, plan.nsplit > 1 ? part : amp, s);
-        else
-            rc = launch_direct_polar(pts, P, rd, plan, part, s);
-        if (rc != NUMAG_OK) return rc;
-        if (rd.kind != NUMAG_GRID_CARTESIAN || plan.nsplit > 1) {
-            rc = launch_combine(part, plan.nsplit, R, amp, 0, s);
-            if (rc != NUMAG_OK) return rc;
+        if (rd.kind == NUMAG_GRID_CARTESIAN) {
+            rc = launch_direct_cartesian(pts, P, rh, plan, plan.nsplit > 1 ? part : amp, s);
+            if (rc == NUMAG_OK && plan.nsplit > 1) rc = launch_combine(part, plan.nsplit, Rh, amp, 0, s);
+            if (rc == NUMAG_OK) rc = launch_mirror_cartesian(amp, R, Rh, s);
+        } else {
+            rc = launch_direct_polar(pts, P, rh, plan, part, s);
+            if (rc == NUMAG_OK)
+                rc = rh.n1 != rd.n1 ? launch_combine_polar_half(part, plan.nsplit, rd.n0, rh.n1, amp, s)
+                                    : launch_combine(part, plan.nsplit, R, amp, 0, s);
         }
+        if (rc != NUMAG_OK) return rc;
         hipLaunchKernelGGL(corr2d_scatter_kernel, dim3((unsigned)((R * 4 + 255) / 256)), dim3(256), 0, s, amp, R, n_f,
                            set0, C);
         NUMAG_HIP_CHECK(hipGetLastError());

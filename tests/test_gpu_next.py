@@ -16,7 +16,8 @@ DEV = "cuda:0"
 
 
 @pytest.mark.parametrize("kind,n0,n1,rkind,r0,r1", [(1, 37, 64, 1, 10, 16), (0, 40, 53, 0, 21, 17),
-                                                     (1, 20, 30, 0, 9, 12), (0, 33, 33, 1, 7, 24)])
+                                                     (1, 20, 30, 0, 9, 12), (0, 33, 33, 1, 7, 24),
+                                                     (1, 20, 30, 1, 9, 15), (0, 25, 31, 0, 1, 8)])
 def test_correlation_2d_vs_oracle(orc, kind, n0, n1, rkind, r0, r1):
     """Six data sets (the four weight channels carry four at a time, plus a partial
     group) on both detector kinds and both real-space grid kinds."""
