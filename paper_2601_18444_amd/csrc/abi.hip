@@ -490,10 +490,6 @@ int numag_grad(const numag_sample *sample, const double *rot, const numag_qgrid 
     if ((rc = check_sample(sample, "numag_grad")) != NUMAG_OK) return rc;
     if ((rc = check_grid(grid, "numag_grad")) != NUMAG_OK) return rc;
     if ((rc = check_rotations(rot, 1, "numag_grad")) != NUMAG_OK) return rc;
-    if (grid->kind != NUMAG_GRID_CARTESIAN) {
-        set_error("numag_grad: only the Cartesian detector is available in this build");
-        return NUMAG_E_UNSUPPORTED;
-    }
     if (consts == nullptr || !(consts->V > 0.0)) return invalid("numag_grad: consts missing or V <= 0");
     if (weight == nullptr) return invalid("numag_grad: weight is required");
     if (target != nullptr && loss_out == nullptr)

@@ -33,24 +33,8 @@ __global__ __launch_bounds__(kResThreads) void residual_kernel(Detector d, numag
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double lp = 0.0;
     if (p < P) {
-        const int row = (int)(p / d.n1), col = (int)(p % d.n1);
         double s, c;
-        const double qy = axis_value(d.origin0, row, d.step0);
-        const double qz = axis_value(d.origin1, col, d.step1);
-        if (qy == 0.0 && qz == 0.0) {
-            s = 0.0;
-            c = 1.0;
-        } else {
-            double qn;
-            {
-#pragma clang fp contract(off)
-                double a2 = qy * qy;
-                double b2 = qz * qz;
-                qn = sqrt(a2 + b2);
-            }
-            s = qy / qn;
-            c = qz / qn;
-        }
+        pixel_qhat(d, p, s, c);
         const double qh[3] = {0.0, s, c};
         const double *A = amp + p * 8;
         double Vr[3], Vi[3];
@@ -77,7 +61,9 @@ __global__ __launch_bounds__(kResThreads) void residual_kernel(Detector d, numag
             dLdI = weight[p];
         }
         const double g = 2.0 * dLdI * cf;
-        double *o = a + p * 8;
+        // polar: column-major [theta][q] so the adjoint stages a column contiguously
+        const int64_t po = d.kind == NUMAG_GRID_CARTESIAN ? p : (p % d.n1) * d.n0 + p / d.n1;
+        double *o = a + po * 8;
         o[0] = g * A[0];
         o[1] = -g * A[1];
         for (int x = 0; x < 3; ++x) {
@@ -186,6 +172,91 @@ __global__ __launch_bounds__(kAdjThreads, 2) void adjoint_cartesian_kernel(
     }
 }
 
+// Polar detector: phase q_i u_m with u_m = Y sin(theta_m) + Z cos(theta_m).  A lane
+// owns kAdjNPL points; per theta column it forms u, the q step exp(-i dq u) (one
+// sincos) and walks the q rows with the two-term recurrence, restarted from a
+// fresh sincos every kPolRestart rows (the error growth of the recurrence stays
+// below kPolRestart^2 / 2 ulp).  The residual weights are column-major
+// [theta][q][8], staged kPolRestart rows at a time.
+// grid.x: point blocks of kAdjThreads * kAdjNPL; grid.y: theta-column ranges.
+constexpr int kPolRestart = 128;
+
+__global__ __launch_bounds__(kAdjThreads, 2) void adjoint_polar_kernel(
+    const PointRec *__restrict__ pts, int64_t W, Detector d, const double *__restrict__ a, int cols_per_split,
+    double *__restrict__ gpart)
+{
+    __shared__ double s_a[kPolRestart * 8];
+    const int64_t jb = (int64_t)blockIdx.x * kAdjThreads * kAdjNPL + threadIdx.x;
+    const int c0 = blockIdx.y * cols_per_split;
+    const int c1 = min(d.n1, c0 + cols_per_split);
+
+    double Y[kAdjNPL], Z[kAdjNPL];
+    double acc[kAdjNPL][4];
+#pragma unroll
+    for (int u = 0; u < kAdjNPL; ++u) {
+        const int64_t j = jb + (int64_t)u * kAdjThreads;
+        const bool ok = j < W;
+        Y[u] = ok ? pts[j].Y : 0.0;
+        Z[u] = ok ? pts[j].Z : 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+    }
+    for (int col = c0; col < c1; ++col) {
+        const double th = (2.0 * 3.141592653589793 * (double)col) / (double)d.n_theta;
+        double sth, cth;
+        sincos(th, &sth, &cth);
+        double uu[kAdjNPL], kq[kAdjNPL];
+        double2 stc[kAdjNPL];  // inverse q step exp(+i dq u)
+#pragma unroll
+        for (int u = 0; u < kAdjNPL; ++u) {
+            uu[u] = Y[u] * sth + Z[u] * cth;
+            const double2 st = twiddle(d.step0 * uu[u]);
+            stc[u] = make_double2(st.x, -st.y);
+            kq[u] = st.x + st.x;
+        }
+        const double *acol = a + (int64_t)col * d.n0 * 8;
+        for (int r0 = 0; r0 < d.n0; r0 += kPolRestart) {
+            const int nr = min(kPolRestart, d.n0 - r0);
+            __syncthreads();
+            for (int i = threadIdx.x; i < nr * 8; i += kAdjThreads) s_a[i] = acol[(int64_t)r0 * 8 + i];
+            __syncthreads();
+            // recurrence restart at row r0: phasors of rows r0 and r0 - 1
+            const double q0 = axis_value(0.0, r0, d.step0);
+            double2 pc[kAdjNPL], pm[kAdjNPL];
+#pragma unroll
+            for (int u = 0; u < kAdjNPL; ++u) {
+                pc[u] = twiddle(q0 * uu[u]);
+                pm[u] = cmul(pc[u], stc[u]);
+            }
+#pragma unroll 2
+            for (int i = 0; i < nr; ++i) {
+                const double *ai = s_a + i * 8;
+                const double a0r = ai[0], a0i = ai[1], a1r = ai[2], a1i = ai[3];
+                const double a2r = ai[4], a2i = ai[5], a3r = ai[6], a3i = ai[7];
+#pragma unroll
+                for (int u = 0; u < kAdjNPL; ++u) {
+                    const double2 p = pc[u];
+                    acc[u][0] = fma(-a0i, p.y, fma(a0r, p.x, acc[u][0]));
+                    acc[u][1] = fma(-a1i, p.y, fma(a1r, p.x, acc[u][1]));
+                    acc[u][2] = fma(-a2i, p.y, fma(a2r, p.x, acc[u][2]));
+                    acc[u][3] = fma(-a3i, p.y, fma(a3r, p.x, acc[u][3]));
+                    pc[u] = make_double2(fma(kq[u], p.x, -pm[u].x), fma(kq[u], p.y, -pm[u].y));
+                    pm[u] = p;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kAdjNPL; ++u) {
+        const int64_t j = jb + (int64_t)u * kAdjThreads;
+        if (j < W) {
+            double *o = gpart + ((int64_t)blockIdx.y * W + j) * 4;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) o[v] = acc[u][v];
+        }
+    }
+}
+
 __global__ void grad_finalize_kernel(const double *__restrict__ gpart, int nsplit, int64_t W, Rot R,
                                      double *__restrict__ dnuc, double *__restrict__ dmag)
 {
@@ -201,12 +272,15 @@ __global__ void grad_finalize_kernel(const double *__restrict__ gpart, int nspli
     }
 }
 
+// Ranges the detector is split into (rows on a Cartesian detector, theta
+// columns on a polar one), so that point blocks x ranges fill the chip.
 static int adjoint_row_splits(const Detector &d, int64_t W)
 {
     int64_t pblocks = (W + kAdjThreads * kAdjNPL - 1) / (kAdjThreads * kAdjNPL);
     if (pblocks < 1) pblocks = 1;
     int64_t want = (2048 + pblocks - 1) / pblocks;
-    if (want > d.n0) want = d.n0;
+    const int extent = d.kind == NUMAG_GRID_CARTESIAN ? d.n0 : d.n1;
+    if (want > extent) want = extent;
     if (want < 1) want = 1;
     return (int)want;
 }
@@ -251,13 +325,18 @@ int launch_grad(const PointRec *pts, int64_t W, const Detector &d, const numag_c
         NUMAG_HIP_CHECK(hipGetLastError());
     }
     if (W <= 0) return NUMAG_OK;
-    const int rows_per = (d.n0 + splits - 1) / splits;
-    const int nsplit = (d.n0 + rows_per - 1) / rows_per;
+    const int extent = d.kind == NUMAG_GRID_CARTESIAN ? d.n0 : d.n1;
+    const int per = (extent + splits - 1) / splits;
+    const int nsplit = (extent + per - 1) / per;
     const int64_t pblocks = (W + kAdjThreads * kAdjNPL - 1) / (kAdjThreads * kAdjNPL);
     {
         TimedLaunch timed(NUMAG_KERNEL_ADJOINT, s);
-        hipLaunchKernelGGL(adjoint_cartesian_kernel, dim3((unsigned)pblocks, nsplit), dim3(kAdjThreads), 0, s,
-                           pts, W, d, a, rows_per, gpart);
+        if (d.kind == NUMAG_GRID_CARTESIAN)
+            hipLaunchKernelGGL(adjoint_cartesian_kernel, dim3((unsigned)pblocks, nsplit), dim3(kAdjThreads), 0, s,
+                               pts, W, d, a, per, gpart);
+        else
+            hipLaunchKernelGGL(adjoint_polar_kernel, dim3((unsigned)pblocks, nsplit), dim3(kAdjThreads), 0, s, pts,
+                               W, d, a, per, gpart);
     }
     NUMAG_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(grad_finalize_kernel, dim3((unsigned)((W + 255) / 256)), dim3(256), 0, s, gpart,

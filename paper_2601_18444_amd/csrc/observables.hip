@@ -27,33 +27,6 @@ __device__ __forceinline__ C cadd(C a, C b) { return C{a.re + b.re, a.im + b.im}
 __device__ __forceinline__ C cscale(double s, C a) { return C{s * a.re, s * a.im}; }
 
 
-// Unit vector of pixel p (Cartesian: q / |q|, q = 0 -> e_z; polar: column angle).
-__device__ __forceinline__ void pixel_qhat(const Detector &d, int64_t p, double &s, double &c)
-{
-    const int row = (int)(p / d.n1), col = (int)(p % d.n1);
-    if (d.kind == NUMAG_GRID_CARTESIAN) {
-        const double qy = axis_value(d.origin0, row, d.step0);
-        const double qz = axis_value(d.origin1, col, d.step1);
-        if (qy == 0.0 && qz == 0.0) {
-            s = 0.0;
-            c = 1.0;
-            return;
-        }
-        double qn;
-        {
-#pragma clang fp contract(off)
-            double a2 = qy * qy;
-            double b2 = qz * qz;
-            qn = sqrt(a2 + b2);
-        }
-        s = qy / qn;
-        c = qz / qn;
-    } else {
-        const double th = (2.0 * 3.141592653589793 * (double)col) / (double)d.n1;
-        sincos(th, &s, &c);
-    }
-}
-
 // ---------------------------------------------------------------------------
 // cross sections
 // ---------------------------------------------------------------------------
