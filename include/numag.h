@@ -157,7 +157,12 @@ size_t numag_workspace_size(const numag_sample *sample, int64_t n_rot, const num
  *             spec_per_object != 0 (one matrix per object, averaged over the
  *             rotations), else 1 (summed over objects).  NULL in COHERENT mode.
  *   path      NUMAG_PATH_*; the separable paths need sample->regular, rot NULL,
- *             K = 1, a Cartesian detector and COHERENT mode.
+ *             K = 1, a Cartesian detector and COHERENT mode; the Hermitian
+ *             path needs COHERENT mode.
+ *   mode      DILUTE and SPLIT need explicit positions (NUMAG_E_UNSUPPORTED for
+ *             a regular-grid sample); SPLIT takes one rotation.  Both run on
+ *             either detector kind (Cartesian: one persistent launch over
+ *             objects x rotations; polar: one direct sum per object and rotation).
  *   workspace device scratch of at least numag_workspace_size() bytes; its
  *             contents are undefined after the call.
  * Empty samples (W = 0) are valid and give zeros.

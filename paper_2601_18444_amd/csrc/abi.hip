@@ -204,12 +204,58 @@ int run_direct(const numag_sample *s, const Rot &R, const Detector &d, double *a
     return launch_combine(part, p.nsplit, P, amp, 0, st);
 }
 
+// Object modes on the polar detector: each (rotation, object) runs the direct
+// polar path into one amplitude buffer and adds F F^H / n_rot into its spectral
+// matrix (split mode: plus the coherent total of the whole sample).  The
+// direct workspace of the whole sample bounds that of every object.
+size_t polar_objects_ws(const numag_sample *s, const Detector &d)
+{
+    return direct_layout(s, d).total + align_up((size_t)d.n0 * d.n1 * 8 * sizeof(double));
+}
+
+int run_objects_polar(const numag_sample *s, const double *rot, int64_t n_rot, const Detector &d, int32_t mode,
+                      int32_t spec_per_object, double *spec_out, double *amp_out, void *ws, hipStream_t st)
+{
+    const int64_t P = (int64_t)d.n0 * d.n1;
+    const int64_t K = s->n_objects;
+    const DirectLayout L = direct_layout(s, d);
+    Carve cv(ws);
+    void *direct_ws = cv.take(L.total);
+    double *F = (double *)cv.take((size_t)P * 8 * sizeof(double));
+    const int64_t n_spec = spec_per_object ? K : 1;
+    int rc = launch_fill(spec_out, n_spec * P * 16, 0.0, st);
+    if (rc != NUMAG_OK) return rc;
+    if (mode == NUMAG_MODE_SPLIT) {
+        rc = run_direct(s, rot_of(rot, 0), d, amp_out, direct_ws, st);
+        if (rc != NUMAG_OK) return rc;
+    }
+    const double scale = 1.0 / (double)n_rot;
+    for (int64_t r = 0; r < n_rot; ++r) {
+        for (int64_t k = 0; k < K; ++k) {
+            const int64_t lo = K > 1 ? s->obj_offsets[k] : 0, hi = K > 1 ? s->obj_offsets[k + 1] : s->n_points;
+            if (hi == lo) continue;
+            numag_sample sk{};
+            sk.n_points = hi - lo;
+            sk.pos = s->pos + 3 * lo;
+            sk.nuc = s->nuc != nullptr ? s->nuc + lo : nullptr;
+            sk.mag = s->mag != nullptr ? s->mag + 3 * lo : nullptr;
+            sk.n_objects = 1;
+            rc = run_direct(&sk, rot_of(rot, r), d, F, direct_ws, st);
+            if (rc != NUMAG_OK) return rc;
+            rc = launch_spectral_matrix(1, P, F, spec_out + (spec_per_object ? k : 0) * P * 16, st, scale, 1);
+            if (rc != NUMAG_OK) return rc;
+        }
+    }
+    return NUMAG_OK;
+}
+
 size_t amplitudes_ws(const numag_sample *s, int64_t n_rot, const Detector &d, int32_t path, int32_t mode,
                      int32_t spec_per_object)
 {
     if (path == NUMAG_PATH_SEPARABLE_F64 || path == NUMAG_PATH_SEPARABLE_BF16X3)
         return align_up(separable_workspace_bytes(*s->regular, d, path, 1));
     if (mode == NUMAG_MODE_COHERENT) return direct_layout(s, d).total;
+    if (d.kind == NUMAG_GRID_POLAR) return polar_objects_ws(s, d);
     return align_up(objects_workspace_bytes(d, s->obj_offsets, s->n_objects, s->n_points, n_rot, mode,
                                             spec_per_object));
 }
@@ -334,10 +380,6 @@ int numag_amplitudes(const numag_sample *sample, int64_t n_rot, const double *ro
     }
     if (mode != NUMAG_MODE_COHERENT) {
         if (mode == NUMAG_MODE_SPLIT && n_rot != 1) return invalid("numag_amplitudes: SPLIT mode takes one rotation");
-        if (grid->kind != NUMAG_GRID_CARTESIAN) {
-            set_error("numag_amplitudes: DILUTE/SPLIT modes need a Cartesian detector in this build");
-            return NUMAG_E_UNSUPPORTED;
-        }
         if (sample->n_points > 0 && sample->pos == nullptr) {
             set_error("numag_amplitudes: DILUTE/SPLIT modes need explicit positions");
             return NUMAG_E_UNSUPPORTED;
@@ -353,6 +395,11 @@ int numag_amplitudes(const numag_sample *sample, int64_t n_rot, const double *ro
     hipStream_t st = (hipStream_t)stream;
     const int64_t P = (int64_t)grid->n0 * grid->n1;
 
+    if (mode != NUMAG_MODE_COHERENT && grid->kind == NUMAG_GRID_POLAR) {
+        forget_workspace(workspace);
+        return run_objects_polar(sample, rot, n_rot, d, mode, spec_per_object ? 1 : 0, spec_out, amp_out, workspace,
+                                 st);
+    }
     if (mode != NUMAG_MODE_COHERENT)
         return launch_objects(*sample, rot, n_rot, d, mode, spec_per_object ? 1 : 0, spec_out, amp_out, workspace,
                               ws_bytes, st);

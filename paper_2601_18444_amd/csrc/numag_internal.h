@@ -111,7 +111,9 @@ void forget_workspace(const void *ws);
 // cross sections from amplitudes ([n_sets][P][8]) or spectra ([n_sets][P][16]).
 int launch_cross_section(const Detector &d, int64_t n_sets, const double *amp, const double *spec,
                          const numag_consts &c, uint32_t mask, double *out, hipStream_t s);
-int launch_spectral_matrix(int64_t n_sets, int64_t P, const double *amp, double *spec, hipStream_t s);
+// spec = scale A A^H per set and pixel (accumulate: spec += scale A A^H)
+int launch_spectral_matrix(int64_t n_sets, int64_t P, const double *amp, double *spec, hipStream_t s,
+                           double scale = 1.0, int accumulate = 0);
 
 // a8
 int launch_azimuthal(const Detector &d, const double *f, int n_f, int n_bins, double qmax_avg,

@@ -144,30 +144,37 @@ int launch_cross_section(const Detector &d, int64_t n_sets, const double *amp, c
 // (Sec. 3.4 export of the Fourier cross-correlation functions, extended by the
 // nuclear channel), packed as 16 reals per pixel.
 // ---------------------------------------------------------------------------
-__global__ void spectral_matrix_kernel(int64_t n, const double *__restrict__ amp, double *__restrict__ G)
+// G = scale A A^H (accumulate: G += scale A A^H)
+__global__ void spectral_matrix_kernel(int64_t n, const double *__restrict__ amp, double scale, int accumulate,
+                                       double *__restrict__ G)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double *A = amp + i * 8;
     double *g = G + i * 16;
+    double v[16];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) g[a] = A[2 * a] * A[2 * a] + A[2 * a + 1] * A[2 * a + 1];
+    for (int a = 0; a < 4; ++a) v[a] = A[2 * a] * A[2 * a] + A[2 * a + 1] * A[2 * a + 1];
     const int pa[6] = {0, 0, 0, 1, 1, 2};
     const int pb[6] = {1, 2, 3, 2, 3, 3};
 #pragma unroll
     for (int t = 0; t < 6; ++t) {
         const double ar = A[2 * pa[t]], ai = A[2 * pa[t] + 1];
         const double br = A[2 * pb[t]], bi = A[2 * pb[t] + 1];
-        g[4 + 2 * t] = ar * br + ai * bi;  // Re(A_a conj(A_b))
-        g[5 + 2 * t] = ai * br - ar * bi;  // Im(A_a conj(A_b))
+        v[4 + 2 * t] = ar * br + ai * bi;  // Re(A_a conj(A_b))
+        v[5 + 2 * t] = ai * br - ar * bi;  // Im(A_a conj(A_b))
     }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) g[e] = accumulate ? g[e] + scale * v[e] : scale * v[e];
 }
 
-int launch_spectral_matrix(int64_t n_sets, int64_t P, const double *amp, double *spec, hipStream_t s)
+int launch_spectral_matrix(int64_t n_sets, int64_t P, const double *amp, double *spec, hipStream_t s,
+                           double scale, int accumulate)
 {
     const int64_t n = n_sets * P;
     if (n <= 0) return NUMAG_OK;
-    hipLaunchKernelGGL(spectral_matrix_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, amp, spec);
+    hipLaunchKernelGGL(spectral_matrix_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, amp, scale,
+                       accumulate, spec);
     NUMAG_HIP_CHECK(hipGetLastError());
     return NUMAG_OK;
 }

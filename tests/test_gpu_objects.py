@@ -214,3 +214,34 @@ def test_empty_and_single_point_objects(orc, mode):
         for c in range(4):
             assert gated_rel_err(gpu[:, c], A[:, c]) <= TOL, c
         _check_spec(spec[0].cpu().numpy(), orc.spectral(F))
+
+
+@pytest.mark.parametrize("mode", ["dilute", "split"])
+def test_object_modes_on_polar_detector(orc, mode):
+    """Dilute (several rotations, one spectral matrix per object) and split modes on
+    the paper's polar (q, theta) detector, with an empty object."""
+    cfg = _objects(48, [90, 0, 33, 150], spread=14.0)
+    nq, nt, qmax = 21, 36, 1.2
+    grid = numag.qgrid(1, nq, nt, qmax)
+    qy, qz, qhat = orc.pixels(1, nq, nt, qmax)
+    off = cfg["obj_offsets"]
+    if mode == "dilute":
+        rots = synth.uniform_rotations(3, np.random.default_rng(49))
+        _, spec = numag.amplitudes(_sample(cfg), grid, rot=rots, mode=numag.MODE_DILUTE, spec_per_object=True)
+        spec = spec.cpu().numpy()
+        for k in range(4):
+            sl = slice(off[k], off[k + 1])
+            if off[k + 1] == off[k]:
+                assert np.count_nonzero(spec[k]) == 0
+                continue
+            Fs = [orc.amplitudes(cfg["pos"][sl], cfg["nuc"][sl], cfg["mag"][sl], qy, qz, R=R) for R in rots]
+            _check_spec(spec[k], orc.spectral(np.stack(Fs)) / len(rots))
+    else:
+        amp, spec = numag.amplitudes(_sample(cfg), grid, mode=numag.MODE_SPLIT)
+        A = orc.amplitudes(cfg["pos"], cfg["nuc"], cfg["mag"], qy, qz, obj_offsets=off, obj_pos=cfg["obj_pos"])
+        F = orc.amplitudes(cfg["pos"], cfg["nuc"], cfg["mag"], qy, qz, obj_offsets=off, obj_pos=cfg["obj_pos"],
+                           per_object=True)
+        gpu = amp_to_complex(amp[0])
+        for c in range(4):
+            assert gated_rel_err(gpu[:, c], A[:, c]) <= TOL, c
+        _check_spec(spec[0].cpu().numpy(), orc.spectral(F))
