@@ -7,12 +7,15 @@
 //   T_c(y, k)   = sum_z S_c(y, z) exp(-i q_z(k) z)         (real x complex contraction)
 //   F_c(i, k)   = sum_y exp(-i q_y(i) y) T_c(y, k)         (complex x complex contraction)
 // The two contractions are dense GEMMs and run on MFMA:
-//   NUMAG_PATH_SEPARABLE_F64:    v_mfma_f64_16x16x4f64, FP64 operands and accumulation;
+//   NUMAG_PATH_SEPARABLE_F64:    FP64 operands and accumulation, the first on
+//                                v_mfma_f64_16x16x4f64 (one wave per 16 x 16 tile),
+//                                the second on v_mfma_f64_4x4x4f64 (register-blocked
+//                                16 x 16 or 32 x 32 tiles, see sep_contract2_f64);
 //   NUMAG_PATH_SEPARABLE_BF16X3: v_mfma_f32_16x16x16bf16_1k with every operand split
 //                                into bf16 hi + lo and the three products hi*hi,
 //                                hi*lo, lo*hi accumulated in FP32.
 // Twiddles are generated in FP64 into the workspace; the projection is a
-// fixed-order FP64 sum.  One wave computes one 16 x 16 output tile.
+// fixed-order FP64 sum.
 //
 // Loop mode (Sec. 3.1 loop modes, Sec. 3.2 data sets m_1 ... m_B): B weight
 // snapshots on the same grid share the twiddles and run as 4 B channel sets
