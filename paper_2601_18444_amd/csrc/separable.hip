@@ -66,6 +66,41 @@ size_t separable_workspace_bytes(const numag_regular &g, const Detector &d, int 
 constexpr int kProjCells = 64;   // (y, z) cells per projection workgroup
 constexpr int kProjSlices = 4;   // x slices per cell (one thread each)
 
+// Sum over the x cells ix = slice, slice + kProjSlices, ... of column rem (a cell
+// (iy, iz)), in x order.  Loads of four x cells are issued before their adds so
+// that several are in flight (the projection is HBM-bound).
+template <bool HN, bool HM>
+__device__ __forceinline__ void project_cells(const double *__restrict__ nuc, const double *__restrict__ mag,
+                                              int64_t rem, int64_t nyz, int nx, int slice, double (&s)[4])
+{
+    constexpr int U = 4;
+    int ix = slice;
+    for (; ix + (U - 1) * kProjSlices < nx; ix += U * kProjSlices) {
+        double vn[U], vm[U][3];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t j = (int64_t)(ix + u * kProjSlices) * nyz + rem;
+            vn[u] = HN ? nuc[j] : 0.0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) vm[u][a] = HM ? mag[3 * j + a] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            s[0] += vn[u];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) s[1 + a] += vm[u][a];
+        }
+    }
+    for (; ix < nx; ix += kProjSlices) {
+        const int64_t j = (int64_t)ix * nyz + rem;
+        if (HN) s[0] += nuc[j];
+        if (HM) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) s[1 + a] += mag[3 * j + a];
+        }
+    }
+}
+
 // One launch for the operands of both contractions.
 // Workgroups [0, n_proj * n_snap): projection S[b][c][iy][iz] = sum_x w_c(x, iy, iz)
 // of snapshot b for 64 cells, x split into 4 slices summed by 4 threads, slices
@@ -88,15 +123,12 @@ __global__ __launch_bounds__(256) void sep_prepare_kernel(Detector d, numag_regu
         const int64_t rem = (int64_t)(blockIdx.x % n_proj) * kProjCells + cell;
         double s[4] = {0.0, 0.0, 0.0, 0.0};
         if (rem < nyz) {
-            for (int ix = slice; ix < g.n[0]; ix += kProjSlices) {
-                const int64_t j = (int64_t)ix * nyz + rem;
-                if (nuc != nullptr) s[0] += nuc[j];
-                if (mag != nullptr) {
-                    s[1] += mag[3 * j];
-                    s[2] += mag[3 * j + 1];
-                    s[3] += mag[3 * j + 2];
-                }
-            }
+            if (nuc != nullptr && mag != nullptr)
+                project_cells<true, true>(nuc, mag, rem, nyz, g.n[0], slice, s);
+            else if (mag != nullptr)
+                project_cells<false, true>(nuc, mag, rem, nyz, g.n[0], slice, s);
+            else if (nuc != nullptr)
+                project_cells<true, false>(nuc, mag, rem, nyz, g.n[0], slice, s);
         }
         for (int c = 0; c < 4; ++c) part[slice][c][cell] = s[c];
         __syncthreads();
