@@ -169,9 +169,11 @@ int run_direct(const numag_sample *s, const Rot &R, const Detector &d, double *a
     if (L.offsets != 0)
         NUMAG_HIP_CHECK(hipMemcpyAsync(d_off, s->obj_offsets, (size_t)(s->n_objects + 1) * sizeof(int64_t),
                                        hipMemcpyHostToDevice, st));
-    if (s->n_points == 0) {
+    if (s->n_points == 0 || (s->nuc == nullptr && s->mag == nullptr)) {
         return launch_fill(amp, P * 8, 0.0, st);
     }
+    // channels summed: a sample without nuclear (magnetic) weights skips those FMAs
+    const int channels = s->nuc == nullptr ? 3 : (s->mag == nullptr ? 1 : 4);
     int rc = launch_prepare_points(s->pos, s->nuc, s->mag, s->n_points, s->regular,
                                    L.offsets != 0 ? d_off : nullptr, s->n_objects, s->obj_pos, R,
                                    pts, st);
@@ -181,6 +183,7 @@ int run_direct(const numag_sample *s, const Rot &R, const Detector &d, double *a
         if (hermitian) dh.n0 = (d.n0 + 1) / 2;  // rows [0, h): the first h n1 pixels of the output
         const int64_t Ph = (int64_t)dh.n0 * d.n1;
         DirectPlan p = plan_direct_cartesian(dh, s->n_points);
+        p.channels = channels;
         if (p.nsplit == 1) {
             rc = launch_direct_cartesian(pts, s->n_points, dh, p, amp, st);
         } else {
@@ -194,11 +197,13 @@ int run_direct(const numag_sample *s, const Rot &R, const Detector &d, double *a
         Detector dh = d;
         dh.n1 = d.n1 / 2;  // columns [0, n_theta / 2); their mirrors are m + n_theta / 2
         DirectPlan p = plan_direct_polar(dh, s->n_points);
+        p.channels = channels;
         rc = launch_direct_polar(pts, s->n_points, dh, p, part, st);
         if (rc != NUMAG_OK) return rc;
         return launch_combine_polar_half(part, p.nsplit, d.n0, dh.n1, amp, st);
     }
     DirectPlan p = plan_direct_polar(d, s->n_points);
+    p.channels = channels;
     rc = launch_direct_polar(pts, s->n_points, d, p, part, st);
     if (rc != NUMAG_OK) return rc;
     return launch_combine(part, p.nsplit, P, amp, 0, st);

@@ -126,7 +126,7 @@ struct PrepLoader {
     }
 };
 
-template <int LR>
+template <int LR, int CH>
 __global__ __launch_bounds__(kThreads, 2) void direct_cartesian_kernel(
     const PointRec *__restrict__ pts, int64_t W, int64_t per, Detector d, double *__restrict__ out)
 {
@@ -136,9 +136,9 @@ __global__ __launch_bounds__(kThreads, 2) void direct_cartesian_kernel(
     const int row0 = blockIdx.y * T::ROWS;
     const int64_t jbeg = (int64_t)blockIdx.z * per;
     const int64_t jend = min(W, jbeg + per);
-    double acc[cart::kB][8];
+    double acc[cart::kB][2 * CH];
     cart::zero(acc);
-    cart::accumulate<LR>(PrepLoader{pts}, jbeg, jend, d, col0, row0, sm, acc);
+    cart::accumulate<LR, CH>(PrepLoader{pts}, jbeg, jend, d, col0, row0, sm, acc);
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t P = (int64_t)d.n0 * d.n1;
@@ -151,7 +151,7 @@ __global__ __launch_bounds__(kThreads, 2) void direct_cartesian_kernel(
         if (col < d.n1) {
             double *o = dst + ((int64_t)row * d.n1 + col) * 8;
 #pragma unroll
-            for (int v = 0; v < 8; ++v) o[v] = acc[c][v];
+            for (int v = 0; v < 8; ++v) o[v] = cart::channel_value<CH>(acc[c], v);
         }
     }
 }
@@ -170,6 +170,7 @@ int target_workgroups()
 DirectPlan plan_direct_cartesian(const Detector &d, int64_t W)
 {
     DirectPlan p{};
+    p.channels = 4;
     p.lanes = cart::choose_lanes(d.n1);
     const int cols = p.lanes * cart::kB, rows = kThreads / p.lanes;
     p.col_blocks = (d.n1 + cols - 1) / cols;
@@ -202,14 +203,21 @@ int launch_direct_cartesian(const PointRec *pts, int64_t W, const Detector &d, c
     dim3 grid(p.col_blocks, p.row_blocks, p.nsplit);
     dim3 block(kThreads);
     TimedLaunch timed(NUMAG_KERNEL_DIRECT, s);
-#define NUMAG_LAUNCH_CART(LR) \
-    hipLaunchKernelGGL((direct_cartesian_kernel<LR>), grid, block, 0, s, pts, W, p.per, d, partial)
-    switch (p.lanes) {
-        case 8: NUMAG_LAUNCH_CART(8); break;
-        case 16: NUMAG_LAUNCH_CART(16); break;
-        case 32: NUMAG_LAUNCH_CART(32); break;
-        default: NUMAG_LAUNCH_CART(64); break;
+#define NUMAG_LAUNCH_CART(LR, CH) \
+    hipLaunchKernelGGL((direct_cartesian_kernel<LR, CH>), grid, block, 0, s, pts, W, p.per, d, partial)
+#define NUMAG_LAUNCH_CART_CH(LR)                      \
+    switch (p.channels) {                             \
+        case 1: NUMAG_LAUNCH_CART(LR, 1); break;      \
+        case 3: NUMAG_LAUNCH_CART(LR, 3); break;      \
+        default: NUMAG_LAUNCH_CART(LR, 4); break;     \
     }
+    switch (p.lanes) {
+        case 8: NUMAG_LAUNCH_CART_CH(8); break;
+        case 16: NUMAG_LAUNCH_CART_CH(16); break;
+        case 32: NUMAG_LAUNCH_CART_CH(32); break;
+        default: NUMAG_LAUNCH_CART_CH(64); break;
+    }
+#undef NUMAG_LAUNCH_CART_CH
 #undef NUMAG_LAUNCH_CART
     NUMAG_HIP_CHECK(hipGetLastError());
     return NUMAG_OK;

@@ -61,6 +61,7 @@ int launch_prepare_points(const double *pos, const double *nuc, const double *ma
 // [P][8] sums when nsplit == 1) for points [0, W).
 struct DirectPlan {
     int lanes;       // lanes per detector row (Cartesian) or 64 (polar)
+    int channels;    // channels summed: 4 (N, M), 3 (M only) or 1 (N only); the rest are written as 0
     int nsplit;      // point ranges summed by different workgroups
     int64_t per;     // points per split (multiple of the chunk)
     int col_blocks, row_blocks;

@@ -48,23 +48,23 @@ __device__ __forceinline__ cart::Operands polar_operands(const double2 (&s_start
 }
 
 // Adds one point to the lane's B q rows: start, one step, then the recurrence.
-template <int B>
-__device__ __forceinline__ void polar_point(const cart::Operands &o, double (&acc)[B][8])
+template <int B, int CH>
+__device__ __forceinline__ void polar_point(const cart::Operands &o, double (&acc)[B][2 * CH])
 {
     double2 pm = o.ez;
     double2 pc = cmul(pm, o.dz);
-    cart::add_weighted(o, pm, acc[0]);
-    cart::add_weighted(o, pc, acc[1]);
+    cart::add_weighted<CH>(o, pm, acc[0]);
+    cart::add_weighted<CH>(o, pc, acc[1]);
 #pragma unroll
     for (int r = 2; r < B; ++r) {
         const double2 pn = make_double2(fma(o.k, pc.x, -pm.x), fma(o.k, pc.y, -pm.y));
-        cart::add_weighted(o, pn, acc[r]);
+        cart::add_weighted<CH>(o, pn, acc[r]);
         pm = pc;
         pc = pn;
     }
 }
 
-template <int WV>
+template <int WV, int CH>
 __global__ __launch_bounds__(64 * WV, 8 / WV) void direct_polar_kernel(const PointRec *__restrict__ pts, int64_t W,
                                                                       int64_t per, Detector d,
                                                                       double *__restrict__ out)
@@ -86,11 +86,11 @@ __global__ __launch_bounds__(64 * WV, 8 / WV) void direct_polar_kernel(const Poi
     const int64_t jbeg = (int64_t)blockIdx.z * per;
     const int64_t jend = min(W, jbeg + per);
 
-    double acc[B][8];
+    double acc[B][2 * CH];
 #pragma unroll
     for (int r = 0; r < B; ++r)
 #pragma unroll
-        for (int v = 0; v < 8; ++v) acc[r][v] = 0.0;
+        for (int v = 0; v < 2 * CH; ++v) acc[r][v] = 0.0;
 
     // generation role: thread t handles column (t & 63) for points wave, wave + WV, ...
     const int gcol = col0 + lane;
@@ -133,14 +133,14 @@ __global__ __launch_bounds__(64 * WV, 8 / WV) void direct_polar_kernel(const Poi
         for (; jj + 1 < nk; jj += 2) {
             const cart::Operands opb = polar_operands<WV>(s_start, s_step, s_k, s_w, jj + 1, lane, wave);
             __builtin_amdgcn_sched_barrier(0);
-            polar_point<B>(opa, acc);
+            polar_point<B, CH>(opa, acc);
             __builtin_amdgcn_sched_barrier(0);
             opa = polar_operands<WV>(s_start, s_step, s_k, s_w, jj + 2, lane, wave);  // row kPolarChunk at most
             __builtin_amdgcn_sched_barrier(0);
-            polar_point<B>(opb, acc);
+            polar_point<B, CH>(opb, acc);
             __builtin_amdgcn_sched_barrier(0);
         }
-        if (jj < nk) polar_point<B>(opa, acc);
+        if (jj < nk) polar_point<B, CH>(opa, acc);
     }
     const int64_t P = (int64_t)d.n0 * d.n1;
     double *dst = out + (int64_t)blockIdx.z * P * 8;
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(64 * WV, 8 / WV) void direct_polar_kernel(const Poi
         if (row < d.n0 && gcol < d.n1) {
             double *o = dst + ((int64_t)row * d.n1 + gcol) * 8;
 #pragma unroll
-            for (int v = 0; v < 8; ++v) o[v] = acc[r][v];
+            for (int v = 0; v < 8; ++v) o[v] = cart::channel_value<CH>(acc[r], v);
         }
     }
 }
@@ -162,6 +162,7 @@ static int polar_waves(const Detector &d) { return d.n0 > 4 * kPolarB ? 8 : 4; }
 DirectPlan plan_direct_polar(const Detector &d, int64_t W)
 {
     DirectPlan p{};
+    p.channels = 4;
     p.lanes = 64;
     const int rows = polar_waves(d) * kPolarB;
     p.col_blocks = (d.n1 + 63) / 64;
@@ -187,10 +188,21 @@ int launch_direct_polar(const PointRec *pts, int64_t W, const Detector &d, const
 {
     dim3 grid(p.col_blocks, p.row_blocks, p.nsplit);
     TimedLaunch timed(NUMAG_KERNEL_DIRECT, s);
-    if (polar_waves(d) == 8)
-        hipLaunchKernelGGL(direct_polar_kernel<8>, grid, dim3(512), 0, s, pts, W, p.per, d, partial);
-    else
-        hipLaunchKernelGGL(direct_polar_kernel<4>, grid, dim3(256), 0, s, pts, W, p.per, d, partial);
+#define NUMAG_LAUNCH_POLAR(WV, CH) \
+    hipLaunchKernelGGL((direct_polar_kernel<WV, CH>), grid, dim3(64 * WV), 0, s, pts, W, p.per, d, partial)
+#define NUMAG_LAUNCH_POLAR_CH(WV)                  \
+    switch (p.channels) {                          \
+        case 1: NUMAG_LAUNCH_POLAR(WV, 1); break;  \
+        case 3: NUMAG_LAUNCH_POLAR(WV, 3); break;  \
+        default: NUMAG_LAUNCH_POLAR(WV, 4); break; \
+    }
+    if (polar_waves(d) == 8) {
+        NUMAG_LAUNCH_POLAR_CH(8);
+    } else {
+        NUMAG_LAUNCH_POLAR_CH(4);
+    }
+#undef NUMAG_LAUNCH_POLAR_CH
+#undef NUMAG_LAUNCH_POLAR
     NUMAG_HIP_CHECK(hipGetLastError());
     return NUMAG_OK;
 }

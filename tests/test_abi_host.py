@@ -174,3 +174,18 @@ def test_hermitian_path_validates():
                      nws=1 << 30) == numag.E_INVALID
     assert _call_amp(s, grid, path=4, ws=0x3000, nws=1 << 30) == numag.E_INVALID
     assert numag._lib.numag_workspace_size(ctypes.byref(s), 1, ctypes.byref(grid), H, 0) > 0
+
+
+def test_binding_refuses_to_import_without_the_library(tmp_path):
+    """No CPU fallback: a copy of the package without libnumag.so fails at import."""
+    import shutil
+    import subprocess
+    import sys
+
+    pkg = os.path.join(ROOT, "paper_2601_18444_amd")
+    dst = tmp_path / "paper_2601_18444_amd"
+    shutil.copytree(pkg, dst, ignore=shutil.ignore_patterns("*.so", "_build", "__pycache__", "csrc"))
+    code = "import paper_2601_18444_amd.numag"
+    r = subprocess.run([sys.executable, "-c", code], cwd=tmp_path, capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "ImportError" in r.stderr and "is not built" in r.stderr

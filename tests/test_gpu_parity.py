@@ -382,3 +382,24 @@ def test_gradient_polar_vs_oracle(orc, nq, nt):
     assert abs(loss.item() - L) <= 1e-9 * abs(L)
     assert max_norm_err(gdn.cpu().numpy(), dn) <= 1e-9
     assert max_norm_err(gdm.cpu().numpy(), dm) <= 1e-9
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("which", ["mag_only", "nuc_only"])
+def test_channel_subsets(orc, kind, which):
+    """A sample without nuclear (or magnetic) weights runs the kernels that sum only
+    the present channels; the absent ones come out exactly zero."""
+    cl = synth.random_cloud(3100, 9.0, seed=37)
+    nuc = None if which == "mag_only" else cl["nuc"]
+    mag = None if which == "nuc_only" else cl["mag"]
+    grid = numag.qgrid(kind, 40, 70, 1.3)
+    R = synth.sample_rotation(55, 5)
+    s = numag.Sample(pos=cl["pos"], nuc=nuc, mag=mag, device=DEV)
+    amp, _ = numag.amplitudes(s, grid, rot=R)
+    a = amp_to_complex(amp[0])
+    qy, qz, _ = orc.pixels(kind, 40, 70, 1.3)
+    ref = orc.amplitudes(cl["pos"], nuc, mag, qy, qz, R=R)
+    off = [0] if which == "mag_only" else [1, 2, 3]
+    for c in off:
+        assert np.count_nonzero(a[:, c]) == 0, c
+    _check_amp(a, ref)
