@@ -164,7 +164,12 @@ size_t numag_workspace_size(const numag_sample *sample, int64_t n_rot, const num
  *             either detector kind (Cartesian: one persistent launch over
  *             objects x rotations; polar: one direct sum per object and rotation).
  *   workspace device scratch of at least numag_workspace_size() bytes; its
- *             contents are undefined after the call.
+ *             contents are undefined after the call.  In DILUTE/SPLIT mode on a
+ *             Cartesian detector the call keeps its planning tables at the start
+ *             of the workspace and a later call on the same workspace with the
+ *             same tables skips their upload (so it enqueues only kernels and can
+ *             be captured into a graph): the caller must not write to the
+ *             workspace between such calls (any numag call on it is fine).
  * Empty samples (W = 0) are valid and give zeros.
  */
 int numag_amplitudes(const numag_sample *sample, int64_t n_rot, const double *rot,
