@@ -52,6 +52,8 @@ def parse():
                     help="pixels of the oracle's bounded sample")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run one plain 1 GiB device-to-device copy (reference for HBM counters)")
+    ap.add_argument("--no-hermitian", action="store_true",
+                    help="skip the half-detector timing (counter runs: only full-detector launches of the kernel)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the separate orientation-batch measurement")
     return ap.parse_args()
@@ -330,18 +332,20 @@ def main():
         t_bf16 = avg_ms(pairs)
 
     # the Hermitian half-detector form of the direct sum, timed outside the step
-    amp_h = torch.empty_like(amp)
-    numag.amplitudes(sample, grid, path=numag.PATH_DIRECT_HERMITIAN, out=amp_h)
-    pairs = []
-    for _ in range(10):
-        a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a0.record()
+    t_herm = herm_err = None
+    if not args.no_hermitian:
+        amp_h = torch.empty_like(amp)
         numag.amplitudes(sample, grid, path=numag.PATH_DIRECT_HERMITIAN, out=amp_h)
-        a1.record()
-        pairs.append((a0, a1))
-    torch.cuda.synchronize()
-    t_herm = avg_ms(pairs)
-    herm_err = float((amp_h - amp).abs().max() / amp.abs().max())
+        pairs = []
+        for _ in range(10):
+            a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a0.record()
+            numag.amplitudes(sample, grid, path=numag.PATH_DIRECT_HERMITIAN, out=amp_h)
+            a1.record()
+            pairs.append((a0, a1))
+        torch.cuda.synchronize()
+        t_herm = avg_ms(pairs)
+        herm_err = float((amp_h - amp).abs().max() / amp.abs().max())
 
     t_direct = avg_ms(ev["direct"])
     t_adj = avg_ms(ev["adjoint"])
@@ -377,8 +381,8 @@ def main():
             "direct_Gterm_s": round(terms / (t_direct * 1e-3) / 1e9, 2),
             "direct_ms": round(t_direct, 4),
             "direct_kernel_ms": round(kernel_ms["direct_cartesian_kernel"], 4),
-            "direct_hermitian_ms": round(t_herm, 4),
-            "direct_hermitian_Gterm_s_effective": round(terms / (t_herm * 1e-3) / 1e9, 2),
+            "direct_hermitian_ms": round(t_herm, 4) if t_herm else None,
+            "direct_hermitian_Gterm_s_effective": round(terms / (t_herm * 1e-3) / 1e9, 2) if t_herm else None,
             "direct_hermitian_max_diff_vs_direct": herm_err,
             "adjoint_Gterm_s": round(terms / (t_adj * 1e-3) / 1e9, 2),
             "adjoint_ms": round(t_adj, 4),

@@ -10,6 +10,7 @@ namespace numag {
 namespace {
 
 struct Record {
+    int id;
     int kernel;
     hipEvent_t start, stop;
     bool closed;
@@ -19,6 +20,7 @@ std::mutex g_mu;
 bool g_enabled = false;
 std::vector<Record> g_records;
 std::vector<hipEvent_t> g_pool;
+int g_next_id = 0;  // record ids stay valid across clears (a stale id finds nothing)
 
 hipEvent_t take_event()
 {
@@ -43,23 +45,27 @@ bool timer_enabled()
 int timer_begin(int kernel, hipStream_t s)
 {
     std::lock_guard<std::mutex> lk(g_mu);
-    Record r{kernel, take_event(), take_event(), false};
+    Record r{g_next_id, kernel, take_event(), take_event(), false};
     if (r.start == nullptr || r.stop == nullptr || hipEventRecord(r.start, s) != hipSuccess) {
         if (r.start != nullptr) g_pool.push_back(r.start);
         if (r.stop != nullptr) g_pool.push_back(r.stop);
         return -1;
     }
+    g_next_id = (g_next_id + 1) & 0x3fffffff;
     g_records.push_back(r);
-    return (int)g_records.size() - 1;
+    return r.id;
 }
 
 void timer_end(int id, hipStream_t s)
 {
     std::lock_guard<std::mutex> lk(g_mu);
-    if (id < 0 || id >= (int)g_records.size()) return;
-    Record &r = g_records[id];
-    r.closed = hipEventRecord(r.stop, s) == hipSuccess;
-    if (!r.closed) r.kernel = -1;  // dropped at the next read
+    if (id < 0) return;
+    for (auto it = g_records.rbegin(); it != g_records.rend(); ++it) {
+        if (it->id != id) continue;
+        it->closed = hipEventRecord(it->stop, s) == hipSuccess;
+        if (!it->closed) it->kernel = -1;  // dropped at the next read
+        return;
+    }
 }
 
 }  // namespace numag
@@ -100,7 +106,7 @@ extern "C" int numag_kernel_timer_read(int32_t kernel, double *total_ms, int64_t
             continue;
         }
         if (r.kernel != kernel || !r.closed) {
-            keep.push_back(r);
+            keep.push_back(r);  // another kernel's, or a launch still being enqueued
             continue;
         }
         float ms = 0.0f;
