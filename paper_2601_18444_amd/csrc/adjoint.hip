@@ -97,17 +97,54 @@ __global__ void loss_sum_kernel(const double *__restrict__ part, int n, double *
 
 constexpr int kAdjThreads = 256;
 constexpr int kAdjNPL = 4;      // points per lane
-constexpr int kAdjMaxCols = 512;  // columns staged per LDS pass
+constexpr int kAdjMaxCols = 256;  // columns staged per LDS pass
 
 // grid.x: point blocks of kAdjThreads * kAdjNPL; grid.y: row ranges.
+// Residual weights of one column as the adjoint reads them (from LDS).
+struct ColW {
+    double a0r, a0i, a1r, a1i, a2r, a2i, a3r, a3i;
+};
+
+__device__ __forceinline__ ColW load_col(const double *p)
+{
+    return ColW{p[0], p[1], p[2], p[3], p[4], p[5], p[6], p[7]};
+}
+
+// One column for the lane's points: Re(a p) (two FMAs per channel), then the
+// recurrence step to the next column.
+__device__ __forceinline__ void adjoint_column(const ColW &w, double2 (&pc)[kAdjNPL], double2 (&pm)[kAdjNPL],
+                                               const double (&kz)[kAdjNPL], double (&acc)[kAdjNPL][4])
+{
+#pragma unroll
+    for (int u = 0; u < kAdjNPL; ++u) {
+        const double2 p = pc[u];
+        acc[u][0] = fma(-w.a0i, p.y, fma(w.a0r, p.x, acc[u][0]));
+        acc[u][1] = fma(-w.a1i, p.y, fma(w.a1r, p.x, acc[u][1]));
+        acc[u][2] = fma(-w.a2i, p.y, fma(w.a2r, p.x, acc[u][2]));
+        acc[u][3] = fma(-w.a3i, p.y, fma(w.a3r, p.x, acc[u][3]));
+        pc[u] = make_double2(fma(kz[u], p.x, -pm[u].x), fma(kz[u], p.y, -pm[u].y));
+        pm[u] = p;
+    }
+}
+
+// The detector rows of the split are walked as segments of at most kAdjMaxCols
+// columns.  While a segment is summed from one LDS buffer, each thread holds the
+// next segment's residual weights in registers (loaded at the segment's start)
+// and stores them into the other buffer afterwards: one barrier per segment and
+// the global-memory latency hidden behind the sums.  Within a segment the
+// weights of column k + 1 are read from LDS before column k is summed.
+constexpr int kAdjPer = kAdjMaxCols * 8 / kAdjThreads;  // doubles per thread per segment
+
 __global__ __launch_bounds__(kAdjThreads, 2) void adjoint_cartesian_kernel(
     const PointRec *__restrict__ pts, int64_t W, Detector d, const double *__restrict__ a,
     int rows_per_split, double *__restrict__ gpart)
 {
-    __shared__ double s_a[kAdjMaxCols * 8];
+    __shared__ double s_a[2][kAdjMaxCols * 8];
     const int64_t jb = (int64_t)blockIdx.x * kAdjThreads * kAdjNPL + threadIdx.x;
     const int r0 = blockIdx.y * rows_per_split;
     const int r1 = min(d.n0, r0 + rows_per_split);
+    const int segs = (d.n1 + kAdjMaxCols - 1) / kAdjMaxCols;  // segments per row
+    const int nseg = (r1 - r0) * segs;
 
     double Y[kAdjNPL], Z[kAdjNPL], kz[kAdjNPL];
     double2 ez0[kAdjNPL], dzc[kAdjNPL];
@@ -127,39 +164,58 @@ __global__ __launch_bounds__(kAdjThreads, 2) void adjoint_cartesian_kernel(
         for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
     }
 
-    for (int row = r0; row < r1; ++row) {
-        const double qy = axis_value(d.origin0, row, d.step0);
-        // pc: phasor of the current column, pm: of the column before it
-        double2 pc[kAdjNPL], pm[kAdjNPL];
+    // residual weights of segment g (row r0 + g / segs, columns from (g % segs) kAdjMaxCols)
+    auto fetch = [&](int g, double (&reg)[kAdjPer]) {
+        const int row = r0 + g / segs, c0 = (g % segs) * kAdjMaxCols;
+        const int nc = min(kAdjMaxCols, d.n1 - c0);
+        const double *src = a + ((int64_t)row * d.n1 + c0) * 8;
 #pragma unroll
-        for (int u = 0; u < kAdjNPL; ++u) {
-            pc[u] = cmul(twiddle(qy * Y[u]), ez0[u]);
-            pm[u] = cmul(pc[u], dzc[u]);
+        for (int e = 0; e < kAdjPer; ++e) {
+            const int i = threadIdx.x + e * kAdjThreads;
+            reg[e] = i < nc * 8 ? src[i] : 0.0;
         }
-        for (int c0 = 0; c0 < d.n1; c0 += kAdjMaxCols) {
-            const int nc = min(kAdjMaxCols, d.n1 - c0);
-            __syncthreads();
-            const double *src = a + ((int64_t)row * d.n1 + c0) * 8;
-            for (int i = threadIdx.x; i < nc * 8; i += kAdjThreads) s_a[i] = src[i];
-            __syncthreads();
-#pragma unroll 2
-            for (int k = 0; k < nc; ++k) {
-                const double *ak = s_a + k * 8;
-                const double a0r = ak[0], a0i = ak[1], a1r = ak[2], a1i = ak[3];
-                const double a2r = ak[4], a2i = ak[5], a3r = ak[6], a3i = ak[7];
+    };
+    double reg[kAdjPer];
+    if (nseg > 0) {
+        fetch(0, reg);
 #pragma unroll
-                for (int u = 0; u < kAdjNPL; ++u) {
-                    // Re(a p) as two FMAs per channel
-                    const double2 p = pc[u];
-                    acc[u][0] = fma(-a0i, p.y, fma(a0r, p.x, acc[u][0]));
-                    acc[u][1] = fma(-a1i, p.y, fma(a1r, p.x, acc[u][1]));
-                    acc[u][2] = fma(-a2i, p.y, fma(a2r, p.x, acc[u][2]));
-                    acc[u][3] = fma(-a3i, p.y, fma(a3r, p.x, acc[u][3]));
-                    pc[u] = make_double2(fma(kz[u], p.x, -pm[u].x), fma(kz[u], p.y, -pm[u].y));
-                    pm[u] = p;
-                }
+        for (int e = 0; e < kAdjPer; ++e) s_a[0][threadIdx.x + e * kAdjThreads] = reg[e];
+    }
+    __syncthreads();
+
+    double2 pc[kAdjNPL], pm[kAdjNPL];  // phasors of the current column and of the one before
+    for (int g = 0; g < nseg; ++g) {
+        const int buf = g & 1;
+        if (g + 1 < nseg) fetch(g + 1, reg);
+        const int c0 = (g % segs) * kAdjMaxCols;
+        const int nc = min(kAdjMaxCols, d.n1 - c0);
+        if (c0 == 0) {  // row start: fresh phasors
+            const double qy = axis_value(d.origin0, r0 + g / segs, d.step0);
+#pragma unroll
+            for (int u = 0; u < kAdjNPL; ++u) {
+                pc[u] = cmul(twiddle(qy * Y[u]), ez0[u]);
+                pm[u] = cmul(pc[u], dzc[u]);
             }
         }
+        const double *sa = s_a[buf];
+        ColW wa = load_col(sa);
+        int k = 0;
+        for (; k + 1 < nc; k += 2) {
+            const ColW wb = load_col(sa + (k + 1) * 8);
+            __builtin_amdgcn_sched_barrier(0);
+            adjoint_column(wa, pc, pm, kz, acc);
+            __builtin_amdgcn_sched_barrier(0);
+            wa = load_col(sa + min(k + 2, nc - 1) * 8);
+            __builtin_amdgcn_sched_barrier(0);
+            adjoint_column(wb, pc, pm, kz, acc);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (k < nc) adjoint_column(wa, pc, pm, kz, acc);
+        if (g + 1 < nseg) {
+#pragma unroll
+            for (int e = 0; e < kAdjPer; ++e) s_a[buf ^ 1][threadIdx.x + e * kAdjThreads] = reg[e];
+        }
+        __syncthreads();
     }
 #pragma unroll
     for (int u = 0; u < kAdjNPL; ++u) {
