@@ -7,8 +7,10 @@
 // with r = I_p - T_p and m' = R m (so dL/dm = R^T dL/dm').
 //
 // The adjoint sum swaps the roles of points and pixels: a lane owns a few
-// points and walks the detector, row by row.  The row-start phasor is a fresh
-// FP64 sincos; along the row the phasors follow the two-term recurrence
+// points and walks the detector, row by row.  The row-start phasor is the
+// previous row's times exp(-i dq_y Y) (one complex product), restarted from a
+// fresh FP64 sincos every kAdjRowRestart rows (at most 2^7 ulp of drift); along
+// the row the phasors follow the two-term recurrence
 //     p_{c+1} = 2 cos(dq_z Z) p_c - p_{c-1}
 // (two FMAs per column; an error made at column k reaches column c multiplied
 // by at most c - k + 1, so a 256-column row keeps about 38 of the 53 bits in
@@ -98,6 +100,7 @@ __global__ void loss_sum_kernel(const double *__restrict__ part, int n, double *
 constexpr int kAdjThreads = 256;
 constexpr int kAdjNPL = 4;      // points per lane
 constexpr int kAdjMaxCols = 256;  // columns staged per LDS pass
+constexpr int kAdjRowRestart = 64;  // rows between fresh row-start phasors
 
 // grid.x: point blocks of kAdjThreads * kAdjNPL; grid.y: row ranges.
 // Residual weights of one column as the adjoint reads them (from LDS).
@@ -147,7 +150,7 @@ __global__ __launch_bounds__(kAdjThreads, 2) void adjoint_cartesian_kernel(
     const int nseg = (r1 - r0) * segs;
 
     double Y[kAdjNPL], Z[kAdjNPL], kz[kAdjNPL];
-    double2 ez0[kAdjNPL], dzc[kAdjNPL];
+    double2 ez0[kAdjNPL], dzc[kAdjNPL], ey[kAdjNPL], dy[kAdjNPL];
     double acc[kAdjNPL][4];
     const double qz0 = axis_value(d.origin1, 0, d.step1);
 #pragma unroll
@@ -160,6 +163,7 @@ __global__ __launch_bounds__(kAdjThreads, 2) void adjoint_cartesian_kernel(
         const double2 dz = twiddle(d.step1 * Z[u]);
         dzc[u] = make_double2(dz.x, -dz.y);  // inverse column step
         kz[u] = dz.x + dz.x;
+        dy[u] = twiddle(d.step0 * Y[u]);     // row step
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
     }
@@ -189,12 +193,18 @@ __global__ __launch_bounds__(kAdjThreads, 2) void adjoint_cartesian_kernel(
         if (g + 1 < nseg) fetch(g + 1, reg);
         const int c0 = (g % segs) * kAdjMaxCols;
         const int nc = min(kAdjMaxCols, d.n1 - c0);
-        if (c0 == 0) {  // row start: fresh phasors
-            const double qy = axis_value(d.origin0, r0 + g / segs, d.step0);
+        if (c0 == 0) {  // row start: fresh column phasors
+            const int rr = g / segs;  // row within the split
+            if (rr % kAdjRowRestart == 0) {
+                const double qy = axis_value(d.origin0, r0 + rr, d.step0);
+#pragma unroll
+                for (int u = 0; u < kAdjNPL; ++u) ey[u] = twiddle(qy * Y[u]);
+            }
 #pragma unroll
             for (int u = 0; u < kAdjNPL; ++u) {
-                pc[u] = cmul(twiddle(qy * Y[u]), ez0[u]);
+                pc[u] = cmul(ey[u], ez0[u]);
                 pm[u] = cmul(pc[u], dzc[u]);
+                ey[u] = cmul(ey[u], dy[u]);  // next row
             }
         }
         const double *sa = s_a[buf];
