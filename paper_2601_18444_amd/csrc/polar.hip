@@ -11,24 +11,12 @@ namespace numag {
 // columns and each walks 8 q rows, the first by the row-group start, the second
 // by one step exp(-i dq u), the rest by the two-term recurrence
 // p_{r+1} = 2 cos(dq u) p_r - p_{r-1}.  A workgroup of WV waves covers 8 WV rows,
-// so the per-(point, column) generation (u, one sincos for the step, the block
-// start step^row0 by squaring, the wave starts by powers of step^8) is shared
+// so the per-(point, column) generation (u, two sincos for the step and the
+// block start exp(-i q(row0) u), the wave starts by powers of step^8) is shared
 // by 8 WV rows.
 // ---------------------------------------------------------------------------
 constexpr int kPolarChunk = 8;
 constexpr int kPolarB = 8;
-
-// z^e for e >= 0 by binary powering (|z| = 1; relative error about e ulp).
-__device__ __forceinline__ double2 cpow_int(double2 z, int e)
-{
-    double2 r = make_double2(1.0, 0.0);
-    while (e > 0) {
-        if (e & 1) r = cmul(r, z);
-        z = cmul(z, z);
-        e >>= 1;
-    }
-    return r;
-}
 
 // Operands of point jj for this lane: ez = the wave's start phasor, dz = the q step.
 template <int WV>
@@ -97,6 +85,7 @@ __global__ __launch_bounds__(64 * WV, 8 / WV) void direct_polar_kernel(const Poi
     const double theta = (2.0 * 3.141592653589793 * (double)gcol) / (double)d.n_theta;
     double sth, cth;
     sincos(theta, &sth, &cth);
+    const double qrow0 = axis_value(d.origin0, row0, d.step0);
 
     for (int64_t j0 = jbeg; j0 < jend; j0 += kPolarChunk) {
         const int nk = (int)min((int64_t)kPolarChunk, jend - j0);
@@ -106,12 +95,11 @@ __global__ __launch_bounds__(64 * WV, 8 / WV) void direct_polar_kernel(const Poi
             const double Y = ok ? pts[j0 + jj].Y : 0.0;
             const double Z = ok ? pts[j0 + jj].Z : 0.0;
             const double u = Y * sth + Z * cth;
-            const double2 step = twiddle(d.step0 * u);
+            const double2 step = twiddle_cw(d.step0 * u);
             double2 sb = cmul(step, step);  // step^8: from one wave's rows to the next
             sb = cmul(sb, sb);
             sb = cmul(sb, sb);
-            // start of the block: q(row0) = row0 dq, so exp(-i q(row0) u) = step^row0
-            double2 st = cpow_int(sb, row0 / B);
+            double2 st = twiddle_cw(qrow0 * u);  // start of the block
             s_step[jj][lane] = step;
             s_k[jj][lane] = step.x + step.x;
 #pragma unroll
