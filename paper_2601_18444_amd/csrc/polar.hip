@@ -59,12 +59,12 @@ __global__ __launch_bounds__(64 * WV, 8 / WV) void direct_polar_kernel(const Poi
 {
     constexpr int B = kPolarB;
     constexpr int ROWS = WV * B;
-    static_assert(kPolarChunk % WV == 0 || WV % kPolarChunk == 0, "chunk and waves");
     // one row per point of a chunk plus one the pipelined loop may read past the end
     __shared__ double2 s_start[kPolarChunk + 1][WV][64];
     __shared__ double2 s_step[kPolarChunk + 1][64];
     __shared__ double s_k[kPolarChunk + 1][64];
     __shared__ double s_w[kPolarChunk + 1][4];
+    __shared__ double2 s_trig[64];  // (sin, cos) of the lane's column angle
 
     const int t = threadIdx.x;
     const int lane = t & 63;
@@ -82,19 +82,38 @@ __global__ __launch_bounds__(64 * WV, 8 / WV) void direct_polar_kernel(const Poi
 
     // generation role: thread t handles column (t & 63) for points wave, wave + WV, ...
     const int gcol = col0 + lane;
-    const double theta = (2.0 * 3.141592653589793 * (double)gcol) / (double)d.n_theta;
-    double sth, cth;
-    sincos(theta, &sth, &cth);
+    if (wave == 0) {
+        const double theta = (2.0 * 3.141592653589793 * (double)gcol) / (double)d.n_theta;
+        double sth, cth;
+        sincos(theta, &sth, &cth);
+        s_trig[lane] = make_double2(sth, cth);
+    }  // published by the first barrier of the chunk loop
     const double qrow0 = axis_value(d.origin0, row0, d.step0);
+
+    // point data of a chunk, loaded one chunk ahead: (Y, Z) of the points
+    // wave + WV i that this wave generates, and weight component t % 4 of point
+    // t / 4 for t < 4 kPolarChunk
+    constexpr int GPW = kPolarChunk / WV;  // points generated per wave
+    static_assert(GPW * WV == kPolarChunk, "chunk and waves");
+    const int wj = t >> 2, wc = t & 3;
+    double nY[GPW], nZ[GPW], nW = 0.0;
+#pragma unroll
+    for (int i = 0; i < GPW; ++i) {
+        const int64_t j = jbeg + wave + WV * i;
+        nY[i] = j < jend ? pts[j].Y : 0.0;
+        nZ[i] = j < jend ? pts[j].Z : 0.0;
+    }
+    if (wj < kPolarChunk && jbeg + wj < jend) nW = pts[jbeg + wj].w[wc];
 
     for (int64_t j0 = jbeg; j0 < jend; j0 += kPolarChunk) {
         const int nk = (int)min((int64_t)kPolarChunk, jend - j0);
         __syncthreads();
-        for (int jj = wave; jj < kPolarChunk; jj += WV) {
-            const bool ok = jj < nk;
-            const double Y = ok ? pts[j0 + jj].Y : 0.0;
-            const double Z = ok ? pts[j0 + jj].Z : 0.0;
-            const double u = Y * sth + Z * cth;
+#pragma unroll
+        for (int i = 0; i < GPW; ++i) {
+            const int jj = wave + WV * i;
+            const double Y = nY[i], Z = nZ[i];  // zero past the end
+            const double2 tr = s_trig[lane];
+            const double u = Y * tr.x + Z * tr.y;
             const double2 step = twiddle_cw(d.step0 * u);
             double2 sb = cmul(step, step);  // step^8: from one wave's rows to the next
             sb = cmul(sb, sb);
@@ -108,11 +127,16 @@ __global__ __launch_bounds__(64 * WV, 8 / WV) void direct_polar_kernel(const Poi
                 st = cmul(st, sb);
             }
         }
-        if (t < kPolarChunk) {
-            const bool ok = t < nk;
+        if (wj < kPolarChunk) s_w[wj][wc] = nW;  // zero past the end
+        // request the next chunk's point data; it arrives during the sums below
+        const int64_t j1 = j0 + kPolarChunk;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) s_w[t][v] = ok ? pts[j0 + t].w[v] : 0.0;
+        for (int i = 0; i < GPW; ++i) {
+            const int64_t j = j1 + wave + WV * i;
+            nY[i] = j < jend ? pts[j].Y : 0.0;
+            nZ[i] = j < jend ? pts[j].Z : 0.0;
         }
+        nW = (wj < kPolarChunk && j1 + wj < jend) ? pts[j1 + wj].w[wc] : 0.0;
         __syncthreads();
         // operands of the next point are requested before the current point is
         // accumulated (as in the Cartesian loop)
