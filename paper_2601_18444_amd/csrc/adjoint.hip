@@ -137,6 +137,7 @@ __device__ __forceinline__ void adjoint_column(const ColW &w, double2 (&pc)[kAdj
 // the global-memory latency hidden behind the sums.  Within a segment the
 // weights of column k + 1 are read from LDS before column k is summed.
 constexpr int kAdjPer = kAdjMaxCols * 8 / kAdjThreads;  // doubles per thread per segment
+static_assert(kAdjPer * kAdjThreads == kAdjMaxCols * 8, "segment split over the threads");
 
 __global__ __launch_bounds__(kAdjThreads, 2) void adjoint_cartesian_kernel(
     const PointRec *__restrict__ pts, int64_t W, Detector d, const double *__restrict__ a,
@@ -243,18 +244,24 @@ __global__ __launch_bounds__(kAdjThreads, 2) void adjoint_cartesian_kernel(
 // sincos) and walks the q rows with the two-term recurrence, restarted from a
 // fresh sincos every kPolRestart rows (the error growth of the recurrence stays
 // below kPolRestart^2 / 2 ulp).  The residual weights are column-major
-// [theta][q][8], staged kPolRestart rows at a time.
+// [theta][q][8] and are walked as segments of kPolRestart rows of one column,
+// double-buffered in LDS like the Cartesian kernel's: the next segment is held
+// in registers while the current one is summed.
 // grid.x: point blocks of kAdjThreads * kAdjNPL; grid.y: theta-column ranges.
 constexpr int kPolRestart = 128;
+constexpr int kPolPer = kPolRestart * 8 / kAdjThreads;  // doubles per thread per segment
+static_assert(kPolPer * kAdjThreads == kPolRestart * 8, "segment split over the threads");
 
 __global__ __launch_bounds__(kAdjThreads, 2) void adjoint_polar_kernel(
     const PointRec *__restrict__ pts, int64_t W, Detector d, const double *__restrict__ a, int cols_per_split,
     double *__restrict__ gpart)
 {
-    __shared__ double s_a[kPolRestart * 8];
+    __shared__ double s_a[2][kPolRestart * 8];
     const int64_t jb = (int64_t)blockIdx.x * kAdjThreads * kAdjNPL + threadIdx.x;
     const int c0 = blockIdx.y * cols_per_split;
     const int c1 = min(d.n1, c0 + cols_per_split);
+    const int rsegs = (d.n0 + kPolRestart - 1) / kPolRestart;  // segments per column
+    const int nseg = max(0, c1 - c0) * rsegs;
 
     double Y[kAdjNPL], Z[kAdjNPL];
     double acc[kAdjNPL][4];
@@ -267,50 +274,75 @@ __global__ __launch_bounds__(kAdjThreads, 2) void adjoint_polar_kernel(
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
     }
-    for (int col = c0; col < c1; ++col) {
-        const double th = (2.0 * 3.141592653589793 * (double)col) / (double)d.n_theta;
-        double sth, cth;
-        sincos(th, &sth, &cth);
-        double uu[kAdjNPL], kq[kAdjNPL];
-        double2 stc[kAdjNPL];  // inverse q step exp(+i dq u)
+
+    // residual weights of segment g (column c0 + g / rsegs, rows from (g % rsegs) kPolRestart)
+    auto fetch = [&](int g, double (&reg)[kPolPer]) {
+        const int col = c0 + g / rsegs, r0 = (g % rsegs) * kPolRestart;
+        const int nr = min(kPolRestart, d.n0 - r0);
+        const double *src = a + ((int64_t)col * d.n0 + r0) * 8;
 #pragma unroll
-        for (int u = 0; u < kAdjNPL; ++u) {
-            uu[u] = Y[u] * sth + Z[u] * cth;
-            const double2 st = twiddle(d.step0 * uu[u]);
-            stc[u] = make_double2(st.x, -st.y);
-            kq[u] = st.x + st.x;
+        for (int e = 0; e < kPolPer; ++e) {
+            const int i = threadIdx.x + e * kAdjThreads;
+            reg[e] = i < nr * 8 ? src[i] : 0.0;
         }
-        const double *acol = a + (int64_t)col * d.n0 * 8;
-        for (int r0 = 0; r0 < d.n0; r0 += kPolRestart) {
-            const int nr = min(kPolRestart, d.n0 - r0);
-            __syncthreads();
-            for (int i = threadIdx.x; i < nr * 8; i += kAdjThreads) s_a[i] = acol[(int64_t)r0 * 8 + i];
-            __syncthreads();
-            // recurrence restart at row r0: phasors of rows r0 and r0 - 1
-            const double q0 = axis_value(0.0, r0, d.step0);
-            double2 pc[kAdjNPL], pm[kAdjNPL];
+    };
+    double reg[kPolPer];
+    if (nseg > 0) {
+        fetch(0, reg);
+#pragma unroll
+        for (int e = 0; e < kPolPer; ++e) s_a[0][threadIdx.x + e * kAdjThreads] = reg[e];
+    }
+    __syncthreads();
+
+    double uu[kAdjNPL], kq[kAdjNPL];
+    double2 stc[kAdjNPL];  // inverse q step exp(+i dq u)
+    for (int g = 0; g < nseg; ++g) {
+        const int buf = g & 1;
+        if (g + 1 < nseg) fetch(g + 1, reg);
+        const int col = c0 + g / rsegs, r0 = (g % rsegs) * kPolRestart;
+        const int nr = min(kPolRestart, d.n0 - r0);
+        if (r0 == 0) {  // new column: u and the q step of every point
+            const double th = (2.0 * 3.141592653589793 * (double)col) / (double)d.n_theta;
+            double sth, cth;
+            sincos(th, &sth, &cth);
 #pragma unroll
             for (int u = 0; u < kAdjNPL; ++u) {
-                pc[u] = twiddle(q0 * uu[u]);
-                pm[u] = cmul(pc[u], stc[u]);
-            }
-#pragma unroll 2
-            for (int i = 0; i < nr; ++i) {
-                const double *ai = s_a + i * 8;
-                const double a0r = ai[0], a0i = ai[1], a1r = ai[2], a1i = ai[3];
-                const double a2r = ai[4], a2i = ai[5], a3r = ai[6], a3i = ai[7];
-#pragma unroll
-                for (int u = 0; u < kAdjNPL; ++u) {
-                    const double2 p = pc[u];
-                    acc[u][0] = fma(-a0i, p.y, fma(a0r, p.x, acc[u][0]));
-                    acc[u][1] = fma(-a1i, p.y, fma(a1r, p.x, acc[u][1]));
-                    acc[u][2] = fma(-a2i, p.y, fma(a2r, p.x, acc[u][2]));
-                    acc[u][3] = fma(-a3i, p.y, fma(a3r, p.x, acc[u][3]));
-                    pc[u] = make_double2(fma(kq[u], p.x, -pm[u].x), fma(kq[u], p.y, -pm[u].y));
-                    pm[u] = p;
-                }
+                uu[u] = Y[u] * sth + Z[u] * cth;
+                const double2 st = twiddle_cw(d.step0 * uu[u]);
+                stc[u] = make_double2(st.x, -st.y);
+                kq[u] = st.x + st.x;
             }
         }
+        // recurrence restart at row r0: phasors of rows r0 and r0 - 1
+        const double q0 = axis_value(0.0, r0, d.step0);
+        double2 pc[kAdjNPL], pm[kAdjNPL];
+#pragma unroll
+        for (int u = 0; u < kAdjNPL; ++u) {
+            pc[u] = twiddle_cw(q0 * uu[u]);
+            pm[u] = cmul(pc[u], stc[u]);
+        }
+        const double *sa = s_a[buf];
+#pragma unroll 2
+        for (int i = 0; i < nr; ++i) {
+            const double *ai = sa + i * 8;
+            const double a0r = ai[0], a0i = ai[1], a1r = ai[2], a1i = ai[3];
+            const double a2r = ai[4], a2i = ai[5], a3r = ai[6], a3i = ai[7];
+#pragma unroll
+            for (int u = 0; u < kAdjNPL; ++u) {
+                const double2 p = pc[u];
+                acc[u][0] = fma(-a0i, p.y, fma(a0r, p.x, acc[u][0]));
+                acc[u][1] = fma(-a1i, p.y, fma(a1r, p.x, acc[u][1]));
+                acc[u][2] = fma(-a2i, p.y, fma(a2r, p.x, acc[u][2]));
+                acc[u][3] = fma(-a3i, p.y, fma(a3r, p.x, acc[u][3]));
+                pc[u] = make_double2(fma(kq[u], p.x, -pm[u].x), fma(kq[u], p.y, -pm[u].y));
+                pm[u] = p;
+            }
+        }
+        if (g + 1 < nseg) {
+#pragma unroll
+            for (int e = 0; e < kPolPer; ++e) s_a[buf ^ 1][threadIdx.x + e * kAdjThreads] = reg[e];
+        }
+        __syncthreads();
     }
 #pragma unroll
     for (int u = 0; u < kAdjNPL; ++u) {
