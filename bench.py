@@ -56,7 +56,33 @@ def parse():
                     help="skip the half-detector timing (counter runs: only full-detector launches of the kernel)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the separate orientation-batch measurement")
+    ap.add_argument("--polar", action="store_true",
+                    help="only time the direct sums of the same points on a 256 q x 256 theta polar "
+                         "detector (a short run for the polar kernel's profiles)")
     return ap.parse_args()
+
+
+def polar_only(torch, numag, synth, launches=5, warmup=3):
+    """Direct sums of the 64^3 vortex on a 256 x 256 polar detector (|q| <= 2 nm^-1).
+    The warm-up launches let the engine clock settle before the timed ones."""
+    cfg = synth.vortex_c2()
+    W = cfg["pos"].shape[0]
+    s = numag.Sample(pos=cfg["pos"], nuc=cfg["nuc"], mag=cfg["mag"], device="cuda:0")
+    pgrid = numag.qgrid(1, 256, 256, 2.0)
+    amp = torch.empty((1, pgrid.n_pixels, 4, 2), dtype=torch.float64, device="cuda:0")
+    for _ in range(warmup):
+        numag.amplitudes(s, pgrid, out=amp)
+    torch.cuda.synchronize()
+    numag.kernel_timer(True)
+    for _ in range(launches):
+        numag.amplitudes(s, pgrid, out=amp)
+    torch.cuda.synchronize()
+    t, n = numag.kernel_timer_read(numag.KERNEL_DIRECT)
+    numag.kernel_timer(False)
+    ms = t / n
+    print(json.dumps({"workload": "vortex grid 64^3 (262144 points), 256 q x 256 theta polar detector, |q| <= 2 nm^-1",
+                      "direct_polar_kernel_ms": round(ms, 4),
+                      "Gterm_s": round(W * pgrid.n_pixels / ms / 1e6, 1), "launches": n}))
 
 
 def measure_batched(torch, numag, synth):
@@ -236,6 +262,10 @@ def main():
         return
 
     from paper_2601_18444_amd import numag, synth
+
+    if args.polar:
+        polar_only(torch, numag, synth)
+        return
 
     dev = "cuda:0"
     torch.cuda.set_device(0)
