@@ -308,7 +308,7 @@ __global__ __launch_bounds__(kAdjThreads, 2) void adjoint_polar_kernel(
 #pragma unroll
             for (int u = 0; u < kAdjNPL; ++u) {
                 uu[u] = Y[u] * sth + Z[u] * cth;
-                const double2 st = twiddle_cw(d.step0 * uu[u]);
+                const double2 st = twiddle(d.step0 * uu[u]);
                 stc[u] = make_double2(st.x, -st.y);
                 kq[u] = st.x + st.x;
             }
@@ -318,7 +318,7 @@ __global__ __launch_bounds__(kAdjThreads, 2) void adjoint_polar_kernel(
         double2 pc[kAdjNPL], pm[kAdjNPL];
 #pragma unroll
         for (int u = 0; u < kAdjNPL; ++u) {
-            pc[u] = twiddle_cw(q0 * uu[u]);
+            pc[u] = twiddle(q0 * uu[u]);
             pm[u] = cmul(pc[u], stc[u]);
         }
         const double *sa = s_a[buf];

@@ -1,6 +1,7 @@
-// Small device helpers shared by the sum kernels: complex product, the unit
-// phasor exp(-i phi), and a detector axis value computed exactly as the
-// detector is defined (one rounded product, one rounded sum, never fused).
+// Small device helpers shared by the sum kernels: complex product, FP64 sine and
+// cosine, the unit phasor exp(-i phi), and a detector axis value computed
+// exactly as the detector is defined (one rounded product, one rounded sum,
+// never fused).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -15,13 +16,6 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b)
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// exp(-i phi) = (cos phi, -sin phi)
-__device__ __forceinline__ double2 twiddle(double phi)
-{
-    double s, c;
-    sincos(phi, &s, &c);
-    return make_double2(c, -s);
-}
 
 // sin x and cos x in FP64 for the sum kernels' generation phases.
 // Cody-Waite reduction (Cody & Waite, Software Manual for the Elementary
@@ -74,8 +68,8 @@ __host__ __device__ __forceinline__ void sincos_cw(double x, double *sp, double 
     *cp = ((n + 1) & 2) ? -c0 : c0;
 }
 
-// exp(-i phi) by sincos_cw
-__host__ __device__ __forceinline__ double2 twiddle_cw(double phi)
+// exp(-i phi) = (cos phi, -sin phi)
+__host__ __device__ __forceinline__ double2 twiddle(double phi)
 {
     double s, c;
     sincos_cw(phi, &s, &c);

@@ -114,11 +114,11 @@ __global__ __launch_bounds__(64 * WV, 8 / WV) void direct_polar_kernel(const Poi
             const double Y = nY[i], Z = nZ[i];  // zero past the end
             const double2 tr = s_trig[lane];
             const double u = Y * tr.x + Z * tr.y;
-            const double2 step = twiddle_cw(d.step0 * u);
+            const double2 step = twiddle(d.step0 * u);
             double2 sb = cmul(step, step);  // step^8: from one wave's rows to the next
             sb = cmul(sb, sb);
             sb = cmul(sb, sb);
-            double2 st = twiddle_cw(qrow0 * u);  // start of the block
+            double2 st = twiddle(qrow0 * u);  // start of the block
             s_step[jj][lane] = step;
             s_k[jj][lane] = step.x + step.x;
 #pragma unroll
