@@ -106,6 +106,16 @@ def measure_batched(torch, numag, synth):
     t_batched = e0.elapsed_time(e1) * 1e-3
     W = cfg["pos"].shape[0]
     terms = W * len(rots) * grid.n_pixels
+    # the same average on the half-detector path (G(-q) = conj G(q)), opt-in
+    bh = numag.BatchedOrientations(s, grid, rots, spec_per_object=True, path=numag.PATH_DIRECT_HERMITIAN)
+    torch.cuda.synchronize()
+    e0.record()
+    bh.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    t_herm = e0.elapsed_time(e1) * 1e-3
+    herm_diff = float((bh.spec - b.spec).abs().max() / b.spec.abs().max())
+    del bh
     # plain direct path: one coherent call per particle and rotation (sample of 8 rotations)
     off = cfg["obj_offsets"]
     parts = [numag.Sample(pos=cfg["pos"][off[k]:off[k + 1]], nuc=cfg["nuc"][off[k]:off[k + 1]],
@@ -128,6 +138,9 @@ def measure_batched(torch, numag, synth):
                     "dilute per-particle orientational average (spectral matrix), persistent launch + HIP graph",
         "batched_Gterm_s": round(terms / t_batched / 1e9, 2),
         "batched_s": round(t_batched, 4),
+        "batched_hermitian_s": round(t_herm, 4),
+        "batched_hermitian_Gterm_s_effective": round(terms / t_herm / 1e9, 2),
+        "batched_hermitian_max_diff": herm_diff,
         "plain_direct_per_orientation_Gterm_s": round(plain_terms / t_plain / 1e9, 2),
         "plain_direct_sample": "same particles, first 8 rotations, one coherent direct call per (particle, rotation)",
     }

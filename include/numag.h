@@ -68,7 +68,9 @@ extern "C" {
    by S(-q) = conj S(q), which holds because the weights are real: half the
    work, the same sums up to rounding (the mirrored pixel takes the conjugate
    of its partner's sum instead of a sum over its own q, which differs from -q
-   by at most an ulp).  COHERENT mode only. */
+   by at most an ulp).  All modes: in DILUTE / SPLIT the spectral matrices
+   follow G(-q) = conj G(q) and the coherent total A(-q) = conj A(q), for
+   every rotation. */
 #define NUMAG_PATH_DIRECT_HERMITIAN 3
 
 /* ---- object modes (Sec. 3.3, summation relation and dilute limit) -------- */

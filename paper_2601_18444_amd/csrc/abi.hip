@@ -219,7 +219,8 @@ size_t polar_objects_ws(const numag_sample *s, const Detector &d)
 }
 
 int run_objects_polar(const numag_sample *s, const double *rot, int64_t n_rot, const Detector &d, int32_t mode,
-                      int32_t spec_per_object, double *spec_out, double *amp_out, void *ws, hipStream_t st)
+                      int32_t spec_per_object, double *spec_out, double *amp_out, void *ws, hipStream_t st,
+                      bool hermitian)
 {
     const int64_t P = (int64_t)d.n0 * d.n1;
     const int64_t K = s->n_objects;
@@ -231,7 +232,7 @@ int run_objects_polar(const numag_sample *s, const double *rot, int64_t n_rot, c
     int rc = launch_fill(spec_out, n_spec * P * 16, 0.0, st);
     if (rc != NUMAG_OK) return rc;
     if (mode == NUMAG_MODE_SPLIT) {
-        rc = run_direct(s, rot_of(rot, 0), d, amp_out, direct_ws, st);
+        rc = run_direct(s, rot_of(rot, 0), d, amp_out, direct_ws, st, hermitian);
         if (rc != NUMAG_OK) return rc;
     }
     const double scale = 1.0 / (double)n_rot;
@@ -245,7 +246,7 @@ int run_objects_polar(const numag_sample *s, const double *rot, int64_t n_rot, c
             sk.nuc = s->nuc != nullptr ? s->nuc + lo : nullptr;
             sk.mag = s->mag != nullptr ? s->mag + 3 * lo : nullptr;
             sk.n_objects = 1;
-            rc = run_direct(&sk, rot_of(rot, r), d, F, direct_ws, st);
+            rc = run_direct(&sk, rot_of(rot, r), d, F, direct_ws, st, hermitian);
             if (rc != NUMAG_OK) return rc;
             rc = launch_spectral_matrix(1, P, F, spec_out + (spec_per_object ? k : 0) * P * 16, st, scale, 1);
             if (rc != NUMAG_OK) return rc;
@@ -261,8 +262,8 @@ size_t amplitudes_ws(const numag_sample *s, int64_t n_rot, const Detector &d, in
         return align_up(separable_workspace_bytes(*s->regular, d, path, 1));
     if (mode == NUMAG_MODE_COHERENT) return direct_layout(s, d).total;
     if (d.kind == NUMAG_GRID_POLAR) return polar_objects_ws(s, d);
-    return align_up(objects_workspace_bytes(d, s->obj_offsets, s->n_objects, s->n_points, n_rot, mode,
-                                            spec_per_object));
+    return align_up(objects_workspace_bytes(objects_detector(d, path == NUMAG_PATH_DIRECT_HERMITIAN), s->obj_offsets,
+                                            s->n_objects, s->n_points, n_rot, mode, spec_per_object));
 }
 
 }  // namespace
@@ -366,7 +367,6 @@ int numag_amplitudes(const numag_sample *sample, int64_t n_rot, const double *ro
     if (path < NUMAG_PATH_DIRECT || path > NUMAG_PATH_DIRECT_HERMITIAN)
         return invalid("numag_amplitudes: unknown path");
     if (path == NUMAG_PATH_DIRECT_HERMITIAN) {
-        if (mode != NUMAG_MODE_COHERENT) return invalid("numag_amplitudes: the Hermitian path is COHERENT only");
         if (grid->kind == NUMAG_GRID_POLAR && grid->n1 % 2 != 0)
             return invalid("numag_amplitudes: the Hermitian path needs an even n_theta on a polar detector");
     }
@@ -403,11 +403,11 @@ int numag_amplitudes(const numag_sample *sample, int64_t n_rot, const double *ro
     if (mode != NUMAG_MODE_COHERENT && grid->kind == NUMAG_GRID_POLAR) {
         forget_workspace(workspace);
         return run_objects_polar(sample, rot, n_rot, d, mode, spec_per_object ? 1 : 0, spec_out, amp_out, workspace,
-                                 st);
+                                 st, path == NUMAG_PATH_DIRECT_HERMITIAN);
     }
     if (mode != NUMAG_MODE_COHERENT)
         return launch_objects(*sample, rot, n_rot, d, mode, spec_per_object ? 1 : 0, spec_out, amp_out, workspace,
-                              ws_bytes, st);
+                              ws_bytes, st, path == NUMAG_PATH_DIRECT_HERMITIAN);
     forget_workspace(workspace);
     if (path == NUMAG_PATH_SEPARABLE_F64 || path == NUMAG_PATH_SEPARABLE_BF16X3)
         return launch_separable(sample->nuc, sample->mag, *sample->regular, d, path, 1, amp_out, workspace,

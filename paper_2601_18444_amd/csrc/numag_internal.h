@@ -102,9 +102,13 @@ struct ObjectsPlan {
 };
 size_t objects_workspace_bytes(const Detector &d, const int64_t *h_off, int64_t K, int64_t W, int64_t n_rot,
                                int mode, int spec_per_object);
+// Detector whose rows the object kernel sums: all of d, or with `hermitian` the
+// first ceil(n0 / 2) rows of a Cartesian detector (the rest follow by
+// G(-q) = conj G(q)); size the workspace with it.
+Detector objects_detector(const Detector &d, bool hermitian);
 int launch_objects(const numag_sample &s, const double *h_rot, int64_t n_rot, const Detector &d, int mode,
                    int spec_per_object, double *spec_out, double *amp_out, void *ws, size_t ws_bytes,
-                   hipStream_t st);
+                   hipStream_t st, bool hermitian = false);
 // Drops the record of tables uploaded into `ws` (any other use of a workspace
 // overwrites them).
 void forget_workspace(const void *ws);

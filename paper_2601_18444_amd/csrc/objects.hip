@@ -147,9 +147,10 @@ __global__ void fill_i32_kernel(int *p, int n, int v)
     if (i < n) p[i] = v;
 }
 
-// out[s][p][v] = scale * sum of the slots of output s (slot_off CSR, ascending)
+// out[s][p][v] = scale * sum of the slots of output s (slot_off CSR, ascending);
+// slots hold P pixels, out rows are P_out >= P pixels apart (the first P filled)
 __global__ void spec_reduce_kernel(const double *__restrict__ slots, const int *__restrict__ slot_off, int n_out,
-                                   int64_t P, double scale, double *__restrict__ out)
+                                   int64_t P, int64_t P_out, double scale, double *__restrict__ out)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)n_out * P * 16) return;
@@ -157,7 +158,25 @@ __global__ void spec_reduce_kernel(const double *__restrict__ slots, const int *
     const int64_t pv = idx % (P * 16);
     double acc = 0.0;
     for (int sl = slot_off[s]; sl < slot_off[s + 1]; ++sl) acc += slots[(int64_t)sl * P * 16 + pv];
-    out[idx] = scale * acc;
+    out[(int64_t)s * P_out * 16 + pv] = scale * acc;
+}
+
+// Hermitian completion of spectral matrices on a centro-symmetric Cartesian
+// detector: pixel P - 1 - p sits at -q(p), and with real weights
+// G(-q) = conj G(q): the real diagonal is copied, the imaginary parts of the six
+// upper entries (odd v >= 5) change sign.  Pixels [0, Ph) are given.
+__global__ void mirror_spec_kernel(double *__restrict__ out, int n_out, int64_t P, int64_t Ph)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n_out * Ph * 16) return;
+    const int s = (int)(idx / (Ph * 16));
+    const int64_t pv = idx % (Ph * 16);
+    const int64_t p = pv >> 4;
+    const int v = (int)(pv & 15);
+    const int64_t q = P - 1 - p;
+    if (q < Ph) return;
+    double *o = out + (int64_t)s * P * 16;
+    o[q * 16 + v] = (v >= 5 && (v & 1)) ? -o[p * 16 + v] : o[p * 16 + v];
 }
 
 __global__ void amp_reduce_kernel(const double *__restrict__ slots, int n_slots, int64_t P,
@@ -291,12 +310,21 @@ size_t objects_workspace_bytes(const Detector &d, const int64_t *h_off, int64_t 
     return b;
 }
 
-int launch_objects(const numag_sample &s, const double *h_rot, int64_t n_rot, const Detector &d, int mode,
+Detector objects_detector(const Detector &d, bool hermitian)
+{
+    Detector dk = d;
+    if (hermitian) dk.n0 = (d.n0 + 1) / 2;  // rows [0, h): the first h n1 pixels of the outputs
+    return dk;
+}
+
+int launch_objects(const numag_sample &s, const double *h_rot, int64_t n_rot, const Detector &d_full, int mode,
                    int spec_per_object, double *spec_out, double *amp_out, void *ws, size_t ws_bytes,
-                   hipStream_t st)
+                   hipStream_t st, bool hermitian)
 {
     const int64_t K = s.n_objects;
+    const Detector d = objects_detector(d_full, hermitian);  // the rows that are summed
     const int64_t P = (int64_t)d.n0 * d.n1;
+    const int64_t P_full = (int64_t)d_full.n0 * d_full.n1;
     const Tables T = make_tables(d, s.obj_offsets, K, s.n_points, n_rot, mode, spec_per_object);
     const ObjectsPlan &p = T.p;
 
@@ -386,12 +414,18 @@ int launch_objects(const numag_sample &s, const double *h_rot, int64_t n_rot, co
 
     const int64_t n_spec = (int64_t)p.n_out * P * 16;
     hipLaunchKernelGGL(spec_reduce_kernel, dim3((unsigned)((n_spec + 255) / 256)), dim3(256), 0, st, d_spec, d_slot_off,
-                       p.n_out, P, 1.0 / (double)n_rot, spec_out);
+                       p.n_out, P, P_full, 1.0 / (double)n_rot, spec_out);
     NUMAG_HIP_CHECK(hipGetLastError());
     if (d_amp != nullptr) {
         hipLaunchKernelGGL(amp_reduce_kernel, dim3((unsigned)((P * 8 + 255) / 256)), dim3(256), 0, st, d_amp,
                            p.n_slots, P, amp_out);
         NUMAG_HIP_CHECK(hipGetLastError());
+    }
+    if (hermitian) {
+        hipLaunchKernelGGL(mirror_spec_kernel, dim3((unsigned)((n_spec + 255) / 256)), dim3(256), 0, st, spec_out,
+                           p.n_out, P_full, P);
+        NUMAG_HIP_CHECK(hipGetLastError());
+        if (amp_out != nullptr && d_amp != nullptr) return launch_mirror_cartesian(amp_out, P_full, P, st);
     }
     return NUMAG_OK;
 }

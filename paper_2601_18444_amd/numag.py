@@ -282,16 +282,18 @@ class BatchedOrientations:
 
     The graph reads the sample's device arrays at replay time, so weights may
     be updated in place between replays; rotations and object offsets are fixed
-    at construction.  The dedicated workspace must not be shared."""
+    at construction.  The dedicated workspace must not be shared.
+    path=PATH_DIRECT_HERMITIAN sums half of a centro-symmetric detector and
+    completes the spectral matrices by G(-q) = conj G(q)."""
 
-    def __init__(self, sample: Sample, grid: QGrid, rotations, spec_per_object: bool = True):
-        self.sample, self.grid = sample, grid
+    def __init__(self, sample: Sample, grid: QGrid, rotations, spec_per_object: bool = True, path: int = PATH_DIRECT):
+        self.sample, self.grid, self.path = sample, grid, path
         self.rot = np.ascontiguousarray(np.asarray(rotations, dtype=np.float64).reshape(-1, 9))
         self.spec_per_object = spec_per_object
         dev = sample.device
         n_spec = sample.n_objects if spec_per_object else 1
         self.spec = torch.empty((n_spec, grid.n_pixels, 16), dtype=torch.float64, device=dev)
-        nws = workspace_size(sample, grid, self.rot.shape[0], PATH_DIRECT, MODE_DILUTE)
+        nws = workspace_size(sample, grid, self.rot.shape[0], path, MODE_DILUTE)
         self.ws = torch.empty(max(nws, 256), dtype=torch.uint8, device=dev)
         self._call()  # uploads the work tables into the dedicated workspace
         torch.cuda.synchronize()
@@ -300,8 +302,8 @@ class BatchedOrientations:
             self._call()
 
     def _call(self):
-        amplitudes(self.sample, self.grid, rot=self.rot, mode=MODE_DILUTE, spec_per_object=self.spec_per_object,
-                   spec_out=self.spec, ws=self.ws)
+        amplitudes(self.sample, self.grid, rot=self.rot, path=self.path, mode=MODE_DILUTE,
+                   spec_per_object=self.spec_per_object, spec_out=self.spec, ws=self.ws)
 
     def eager(self) -> torch.Tensor:
         self._call()

@@ -169,11 +169,18 @@ def test_hermitian_path_validates():
     H = numag.PATH_DIRECT_HERMITIAN
     assert _call_amp(s, pol_odd, path=H, ws=0x3000, nws=1 << 30) == numag.E_INVALID
     assert "even n_theta" in numag.last_error()
-    grid = numag.qgrid(0, 8, 8, 1.0)
-    assert _call_amp(s, grid, path=H, mode=numag.MODE_DILUTE, amp=None, spec=0x4000, ws=0x3000,
+    # object modes take the Hermitian path too, with the same even-n_theta rule
+    assert _call_amp(s, pol_odd, path=H, mode=numag.MODE_DILUTE, amp=None, spec=0x4000, ws=0x3000,
                      nws=1 << 30) == numag.E_INVALID
+    assert "even n_theta" in numag.last_error()
+    grid = numag.qgrid(0, 8, 8, 1.0)
     assert _call_amp(s, grid, path=4, ws=0x3000, nws=1 << 30) == numag.E_INVALID
     assert numag._lib.numag_workspace_size(ctypes.byref(s), 1, ctypes.byref(grid), H, 0) > 0
+    # the object workspace of the Hermitian path holds slots for half of the rows
+    big = numag.qgrid(0, 64, 64, 1.0)
+    full = numag._lib.numag_workspace_size(ctypes.byref(s), 3, ctypes.byref(big), numag.PATH_DIRECT, numag.MODE_DILUTE)
+    half = numag._lib.numag_workspace_size(ctypes.byref(s), 3, ctypes.byref(big), H, numag.MODE_DILUTE)
+    assert 0 < half < full
 
 
 def test_binding_refuses_to_import_without_the_library(tmp_path):

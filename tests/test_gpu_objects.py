@@ -245,3 +245,58 @@ def test_object_modes_on_polar_detector(orc, mode):
         for c in range(4):
             assert gated_rel_err(gpu[:, c], A[:, c]) <= TOL, c
         _check_spec(spec[0].cpu().numpy(), orc.spectral(F))
+
+
+@pytest.mark.parametrize("kind,n0,n1,mode", [(0, 33, 40, "dilute"), (0, 32, 41, "split"), (1, 17, 36, "dilute"),
+                                             (1, 16, 24, "split")])
+def test_hermitian_object_modes(orc, kind, n0, n1, mode):
+    """The half-detector path in the object modes: rows [0, ceil(n0/2)) of a
+    Cartesian detector (theta in [0, pi) of a polar one) are summed and the rest
+    follows from G(-q) = conj G(q) and, in split mode, A(-q) = conj A(q) (real
+    weights, also after rotation).  Checked against the oracle at every pixel and
+    against the full path, which it must equal up to rounding (a mirrored pixel
+    takes its partner's conjugate, at -q within an ulp).  With an empty object
+    and, for the dilute Cartesian case, the batched graph replay."""
+    cfg = _objects(50, [70, 0, 25, 120], spread=12.0)
+    qmax = 1.1
+    grid = numag.qgrid(kind, n0, n1, qmax)
+    qy, qz, qhat = orc.pixels(kind, n0, n1, qmax)
+    off = cfg["obj_offsets"]
+    H = numag.PATH_DIRECT_HERMITIAN
+    if mode == "dilute":
+        rots = synth.uniform_rotations(3, np.random.default_rng(51))
+        _, spec = numag.amplitudes(_sample(cfg), grid, rot=rots, path=H, mode=numag.MODE_DILUTE,
+                                   spec_per_object=True)
+        _, full = numag.amplitudes(_sample(cfg), grid, rot=rots, mode=numag.MODE_DILUTE, spec_per_object=True)
+        spec, full = spec.cpu().numpy(), full.cpu().numpy()
+        for k in range(4):
+            sl = slice(off[k], off[k + 1])
+            if off[k + 1] == off[k]:
+                assert np.count_nonzero(spec[k]) == 0
+                continue
+            Fs = [orc.amplitudes(cfg["pos"][sl], cfg["nuc"][sl], cfg["mag"][sl], qy, qz, R=R) for R in rots]
+            _check_spec(spec[k], orc.spectral(np.stack(Fs)) / len(rots))
+            assert max_norm_err(spec[k], full[k]) <= 1e-11, k
+        if kind == 0:
+            b = numag.BatchedOrientations(_sample(cfg), grid, rots, spec_per_object=True, path=H)
+            ref = b.eager().clone()
+            torch.cuda.synchronize()
+            assert max_norm_err(ref.cpu().numpy(), spec) <= 1e-14
+            for _ in range(2):
+                out = b.replay()
+                torch.cuda.synchronize()
+                assert torch.equal(out, ref)
+                _ = torch.ones(1000, device=DEV).sum().item()  # eager work between replays
+    else:
+        R = synth.sample_rotation(20.0, 50.0)
+        amp, spec = numag.amplitudes(_sample(cfg), grid, rot=R, path=H, mode=numag.MODE_SPLIT)
+        ampf, specf = numag.amplitudes(_sample(cfg), grid, rot=R, mode=numag.MODE_SPLIT)
+        A = orc.amplitudes(cfg["pos"], cfg["nuc"], cfg["mag"], qy, qz, R=R, obj_offsets=off, obj_pos=cfg["obj_pos"])
+        F = orc.amplitudes(cfg["pos"], cfg["nuc"], cfg["mag"], qy, qz, R=R, obj_offsets=off, obj_pos=cfg["obj_pos"],
+                           per_object=True)
+        gpu = amp_to_complex(amp[0])
+        for c in range(4):
+            assert gated_rel_err(gpu[:, c], A[:, c]) <= TOL, c
+        _check_spec(spec[0].cpu().numpy(), orc.spectral(F))
+        assert max_norm_err(amp.cpu().numpy(), ampf.cpu().numpy()) <= 1e-11
+        assert max_norm_err(spec.cpu().numpy(), specf.cpu().numpy()) <= 1e-11
