@@ -376,7 +376,7 @@ def main():
         t_bf16 = avg_ms(pairs)
 
     # the Hermitian half-detector form of the direct sum, timed outside the step
-    t_herm = herm_err = None
+    t_herm = herm_err = t_adj_herm = adj_herm_err = None
     if not args.no_hermitian:
         amp_h = torch.empty_like(amp)
         numag.amplitudes(sample, grid, path=numag.PATH_DIRECT_HERMITIAN, out=amp_h)
@@ -390,6 +390,20 @@ def main():
         torch.cuda.synchronize()
         t_herm = avg_ms(pairs)
         herm_err = float((amp_h - amp).abs().max() / amp.abs().max())
+        # and of the gradient: the adjoint over half of the detector with folded residual weights
+        _, fdn, fdm = numag.grad(sample, grid, k, weight=w, target=T, amp=amp[0])
+        _, hdn, hdm = numag.grad(sample, grid, k, weight=w, target=T, amp=amp[0], path=numag.PATH_DIRECT_HERMITIAN)
+        pairs = []
+        for _ in range(10):
+            a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a0.record()
+            numag.grad(sample, grid, k, weight=w, target=T, amp=amp[0], path=numag.PATH_DIRECT_HERMITIAN)
+            a1.record()
+            pairs.append((a0, a1))
+        torch.cuda.synchronize()
+        t_adj_herm = avg_ms(pairs)
+        adj_herm_err = max(float((hdn - fdn).abs().max() / fdn.abs().max()),
+                           float((hdm - fdm).abs().max() / fdm.abs().max()))
 
     t_direct = avg_ms(ev["direct"])
     t_adj = avg_ms(ev["adjoint"])
@@ -431,6 +445,9 @@ def main():
             "adjoint_Gterm_s": round(terms / (t_adj * 1e-3) / 1e9, 2),
             "adjoint_ms": round(t_adj, 4),
             "adjoint_kernel_ms": round(kernel_ms["adjoint_cartesian_kernel"], 4),
+            "adjoint_hermitian_ms": round(t_adj_herm, 4) if t_adj_herm else None,
+            "adjoint_hermitian_Gterm_s_effective": round(terms / (t_adj_herm * 1e-3) / 1e9, 2) if t_adj_herm else None,
+            "adjoint_hermitian_max_diff_vs_adjoint": adj_herm_err,
             "separable_f64_Gterm_s_effective": round(terms / (t_sep * 1e-3) / 1e9, 2) if have_sep else None,
             "separable_ms": round(t_sep, 4) if have_sep else None,
             "separable_bf16x3_Gterm_s_effective": round(terms / (t_bf16 * 1e-3) / 1e9, 2) if t_bf16 else None,

@@ -160,7 +160,7 @@ size_t numag_workspace_size(const numag_sample *sample, int64_t n_rot, const num
  *             rotations), else 1 (summed over objects).  NULL in COHERENT mode.
  *   path      NUMAG_PATH_*; the separable paths need sample->regular, rot NULL,
  *             K = 1, a Cartesian detector and COHERENT mode; the Hermitian
- *             path needs COHERENT mode.
+ *             path needs an even n_theta on a polar detector.
  *   mode      DILUTE and SPLIT need explicit positions (NUMAG_E_UNSUPPORTED for
  *             a regular-grid sample); SPLIT takes one rotation.  Both run on
  *             either detector kind (Cartesian: one persistent launch over
@@ -261,11 +261,24 @@ int numag_correlation(const double *q, const double *I, int32_t n_q, int32_t n_f
  *   target NULL: `weight` holds an upstream gradient dL/dI_p instead (the
  *             backward of an autograd function) and loss_out may be NULL;
  *   dnuc_out  [W] or NULL;  dmag_out [W][3] or NULL.
+ *   workspace of at least numag_workspace_size(sample, 1, grid, path,
+ *             NUMAG_MODE_COHERENT) bytes.
+ * numag_grad is numag_grad_path with NUMAG_PATH_DIRECT.  With
+ * NUMAG_PATH_DIRECT_HERMITIAN (a polar detector needs an even n_theta) the
+ * sums (when amp_in is NULL) and the adjoint run on half of the detector: the
+ * residual weight of each pixel's mirror p' (at -q within an ulp) is folded
+ * onto it as a(p) + conj a(p'), since Re[a(p') exp(+i q.X)] =
+ * Re[conj a(p') exp(-i q.X)]; this holds for any target and loss weights.  The
+ * loss is evaluated over the whole detector.
  */
 int numag_grad(const numag_sample *sample, const double *rot, const numag_qgrid *grid,
                const numag_consts *consts, const double *amp_in, const double *target,
                const double *weight, double *loss_out, double *dnuc_out, double *dmag_out,
                void *workspace, size_t ws_bytes, void *stream);
+int numag_grad_path(const numag_sample *sample, const double *rot, const numag_qgrid *grid, int32_t path,
+                    const numag_consts *consts, const double *amp_in, const double *target,
+                    const double *weight, double *loss_out, double *dnuc_out, double *dmag_out,
+                    void *workspace, size_t ws_bytes, void *stream);
 
 /*
  * Two-dimensional correlation function, eq. crav2d,

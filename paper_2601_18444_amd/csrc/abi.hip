@@ -345,7 +345,7 @@ size_t numag_workspace_size(const numag_sample *sample, int64_t n_rot, const num
     // object modes: enough for both spectral layouts (per object or summed)
     size_t amp = std::max(amplitudes_ws(sample, n_rot, d, path, mode, 0), amplitudes_ws(sample, n_rot, d, path, mode, 1));
     size_t grad = 0;
-    if (path == NUMAG_PATH_DIRECT && mode == NUMAG_MODE_COHERENT && grid->kind == NUMAG_GRID_CARTESIAN) {
+    if ((path == NUMAG_PATH_DIRECT || path == NUMAG_PATH_DIRECT_HERMITIAN) && mode == NUMAG_MODE_COHERENT) {
         // numag_grad: points + amplitudes (when not given) + direct partials + adjoint scratch
         const int64_t P = (int64_t)grid->n0 * grid->n1;
         grad = direct_layout(sample, d).total + align_up((size_t)P * 8 * sizeof(double)) +
@@ -537,8 +537,20 @@ int numag_grad(const numag_sample *sample, const double *rot, const numag_qgrid 
                double *loss_out, double *dnuc_out, double *dmag_out, void *workspace, size_t ws_bytes,
                void *stream)
 {
+    return numag_grad_path(sample, rot, grid, NUMAG_PATH_DIRECT, consts, amp_in, target, weight, loss_out, dnuc_out,
+                           dmag_out, workspace, ws_bytes, stream);
+}
+
+int numag_grad_path(const numag_sample *sample, const double *rot, const numag_qgrid *grid, int32_t path,
+                    const numag_consts *consts, const double *amp_in, const double *target, const double *weight,
+                    double *loss_out, double *dnuc_out, double *dmag_out, void *workspace, size_t ws_bytes,
+                    void *stream)
+{
     clear_error();
     int rc;
+    if (path != NUMAG_PATH_DIRECT && path != NUMAG_PATH_DIRECT_HERMITIAN)
+        return invalid("numag_grad: path must be NUMAG_PATH_DIRECT or NUMAG_PATH_DIRECT_HERMITIAN");
+    const bool hermitian = path == NUMAG_PATH_DIRECT_HERMITIAN;
     if ((rc = check_sample(sample, "numag_grad")) != NUMAG_OK) return rc;
     if ((rc = check_grid(grid, "numag_grad")) != NUMAG_OK) return rc;
     if ((rc = check_rotations(rot, 1, "numag_grad")) != NUMAG_OK) return rc;
@@ -546,6 +558,8 @@ int numag_grad(const numag_sample *sample, const double *rot, const numag_qgrid 
     if (weight == nullptr) return invalid("numag_grad: weight is required");
     if (target != nullptr && loss_out == nullptr)
         return invalid("numag_grad: loss_out is required when a target is given");
+    if (hermitian && grid->kind == NUMAG_GRID_POLAR && grid->n1 % 2 != 0)
+        return invalid("numag_grad: the Hermitian path needs an even n_theta on a polar detector");
     Detector d = make_detector(*grid);
     const int64_t P = (int64_t)grid->n0 * grid->n1;
     DirectLayout L = direct_layout(sample, d);
@@ -563,7 +577,7 @@ int numag_grad(const numag_sample *sample, const double *rot, const numag_qgrid 
     void *gws = cv.take(grad_workspace_bytes(d, sample->n_points));
     const Rot R = rot_of(rot, 0);
     if (amp_in == nullptr) {
-        rc = run_direct(sample, R, d, amp, direct_ws, st);
+        rc = run_direct(sample, R, d, amp, direct_ws, st, hermitian);
         if (rc != NUMAG_OK) return rc;
         amp_in = amp;
     } else {
@@ -582,7 +596,7 @@ int numag_grad(const numag_sample *sample, const double *rot, const numag_qgrid 
     }
     const PointRec *pts = (const PointRec *)(direct_ws + L.offsets);
     return launch_grad(pts, sample->n_points, d, *consts, amp_in, target, weight, loss_out, dnuc_out, dmag_out,
-                       R, gws, grad_workspace_bytes(d, sample->n_points), st);
+                       R, gws, grad_workspace_bytes(d, sample->n_points), st, hermitian);
 }
 
 }  // extern "C"

@@ -395,13 +395,41 @@ size_t grad_workspace_bytes(const Detector &d, int64_t W)
     return b + 3 * 256;
 }
 
-int launch_grad(const PointRec *pts, int64_t W, const Detector &d, const numag_consts &c,
-                const double *amp, const double *target, const double *weight, double *loss,
-                double *dnuc, double *dmag, const Rot &R, void *ws, size_t ws_bytes, hipStream_t s)
+// Residual weights folded onto half of a detector that is symmetric about q = 0:
+// the term of the mirror pixel p' (at -q_p within an ulp) is
+// Re[a(p') exp(+i q_p X)] = Re[conj a(p') exp(-i q_p X)], so the adjoint over the
+// half with a(p) + conj a(p') equals the full one, whatever the target and the
+// loss weights.  Cartesian: p' = P - 1 - p for p < Ph (pixels whose mirror lies
+// in the half, the middle row of an odd n0, keep their own weight); polar
+// (column-major [theta][q], even n_theta): p' = p + Ph.
+__global__ void fold_residual_kernel(double *__restrict__ a, int64_t P, int64_t Ph, int polar)
 {
-    const int64_t P = (int64_t)d.n0 * d.n1;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= Ph * 8) return;
+    const int64_t p = idx >> 3;
+    const int v = (int)(idx & 7);
+    const int64_t q = polar ? p + Ph : P - 1 - p;
+    if (q < Ph) return;
+    a[idx] += (v & 1) ? -a[q * 8 + v] : a[q * 8 + v];
+}
+
+int launch_grad(const PointRec *pts, int64_t W, const Detector &d_full, const numag_consts &c,
+                const double *amp, const double *target, const double *weight, double *loss,
+                double *dnuc, double *dmag, const Rot &R, void *ws, size_t ws_bytes, hipStream_t s,
+                bool hermitian)
+{
+    const Detector &dr = d_full;  // the residual and the loss cover the whole detector
+    const int64_t P = (int64_t)dr.n0 * dr.n1;
     const int64_t nres = (P + kResThreads - 1) / kResThreads;
-    const int splits = adjoint_row_splits(d, W);
+    // the adjoint sums the whole detector, or half of it with folded weights
+    Detector d = d_full;
+    if (hermitian) {
+        if (d.kind == NUMAG_GRID_CARTESIAN)
+            d.n0 = (d.n0 + 1) / 2;
+        else
+            d.n1 = d.n1 / 2;  // theta_m, m < n_theta / 2 (d.n_theta unchanged)
+    }
+    const int splits = adjoint_row_splits(d, W);  // at most those of the whole detector
     char *base = (char *)ws;
     auto take = [&](size_t bytes) {
         char *r = base;
@@ -415,7 +443,7 @@ int launch_grad(const PointRec *pts, int64_t W, const Detector &d, const numag_c
         set_error("numag_grad: workspace too small");
         return NUMAG_E_WORKSPACE;
     }
-    hipLaunchKernelGGL(residual_kernel, dim3((unsigned)nres), dim3(kResThreads), 0, s, d, c, amp, target,
+    hipLaunchKernelGGL(residual_kernel, dim3((unsigned)nres), dim3(kResThreads), 0, s, dr, c, amp, target,
                        weight, a, lpart);
     NUMAG_HIP_CHECK(hipGetLastError());
     if (loss != nullptr) {
@@ -423,6 +451,12 @@ int launch_grad(const PointRec *pts, int64_t W, const Detector &d, const numag_c
         NUMAG_HIP_CHECK(hipGetLastError());
     }
     if (W <= 0) return NUMAG_OK;
+    if (hermitian) {
+        const int64_t Ph = (int64_t)d.n0 * d.n1;
+        hipLaunchKernelGGL(fold_residual_kernel, dim3((unsigned)((Ph * 8 + 255) / 256)), dim3(256), 0, s, a, P, Ph,
+                           d.kind == NUMAG_GRID_POLAR ? 1 : 0);
+        NUMAG_HIP_CHECK(hipGetLastError());
+    }
     const int extent = d.kind == NUMAG_GRID_CARTESIAN ? d.n0 : d.n1;
     const int per = (extent + splits - 1) / splits;
     const int nsplit = (extent + per - 1) / per;

@@ -128,10 +128,12 @@ int launch_azimuthal(const Detector &d, const double *f, int n_f, int n_bins, do
 int launch_correlation(const double *q, const double *I, int n_q, int n_f, const double *r, int n_r,
                        double scale, double *c, double *p, hipStream_t s);
 
-// residual weights, loss, adjoint sum.
+// residual weights, loss, adjoint sum (hermitian: over half of a detector that
+// is symmetric about q = 0, with the residual weights folded onto it).
 int launch_grad(const PointRec *pts, int64_t W, const Detector &d, const numag_consts &c,
                 const double *amp, const double *target, const double *weight, double *loss,
-                double *dnuc, double *dmag, const Rot &R, void *ws, size_t ws_bytes, hipStream_t s);
+                double *dnuc, double *dmag, const Rot &R, void *ws, size_t ws_bytes, hipStream_t s,
+                bool hermitian = false);
 size_t grad_workspace_bytes(const Detector &d, int64_t W);
 
 // 2D correlation function (eq. crav2d) from data on detector d onto real-space grid rd.

@@ -69,6 +69,7 @@ def _load():
         "numag_azimuthal_average": (ctypes.c_int, [P, P, i32, i32, d, P, P, P]),
         "numag_correlation": (ctypes.c_int, [P, P, i32, i32, P, i32, d, P, P, P]),
         "numag_grad": (ctypes.c_int, [P, P, P, P, P, P, P, P, P, P, P, sz, P]),
+        "numag_grad_path": (ctypes.c_int, [P, P, P, i32, P, P, P, P, P, P, P, P, sz, P]),
         "numag_correlation_2d_workspace_size": (sz, [P, P]),
         "numag_correlation_2d": (ctypes.c_int, [P, P, i32, P, P, P, sz, P]),
         "numag_angular_spectrum": (ctypes.c_int, [P, P, i32, i32, P, P, P, P, P]),
@@ -415,8 +416,9 @@ def angular_spectrum(grid: QGrid, f: torch.Tensor, k_max: int, amplitudes: bool 
 
 
 def grad(sample: Sample, grid: QGrid, c: Consts, weight: torch.Tensor, target: Optional[torch.Tensor] = None,
-         rot=None, amp: Optional[torch.Tensor] = None, want_nuc=True, want_mag=True):
-    """numag_grad.  Returns (loss [1] or None, dnuc [W] or None, dmag [W, 3] or None)."""
+         rot=None, amp: Optional[torch.Tensor] = None, want_nuc=True, want_mag=True, path=PATH_DIRECT):
+    """numag_grad_path.  Returns (loss [1] or None, dnuc [W] or None, dmag [W, 3] or None).
+    path=PATH_DIRECT_HERMITIAN runs the sums and the adjoint on half of the detector."""
     r, n_rot = _rot_array(rot)
     if n_rot != 1:
         raise ValueError("grad takes one rotation")
@@ -425,12 +427,12 @@ def grad(sample: Sample, grid: QGrid, c: Consts, weight: torch.Tensor, target: O
     loss = torch.empty(1, dtype=torch.float64, device=dev) if target is not None else None
     dn = torch.empty(W, dtype=torch.float64, device=dev) if want_nuc else None
     dm = torch.empty((W, 3), dtype=torch.float64, device=dev) if want_mag else None
-    nws = workspace_size(sample, grid, 1, PATH_DIRECT, MODE_COHERENT)
+    nws = workspace_size(sample, grid, 1, path, MODE_COHERENT)
     ws = workspace(nws, dev)
-    rc = _lib.numag_grad(sample.c, r.ctypes.data_as(ctypes.c_void_p) if r is not None else None,
-                         ctypes.byref(grid), ctypes.byref(c), _ptr(amp), _ptr(target), _ptr(weight), _ptr(loss),
-                         _ptr(dn), _ptr(dm), _ptr(ws), ws.numel(), _stream())
-    _check("numag_grad", rc)
+    rc = _lib.numag_grad_path(sample.c, r.ctypes.data_as(ctypes.c_void_p) if r is not None else None,
+                              ctypes.byref(grid), int(path), ctypes.byref(c), _ptr(amp), _ptr(target), _ptr(weight),
+                              _ptr(loss), _ptr(dn), _ptr(dm), _ptr(ws), ws.numel(), _stream())
+    _check("numag_grad_path", rc)
     return loss, dn, dm
 
 

@@ -365,7 +365,10 @@ def test_hermitian_path_matches_direct(orc, kind, n0, n1):
 def test_gradient_polar_vs_oracle(orc, nq, nt):
     """Loss and gradient on the polar detector (the adjoint walks the q rows of each
     theta column with the recurrence, restarted every 128 rows: 300 rows cross two
-    restarts), with a rotation, against the oracle's chain-rule gradient."""
+    restarts), with a rotation, against the oracle's chain-rule gradient.  The
+    workspace cache is emptied first, so the call runs on exactly the size that
+    numag_workspace_size reports for this detector."""
+    numag._ws_cache.clear()
     rng = np.random.default_rng(36)
     W = 600
     cl = {"pos": rng.uniform(-6, 6, (W, 3)), "nuc": rng.standard_normal(W), "mag": rng.standard_normal((W, 3))}
@@ -427,3 +430,37 @@ def test_fp64_level_accuracy_c1_and_vortex_sample(orc):
         zq = zero_q_mask(qy[idx], qz[idx])
         for i, name in enumerate(numag.OBSERVABLES):
             assert gated_rel_err(xs[i], oref[name], zq) <= 1e-9, name
+
+
+@pytest.mark.parametrize("kind,n0,n1,amp_given", [(0, 25, 40, False), (0, 24, 33, True), (1, 30, 40, False),
+                                                  (1, 140, 12, True)])
+def test_gradient_hermitian_path(orc, kind, n0, n1, amp_given):
+    """numag_grad_path on half of the detector with folded residual weights
+    a(p) + conj a(p'): an asymmetric target and asymmetric loss weights (the
+    fold needs no symmetry of the residual), odd and even Cartesian row counts
+    (the middle row of an odd n0 keeps its own weights), polar with even n_theta
+    (140 q rows cross a recurrence restart), sums computed inside or given.
+    Against the oracle and against the full path."""
+    numag._ws_cache.clear()
+    rng = np.random.default_rng(61)
+    W = 500
+    cl = {"pos": rng.uniform(-6, 6, (W, 3)), "nuc": rng.standard_normal(W), "mag": rng.standard_normal((W, 3))}
+    R = synth.sample_rotation(35, -70)
+    qmax = 1.2
+    grid = numag.qgrid(kind, n0, n1, qmax)
+    qy, qz, qhat = orc.pixels(kind, n0, n1, qmax)
+    T = rng.uniform(0, 50, qy.size)
+    w = rng.uniform(0.5, 1.5, qy.size)
+    k = dict(V=2.0, bH=0.8, scale=1.3)
+    L, dn, dm = orc.loss_grad(cl["pos"], cl["nuc"], cl["mag"], qy, qz, qhat, T, w, R=R, **k)
+    s = _sample(cl)
+    amp = numag.amplitudes(s, grid, rot=R)[0][0] if amp_given else None
+    args = dict(weight=torch.as_tensor(w, device=DEV), target=torch.as_tensor(T, device=DEV), rot=R, amp=amp)
+    loss, gdn, gdm = numag.grad(s, grid, numag.consts(**k), path=numag.PATH_DIRECT_HERMITIAN, **args)
+    lf, fdn, fdm = numag.grad(s, grid, numag.consts(**k), **args)
+    assert abs(loss.item() - L) <= 1e-9 * abs(L)
+    assert max_norm_err(gdn.cpu().numpy(), dn) <= 1e-9
+    assert max_norm_err(gdm.cpu().numpy(), dm) <= 1e-9
+    assert abs(loss.item() - lf.item()) <= 1e-12 * abs(lf.item())
+    assert max_norm_err(gdn.cpu().numpy(), fdn.cpu().numpy()) <= 1e-11
+    assert max_norm_err(gdm.cpu().numpy(), fdm.cpu().numpy()) <= 1e-11
