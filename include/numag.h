@@ -144,6 +144,13 @@ size_t numag_workspace_size(const numag_sample *sample, int64_t n_rot, const num
                             int32_t path, int32_t mode);
 
 /*
+ * Drops the library's record of planning tables held in `workspace` (see
+ * numag_amplitudes, object modes).  Call it before freeing a workspace that an
+ * object-mode call used.  Host-only; NULL or an unknown address is a no-op.
+ */
+void numag_release_workspace(const void *workspace);
+
+/*
  * Direct Fourier sums, Sec. 3.3 (DSFT and its cos/sin split), per object mode
  * (Sec. 3.3 summation relation and dilute approximation), for n_rot sample
  * rotations (Sec. 3.1; any R in SO(3)).
@@ -171,7 +178,10 @@ size_t numag_workspace_size(const numag_sample *sample, int64_t n_rot, const num
  *             of the workspace and a later call on the same workspace with the
  *             same tables skips their upload (so it enqueues only kernels and can
  *             be captured into a graph): the caller must not write to the
- *             workspace between such calls (any numag call on it is fine).
+ *             workspace between such calls (any numag call on it is fine), and
+ *             must call numag_release_workspace() on it before freeing that memory
+ *             (the record is kept by address; a new buffer at the same address
+ *             would otherwise be taken to hold the tables).
  * Empty samples (W = 0) are valid and give zeros.
  */
 int numag_amplitudes(const numag_sample *sample, int64_t n_rot, const double *rot,

@@ -354,6 +354,11 @@ size_t numag_workspace_size(const numag_sample *sample, int64_t n_rot, const num
     return std::max(amp, grad);
 }
 
+void numag_release_workspace(const void *workspace)
+{
+    if (workspace != nullptr) forget_workspace(workspace);
+}
+
 int numag_amplitudes(const numag_sample *sample, int64_t n_rot, const double *rot, const numag_qgrid *grid,
                      int32_t path, int32_t mode, int32_t spec_per_object, double *amp_out, double *spec_out,
                      void *workspace, size_t ws_bytes, void *stream)

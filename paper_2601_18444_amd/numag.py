@@ -70,6 +70,7 @@ def _load():
         "numag_correlation": (ctypes.c_int, [P, P, i32, i32, P, i32, d, P, P, P]),
         "numag_grad": (ctypes.c_int, [P, P, P, P, P, P, P, P, P, P, P, sz, P]),
         "numag_grad_path": (ctypes.c_int, [P, P, P, i32, P, P, P, P, P, P, P, P, sz, P]),
+        "numag_release_workspace": (None, [P]),
         "numag_correlation_2d_workspace_size": (sz, [P, P]),
         "numag_correlation_2d": (ctypes.c_int, [P, P, i32, P, P, P, sz, P]),
         "numag_angular_spectrum": (ctypes.c_int, [P, P, i32, i32, P, P, P, P, P]),
@@ -149,9 +150,24 @@ def workspace(nbytes: int, device) -> torch.Tensor:
     key = str(torch.device(device))
     buf = _ws_cache.get(key)
     if buf is None or buf.numel() < nbytes:
+        if buf is not None:
+            release_workspace(buf)  # its memory may be reused by anything from here on
         buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
         _ws_cache[key] = buf
     return buf
+
+
+def clear_workspace_cache() -> None:
+    """Release and drop the cached workspaces (the next call allocates exactly what it needs)."""
+    for buf in _ws_cache.values():
+        release_workspace(buf)
+    _ws_cache.clear()
+
+
+def release_workspace(ws: torch.Tensor) -> None:
+    """numag_release_workspace: forget planning tables kept in `ws` before it is freed."""
+    if ws is not None and _lib is not None:
+        _lib.numag_release_workspace(_ptr(ws))
 
 
 def qgrid(kind: int, n0: int, n1: int, qmax: float) -> QGrid:
@@ -309,6 +325,12 @@ class BatchedOrientations:
     def eager(self) -> torch.Tensor:
         self._call()
         return self.spec
+
+    def __del__(self):
+        try:
+            release_workspace(getattr(self, "ws", None))
+        except Exception:  # interpreter shutdown: the library may be gone already
+            pass
 
     def replay(self) -> torch.Tensor:
         self.graph.replay()

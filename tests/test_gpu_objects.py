@@ -300,3 +300,27 @@ def test_hermitian_object_modes(orc, kind, n0, n1, mode):
         _check_spec(spec[0].cpu().numpy(), orc.spectral(F))
         assert max_norm_err(amp.cpu().numpy(), ampf.cpu().numpy()) <= 1e-11
         assert max_norm_err(spec.cpu().numpy(), specf.cpu().numpy()) <= 1e-11
+
+
+def test_released_workspace_tables_are_uploaded_again():
+    """The planning tables of the object modes are kept in the workspace and a
+    repeated call skips their upload; numag_release_workspace drops that record.
+    After a release the memory is overwritten (zeros stand in for other data and
+    keep every table index in bounds) and the same call must upload the tables
+    again and give the same result bit for bit."""
+    cfg = _objects(52, [40, 90, 15], spread=0.0)
+    rots = synth.uniform_rotations(4, np.random.default_rng(53))
+    grid = numag.qgrid(0, 20, 28, 1.0)
+    s = _sample(cfg)
+    nws = numag.workspace_size(s, grid, len(rots), numag.PATH_DIRECT, numag.MODE_DILUTE)
+    ws = torch.empty(nws, dtype=torch.uint8, device=DEV)
+    _, a = numag.amplitudes(s, grid, rot=rots, mode=numag.MODE_DILUTE, spec_per_object=True, ws=ws)
+    ref = a.clone()
+    _, a2 = numag.amplitudes(s, grid, rot=rots, mode=numag.MODE_DILUTE, spec_per_object=True, ws=ws)
+    assert torch.equal(a2, ref)  # tables reused
+    numag.release_workspace(ws)
+    ws.zero_()
+    _, b = numag.amplitudes(s, grid, rot=rots, mode=numag.MODE_DILUTE, spec_per_object=True, ws=ws)
+    torch.cuda.synchronize()
+    assert torch.equal(b, ref)
+    assert float(ref.abs().max()) > 0.0

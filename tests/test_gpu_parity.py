@@ -368,7 +368,7 @@ def test_gradient_polar_vs_oracle(orc, nq, nt):
     restarts), with a rotation, against the oracle's chain-rule gradient.  The
     workspace cache is emptied first, so the call runs on exactly the size that
     numag_workspace_size reports for this detector."""
-    numag._ws_cache.clear()
+    numag.clear_workspace_cache()
     rng = np.random.default_rng(36)
     W = 600
     cl = {"pos": rng.uniform(-6, 6, (W, 3)), "nuc": rng.standard_normal(W), "mag": rng.standard_normal((W, 3))}
@@ -441,7 +441,7 @@ def test_gradient_hermitian_path(orc, kind, n0, n1, amp_given):
     (the middle row of an odd n0 keeps its own weights), polar with even n_theta
     (140 q rows cross a recurrence restart), sums computed inside or given.
     Against the oracle and against the full path."""
-    numag._ws_cache.clear()
+    numag.clear_workspace_cache()
     rng = np.random.default_rng(61)
     W = 500
     cl = {"pos": rng.uniform(-6, 6, (W, 3)), "nuc": rng.standard_normal(W), "mag": rng.standard_normal((W, 3))}
