@@ -460,14 +460,16 @@ def grad(sample: Sample, grid: QGrid, c: Consts, weight: torch.Tensor, target: O
 
 class UnpolarizedCrossSection(torch.autograd.Function):
     """Unpolarized 2D cross section (Sec. 2.4) as a differentiable function of
-    the nuclear and magnetic weights; backward is the adjoint Fourier sum."""
+    the nuclear and magnetic weights; backward is the adjoint Fourier sum.
+    path=PATH_DIRECT_HERMITIAN runs the sums and the adjoint on half of a
+    symmetric detector."""
 
     @staticmethod
-    def forward(ctx, nuc, mag, sample: Sample, grid: QGrid, c: Consts, rot=None):
+    def forward(ctx, nuc, mag, sample: Sample, grid: QGrid, c: Consts, rot=None, path=PATH_DIRECT):
         s = sample.with_weights(nuc.detach(), mag.detach())
-        amp, _ = amplitudes(s, grid, rot=rot)
+        amp, _ = amplitudes(s, grid, rot=rot, path=path)
         I = cross_section(grid, amp=amp, c=c, obs=("UNPOL",))[0, 0]
-        ctx.sample, ctx.grid, ctx.c, ctx.rot = s, grid, c, rot
+        ctx.sample, ctx.grid, ctx.c, ctx.rot, ctx.path = s, grid, c, rot, path
         ctx.save_for_backward(amp)
         return I
 
@@ -475,9 +477,9 @@ class UnpolarizedCrossSection(torch.autograd.Function):
     def backward(ctx, gI):
         (amp,) = ctx.saved_tensors
         _, dn, dm = grad(ctx.sample, ctx.grid, ctx.c, weight=gI.contiguous().to(torch.float64), target=None,
-                         rot=ctx.rot, amp=amp[0])
-        return dn, dm, None, None, None, None
+                         rot=ctx.rot, amp=amp[0], path=ctx.path)
+        return dn, dm, None, None, None, None, None
 
 
-def unpolarized(nuc, mag, sample: Sample, grid: QGrid, c: Consts, rot=None):
-    return UnpolarizedCrossSection.apply(nuc, mag, sample, grid, c, rot)
+def unpolarized(nuc, mag, sample: Sample, grid: QGrid, c: Consts, rot=None, path=PATH_DIRECT):
+    return UnpolarizedCrossSection.apply(nuc, mag, sample, grid, c, rot, path)

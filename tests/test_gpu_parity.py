@@ -226,8 +226,11 @@ def test_gradient_small_vs_oracle(orc):
     assert max_norm_err(gdm.cpu().numpy(), dm) <= 1e-9
 
 
-def test_autograd_function_backward_matches_loss_gradient(orc):
-    """torch.autograd through UnpolarizedCrossSection equals the oracle gradient."""
+@pytest.mark.parametrize("path", [0, 3])
+def test_autograd_function_backward_matches_loss_gradient(orc, path):
+    """torch.autograd through UnpolarizedCrossSection equals the oracle gradient, on
+    the direct path and on the half-detector path (sums and adjoint over half of
+    the detector; the upstream gradient 2 w (I - T) has no symmetry)."""
     rng = np.random.default_rng(29)
     W = 500
     cl = {"pos": rng.uniform(-4, 4, (W, 3)), "nuc": rng.standard_normal(W), "mag": rng.standard_normal((W, 3))}
@@ -239,7 +242,7 @@ def test_autograd_function_backward_matches_loss_gradient(orc):
     s = _sample(cl)
     nuc = torch.as_tensor(cl["nuc"], device=DEV).requires_grad_(True)
     mag = torch.as_tensor(cl["mag"], device=DEV).requires_grad_(True)
-    I = numag.unpolarized(nuc, mag, s, grid, numag.consts())
+    I = numag.unpolarized(nuc, mag, s, grid, numag.consts(), path=path)
     Tt, wt = torch.as_tensor(T, device=DEV), torch.as_tensor(w, device=DEV)
     loss = torch.sum(wt * (I - Tt) ** 2)
     loss.backward()
