@@ -176,11 +176,30 @@ __global__ __launch_bounds__(256) void sep_contract1_f64(const double *__restric
     const int ai = m0 + (lane & 15), bj = n0 + (lane & 15), kq = lane >> 4;
     const double *Sc = S + (int64_t)c * ny * nz;
     v4d accR = {0.0, 0.0, 0.0, 0.0}, accI = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 8
-    for (int k = 0; k < nz; k += 4) {
+    auto load = [&](int k, double &a, double2 &b) {
         const int kk = k + kq;
-        const double a = (ai < ny && kk < nz) ? Sc[(int64_t)ai * nz + kk] : 0.0;
-        const double2 b = (bj < n1 && kk < nz) ? Ez[(int64_t)kk * n1 + bj] : make_double2(0.0, 0.0);
+        a = (ai < ny && kk < nz) ? Sc[(int64_t)ai * nz + kk] : 0.0;
+        b = (bj < n1 && kk < nz) ? Ez[(int64_t)kk * n1 + bj] : make_double2(0.0, 0.0);
+    };
+    // four K steps at a time: their loads are issued before their MFMAs (the
+    // accumulation order is the same as one step at a time)
+    constexpr int U = 4;
+    int k = 0;
+    for (; k + 4 * (U - 1) < nz; k += 4 * U) {
+        double a[U];
+        double2 b[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) load(k + 4 * u, a[u], b[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            accR = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u].x, accR, 0, 0, 0);
+            accI = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u].y, accI, 0, 0, 0);
+        }
+    }
+    for (; k < nz; k += 4) {
+        double a;
+        double2 b;
+        load(k, a, b);
         accR = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b.x, accR, 0, 0, 0);
         accI = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b.y, accI, 0, 0, 0);
     }
