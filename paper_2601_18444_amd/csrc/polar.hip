@@ -180,7 +180,9 @@ DirectPlan plan_direct_polar(const Detector &d, int64_t W)
     p.col_blocks = (d.n1 + 63) / 64;
     p.row_blocks = (d.n0 + rows - 1) / rows;
     int64_t blocks = (int64_t)p.col_blocks * p.row_blocks;
-    int64_t want = (target_workgroups() * 4 / polar_waves(d) + blocks - 1) / blocks;
+    // half the Cartesian path's wave count: a polar workgroup holds its CU alone, and
+    // two rounds of them over the chip measured faster than four (fewer partials too)
+    int64_t want = (target_workgroups() * 2 / polar_waves(d) + blocks - 1) / blocks;
     int64_t max_split = (W + 8 * kPolarChunk - 1) / (8 * kPolarChunk);
     if (max_split < 1) max_split = 1;
     if (want > max_split) want = max_split;
