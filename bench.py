@@ -436,6 +436,9 @@ def main():
             "points": W, "pixels": P, "sums_per_step": sums_per_step,
         },
         "paths": {
+            # the step rate counting only the sums whose terms are evaluated one by one
+            # (direct and adjoint; the separable sums are equivalent terms)
+            "step_evaluated_terms_Gterm_s": round(2 * terms / (ms_per_step * 1e-3) / 1e9, 2),
             "direct_Gterm_s": round(terms / (t_direct * 1e-3) / 1e9, 2),
             "direct_ms": round(t_direct, 4),
             "direct_kernel_ms": round(kernel_ms["direct_cartesian_kernel"], 4),
