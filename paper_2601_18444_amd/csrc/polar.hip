@@ -19,11 +19,11 @@ constexpr int kPolarChunk = 8;
 constexpr int kPolarB = 8;
 
 // Operands of point jj for this lane: ez = the wave's start phasor, dz = the q step.
-template <int WV>
-__device__ __forceinline__ cart::Operands polar_operands(const double2 (&s_start)[kPolarChunk + 1][WV][64],
-                                                         const double2 (&s_step)[kPolarChunk + 1][64],
-                                                         const double (&s_k)[kPolarChunk + 1][64],
-                                                         const double (&s_w)[kPolarChunk + 1][4], int jj, int lane,
+template <int WV, int R>
+__device__ __forceinline__ cart::Operands polar_operands(const double2 (&s_start)[R][WV][64],
+                                                         const double2 (&s_step)[R][64],
+                                                         const double (&s_k)[R][64],
+                                                         const double (&s_w)[R][4], int jj, int lane,
                                                          int wave)
 {
     cart::Operands o;
@@ -52,6 +52,15 @@ __device__ __forceinline__ void polar_point(const cart::Operands &o, double (&ac
     }
 }
 
+// LDS buffers of the polar kernel: two at WV = 8 (the next chunk is generated into
+// one while the other is summed, one barrier per chunk, 157 KB), one at WV = 4
+// (two workgroups per CU).
+template <int WV>
+constexpr int polar_buffers()
+{
+    return WV == 8 ? 2 : 1;
+}
+
 template <int WV, int CH>
 __global__ __launch_bounds__(64 * WV, 8 / WV) void direct_polar_kernel(const PointRec *__restrict__ pts, int64_t W,
                                                                       int64_t per, Detector d,
@@ -59,11 +68,15 @@ __global__ __launch_bounds__(64 * WV, 8 / WV) void direct_polar_kernel(const Poi
 {
     constexpr int B = kPolarB;
     constexpr int ROWS = WV * B;
-    // one row per point of a chunk plus one the pipelined loop may read past the end
-    __shared__ double2 s_start[kPolarChunk + 1][WV][64];
-    __shared__ double2 s_step[kPolarChunk + 1][64];
-    __shared__ double s_k[kPolarChunk + 1][64];
-    __shared__ double s_w[kPolarChunk + 1][4];
+    constexpr int CHK = kPolarChunk;
+    constexpr int NB = polar_buffers<WV>();
+    // one row per point of a chunk; single-buffered, plus one the pipelined loop
+    // may read past the end (double-buffered, that read is clamped instead)
+    constexpr int R = NB == 2 ? CHK : CHK + 1;
+    __shared__ double2 s_start[NB][R][WV][64];
+    __shared__ double2 s_step[NB][R][64];
+    __shared__ double s_k[NB][R][64];
+    __shared__ double s_w[NB][R][4];
     __shared__ double2 s_trig[64];  // (sin, cos) of the lane's column angle
 
     const int t = threadIdx.x;
@@ -87,72 +100,92 @@ __global__ __launch_bounds__(64 * WV, 8 / WV) void direct_polar_kernel(const Poi
         double sth, cth;
         sincos(theta, &sth, &cth);
         s_trig[lane] = make_double2(sth, cth);
-    }  // published by the first barrier of the chunk loop
+    }
+    __syncthreads();
     const double qrow0 = axis_value(d.origin0, row0, d.step0);
 
-    // point data of a chunk, loaded one chunk ahead: (Y, Z) of the points
-    // wave + WV i that this wave generates, and weight component t % 4 of point
-    // t / 4 for t < 4 kPolarChunk
-    constexpr int GPW = kPolarChunk / WV;  // points generated per wave
-    static_assert(GPW * WV == kPolarChunk, "chunk and waves");
+    // point data of a chunk, loaded one chunk ahead of its generation: (Y, Z) of
+    // the points wave + WV i that this wave generates, and weight component t % 4
+    // of point t / 4 for t < 4 CHK
+    constexpr int GPW = CHK / WV;  // points generated per wave
+    static_assert(GPW * WV == CHK, "chunk and waves");
     const int wj = t >> 2, wc = t & 3;
     double nY[GPW], nZ[GPW], nW = 0.0;
-#pragma unroll
-    for (int i = 0; i < GPW; ++i) {
-        const int64_t j = jbeg + wave + WV * i;
-        nY[i] = j < jend ? pts[j].Y : 0.0;
-        nZ[i] = j < jend ? pts[j].Z : 0.0;
-    }
-    if (wj < kPolarChunk && jbeg + wj < jend) nW = pts[jbeg + wj].w[wc];
-
-    for (int64_t j0 = jbeg; j0 < jend; j0 += kPolarChunk) {
-        const int nk = (int)min((int64_t)kPolarChunk, jend - j0);
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < GPW; ++i) {
-            const int jj = wave + WV * i;
-            const double Y = nY[i], Z = nZ[i];  // zero past the end
-            const double2 tr = s_trig[lane];
-            const double u = Y * tr.x + Z * tr.y;
-            const double2 step = twiddle(d.step0 * u);
-            double2 sb = cmul(step, step);  // step^8: from one wave's rows to the next
-            sb = cmul(sb, sb);
-            sb = cmul(sb, sb);
-            double2 st = twiddle(qrow0 * u);  // start of the block
-            s_step[jj][lane] = step;
-            s_k[jj][lane] = step.x + step.x;
-#pragma unroll
-            for (int w = 0; w < WV; ++w) {
-                s_start[jj][w][lane] = st;
-                st = cmul(st, sb);
-            }
-        }
-        if (wj < kPolarChunk) s_w[wj][wc] = nW;  // zero past the end
-        // request the next chunk's point data; it arrives during the sums below
-        const int64_t j1 = j0 + kPolarChunk;
+    auto fetch = [&](int64_t j1) {
 #pragma unroll
         for (int i = 0; i < GPW; ++i) {
             const int64_t j = j1 + wave + WV * i;
             nY[i] = j < jend ? pts[j].Y : 0.0;
             nZ[i] = j < jend ? pts[j].Z : 0.0;
         }
-        nW = (wj < kPolarChunk && j1 + wj < jend) ? pts[j1 + wj].w[wc] : 0.0;
-        __syncthreads();
-        // operands of the next point are requested before the current point is
-        // accumulated (as in the Cartesian loop)
-        cart::Operands opa = polar_operands<WV>(s_start, s_step, s_k, s_w, 0, lane, wave);
+        nW = (wj < CHK && j1 + wj < jend) ? pts[j1 + wj].w[wc] : 0.0;
+    };
+    // twiddles of the fetched chunk into LDS buffer b (zeros past the end)
+    auto generate = [&](int b) {
+#pragma unroll
+        for (int i = 0; i < GPW; ++i) {
+            const int jj = wave + WV * i;
+            const double2 tr = s_trig[lane];
+            const double u = nY[i] * tr.x + nZ[i] * tr.y;
+            const double2 step = twiddle(d.step0 * u);
+            double2 sb = cmul(step, step);  // step^8: from one wave's rows to the next
+            sb = cmul(sb, sb);
+            sb = cmul(sb, sb);
+            double2 st = twiddle(qrow0 * u);  // start of the block
+            s_step[b][jj][lane] = step;
+            s_k[b][jj][lane] = step.x + step.x;
+#pragma unroll
+            for (int w = 0; w < WV; ++w) {
+                s_start[b][jj][w][lane] = st;
+                st = cmul(st, sb);
+            }
+        }
+        if (wj < CHK) s_w[b][wj][wc] = nW;
+    };
+    // sums of the nk points in buffer b; the operands of the next point are
+    // requested before the current point is accumulated (as in the Cartesian loop)
+    auto sum = [&](int b, int nk) {
+        cart::Operands opa = polar_operands<WV, R>(s_start[b], s_step[b], s_k[b], s_w[b], 0, lane, wave);
         int jj = 0;
         for (; jj + 1 < nk; jj += 2) {
-            const cart::Operands opb = polar_operands<WV>(s_start, s_step, s_k, s_w, jj + 1, lane, wave);
+            const cart::Operands opb = polar_operands<WV, R>(s_start[b], s_step[b], s_k[b], s_w[b], jj + 1, lane, wave);
             __builtin_amdgcn_sched_barrier(0);
             polar_point<B, CH>(opa, acc);
             __builtin_amdgcn_sched_barrier(0);
-            opa = polar_operands<WV>(s_start, s_step, s_k, s_w, jj + 2, lane, wave);  // row kPolarChunk at most
+            const int nxt = NB == 2 ? min(jj + 2, CHK - 1) : jj + 2;  // past the end: discarded
+            opa = polar_operands<WV, R>(s_start[b], s_step[b], s_k[b], s_w[b], nxt, lane, wave);
             __builtin_amdgcn_sched_barrier(0);
             polar_point<B, CH>(opb, acc);
             __builtin_amdgcn_sched_barrier(0);
         }
         if (jj < nk) polar_point<B, CH>(opa, acc);
+    };
+
+    fetch(jbeg);
+    if (NB == 2) {
+        // chunk c sits in buffer c & 1; chunk c + 1 is generated while chunk c is summed
+        if (jbeg < jend) {
+            generate(0);
+            fetch(jbeg + CHK);
+        }
+        __syncthreads();
+        int b = 0;
+        for (int64_t j0 = jbeg; j0 < jend; j0 += CHK, b ^= 1) {
+            if (j0 + CHK < jend) {
+                generate(b ^ 1);  // its buffer was last read before the previous barrier
+                fetch(j0 + 2 * CHK);
+            }
+            sum(b, (int)min((int64_t)CHK, jend - j0));
+            __syncthreads();
+        }
+    } else {
+        for (int64_t j0 = jbeg; j0 < jend; j0 += CHK) {
+            if (j0 != jbeg) __syncthreads();  // the previous chunk's sums are done
+            generate(0);
+            fetch(j0 + CHK);  // arrives during the sums below
+            __syncthreads();
+            sum(0, (int)min((int64_t)CHK, jend - j0));
+        }
     }
     const int64_t P = (int64_t)d.n0 * d.n1;
     double *dst = out + (int64_t)blockIdx.z * P * 8;
