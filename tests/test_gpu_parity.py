@@ -467,3 +467,32 @@ def test_gradient_hermitian_path(orc, kind, n0, n1, amp_given):
     assert abs(loss.item() - lf.item()) <= 1e-12 * abs(lf.item())
     assert max_norm_err(gdn.cpu().numpy(), fdn.cpu().numpy()) <= 1e-11
     assert max_norm_err(gdm.cpu().numpy(), fdm.cpu().numpy()) <= 1e-11
+
+
+def test_hermitian_path_edge_cases(orc):
+    """The half-detector path on degenerate detectors and samples: W = 0 gives
+    zeros (and the loss of a zero pattern, no gradient entries); a 1 x 1 and a
+    1 x 7 detector have no mirrored pixel outside the summed half; a 2 x 3
+    detector mirrors its second row from the first; a polar detector with
+    n_theta = 2 mirrors its second column.  Every case equals the full path."""
+    H = numag.PATH_DIRECT_HERMITIAN
+    empty = numag.Sample(pos=np.zeros((0, 3)), nuc=np.zeros(0), mag=np.zeros((0, 3)), device=DEV)
+    for kind, n0, n1 in ((0, 15, 16), (1, 8, 10)):
+        amp, _ = numag.amplitudes(empty, numag.qgrid(kind, n0, n1, 1.0), path=H)
+        assert torch.count_nonzero(amp).item() == 0
+    cl = synth.random_cloud(300, 5.0, seed=62)
+    s = _sample(cl)
+    for kind, n0, n1 in ((0, 1, 1), (0, 1, 7), (0, 2, 3), (1, 5, 2), (1, 1, 4)):
+        grid = numag.qgrid(kind, n0, n1, 0.9)
+        h, _ = numag.amplitudes(s, grid, path=H)
+        f, _ = numag.amplitudes(s, grid)
+        assert max_norm_err(h.cpu().numpy(), f.cpu().numpy()) <= 1e-12, (kind, n0, n1)
+        qy, qz, _ = orc.pixels(kind, n0, n1, 0.9)
+        _check_amp(amp_to_complex(h[0]), _oracle_amp(orc, cl, qy, qz))
+    grid = numag.qgrid(0, 6, 6, 1.0)
+    T = torch.ones(36, dtype=torch.float64, device=DEV)
+    w = torch.ones(36, dtype=torch.float64, device=DEV)
+    loss_h, dn_h, dm_h = numag.grad(empty, grid, numag.consts(), weight=w, target=T, path=H)
+    loss_f, _, _ = numag.grad(empty, grid, numag.consts(), weight=w, target=T)
+    assert loss_h.item() == loss_f.item() == 36.0  # sum_p w (0 - 1)^2
+    assert dn_h.numel() == 0 and dm_h.numel() == 0
