@@ -60,6 +60,10 @@ def parse():
     ap.add_argument("--polar", action="store_true",
                     help="only time the direct sums of the same points on a 256 q x 256 theta polar "
                          "detector (a short run for the polar kernel's profiles)")
+    ap.add_argument("--snapshots", action="store_true",
+                    help="only run the loop-mode snapshot measurement (64 snapshots, separable path)")
+    ap.add_argument("--batched", action="store_true",
+                    help="only run the orientation-batch measurement (64 particles x 1000 rotations)")
     return ap.parse_args()
 
 
@@ -290,6 +294,12 @@ def main():
 
     if args.polar:
         polar_only(torch, numag, synth)
+        return
+    if args.snapshots:
+        print(json.dumps(measure_snapshots(torch, numag, synth)))
+        return
+    if args.batched:
+        print(json.dumps(measure_batched(torch, numag, synth)))
         return
 
     dev = "cuda:0"
