@@ -496,3 +496,46 @@ def test_hermitian_path_edge_cases(orc):
     loss_f, _, _ = numag.grad(empty, grid, numag.consts(), weight=w, target=T)
     assert loss_h.item() == loss_f.item() == 36.0  # sum_p w (0 - 1)^2
     assert dn_h.numel() == 0 and dm_h.numel() == 0
+
+
+def test_c5_gradient_full_size_directional_derivative():
+    """The gradient at full size (64^3 vortex, 256 x 256 detector, the benchmark's
+    loss): its directional derivative along a random weight direction v equals
+    the central difference (L(w + h v) - L(w - h v)) / 2h of the loss evaluated by
+    the forward path.  L is quartic in the weights, so the difference is exact
+    up to h^2 terms (h = 1e-4: about 1e-8 relative).  The half-detector gradient
+    equals the full one at this size too."""
+    cfg = synth.vortex_c5()
+    g = cfg["grid"]
+    grid = _grid(g)
+    s = _sample(cfg)
+    tf = cfg["target_field"]
+    k = numag.consts()
+    tamp, _ = numag.amplitudes(_sample(tf), grid)
+    T = numag.cross_section(grid, amp=tamp, c=k, obs=("UNPOL",))[0, 0].clone()
+    n = g["n0"]
+    qax = -g["qmax"] + torch.arange(n, dtype=torch.float64, device=DEV) * (2 * g["qmax"] / (n - 1))
+    qn = torch.sqrt(qax[:, None] ** 2 + qax[None, :] ** 2).reshape(-1)
+    w = torch.where(qn <= g["qmax"], 1.0 / (T + 1e-3 * T.max()) ** 2, torch.zeros_like(T)).contiguous()
+    loss, dn, dm = numag.grad(s, grid, k, weight=w, target=T)
+    _, hn, hm = numag.grad(s, grid, k, weight=w, target=T, path=numag.PATH_DIRECT_HERMITIAN)
+    assert max_norm_err(hn.cpu().numpy(), dn.cpu().numpy()) <= 1e-11
+    assert max_norm_err(hm.cpu().numpy(), dm.cpu().numpy()) <= 1e-11
+
+    rng = np.random.default_rng(63)
+    vn = torch.as_tensor(rng.standard_normal(cfg["nuc"].shape), device=DEV)
+    vm = torch.as_tensor(rng.standard_normal(cfg["mag"].shape), device=DEV)
+    nuc0 = torch.as_tensor(cfg["nuc"], device=DEV)
+    mag0 = torch.as_tensor(cfg["mag"], device=DEV)
+
+    def L(t):
+        st = s.with_weights(nuc0 + t * vn, mag0 + t * vm)
+        amp, _ = numag.amplitudes(st, grid)
+        I = numag.cross_section(grid, amp=amp, c=k, obs=("UNPOL",))[0, 0]
+        return float(torch.sum(w * (I - T) ** 2))
+
+    h = 1e-4
+    fd = (L(h) - L(-h)) / (2 * h)
+    an = float(torch.sum(dn * vn) + torch.sum(dm * vm))
+    assert abs(L(0.0) - loss.item()) <= 1e-12 * abs(loss.item())
+    assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)
