@@ -213,9 +213,70 @@ int run_direct(const numag_sample *s, const Rot &R, const Detector &d, double *a
 // polar path into one amplitude buffer and adds F F^H / n_rot into its spectral
 // matrix (split mode: plus the coherent total of the whole sample).  The
 // direct workspace of the whole sample bounds that of every object.
-size_t polar_objects_ws(const numag_sample *s, const Detector &d)
+size_t polar_objects_ws(const numag_sample *s, const Detector &d, int64_t n_rot)
 {
-    return direct_layout(s, d).total + align_up((size_t)d.n0 * d.n1 * 8 * sizeof(double));
+    return direct_layout(s, d).total + align_up((size_t)d.n0 * d.n1 * 8 * sizeof(double)) +
+           align_up((size_t)n_rot * 9 * sizeof(double));
+}
+
+// Dilute mode on a polar detector: per object, groups of rotations share one
+// point-preparation launch, one polar-sum launch (grid z = rotation x split) and
+// one reduction that adds F F^H / n_rot of each rotation in order.  Splits over
+// the points keep at least kGroupSplitPoints points each (fewer split partial
+// sums to write and read per rotation), and a group is as large as fills the chip
+// (about target_workgroups() / 4 workgroups of 8 waves) within the point and
+// partial buffers of the whole sample.
+constexpr int64_t kGroupSplitPoints = 8192;  // measured: 4096 and 16384 about 4 % slower
+
+int run_dilute_polar(const numag_sample *s, const double *rot, int64_t n_rot, const Detector &d,
+                     int32_t spec_per_object, double *spec_out, const DirectLayout &L, void *direct_ws,
+                     double *d_rot, hipStream_t st, bool hermitian)
+{
+    const int64_t P = (int64_t)d.n0 * d.n1;
+    const int64_t K = s->n_objects;
+    if (s->nuc == nullptr && s->mag == nullptr) return NUMAG_OK;  // all sums vanish
+    const int channels = s->nuc == nullptr ? 3 : (s->mag == nullptr ? 1 : 4);
+    if (rot != nullptr) {
+        NUMAG_HIP_CHECK(hipMemcpyAsync(d_rot, rot, (size_t)n_rot * 9 * sizeof(double), hipMemcpyHostToDevice, st));
+    } else {
+        static const double I3[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+        NUMAG_HIP_CHECK(hipMemcpyAsync(d_rot, I3, sizeof(I3), hipMemcpyHostToDevice, st));
+    }
+    NUMAG_HIP_CHECK(hipStreamSynchronize(st));  // the host rotations may be pageable
+    Carve cv(direct_ws);
+    cv.take(L.offsets);
+    PointRec *pts = (PointRec *)cv.take(L.points);
+    double *part = (double *)cv.take(L.partial);
+    Detector dk = d;
+    if (hermitian) dk.n1 = d.n1 / 2;  // theta in [0, pi); the rest by conjugation
+    const int64_t Pk = (int64_t)dk.n0 * dk.n1;
+    const int nh = hermitian ? dk.n1 : 0;
+    const double scale = 1.0 / (double)n_rot;
+    for (int64_t k = 0; k < K; ++k) {
+        const int64_t lo = K > 1 ? s->obj_offsets[k] : 0, hi = K > 1 ? s->obj_offsets[k + 1] : s->n_points;
+        const int64_t Wk = hi - lo;
+        if (Wk == 0) continue;
+        DirectPlan p = plan_direct_polar(dk, Wk, (Wk + kGroupSplitPoints - 1) / kGroupSplitPoints);
+        p.channels = channels;
+        const int64_t blocks = (int64_t)p.col_blocks * p.row_blocks;
+        int64_t rg = (target_workgroups() / 4) / (blocks * p.nsplit);
+        rg = std::min<int64_t>(rg, n_rot);
+        rg = std::min<int64_t>(rg, (int64_t)(L.points / ((size_t)Wk * sizeof(PointRec))));
+        rg = std::min<int64_t>(rg, (int64_t)(L.partial / ((size_t)p.nsplit * Pk * 8 * sizeof(double))));
+        rg = std::min<int64_t>(rg, 65535 / p.nsplit);
+        rg = std::max<int64_t>(rg, 1);  // the buffers hold one rotation of any object
+        double *spec = spec_out + (spec_per_object ? k : 0) * P * 16;
+        for (int64_t r0 = 0; r0 < n_rot; r0 += rg) {
+            const int nr = (int)std::min<int64_t>(rg, n_rot - r0);
+            int rc = launch_prepare_rotations(s->pos + 3 * lo, s->nuc != nullptr ? s->nuc + lo : nullptr,
+                                              s->mag != nullptr ? s->mag + 3 * lo : nullptr, Wk, d_rot + 9 * r0, nr,
+                                              pts, st);
+            if (rc == NUMAG_OK) rc = launch_direct_polar(pts, Wk, dk, p, part, st, nr);
+            if (rc == NUMAG_OK) rc = launch_spectral_rotations(part, nr, p.nsplit, Pk, d.n1, nh, scale, spec, st);
+            if (rc != NUMAG_OK) return rc;
+        }
+    }
+    return NUMAG_OK;
 }
 
 int run_objects_polar(const numag_sample *s, const double *rot, int64_t n_rot, const Detector &d, int32_t mode,
@@ -228,9 +289,12 @@ int run_objects_polar(const numag_sample *s, const double *rot, int64_t n_rot, c
     Carve cv(ws);
     void *direct_ws = cv.take(L.total);
     double *F = (double *)cv.take((size_t)P * 8 * sizeof(double));
+    double *d_rot = (double *)cv.take((size_t)n_rot * 9 * sizeof(double));
     const int64_t n_spec = spec_per_object ? K : 1;
     int rc = launch_fill(spec_out, n_spec * P * 16, 0.0, st);
     if (rc != NUMAG_OK) return rc;
+    if (mode == NUMAG_MODE_DILUTE)
+        return run_dilute_polar(s, rot, n_rot, d, spec_per_object, spec_out, L, direct_ws, d_rot, st, hermitian);
     if (mode == NUMAG_MODE_SPLIT) {
         rc = run_direct(s, rot_of(rot, 0), d, amp_out, direct_ws, st, hermitian);
         if (rc != NUMAG_OK) return rc;
@@ -261,7 +325,7 @@ size_t amplitudes_ws(const numag_sample *s, int64_t n_rot, const Detector &d, in
     if (path == NUMAG_PATH_SEPARABLE_F64 || path == NUMAG_PATH_SEPARABLE_BF16X3)
         return align_up(separable_workspace_bytes(*s->regular, d, path, 1));
     if (mode == NUMAG_MODE_COHERENT) return direct_layout(s, d).total;
-    if (d.kind == NUMAG_GRID_POLAR) return polar_objects_ws(s, d);
+    if (d.kind == NUMAG_GRID_POLAR) return polar_objects_ws(s, d, n_rot);
     return align_up(objects_workspace_bytes(objects_detector(d, path == NUMAG_PATH_DIRECT_HERMITIAN), s->obj_offsets,
                                             s->n_objects, s->n_points, n_rot, mode, spec_per_object));
 }

@@ -43,6 +43,28 @@ Detector make_detector(const numag_qgrid &g)
 // ---------------------------------------------------------------------------
 // sample assembly and rotation (Sec. 3.2): X = R (x + r^k), w' = (n, R m).
 // ---------------------------------------------------------------------------
+// Lab-frame record of point j at sample-frame position x: X = R x (only Y, Z enter
+// the phase), weights (n, R m).
+__device__ __forceinline__ PointRec point_record(const double (&x)[3], const Rot &R, const double *__restrict__ nuc,
+                                                 const double *__restrict__ mag, int64_t j)
+{
+    PointRec r;
+    r.Y = R.m[3] * x[0] + R.m[4] * x[1] + R.m[5] * x[2];
+    r.Z = R.m[6] * x[0] + R.m[7] * x[1] + R.m[8] * x[2];
+    r.w[0] = nuc != nullptr ? nuc[j] : 0.0;
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0;
+    if (mag != nullptr) {
+        m0 = mag[3 * j + 0];
+        m1 = mag[3 * j + 1];
+        m2 = mag[3 * j + 2];
+    }
+    r.w[1] = R.m[0] * m0 + R.m[1] * m1 + R.m[2] * m2;
+    r.w[2] = R.m[3] * m0 + R.m[4] * m1 + R.m[5] * m2;
+    r.w[3] = R.m[6] * m0 + R.m[7] * m1 + R.m[8] * m2;
+    r.pad[0] = r.pad[1] = 0.0;
+    return r;
+}
+
 __global__ void prepare_points_kernel(const double *__restrict__ pos, const double *__restrict__ nuc,
                                       const double *__restrict__ mag, int64_t W, int reg,
                                       numag_regular g, const int64_t *__restrict__ off, int64_t K,
@@ -78,21 +100,35 @@ __global__ void prepare_points_kernel(const double *__restrict__ pos, const doub
         x[1] += obj_pos[3 * k + 1];
         x[2] += obj_pos[3 * k + 2];
     }
-    PointRec r;
-    r.Y = R.m[3] * x[0] + R.m[4] * x[1] + R.m[5] * x[2];
-    r.Z = R.m[6] * x[0] + R.m[7] * x[1] + R.m[8] * x[2];
-    r.w[0] = nuc != nullptr ? nuc[j] : 0.0;
-    double m0 = 0.0, m1 = 0.0, m2 = 0.0;
-    if (mag != nullptr) {
-        m0 = mag[3 * j + 0];
-        m1 = mag[3 * j + 1];
-        m2 = mag[3 * j + 2];
-    }
-    r.w[1] = R.m[0] * m0 + R.m[1] * m1 + R.m[2] * m2;
-    r.w[2] = R.m[3] * m0 + R.m[4] * m1 + R.m[5] * m2;
-    r.w[3] = R.m[6] * m0 + R.m[7] * m1 + R.m[8] * m2;
-    r.pad[0] = r.pad[1] = 0.0;
-    out[j] = r;
+    out[j] = point_record(x, R, nuc, mag, j);
+}
+
+// Points of one object (explicit positions, no object offset) under a group of
+// rotations: out[r][j] for rotation r < nr of rots[r][9] (device), the same
+// records prepare_points_kernel writes for each rotation.
+__global__ void prepare_rotations_kernel(const double *__restrict__ pos, const double *__restrict__ nuc,
+                                         const double *__restrict__ mag, int64_t W,
+                                         const double *__restrict__ rots, PointRec *__restrict__ out)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= W) return;
+    const int r = blockIdx.y;
+    Rot R;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) R.m[a] = rots[9 * r + a];
+    const double x[3] = {pos[3 * j + 0], pos[3 * j + 1], pos[3 * j + 2]};
+    out[(int64_t)r * W + j] = point_record(x, R, nuc, mag, j);
+}
+
+int launch_prepare_rotations(const double *pos, const double *nuc, const double *mag, int64_t W,
+                             const double *d_rots, int nr, PointRec *out, hipStream_t s)
+{
+    if (W <= 0 || nr <= 0) return NUMAG_OK;
+    if (nr > 65535) return NUMAG_E_INVALID;
+    dim3 grid((unsigned)((W + 255) / 256), (unsigned)nr);
+    hipLaunchKernelGGL(prepare_rotations_kernel, grid, dim3(256), 0, s, pos, nuc, mag, W, d_rots, out);
+    NUMAG_HIP_CHECK(hipGetLastError());
+    return NUMAG_OK;
 }
 
 int launch_prepare_points(const double *pos, const double *nuc, const double *mag, int64_t W,

@@ -78,9 +78,19 @@ int launch_direct_cartesian(const PointRec *pts, int64_t W, const Detector &d, c
                             double *partial, hipStream_t s);
 
 // Polar detector direct sum: [nsplit][P][8] partials.
-DirectPlan plan_direct_polar(const Detector &d, int64_t W);
+// max_splits > 0 caps the point splits (rotation groups trade splits for rotations).
+DirectPlan plan_direct_polar(const Detector &d, int64_t W, int64_t max_splits = 0);
+// n_rot > 1: pts holds n_rot consecutive copies of W points (one per rotation of a
+// group) and the partials are [n_rot][p.nsplit][P][8].
 int launch_direct_polar(const PointRec *pts, int64_t W, const Detector &d, const DirectPlan &p,
-                        double *partial, hipStream_t s);
+                        double *partial, hipStream_t s, int n_rot = 1);
+// Points of one object under nr rotations (d_rots: device [nr][9]) into out[nr][W].
+int launch_prepare_rotations(const double *pos, const double *nuc, const double *mag, int64_t W,
+                             const double *d_rots, int nr, PointRec *out, hipStream_t s);
+// spec[p] += scale sum over the group's rotations of F F^H from polar partials
+// [nr][nsp][Ph][8]; nh > 0: half-detector partials, mirrored into column m + nh.
+int launch_spectral_rotations(const double *part, int nr, int nsp, int64_t Ph, int n1, int nh, double scale,
+                              double *spec, hipStream_t s);
 
 // out[i] = value for i < n (a kernel, so that callers may capture it in a graph).
 int launch_fill(double *out, int64_t n, double value, hipStream_t s);

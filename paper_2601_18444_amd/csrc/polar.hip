@@ -61,9 +61,11 @@ constexpr int polar_buffers()
     return WV == 8 ? 2 : 1;
 }
 
+// grid.z = rotation r of a group x split sp (nsp splits per rotation); the points of
+// rotation r are pts[r wrot, (r + 1) wrot).  One rotation: wrot = W, nsp = grid.z.
 template <int WV, int CH>
-__global__ __launch_bounds__(64 * WV, 8 / WV) void direct_polar_kernel(const PointRec *__restrict__ pts, int64_t W,
-                                                                      int64_t per, Detector d,
+__global__ __launch_bounds__(64 * WV, 8 / WV) void direct_polar_kernel(const PointRec *__restrict__ pts,
+                                                                      int64_t wrot, int64_t per, int nsp, Detector d,
                                                                       double *__restrict__ out)
 {
     constexpr int B = kPolarB;
@@ -84,8 +86,9 @@ __global__ __launch_bounds__(64 * WV, 8 / WV) void direct_polar_kernel(const Poi
     const int wave = t >> 6;
     const int col0 = blockIdx.x * 64;
     const int row0 = blockIdx.y * ROWS;
-    const int64_t jbeg = (int64_t)blockIdx.z * per;
-    const int64_t jend = min(W, jbeg + per);
+    const int64_t rbase = (int64_t)(blockIdx.z / nsp) * wrot;
+    const int64_t jbeg = rbase + (int64_t)(blockIdx.z % nsp) * per;
+    const int64_t jend = min(rbase + wrot, jbeg + per);
 
     double acc[B][2 * CH];
 #pragma unroll
@@ -204,7 +207,7 @@ __global__ __launch_bounds__(64 * WV, 8 / WV) void direct_polar_kernel(const Poi
 // at most 32 q rows.
 static int polar_waves(const Detector &d) { return d.n0 > 4 * kPolarB ? 8 : 4; }
 
-DirectPlan plan_direct_polar(const Detector &d, int64_t W)
+DirectPlan plan_direct_polar(const Detector &d, int64_t W, int64_t max_splits)
 {
     DirectPlan p{};
     p.channels = 4;
@@ -219,6 +222,7 @@ DirectPlan plan_direct_polar(const Detector &d, int64_t W)
     int64_t max_split = (W + 8 * kPolarChunk - 1) / (8 * kPolarChunk);
     if (max_split < 1) max_split = 1;
     if (want > max_split) want = max_split;
+    if (max_splits > 0 && want > max_splits) want = max_splits;
     if (want > 65535) want = 65535;
     if (want < 1) want = 1;
     int64_t per = (W + want - 1) / want;
@@ -231,12 +235,14 @@ DirectPlan plan_direct_polar(const Detector &d, int64_t W)
 }
 
 int launch_direct_polar(const PointRec *pts, int64_t W, const Detector &d, const DirectPlan &p,
-                        double *partial, hipStream_t s)
+                        double *partial, hipStream_t s, int n_rot)
 {
-    dim3 grid(p.col_blocks, p.row_blocks, p.nsplit);
+    if ((int64_t)p.nsplit * n_rot > 65535) return NUMAG_E_INVALID;
+    dim3 grid(p.col_blocks, p.row_blocks, p.nsplit * n_rot);
     TimedLaunch timed(NUMAG_KERNEL_DIRECT, s);
-#define NUMAG_LAUNCH_POLAR(WV, CH) \
-    hipLaunchKernelGGL((direct_polar_kernel<WV, CH>), grid, dim3(64 * WV), 0, s, pts, W, p.per, d, partial)
+#define NUMAG_LAUNCH_POLAR(WV, CH)                                                                          \
+    hipLaunchKernelGGL((direct_polar_kernel<WV, CH>), grid, dim3(64 * WV), 0, s, pts, W, p.per, p.nsplit, d, \
+                       partial)
 #define NUMAG_LAUNCH_POLAR_CH(WV)                  \
     switch (p.channels) {                          \
         case 1: NUMAG_LAUNCH_POLAR(WV, 1); break;  \
@@ -250,6 +256,62 @@ int launch_direct_polar(const PointRec *pts, int64_t W, const Detector &d, const
     }
 #undef NUMAG_LAUNCH_POLAR_CH
 #undef NUMAG_LAUNCH_POLAR
+    NUMAG_HIP_CHECK(hipGetLastError());
+    return NUMAG_OK;
+}
+
+// Dilute orientational average on a polar detector, one object and a group of nr
+// rotations: F_r(p) = sum of the nsp split partials of rotation r (part[r nsp + s]
+// over the Ph pixels summed), and spec[p] += scale sum_r F_r(p) F_r(p)^H in
+// rotation order.  nh > 0: the partials cover the theta columns [0, nh) of a
+// detector with 2 nh columns, and column m + nh receives conj G (real weights).
+__global__ void spectral_rotations_kernel(const double *__restrict__ part, int nr, int nsp, int64_t Ph, int n1,
+                                          int nh, double scale, double *__restrict__ spec)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= Ph) return;
+    double g[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) g[v] = 0.0;
+    for (int r = 0; r < nr; ++r) {
+        double F[8];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) F[v] = 0.0;
+        for (int sp = 0; sp < nsp; ++sp) {
+            const double *src = part + ((int64_t)(r * nsp + sp) * Ph + p) * 8;
+#pragma unroll
+            for (int v = 0; v < 8; ++v) F[v] += src[v];
+        }
+        // G_ab += F_a conj(F_b): diagonal, then the upper triangle
+#pragma unroll
+        for (int a = 0; a < 4; ++a) g[a] += F[2 * a] * F[2 * a] + F[2 * a + 1] * F[2 * a + 1];
+        const int pa[6] = {0, 0, 0, 1, 1, 2};
+        const int pb[6] = {1, 2, 3, 2, 3, 3};
+#pragma unroll
+        for (int t = 0; t < 6; ++t) {
+            const double ar = F[2 * pa[t]], ai = F[2 * pa[t] + 1];
+            const double br = F[2 * pb[t]], bi = F[2 * pb[t] + 1];
+            g[4 + 2 * t] += ar * br + ai * bi;
+            g[5 + 2 * t] += ai * br - ar * bi;
+        }
+    }
+    const int64_t pf = nh > 0 ? (p / nh) * n1 + p % nh : p;
+    double *o = spec + pf * 16;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) o[v] += scale * g[v];
+    if (nh > 0) {
+        double *m = spec + (pf + nh) * 16;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) m[v] += (v >= 5 && (v & 1)) ? -scale * g[v] : scale * g[v];
+    }
+}
+
+int launch_spectral_rotations(const double *part, int nr, int nsp, int64_t Ph, int n1, int nh, double scale,
+                              double *spec, hipStream_t s)
+{
+    if (Ph <= 0 || nr <= 0) return NUMAG_OK;
+    hipLaunchKernelGGL(spectral_rotations_kernel, dim3((unsigned)((Ph + 255) / 256)), dim3(256), 0, s, part, nr, nsp,
+                       Ph, n1, nh, scale, spec);
     NUMAG_HIP_CHECK(hipGetLastError());
     return NUMAG_OK;
 }

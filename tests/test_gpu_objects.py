@@ -324,3 +324,32 @@ def test_released_workspace_tables_are_uploaded_again():
     torch.cuda.synchronize()
     assert torch.equal(b, ref)
     assert float(ref.abs().max()) > 0.0
+
+
+@pytest.mark.parametrize("nq,nt,path", [(24, 30, 0), (40, 36, 0), (40, 36, 3)])
+def test_dilute_polar_rotation_groups(orc, nq, nt, path):
+    """Dilute mode on a polar detector runs each object over groups of rotations
+    (one launch sequence per group, as many rotations as the sample's buffers
+    and the chip take): objects from 1 to 3000 points and an empty one give
+    groups of one rotation up to all 37, on 4-wave (24 q rows) and 8-wave (40 q
+    rows) kernels and on the half-detector path; every object's orientational
+    average against the oracle."""
+    cfg = _objects(64, [5, 200, 3000, 0, 40, 1, 800], spread=0.0)
+    rots = synth.uniform_rotations(37, np.random.default_rng(65))
+    qmax = 1.1
+    grid = numag.qgrid(1, nq, nt, qmax)
+    qy, qz, _ = orc.pixels(1, nq, nt, qmax)
+    _, spec = numag.amplitudes(_sample(cfg), grid, rot=rots, path=path, mode=numag.MODE_DILUTE,
+                               spec_per_object=True)
+    spec = spec.cpu().numpy()
+    off = cfg["obj_offsets"]
+    for k in range(len(off) - 1):
+        sl = slice(off[k], off[k + 1])
+        if off[k + 1] == off[k]:
+            assert np.count_nonzero(spec[k]) == 0
+            continue
+        Fs = [orc.amplitudes(cfg["pos"][sl], cfg["nuc"][sl], cfg["mag"][sl], qy, qz, R=R) for R in rots]
+        _check_spec(spec[k], orc.spectral(np.stack(Fs)) / len(rots))
+    # summed over objects
+    _, tot = numag.amplitudes(_sample(cfg), grid, rot=rots, path=path, mode=numag.MODE_DILUTE)
+    assert max_norm_err(tot[0].cpu().numpy(), spec.sum(axis=0)) <= 1e-12
