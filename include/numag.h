@@ -32,6 +32,12 @@
  * before it completes.  Every entry point validates all arguments before any
  * work is enqueued; an invalid call returns a negative status, enqueues
  * nothing and leaves a message for numag_last_error() (per thread).
+ *
+ * Tuning: the environment variable NUMAG_TARGET_WGS (read once per process)
+ * sets the number of workgroups the direct sums aim for per launch (default
+ * 2048, the value measured best on MI355X; the polar sums take half, the
+ * adjoint twice).  It changes how the points are split, never a result's
+ * definition; sums split differently agree to rounding.
  */
 #ifndef NUMAG_H
 #define NUMAG_H
