@@ -304,6 +304,9 @@ class BatchedOrientations:
     completes the spectral matrices by G(-q) = conj G(q)."""
 
     def __init__(self, sample: Sample, grid: QGrid, rotations, spec_per_object: bool = True, path: int = PATH_DIRECT):
+        if grid.kind != 0:
+            raise ValueError("BatchedOrientations records the persistent object kernel of a Cartesian detector; "
+                             "on a polar detector call amplitudes(..., mode=MODE_DILUTE) directly")
         self.sample, self.grid, self.path = sample, grid, path
         self.rot = np.ascontiguousarray(np.asarray(rotations, dtype=np.float64).reshape(-1, 9))
         self.spec_per_object = spec_per_object

@@ -196,3 +196,10 @@ def test_binding_refuses_to_import_without_the_library(tmp_path):
     r = subprocess.run([sys.executable, "-c", code], cwd=tmp_path, capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
     assert "ImportError" in r.stderr and "is not built" in r.stderr
+
+
+def test_batched_orientations_refuses_a_polar_detector():
+    """The graph-recorded orientation batch is the Cartesian persistent kernel; a
+    polar detector is refused before anything is allocated or launched."""
+    with pytest.raises(ValueError, match="Cartesian"):
+        numag.BatchedOrientations(None, numag.qgrid(1, 8, 8, 1.0), np.eye(3).reshape(1, 9))
