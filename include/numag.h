@@ -177,7 +177,10 @@ void numag_release_workspace(const void *workspace);
  *   mode      DILUTE and SPLIT need explicit positions (NUMAG_E_UNSUPPORTED for
  *             a regular-grid sample); SPLIT takes one rotation.  Both run on
  *             either detector kind (Cartesian: one persistent launch over
- *             objects x rotations; polar: one direct sum per object and rotation).
+ *             objects x rotations; polar: per object, groups of rotations in one
+ *             launch each, or one direct sum per object in SPLIT mode).  On a
+ *             polar detector DILUTE copies the host rotations to the workspace
+ *             and waits for `stream` once before enqueuing the sums.
  *   workspace device scratch of at least numag_workspace_size() bytes; its
  *             contents are undefined after the call.  In DILUTE/SPLIT mode on a
  *             Cartesian detector the call keeps its planning tables at the start
