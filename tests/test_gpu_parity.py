@@ -539,3 +539,25 @@ def test_c5_gradient_full_size_directional_derivative():
     an = float(torch.sum(dn * vn) + torch.sum(dm * vm))
     assert abs(L(0.0) - loss.item()) <= 1e-12 * abs(loss.item())
     assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)
+
+
+@pytest.mark.parametrize("n0,n1", [(3, 1000), (5, 613)])
+def test_gradient_wide_cartesian_rows(orc, n0, n1):
+    """The Cartesian adjoint walks each detector row in LDS segments of 256
+    columns with one recurrence across them: rows of 1000 and 613 columns (four
+    and three segments, ragged ends) against the oracle gradient, with large
+    phases (|X| up to 30 nm at q_max = 2 nm^-1)."""
+    rng = np.random.default_rng(66)
+    W = 300
+    cl = {"pos": rng.uniform(-30, 30, (W, 3)), "nuc": rng.standard_normal(W), "mag": rng.standard_normal((W, 3))}
+    qmax = 2.0
+    grid = numag.qgrid(0, n0, n1, qmax)
+    qy, qz, qhat = orc.pixels(0, n0, n1, qmax)
+    T = rng.uniform(0, 50, qy.size)
+    w = rng.uniform(0.5, 1.5, qy.size)
+    L, dn, dm = orc.loss_grad(cl["pos"], cl["nuc"], cl["mag"], qy, qz, qhat, T, w)
+    loss, gdn, gdm = numag.grad(_sample(cl), grid, numag.consts(), weight=torch.as_tensor(w, device=DEV),
+                                target=torch.as_tensor(T, device=DEV))
+    assert abs(loss.item() - L) <= 1e-9 * abs(L)
+    assert max_norm_err(gdn.cpu().numpy(), dn) <= 1e-9
+    assert max_norm_err(gdm.cpu().numpy(), dm) <= 1e-9
