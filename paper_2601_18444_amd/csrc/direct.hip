@@ -194,12 +194,11 @@ __global__ __launch_bounds__(kThreads, 2) void direct_cartesian_kernel(
 
 int target_workgroups()
 {
-    static int cached = -1;
-    if (cached < 0) {
+    static const int cached = [] {  // thread-safe one-time initialisation
         const char *e = getenv("NUMAG_TARGET_WGS");
-        cached = e != nullptr ? atoi(e) : 0;
-        if (cached <= 0) cached = 2048;
-    }
+        const int v = e != nullptr ? atoi(e) : 0;
+        return v > 0 ? v : 2048;
+    }();
     return cached;
 }
 

@@ -191,13 +191,13 @@ __global__ void amp_reduce_kernel(const double *__restrict__ slots, int n_slots,
 
 int device_cus()
 {
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0;
+    static const int cus = [] {  // thread-safe one-time initialisation
+        int dev = 0, n = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-            cus = 256;
-    }
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+            n = 256;
+        return n;
+    }();
     return cus;
 }
 
