@@ -281,8 +281,8 @@ def calibrate_copy(torch):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(the multi-GPU layout is described in DESIGN.md)"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 "
+                                   "(splitting a job over several GPUs is not implemented)"}))
         sys.exit(2)
     import torch
 

@@ -11,7 +11,7 @@
  * or reordering: double loops in FP64 with libm sin/cos, OpenMP only over
  * independent output elements.  Complex arithmetic uses C99 complex.
  *
- * Conventions frozen here (each listed with its reading in the design doc):
+ * Conventions frozen here (each is a reading of the paper):
  *   - sums are the raw discrete sums S(q) = sum_j w_j exp(-i q.r_j); the
  *     (2 pi)^{-3/2} of the DSFT and the 8 pi^3 of the cross sections cancel
  *     (Sec. 2.1 eqs. NuclearSANS/MagneticSANS with Sec. 3.3), and the

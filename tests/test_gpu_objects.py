@@ -4,7 +4,7 @@ rotations, persistent launch, HIP-graph replay) with the FP64 oracle.
 The oracle side forms the dilute cross sections as sum_k obs(F_k) and the
 spectral matrix as sum_k F_k F_k^H from its per-object sums; the GPU side
 accumulates the spectral matrix in its kernel and evaluates the cross
-sections as linear functionals of it.  Tolerance: the spec gate
+sections as linear functionals of it.  Tolerance: the accuracy gate
 (relative error <= 1e-5 at pixels >= 1e-6 of the maximum)."""
 import numpy as np
 import pytest

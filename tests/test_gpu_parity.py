@@ -1,6 +1,6 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
-Tolerance: the spec gate, relative error <= 1e-5 per observable at the
+Tolerance: the accuracy gate, relative error <= 1e-5 per observable at the
 pixels whose reference magnitude is >= 1e-6 of its maximum (q = 0 excluded);
 integer outputs (bin counts) are compared bit-exactly.
 """

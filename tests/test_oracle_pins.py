@@ -134,7 +134,7 @@ def test_tiny_inputs_brute_force(orc):
 
 
 def test_forward_sum_at_q0_is_total_weight(orc):
-    """S(0) = sum_j w_j exactly (spec pin F(0) = sum of moments)."""
+    """S(0) = sum_j w_j exactly (the q = 0 sum is the sum of the weights)."""
     cl = synth.random_cloud(300, 20.0, seed=5)
     A = orc.amplitudes(cl["pos"], cl["nuc"], cl["mag"], np.zeros(1), np.zeros(1),
                        R=synth.sample_rotation(40, 10))
@@ -436,8 +436,7 @@ def test_azimuthal_average_cartesian_annuli(orc):
 def test_rotation_about_beam_shifts_polar_pattern(orc):
     """A sample rotation about the beam axis by one angular step rotates the
     unpolarized 2D pattern by one column (positions AND moments rotate), so its
-    azimuthal average is unchanged (spec pin: averages of a rotated
-    sample)."""
+    azimuthal average is unchanged."""
     cl = synth.random_cloud(150, 6.0, seed=15)
     nq, nt = 5, 24
     qy, qz, qhat = orc.pixels(orc.POLAR, nq, nt, 1.0)
