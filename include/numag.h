@@ -54,7 +54,7 @@ extern "C" {
 #define NUMAG_E_INVALID     -1  /* a bad argument; nothing was enqueued          */
 #define NUMAG_E_WORKSPACE   -2  /* workspace too small; nothing was enqueued     */
 #define NUMAG_E_HIP         -4  /* a HIP runtime call failed                     */
-#define NUMAG_E_UNSUPPORTED -5  /* valid request this build does not implement   */
+#define NUMAG_E_UNSUPPORTED -5  /* valid request the library does not implement  */
 
 /* ---- detector kinds ----------------------------------------------------- */
 #define NUMAG_GRID_CARTESIAN 0
