@@ -70,7 +70,7 @@ def parse():
 def polar_only(torch, numag, synth, launches=5, warmup=3):
     """Direct sums of the 64^3 vortex on a 256 x 256 polar detector (|q| <= 2 nm^-1).
     The warm-up launches let the engine clock settle before the timed ones."""
-    cfg = synth.vortex_c2()
+    cfg = synth.vortex_grid()
     W = cfg["pos"].shape[0]
     s = numag.Sample(pos=cfg["pos"], nuc=cfg["nuc"], mag=cfg["mag"], device="cuda:0")
     pgrid = numag.qgrid(1, 256, 256, 2.0)
@@ -95,7 +95,7 @@ def measure_batched(torch, numag, synth):
     128 x 128 detector: one persistent launch replayed from a HIP graph, next to the
     plain direct path run per (particle, rotation) on a sample of the rotations."""
     dev = "cuda:0"
-    cfg = synth.particles_c4()
+    cfg = synth.particles_rotations()
     g = cfg["grid"]
     grid = numag.qgrid(g["kind"], g["n0"], g["n1"], g["qmax"])
     s = numag.Sample(pos=cfg["pos"], nuc=cfg["nuc"], mag=cfg["mag"], obj_offsets=cfg["obj_offsets"], device=dev)
@@ -200,7 +200,7 @@ def measure_paper_scale(torch, numag, synth):
     grid): the 512-sphere ensemble (2.6e6 points) summed on a 1000 x 1000 polar
     detector, the unpolarized cross section, and its 2D correlation function."""
     dev = "cuda:0"
-    cfg = synth.spheres_c3()
+    cfg = synth.sphere_ensemble()
     W = cfg["pos"].shape[0]
     grid = numag.qgrid(1, 1000, 1000, 1.5)
     rgrid = numag.qgrid(1, 1000, 1000, 100.0)
@@ -304,7 +304,7 @@ def main():
 
     dev = "cuda:0"
     torch.cuda.set_device(0)
-    cfg = synth.vortex_c5()
+    cfg = synth.vortex_grid_gradient()
     g = cfg["grid"]
     grid = numag.qgrid(g["kind"], g["n0"], g["n1"], g["qmax"])
     W = cfg["pos"].shape[0]

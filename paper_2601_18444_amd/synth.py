@@ -9,19 +9,19 @@ the HIP path can both be fed from it.
 The paper's benchmark data (Sec. 4, published separately) is not used; these
 generators stand in for it with the shapes and structure of its examples:
 
-* ``sphere_c1``   -- the runtime-experiment particle of Sec. 4.4 (D = 40 nm on a
+* ``sphere_40nm``   -- the runtime-experiment particle of Sec. 4.4 (D = 40 nm on a
   2 nm simple-cubic lattice, 4169 cells) with the uniform magnetization of
   Sec. 4.1, on a 128 x 128 detector, |q_y|, |q_z| <= 1 nm^-1.
-* ``vortex_c2``   -- a 64^3 micromagnetic-style grid at 1 nm holding a vortex
+* ``vortex_grid``   -- a 64^3 micromagnetic-style grid at 1 nm holding a vortex
   (in-plane curl, Gaussian core of 5 nm, 2 % noise) inside a cylinder, on a
   256 x 256 detector, |q_y|, |q_z| <= 2 nm^-1.
-* ``spheres_c3``  -- 512 spheres (radii U(5, 15) nm) at random non-overlapping
+* ``sphere_ensemble``  -- 512 spheres (radii U(5, 15) nm) at random non-overlapping
   centres in a 500 nm cube, 1 nm lattice, tilted uniform moments; stands in for
   the iron-nanoparticle ensemble of Sec. 4.3.  512 x 512 detector, 1.5 nm^-1.
-* ``particles_c4`` -- 64 particles (spheres, cubes, cylinders) with point counts
+* ``particles_rotations`` -- 64 particles (spheres, cubes, cylinders) with point counts
   log-uniform in [1e3, 2e5] and smooth random unit fields, plus 1000 rotations
   uniform on SO(3); 128 x 128 detector, 1 nm^-1.
-* ``vortex_c5``   -- the c2 grid and a perturbed copy (core shifted 3 nm along x)
+* ``vortex_grid_gradient`` -- the vortex grid and a perturbed copy (core shifted 3 nm along x)
   from which the tests make a target cross section.
 """
 from __future__ import annotations
@@ -116,7 +116,7 @@ def detector(kind: int, n0: int, n1: int, qmax: float) -> dict:
 # ---------------------------------------------------------------------------
 # workloads
 # ---------------------------------------------------------------------------
-def sphere_c1() -> dict:
+def sphere_40nm() -> dict:
     """Uniform sphere, R = 20 nm, 2 nm lattice (W = 4169), N = 1, M = e_z."""
     pos = sphere_lattice(20.0, 2.0)
     W = pos.shape[0]
@@ -153,7 +153,7 @@ def vortex_field(n: int = 64, a: float = 1.0, core: float = 5.0, noise: float = 
     return pos, nuc, m
 
 
-def vortex_c2(n: int = 64, det: int = 256, qmax: float = 2.0, seed: int = 2) -> dict:
+def vortex_grid(n: int = 64, det: int = 256, qmax: float = 2.0, seed: int = 2) -> dict:
     pos, nuc, mag = vortex_field(n=n, seed=seed)
     c0 = -(n - 1) / 2.0
     return {
@@ -164,9 +164,9 @@ def vortex_c2(n: int = 64, det: int = 256, qmax: float = 2.0, seed: int = 2) -> 
     }
 
 
-def vortex_c5(n: int = 64, det: int = 256, qmax: float = 2.0, seed: int = 2, shift: float = 3.0):
-    """Configuration for the gradient: the c2 field and the perturbed target field."""
-    base = vortex_c2(n=n, det=det, qmax=qmax, seed=seed)
+def vortex_grid_gradient(n: int = 64, det: int = 256, qmax: float = 2.0, seed: int = 2, shift: float = 3.0):
+    """Configuration for the gradient: the vortex grid and the perturbed target field."""
+    base = vortex_grid(n=n, det=det, qmax=qmax, seed=seed)
     tpos, tnuc, tmag = vortex_field(n=n, seed=seed, centre_x=shift)
     base["target_field"] = {"pos": tpos, "nuc": tnuc, "mag": tmag}
     base["name"] = f"vortex_grid{n}_det{det}_grad"
@@ -206,7 +206,7 @@ def tilted_moment(e: np.ndarray, tilt_deg: float) -> np.ndarray:
     return math.cos(new) * z + math.sin(new) * perp
 
 
-def spheres_c3(n_spheres: int = 512, box: float = 500.0, rmin: float = 5.0, rmax: float = 15.0,
+def sphere_ensemble(n_spheres: int = 512, box: float = 500.0, rmin: float = 5.0, rmax: float = 15.0,
                a: float = 1.0, det: int = 512, qmax: float = 1.5, seed: int = 3) -> dict:
     """Ensemble of non-overlapping spheres by random sequential addition."""
     rng = np.random.default_rng(seed)
@@ -260,7 +260,7 @@ def _shape_points(shape: str, n_target: float, a: float = 1.0) -> np.ndarray:
     return pts[keep]
 
 
-def particles_c4(n_particles: int = 64, n_rot: int = 1000, nmin: float = 1e3, nmax: float = 2e5,
+def particles_rotations(n_particles: int = 64, n_rot: int = 1000, nmin: float = 1e3, nmax: float = 2e5,
                  det: int = 128, qmax: float = 1.0, seed: int = 4, scale_counts: float = 1.0) -> dict:
     """Particles of uneven size with smooth random unit magnetization fields and
     shared uniform rotations (dilute sample, orientational average)."""

@@ -37,7 +37,7 @@ def test_correlation_2d_of_sphere_cross_section(orc):
     """C of the unpolarized sphere cross section on a polar detector (the use of
     Sec. 4.1, Fig. 6d): the GPU pipeline sums -> cross section -> correlation
     against the oracle's."""
-    cfg = synth.sphere_c1()
+    cfg = synth.sphere_40nm()
     nq, nt, qmax = 48, 72, 1.0
     grid = numag.qgrid(1, nq, nt, qmax)
     s = numag.Sample(pos=cfg["pos"], nuc=cfg["nuc"], mag=cfg["mag"], device=DEV)

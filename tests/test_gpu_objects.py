@@ -120,7 +120,7 @@ def test_batched_orientations_graph_replay_c4_subsample(orc):
     replays (with eager work in between) equal the eager result bit for bit,
     and the two smallest particles are checked against the oracle over all
     1000 rotations on 48 sampled pixels."""
-    cfg = synth.particles_c4()
+    cfg = synth.particles_rotations()
     g = cfg["grid"]
     grid = numag.qgrid(g["kind"], g["n0"], g["n1"], g["qmax"])
     s = numag.Sample(pos=cfg["pos"], nuc=cfg["nuc"], mag=cfg["mag"], obj_offsets=cfg["obj_offsets"], device=DEV)
@@ -151,11 +151,11 @@ def test_batched_orientations_graph_replay_c4_subsample(orc):
     assert np.all(np.isfinite(un)) and un.min() >= -1e-9 * un.max()
 
 
-def test_c3_sphere_ensemble_split_full_size_sampled(orc):
+def test_sphere_ensemble_split_full_size_sampled(orc):
     """512 spheres (2.6e6 points, random non-overlapping centres in a 500 nm cube)
     on a 512 x 512 detector in split mode: form factor, interparticle
     interference and the spin-flip cross section, on 40 sampled pixels."""
-    cfg = synth.spheres_c3()
+    cfg = synth.sphere_ensemble()
     g = cfg["grid"]
     grid = numag.qgrid(g["kind"], g["n0"], g["n1"], g["qmax"])
     amp, spec = numag.amplitudes(_sample(cfg), grid, mode=numag.MODE_SPLIT)

@@ -45,10 +45,10 @@ def _check_amp(gpu, ref, exclude=None):
         assert e <= TOL, f"channel {c}: gated rel err {e:.3e}"
 
 
-def test_c1_sphere_full_pipeline(orc):
+def test_sphere_40nm_full_pipeline(orc):
     """Uniform sphere, 4169 points, 128x128 detector: sums, all 13 cross
     sections, the 64-bin azimuthal average and the correlation function."""
-    cfg = synth.sphere_c1()
+    cfg = synth.sphere_40nm()
     g = cfg["grid"]
     grid = _grid(g)
     s = _sample(cfg)
@@ -182,12 +182,12 @@ def test_determinism_bitwise(orc):
     assert torch.equal(a1, a2)
 
 
-def test_c2_vortex_full_size_sampled(orc):
+def test_vortex_grid_full_size_sampled(orc):
     """64^3 vortex grid, 256x256 detector at full size in the launch configuration
     the benchmark times; compared on 192 sampled pixels the oracle computes one
     by one, plus the whole detector's q_y <-> -q_y symmetry of |S_N| (a real
     weight field gives S(-q) = conj S(q))."""
-    cfg = synth.vortex_c2()
+    cfg = synth.vortex_grid()
     g = cfg["grid"]
     grid = _grid(g)
     amp, _ = numag.amplitudes(_sample(cfg), grid)
@@ -277,7 +277,7 @@ def test_separable_paths_c2_full_size(orc):
     """64^3 vortex grid, 256 x 256 detector: the FP64 separable path meets the
     1e-5 gate against the oracle (sampled pixels) and matches the direct path
     everywhere; the BF16x3 path's gated error is measured and reported."""
-    cfg = synth.vortex_c2()
+    cfg = synth.vortex_grid()
     g = cfg["grid"]
     grid = _grid(g)
     W = cfg["pos"].shape[0]
@@ -416,7 +416,7 @@ def test_fp64_level_accuracy_c1_and_vortex_sample(orc):
     and of every observable stay below 1e-9 (FP64 rounding relative to values at
     1e-6 of the maximum) on the sphere and on sampled pixels of the 64^3 vortex
     (phases up to about 126 rad)."""
-    for cfg, npix in ((synth.sphere_c1(), None), (synth.vortex_c2(), 96)):
+    for cfg, npix in ((synth.sphere_40nm(), None), (synth.vortex_grid(), 96)):
         g = cfg["grid"]
         grid = _grid(g)
         amp, _ = numag.amplitudes(_sample(cfg), grid)
@@ -498,14 +498,14 @@ def test_hermitian_path_edge_cases(orc):
     assert dn_h.numel() == 0 and dm_h.numel() == 0
 
 
-def test_c5_gradient_full_size_directional_derivative():
+def test_vortex_gradient_full_size_directional_derivative():
     """The gradient at full size (64^3 vortex, 256 x 256 detector, the benchmark's
     loss): its directional derivative along a random weight direction v equals
     the central difference (L(w + h v) - L(w - h v)) / 2h of the loss evaluated by
     the forward path.  L is quartic in the weights, so the difference is exact
     up to h^2 terms (h = 1e-4: about 1e-8 relative).  The half-detector gradient
     equals the full one at this size too."""
-    cfg = synth.vortex_c5()
+    cfg = synth.vortex_grid_gradient()
     g = cfg["grid"]
     grid = _grid(g)
     s = _sample(cfg)
