@@ -11,9 +11,9 @@ namespace numag {
 // columns and each walks 8 q rows, the first by the row-group start, the second
 // by one step exp(-i dq u), the rest by the two-term recurrence
 // p_{r+1} = 2 cos(dq u) p_r - p_{r-1}.  A workgroup of WV waves covers 8 WV rows,
-// so the per-(point, column) generation (u, two sincos for the step and the
-// block start exp(-i q(row0) u), the wave starts by powers of step^8) is shared
-// by 8 WV rows.
+// so the per-(point, column) generation (u, one sincos for the step, the block
+// start exp(-i q(row0) u) as a power of the step, the wave starts by the same
+// recurrence with step^8) is shared by 8 WV rows.
 // ---------------------------------------------------------------------------
 constexpr int kPolarChunk = 8;
 constexpr int kPolarB = 8;
@@ -134,13 +134,37 @@ __global__ __launch_bounds__(64 * WV, 8 / WV) void direct_polar_kernel(const Poi
             double2 sb = cmul(step, step);  // step^8: from one wave's rows to the next
             sb = cmul(sb, sb);
             sb = cmul(sb, sb);
-            double2 st = twiddle(qrow0 * u);  // start of the block
+            // start of the block exp(-i q(row0) u): with q rows from zero it is
+            // step^row0 = (step^(8 WV))^blockIdx.y by binary powering (uniform over
+            // the workgroup; the phase error is that of one product q(row0) u,
+            // plus about one rounding per squaring per doubling)
+            double2 st;
+            if (d.origin0 == 0.0) {
+                double2 base = sb;
+#pragma unroll
+                for (int w = 1; w < WV; w += w) base = cmul(base, base);
+                st = make_double2(1.0, 0.0);
+                for (unsigned e = blockIdx.y; e != 0; e >>= 1) {
+                    if (e & 1) st = cmul(st, base);
+                    if (e > 1) base = cmul(base, base);
+                }
+            } else {
+                st = twiddle(qrow0 * u);
+            }
             s_step[b][jj][lane] = step;
             s_k[b][jj][lane] = step.x + step.x;
+            // wave starts st sb^w by the two-term recurrence in w (7 steps: the error
+            // grows at most linearly in w)
+            const double k8 = sb.x + sb.x;
+            double2 pm = st, pc = cmul(st, sb);
+            s_start[b][jj][0][lane] = pm;
+            s_start[b][jj][1][lane] = pc;
 #pragma unroll
-            for (int w = 0; w < WV; ++w) {
-                s_start[b][jj][w][lane] = st;
-                st = cmul(st, sb);
+            for (int w = 2; w < WV; ++w) {
+                const double2 pn = make_double2(fma(k8, pc.x, -pm.x), fma(k8, pc.y, -pm.y));
+                s_start[b][jj][w][lane] = pn;
+                pm = pc;
+                pc = pn;
             }
         }
         if (wj < CHK) s_w[b][wj][wc] = nW;

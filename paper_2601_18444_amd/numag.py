@@ -131,7 +131,10 @@ def _dev(x, device, shape=None):
     if isinstance(x, torch.Tensor):
         t = x.to(device=device, dtype=torch.float64)
     else:
-        t = torch.as_tensor(np.asarray(x, dtype=np.float64), device=device)
+        a = np.asarray(x, dtype=np.float64)
+        if not a.flags.writeable:  # read-only views (broadcasts): torch wants a writable buffer
+            a = a.copy()
+        t = torch.as_tensor(a, device=device)
     t = t.contiguous()
     if shape is not None:
         t = t.reshape(shape)

@@ -148,6 +148,23 @@ def test_polar_detector_row_blocks(orc, nq, nt):
     _check_amp(amp_to_complex(amp[0]), _oracle_amp(orc, cl, qy, qz, R=R))
 
 
+def test_polar_detector_many_row_blocks_large_phases(orc):
+    """Ten 64-row q blocks (block starts up to step^576 by binary powering) with
+    phases to about 500 rad: every channel within 1e-11 of the largest oracle
+    amplitude, far inside the gated tolerance."""
+    cl = synth.random_cloud(1200, 120.0, seed=31)
+    nq, nt = 640, 24
+    grid = numag.qgrid(1, nq, nt, 3.0)
+    R = synth.sample_rotation(-20, 65)
+    amp, _ = numag.amplitudes(_sample(cl), grid, rot=R)
+    qy, qz, _ = orc.pixels(1, nq, nt, 3.0)
+    gpu = amp_to_complex(amp[0])
+    ref = _oracle_amp(orc, cl, qy, qz, R=R)
+    _check_amp(gpu, ref)
+    for c in range(4):
+        assert max_norm_err(gpu[:, c], ref[:, c]) <= 1e-11, c
+
+
 def test_edge_cases_empty_single_pixel_zero_q(orc):
     """W = 0 gives zeros; a 1x1 detector is the q = 0 pixel; odd n includes q = 0."""
     grid = numag.qgrid(0, 16, 16, 1.0)
