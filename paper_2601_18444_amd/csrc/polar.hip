@@ -18,18 +18,18 @@ namespace numag {
 constexpr int kPolarChunk = 8;
 constexpr int kPolarB = 8;
 
-// Operands of point jj for this lane: ez = the wave's start phasor, dz = the q step.
+// Operands of point jj for this lane: ez = the wave's start phasor, dz = the q step
+// (the recurrence coefficient 2 Re dz is formed where it is used).
 template <int WV, int R>
 __device__ __forceinline__ cart::Operands polar_operands(const double2 (&s_start)[R][WV][64],
                                                          const double2 (&s_step)[R][64],
-                                                         const double (&s_k)[R][64],
                                                          const double (&s_w)[R][4], int jj, int lane,
                                                          int wave)
 {
     cart::Operands o;
     o.ez = s_start[jj][wave][lane];
     o.dz = s_step[jj][lane];
-    o.k = s_k[jj][lane];
+    o.k = 0.0;
 #pragma unroll
     for (int v = 0; v < 4; ++v) o.w[v] = s_w[jj][v];
     return o;
@@ -39,13 +39,14 @@ __device__ __forceinline__ cart::Operands polar_operands(const double2 (&s_start
 template <int B, int CH>
 __device__ __forceinline__ void polar_point(const cart::Operands &o, double (&acc)[B][2 * CH])
 {
+    const double k = o.dz.x + o.dz.x;
     double2 pm = o.ez;
     double2 pc = cmul(pm, o.dz);
     cart::add_weighted<CH>(o, pm, acc[0]);
     cart::add_weighted<CH>(o, pc, acc[1]);
 #pragma unroll
     for (int r = 2; r < B; ++r) {
-        const double2 pn = make_double2(fma(o.k, pc.x, -pm.x), fma(o.k, pc.y, -pm.y));
+        const double2 pn = make_double2(fma(k, pc.x, -pm.x), fma(k, pc.y, -pm.y));
         cart::add_weighted<CH>(o, pn, acc[r]);
         pm = pc;
         pc = pn;
@@ -53,7 +54,7 @@ __device__ __forceinline__ void polar_point(const cart::Operands &o, double (&ac
 }
 
 // LDS buffers of the polar kernel: two at WV = 8 (the next chunk is generated into
-// one while the other is summed, one barrier per chunk, 157 KB), one at WV = 4
+// one while the other is summed, one barrier per chunk, 149 KB), one at WV = 4
 // (two workgroups per CU).
 template <int WV>
 constexpr int polar_buffers()
@@ -77,7 +78,6 @@ __global__ __launch_bounds__(64 * WV, 8 / WV) void direct_polar_kernel(const Poi
     constexpr int R = NB == 2 ? CHK : CHK + 1;
     __shared__ double2 s_start[NB][R][WV][64];
     __shared__ double2 s_step[NB][R][64];
-    __shared__ double s_k[NB][R][64];
     __shared__ double s_w[NB][R][4];
     __shared__ double2 s_trig[64];  // (sin, cos) of the lane's column angle
 
@@ -136,8 +136,9 @@ __global__ __launch_bounds__(64 * WV, 8 / WV) void direct_polar_kernel(const Poi
             sb = cmul(sb, sb);
             // start of the block exp(-i q(row0) u): with q rows from zero it is
             // step^row0 = (step^(8 WV))^blockIdx.y by binary powering (uniform over
-            // the workgroup; the phase error is that of one product q(row0) u,
-            // plus about one rounding per squaring per doubling)
+            // the workgroup; the rounding of dq u is carried row0 times, a few
+            // times the error of a sincos of q(row0) u, and each squaring adds one
+            // rounding)
             double2 st;
             if (d.origin0 == 0.0) {
                 double2 base = sb;
@@ -152,7 +153,6 @@ __global__ __launch_bounds__(64 * WV, 8 / WV) void direct_polar_kernel(const Poi
                 st = twiddle(qrow0 * u);
             }
             s_step[b][jj][lane] = step;
-            s_k[b][jj][lane] = step.x + step.x;
             // wave starts st sb^w by the two-term recurrence in w (7 steps: the error
             // grows at most linearly in w)
             const double k8 = sb.x + sb.x;
@@ -172,15 +172,15 @@ __global__ __launch_bounds__(64 * WV, 8 / WV) void direct_polar_kernel(const Poi
     // sums of the nk points in buffer b; the operands of the next point are
     // requested before the current point is accumulated (as in the Cartesian loop)
     auto sum = [&](int b, int nk) {
-        cart::Operands opa = polar_operands<WV, R>(s_start[b], s_step[b], s_k[b], s_w[b], 0, lane, wave);
+        cart::Operands opa = polar_operands<WV, R>(s_start[b], s_step[b], s_w[b], 0, lane, wave);
         int jj = 0;
         for (; jj + 1 < nk; jj += 2) {
-            const cart::Operands opb = polar_operands<WV, R>(s_start[b], s_step[b], s_k[b], s_w[b], jj + 1, lane, wave);
+            const cart::Operands opb = polar_operands<WV, R>(s_start[b], s_step[b], s_w[b], jj + 1, lane, wave);
             __builtin_amdgcn_sched_barrier(0);
             polar_point<B, CH>(opa, acc);
             __builtin_amdgcn_sched_barrier(0);
             const int nxt = NB == 2 ? min(jj + 2, CHK - 1) : jj + 2;  // past the end: discarded
-            opa = polar_operands<WV, R>(s_start[b], s_step[b], s_k[b], s_w[b], nxt, lane, wave);
+            opa = polar_operands<WV, R>(s_start[b], s_step[b], s_w[b], nxt, lane, wave);
             __builtin_amdgcn_sched_barrier(0);
             polar_point<B, CH>(opb, acc);
             __builtin_amdgcn_sched_barrier(0);
