@@ -58,8 +58,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the separate orientation-batch measurement")
     ap.add_argument("--polar", action="store_true",
-                    help="only time the direct sums of the same points on a 256 q x 256 theta polar "
-                         "detector (a short run for the polar kernel's profiles)")
+                    help="only time the direct sums and the loss gradient of the same points on a "
+                         "256 q x 256 theta polar detector (a short run for the polar kernels' profiles)")
     ap.add_argument("--snapshots", action="store_true",
                     help="only run the loop-mode snapshot measurement (64 snapshots, separable path)")
     ap.add_argument("--batched", action="store_true",
@@ -68,8 +68,9 @@ def parse():
 
 
 def polar_only(torch, numag, synth, launches=5, warmup=3):
-    """Direct sums of the 64^3 vortex on a 256 x 256 polar detector (|q| <= 2 nm^-1).
-    The warm-up launches let the engine clock settle before the timed ones."""
+    """Direct sums of the 64^3 vortex on a 256 x 256 polar detector (|q| <= 2 nm^-1),
+    then the loss gradient's adjoint sum on the same detector.  The warm-up launches
+    let the engine clock settle before the timed ones."""
     cfg = synth.vortex_grid()
     W = cfg["pos"].shape[0]
     s = numag.Sample(pos=cfg["pos"], nuc=cfg["nuc"], mag=cfg["mag"], device="cuda:0")
@@ -85,9 +86,26 @@ def polar_only(torch, numag, synth, launches=5, warmup=3):
     t, n = numag.kernel_timer_read(numag.KERNEL_DIRECT)
     numag.kernel_timer(False)
     ms = t / n
+    # the loss gradient on the same detector (adjoint sum over every term): target =
+    # 0.9 x the sample's own unpolarized cross section, weights 1 / (T + 1e-3 max T)^2
+    k = numag.consts(V=1.0, bH=1.0, scale=1.0, P=(0.0, 0.0, 1.0))
+    T = (0.9 * numag.cross_section(pgrid, amp=amp, c=k, obs=("UNPOL",))[0, 0]).contiguous()
+    w = (1.0 / (T + 1e-3 * T.max()) ** 2).contiguous()
+    for _ in range(warmup):
+        numag.grad(s, pgrid, k, weight=w, target=T, amp=amp[0])
+    torch.cuda.synchronize()
+    numag.kernel_timer(True)
+    for _ in range(launches):
+        numag.grad(s, pgrid, k, weight=w, target=T, amp=amp[0])
+    torch.cuda.synchronize()
+    ta, na = numag.kernel_timer_read(numag.KERNEL_ADJOINT)
+    numag.kernel_timer(False)
+    ams = ta / na
     print(json.dumps({"workload": "vortex grid 64^3 (262144 points), 256 q x 256 theta polar detector, |q| <= 2 nm^-1",
                       "direct_polar_kernel_ms": round(ms, 4),
-                      "Gterm_s": round(W * pgrid.n_pixels / ms / 1e6, 1), "launches": n}))
+                      "Gterm_s": round(W * pgrid.n_pixels / ms / 1e6, 1), "launches": n,
+                      "adjoint_polar_kernel_ms": round(ams, 4),
+                      "adjoint_Gterm_s": round(W * pgrid.n_pixels / ams / 1e6, 1), "adjoint_launches": na}))
 
 
 def measure_batched(torch, numag, synth):
