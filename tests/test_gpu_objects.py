@@ -326,14 +326,15 @@ def test_released_workspace_tables_are_uploaded_again():
     assert float(ref.abs().max()) > 0.0
 
 
-@pytest.mark.parametrize("nq,nt,path", [(24, 30, 0), (40, 36, 0), (40, 36, 3)])
+@pytest.mark.parametrize("nq,nt,path", [(24, 30, 0), (40, 36, 0), (40, 36, 3), (130, 20, 0), (130, 20, 3)])
 def test_dilute_polar_rotation_groups(orc, nq, nt, path):
     """Dilute mode on a polar detector runs each object over groups of rotations
     (one launch sequence per group, as many rotations as the sample's buffers
     and the chip take): objects from 1 to 3000 points and an empty one give
     groups of one rotation up to all 37, on 4-wave (24 q rows) and 8-wave (40 q
-    rows) kernels and on the half-detector path; every object's orientational
-    average against the oracle."""
+    rows; 130 q rows: three row blocks, whose starts are powers of the q step)
+    kernels and on the half-detector path; every object's orientational average
+    against the oracle."""
     cfg = _objects(64, [5, 200, 3000, 0, 40, 1, 800], spread=0.0)
     rots = synth.uniform_rotations(37, np.random.default_rng(65))
     qmax = 1.1
