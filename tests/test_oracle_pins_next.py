@@ -65,3 +65,40 @@ def test_modal_amplitudes_sin2cos2(orc):
     assert np.max(np.abs(Ic[:, others])) < 1e-13 and np.max(np.abs(Is)) < 1e-13
     As, Ac = orc.modal_amplitudes(Is, Ic)
     assert abs(Ac[0] / Ac[4] + 1.0) < 1e-12
+
+
+def test_correlation_2d_abel_relation_to_1d_correlation(orc):
+    """Sec. 2.6: for an isotropic cross section the azimuthally constant C(rho) and
+    c(r) of eq. crrad are related by an Abel transform.  The detector plane is the
+    q_x = 0 slice of the 3D transform, so its 2D inverse transform is the projection
+    of c along the beam: C(rho) = 4 pi^2 int c(sqrt(rho^2 + x^2)) dx over the whole
+    x axis.  Both sides come from the oracle (eq. crav2d on a polar detector, eq.
+    crrad on its q axis) for I(q) = (1 + q^2 a^2) exp(-q^2 b^2), which is not a
+    Hankel pair of either closed form; the x integral uses Gauss-Legendre nodes.
+    The two q quadratures are both second order and differ by the weight of the
+    detector's centre, 2 pi h^2 / 12 f(0) for the q step h, which bounds the
+    comparison.  The paper's remark that c is not the azimuthal average of C is
+    checked too: C(rho) / C(0) and c(rho) / c(0) differ by far more."""
+    a, b = 3.0, 1.5
+    nq, nt, qmax = 400, 64, 6.0
+    qy, qz, _ = orc.pixels(orc.POLAR, nq, nt, qmax)
+    q2 = qy ** 2 + qz ** 2
+    f = (1.0 + q2 * a * a) * np.exp(-q2 * b * b)
+    nr, na, rmax = 11, 5, 10.0
+    C = orc.correlation_2d(orc.POLAR, nq, nt, qmax, f, orc.POLAR, nr, na, rmax)[0].reshape(nr, na)
+    # isotropic data: the same value at every alpha, and real
+    assert np.max(np.abs(C - C[:, :1])) < 1e-12 * np.abs(C).max()
+    assert np.max(np.abs(C.imag)) < 1e-12 * np.abs(C).max()
+    rho = np.arange(nr) * rmax / (nr - 1)
+    q = np.arange(1, nq) * qmax / (nq - 1)  # the detector's q rows (q = 0 adds nothing)
+    Iq = (1.0 + q * q * a * a) * np.exp(-q * q * b * b)
+    x, wx = np.polynomial.legendre.leggauss(160)
+    X = 24.0  # c(r) < 1e-25 c(0) beyond
+    x, wx = (x + 1.0) * X / 2.0, wx * X / 2.0
+    r = np.sqrt(rho[:, None] ** 2 + x[None, :] ** 2)
+    c, _ = orc.correlation(q, Iq[None, :], r.reshape(-1))
+    abel = 8.0 * math.pi ** 2 * (c[0].reshape(r.shape) @ wx)
+    h = qmax / (nq - 1)
+    assert np.max(np.abs(C[:, 0].real - abel)) < 2.0 * (2.0 * math.pi * h * h / 12.0) * f.max()
+    c_rho, _ = orc.correlation(q, Iq[None, :], rho)
+    assert np.max(np.abs(C[:, 0].real / C[0, 0].real - c_rho[0] / c_rho[0, 0])) > 0.05
