@@ -75,9 +75,10 @@ def test_correlation_2d_abel_relation_to_1d_correlation(orc):
     x axis.  Both sides come from the oracle (eq. crav2d on a polar detector, eq.
     crrad on its q axis) for I(q) = (1 + q^2 a^2) exp(-q^2 b^2), which is not a
     Hankel pair of either closed form; the x integral uses Gauss-Legendre nodes.
-    The two q quadratures are both second order and differ by the weight of the
-    detector's centre, 2 pi h^2 / 12 f(0) for the q step h, which bounds the
-    comparison.  The paper's remark that c is not the azimuthal average of C is
+    The two trapezoidal rules in q differ by their Euler-Maclaurin end terms at
+    q = 0: the 2D integrand q f J0 has slope f(0) there, the 1D one q^2 I j0 slope
+    zero, so the 2D sum lies 2 pi h^2 / 12 f(0) below the integral (q step h); that
+    term bounds the comparison.  The paper's remark that c is not the azimuthal average of C is
     checked too: C(rho) / C(0) and c(rho) / c(0) differ by far more."""
     a, b = 3.0, 1.5
     nq, nt, qmax = 400, 64, 6.0
@@ -102,3 +103,38 @@ def test_correlation_2d_abel_relation_to_1d_correlation(orc):
     assert np.max(np.abs(C[:, 0].real - abel)) < 2.0 * (2.0 * math.pi * h * h / 12.0) * f.max()
     c_rho, _ = orc.correlation(q, Iq[None, :], rho)
     assert np.max(np.abs(C[:, 0].real / C[0, 0].real - c_rho[0] / c_rho[0, 0])) > 0.05
+
+
+def test_correlation_2d_of_uniform_sphere(orc):
+    """For a uniform sphere of radius R, f = |F|^2 with F = V 3 j1(qR) / (qR) is the
+    transform of the autocorrelation V gamma0(r), gamma0 = 1 - 3r/(4R) + r^3/(16R^3)
+    for r <= 2R (the same closed form as the 1D sphere pin), so eq. crav2d gives
+    C(rho) = 8 pi^2 V int_0^sqrt(4R^2 - rho^2) gamma0(sqrt(rho^2 + x^2)) dx.  The
+    oracle's trapezoid in q lies 2 pi h^2 / 12 f(0) below the integral (the
+    Euler-Maclaurin end term at q = 0, q step h) and misses the tail beyond q_max,
+    at most 2 pi int |F|^2 q dq ~ 4.5 pi V^2 / (R^4 q_max^2) (at rho = 0); the
+    theta trapezoid is exact once n_theta exceeds q_max rho."""
+    R = 5.0
+    V = 4.0 / 3.0 * math.pi * R ** 3
+    nq, nt, qmax = 2001, 256, 20.0
+    qy, qz, _ = orc.pixels(orc.POLAR, nq, nt, qmax)
+    x = np.sqrt(qy ** 2 + qz ** 2) * R
+    xs = np.where(x > 1e-3, x, 1.0)
+    F = V * np.where(x > 1e-3, 3.0 * (np.sin(xs) - xs * np.cos(xs)) / xs ** 3, 1.0 - x * x / 10.0)
+    f = F * F
+    nr, na, rmax = 6, 4, 2.0 * R * 5.0 / 6.0
+    C = orc.correlation_2d(orc.POLAR, nq, nt, qmax, f, orc.POLAR, nr, na, rmax)[0].reshape(nr, na)
+    rho = np.arange(nr) * rmax / (nr - 1)
+    g, w = np.polynomial.legendre.leggauss(64)
+    expect = np.empty(nr)
+    for i, p in enumerate(rho):
+        L = math.sqrt(4.0 * R * R - p * p)
+        r = np.sqrt(p * p + ((g + 1.0) * L / 2.0) ** 2)
+        expect[i] = 8.0 * math.pi ** 2 * V * np.sum((1.0 - 0.75 * r / R + r ** 3 / (16.0 * R ** 3)) * w * L / 2.0)
+    h = qmax / (nq - 1)
+    end = 2.0 * math.pi * h * h / 12.0 * V * V
+    tail = 4.5 * math.pi * V * V / (R ** 4 * qmax ** 2)
+    for j in range(na):
+        assert np.max(np.abs(C[:, j].real - (expect - end))) < 1.25 * tail
+    assert np.max(np.abs(C.imag)) < 1e-9 * expect[0]
+    assert tail < 2e-4 * expect[0]
