@@ -155,6 +155,18 @@ def measure_batched(torch, numag, synth):
     torch.cuda.synchronize()
     t_plain = e0.elapsed_time(e1) * 1e-3
     plain_terms = W * len(sample_rots) * grid.n_pixels
+    # the same particles and average on a polar detector of the same size, first 50
+    # rotations: rotation groups on the polar direct kernel
+    pgrid = numag.qgrid(1, g["n0"], g["n1"], g["qmax"])
+    prots = rots[:50]
+    numag.amplitudes(s, pgrid, rot=prots[:2], mode=numag.MODE_DILUTE, spec_per_object=True)  # warm-up
+    torch.cuda.synchronize()
+    e0.record()
+    numag.amplitudes(s, pgrid, rot=prots, mode=numag.MODE_DILUTE, spec_per_object=True)
+    e1.record()
+    torch.cuda.synchronize()
+    t_polar = e0.elapsed_time(e1) * 1e-3
+    polar_terms = W * len(prots) * pgrid.n_pixels
     return {
         "workload": "64 particles (1331-173157 points, 2298012 total) x 1000 rotations, 128x128 detector, "
                     "dilute per-particle orientational average (spectral matrix), persistent launch + HIP graph",
@@ -165,6 +177,10 @@ def measure_batched(torch, numag, synth):
         "batched_hermitian_max_diff": herm_diff,
         "plain_direct_per_orientation_Gterm_s": round(plain_terms / t_plain / 1e9, 2),
         "plain_direct_sample": "same particles, first 8 rotations, one coherent direct call per (particle, rotation)",
+        "polar_dilute_s": round(t_polar, 4),
+        "polar_dilute_Gterm_s": round(polar_terms / t_polar / 1e9, 2),
+        "polar_dilute_sample": "same particles, first 50 rotations, 128 q x 128 theta polar detector, dilute "
+                               "per-particle average (rotation groups on the polar direct kernel)",
     }
 
 
