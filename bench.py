@@ -105,7 +105,10 @@ def polar_only(torch, numag, synth, launches=5, warmup=3):
                       "direct_polar_kernel_ms": round(ms, 4),
                       "Gterm_s": round(W * pgrid.n_pixels / ms / 1e6, 1), "launches": n,
                       "adjoint_polar_kernel_ms": round(ams, 4),
-                      "adjoint_Gterm_s": round(W * pgrid.n_pixels / ams / 1e6, 1), "adjoint_launches": na}))
+                      "adjoint_Gterm_s": round(W * pgrid.n_pixels / ams / 1e6, 1), "adjoint_launches": na,
+                      "direct_polar_frac": round(FLOPS_PER_TERM * W * pgrid.n_pixels / (ms * 1e-3) / PEAK_FP64_VALU, 4),
+                      "adjoint_polar_frac": round(FLOPS_PER_TERM * W * pgrid.n_pixels / (ams * 1e-3) / PEAK_FP64_VALU,
+                                                  4)}))
 
 
 def measure_batched(torch, numag, synth):
@@ -503,6 +506,13 @@ def main():
             "adjoint_Gterm_s": round(terms / (t_adj * 1e-3) / 1e9, 2),
             "adjoint_ms": round(t_adj, 4),
             "adjoint_kernel_ms": round(kernel_ms["adjoint_cartesian_kernel"], 4),
+            # the adjoint kernel against the same FP64 VALU peak (20 flops per term)
+            "adjoint_roofline": {
+                "achieved": round(FLOPS_PER_TERM * terms / (kernel_ms["adjoint_cartesian_kernel"] * 1e-3) / 1e12, 3),
+                "frac": round(FLOPS_PER_TERM * terms / (kernel_ms["adjoint_cartesian_kernel"] * 1e-3)
+                              / PEAK_FP64_VALU, 4),
+                "traffic": traffic_per_launch("adjoint_cartesian_kernel"),
+            },
             "adjoint_hermitian_ms": round(t_adj_herm, 4) if t_adj_herm else None,
             "adjoint_hermitian_Gterm_s_effective": round(terms / (t_adj_herm * 1e-3) / 1e9, 2) if t_adj_herm else None,
             "adjoint_hermitian_max_diff_vs_adjoint": adj_herm_err,
