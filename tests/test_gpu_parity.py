@@ -318,7 +318,9 @@ def test_separable_paths_c2_full_size(orc):
                               obs=("N", "M", "UNPOL"))[0].cpu().numpy()
     errs = [gated_rel_err(xbf[i], x64[i]) for i in range(3)]
     print(f"BF16x3 separable gated rel err N/M/unpol: {errs}")
-    assert max(errs) < 5e-2
+    # measured about 2e-3: the BF16x3 split misses the 1e-4 matrix-core gate, and this
+    # bound only guards against a regression of that level
+    assert max(errs) < 5e-3
 
 
 @pytest.mark.parametrize("n0,n1", [(13, 50), (11, 100), (9, 200), (7, 300), (5, 700)])
