@@ -6,9 +6,12 @@ A step is one pass of the whole hot path over the 64^3 vortex grid on a
   the 128-bin azimuthal average, the correlation function (256 radii), the
   regular-grid separable sums on the matrix cores (when built), and the loss
   gradient through the adjoint sum.
-Every W x P point-pixel sum the step performs counts W*P terms; `value` is
-terms per second of the whole step (G terms/s).  Inputs are resident in HBM
-before timing starts.  Prints one JSON line.
+`value` counts the terms the step evaluates one by one -- W*P for the direct
+sums and W*P for the adjoint sums -- over the time of the whole step (every
+other part of the step, the separable matrix-core sums included, adds time but
+no terms); the separable path's equivalent-term rate and the rate of the direct
+call alone are reported under `paths`.  Inputs are resident in HBM before
+timing starts.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -28,6 +31,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP64_VALU = 256 * 2.4e9 * 64 * 2  # 78.6 TFLOP/s: 256 CUs x 64 FP64 FMA lanes x 2 flops x 2.4 GHz
+PEAK_FP32_VALU = 157.3e12              # packed FP32 vector peak (datasheet)
+PEAK_FP64_MFMA = 78.6e12               # FP64 dense matrix peak (datasheet)
 # algorithmic work of one (point, pixel) term: the phase q.X (2 FMA) and the
 # four channel sums, real and imaginary parts (8 FMA); the sine and cosine are
 # not counted
@@ -40,6 +45,11 @@ KERNELS = {
     "adjoint_cartesian_kernel": (1, ["adjoint.hip", "phasor.h", "types.h"],
                                  "adjoint_cartesian_kernel_vortex64_256x256_pmc.md"),
 }
+# kernels measured outside the step (their counter summaries, same format)
+SIDE_KERNELS = {
+    "direct_polar_kernel": (0, ["cartesian_sum.h", "polar.hip", "phasor.h", "types.h"],
+                            "direct_polar_kernel_vortex64_polar256x256.md"),
+}
 
 
 def parse():
@@ -51,6 +61,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=49152,
                     help="pixels of the oracle's bounded sample")
+    ap.add_argument("--cpu-pixels-1core", type=int, default=1024,
+                    help="pixels of the oracle's one-thread sample (a subset of the above)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run one plain 1 GiB device-to-device copy (reference for HBM counters)")
     ap.add_argument("--no-hermitian", action="store_true",
@@ -64,6 +76,8 @@ def parse():
                     help="only run the loop-mode snapshot measurement (64 snapshots, separable path)")
     ap.add_argument("--batched", action="store_true",
                     help="only run the orientation-batch measurement (64 particles x 1000 rotations)")
+    ap.add_argument("--ensemble", action="store_true",
+                    help="only run the 512-sphere split-mode measurement (512 x 512 detector)")
     return ap.parse_args()
 
 
@@ -101,14 +115,20 @@ def polar_only(torch, numag, synth, launches=5, warmup=3):
     ta, na = numag.kernel_timer_read(numag.KERNEL_ADJOINT)
     numag.kernel_timer(False)
     ams = ta / na
-    print(json.dumps({"workload": "vortex grid 64^3 (262144 points), 256 q x 256 theta polar detector, |q| <= 2 nm^-1",
-                      "direct_polar_kernel_ms": round(ms, 4),
-                      "Gterm_s": round(W * pgrid.n_pixels / ms / 1e6, 1), "launches": n,
-                      "adjoint_polar_kernel_ms": round(ams, 4),
-                      "adjoint_Gterm_s": round(W * pgrid.n_pixels / ams / 1e6, 1), "adjoint_launches": na,
-                      "direct_polar_frac": round(FLOPS_PER_TERM * W * pgrid.n_pixels / (ms * 1e-3) / PEAK_FP64_VALU, 4),
-                      "adjoint_polar_frac": round(FLOPS_PER_TERM * W * pgrid.n_pixels / (ams * 1e-3) / PEAK_FP64_VALU,
-                                                  4)}))
+    flops = FLOPS_PER_TERM * W * pgrid.n_pixels
+    return {"workload": "vortex grid 64^3 (262144 points), 256 q x 256 theta polar detector, |q| <= 2 nm^-1",
+            "direct_polar_kernel_ms": round(ms, 4),
+            "Gterm_s": round(W * pgrid.n_pixels / ms / 1e6, 1), "launches": n,
+            "adjoint_polar_kernel_ms": round(ams, 4),
+            "adjoint_Gterm_s": round(W * pgrid.n_pixels / ams / 1e6, 1), "adjoint_launches": na,
+            "roofline": {"kernel": "direct_polar_kernel", "bound": "alu",
+                         "achieved": round(flops / (ms * 1e-3) / 1e12, 3), "peak": round(PEAK_FP64_VALU / 1e12, 3),
+                         "unit": "TFLOP/s", "frac": round(flops / (ms * 1e-3) / PEAK_FP64_VALU, 4),
+                         "frac_fp32_valu": round(flops / (ms * 1e-3) / PEAK_FP32_VALU, 4),
+                         "traffic": traffic_per_launch("direct_polar_kernel")},
+            "adjoint_roofline": {"kernel": "adjoint_polar_kernel", "bound": "alu",
+                                 "achieved": round(flops / (ams * 1e-3) / 1e12, 3),
+                                 "frac": round(flops / (ams * 1e-3) / PEAK_FP64_VALU, 4)}}
 
 
 def measure_batched(torch, numag, synth):
@@ -228,6 +248,11 @@ def measure_snapshots(torch, numag, synth, n_snap=64):
         "batched_Gterm_s_effective": round(n_snap * W * grid.n_pixels / t_batch / 1e9, 1),
         "batched_mfma_TFLOP_s": round(flops / t_batch / 1e12, 3),
         "single_calls_per_snapshot_us": round(t_single / n_snap * 1e6, 2),
+        # the whole batched call (projection, twiddles, both contractions) against the
+        # FP64 matrix peak, the flops being those of the two contractions
+        "roofline": {"bound": "mfma", "achieved": round(flops / t_batch / 1e12, 3),
+                     "peak": round(PEAK_FP64_MFMA / 1e12, 1), "unit": "TFLOP/s",
+                     "frac": round(flops / t_batch / PEAK_FP64_MFMA, 4), "flops_per_call": flops},
     }
 
 
@@ -277,6 +302,60 @@ def measure_paper_scale(torch, numag, synth):
     }
 
 
+def measure_ensemble_split(torch, numag, synth, reps=3):
+    """The 512-sphere ensemble (about 2.6e6 points, random non-overlapping centres
+    in a 500 nm cube) on a 512 x 512 Cartesian detector (|q_y|, |q_z| <= 1.5 nm^-1)
+    in split mode: one call gives the coherent sums and the form-factor spectral
+    matrix; the form factor, the interparticle interference (coherent minus form
+    factor) and the spin-flip cross section follow from them."""
+    dev = "cuda:0"
+    cfg = synth.sphere_ensemble()
+    g = cfg["grid"]
+    grid = numag.qgrid(g["kind"], g["n0"], g["n1"], g["qmax"])
+    s = numag.Sample(pos=cfg["pos"], nuc=cfg["nuc"], mag=cfg["mag"], obj_offsets=cfg["obj_offsets"],
+                     obj_pos=cfg["obj_pos"], device=dev)
+    W = cfg["pos"].shape[0]
+    P = grid.n_pixels
+    k = numag.consts(V=1.0, bH=1.0, scale=1.0, P=(0.0, 0.0, 1.0))
+    obs = ("N", "M", "SF", "UNPOL")
+    nws = numag.workspace_size(s, grid, 1, numag.PATH_DIRECT, numag.MODE_SPLIT)
+    ws = torch.empty(nws, dtype=torch.uint8, device=dev)
+    amp = torch.empty((1, P, 4, 2), dtype=torch.float64, device=dev)
+    spec = torch.empty((1, P, 16), dtype=torch.float64, device=dev)
+
+    def run():
+        numag.amplitudes(s, grid, mode=numag.MODE_SPLIT, out=amp, spec_out=spec, ws=ws)
+        ff = numag.cross_section(grid, spec=spec, c=k, obs=obs)
+        tot = numag.cross_section(grid, amp=amp, c=k, obs=obs)
+        return ff, tot - ff
+
+    run()  # warm-up
+    torch.cuda.synchronize()
+    numag.kernel_timer(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / reps
+    tk, nk = numag.kernel_timer_read(numag.KERNEL_OBJECTS)
+    numag.kernel_timer(False)
+    kms = tk / nk
+    flops = FLOPS_PER_TERM * W * P
+    return {
+        "workload": f"512-sphere ensemble ({W} points) on a 512x512 detector |q|<=1.5 nm^-1, split mode: "
+                    "coherent sums + form-factor spectral matrix, then form factor, interference and spin-flip "
+                    "cross sections",
+        "call_s": round(t, 4),
+        "Gterm_s": round(W * P / t / 1e9, 1),
+        "objects_kernel_ms": round(kms, 3),
+        "roofline": {"kernel": "objects_kernel", "bound": "alu", "achieved": round(flops / (kms * 1e-3) / 1e12, 3),
+                     "peak": round(PEAK_FP64_VALU / 1e12, 3), "unit": "TFLOP/s",
+                     "frac": round(flops / (kms * 1e-3) / PEAK_FP64_VALU, 4)},
+    }
+
+
 def sources_sha256(names):
     h = hashlib.sha256()
     for n in names:
@@ -288,7 +367,7 @@ def sources_sha256(names):
 def traffic_per_launch(kernel):
     """HBM bytes per launch of `kernel` from its committed counter summary, or None
     when there is none or the kernel's sources changed since it was taken."""
-    _, srcs, name = KERNELS[kernel]
+    _, srcs, name = {**KERNELS, **SIDE_KERNELS}[kernel]
     path = os.path.join(PROFILES, name)
     if not os.path.exists(path):
         return None
@@ -303,6 +382,40 @@ def traffic_per_launch(kernel):
         return int(float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"]))
     except KeyError:
         return None
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def one_core_oracle_rate(cfg, qy, qz):
+    """The oracle's direct sums on one thread (OMP_NUM_THREADS=1 in a child process):
+    the same points at the given pixels."""
+    import subprocess
+    import tempfile
+
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "in.npz")
+        np.savez(path, pos=cfg["pos"], nuc=cfg["nuc"], mag=cfg["mag"], qy=qy, qz=qz)
+        code = ("import sys, time, numpy as np; sys.path.insert(0, sys.argv[1]); import oracle; "
+                "d = np.load(sys.argv[2]); oracle.threads(); t0 = time.perf_counter(); "
+                "oracle.amplitudes(d['pos'], d['nuc'], d['mag'], d['qy'], d['qz']); "
+                "print(time.perf_counter() - t0, oracle.threads())")
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        res = subprocess.run([sys.executable, "-c", code, ROOT, path], env=env, capture_output=True, text=True,
+                             timeout=300)
+    if res.returncode != 0:
+        return {"error": res.stderr.strip()[-300:]}
+    dt, thr = res.stdout.split()
+    terms = cfg["pos"].shape[0] * qy.size
+    return {"value": round(terms / float(dt) / 1e9, 5), "unit": "Gterm/s", "cores": int(thr),
+            "sample": f"{qy.size} of the same pixels ({terms:.3g} terms, {float(dt):.1f} s)"}
 
 
 def calibrate_copy(torch):
@@ -330,7 +443,10 @@ def main():
     from paper_2601_18444_amd import numag, synth
 
     if args.polar:
-        polar_only(torch, numag, synth)
+        print(json.dumps(polar_only(torch, numag, synth)))
+        return
+    if args.ensemble:
+        print(json.dumps(measure_ensemble_split(torch, numag, synth)))
         return
     if args.snapshots:
         print(json.dumps(measure_snapshots(torch, numag, synth)))
@@ -467,8 +583,8 @@ def main():
     t_adj = avg_ms(ev["adjoint"])
     t_sep = avg_ms(ev["separable"]) if have_sep else None
     terms = W * P
-    sums_per_step = 2 + (1 if have_sep else 0)
-    value = sums_per_step * terms / (ms_per_step * 1e-3) / 1e9
+    # terms evaluated one by one per step: the direct sums and the adjoint sums
+    value = 2 * terms / (ms_per_step * 1e-3) / 1e9
 
     dominant = max(kernel_ms, key=lambda k: kernel_ms[k])
     t_kernel = kernel_ms[dominant]
@@ -491,12 +607,13 @@ def main():
             "workload": "vortex grid 64^3 at 1 nm (262144 points), 256x256 detector |q|<=2 nm^-1: "
                         "direct sums + 13 cross sections + azimuthal average + correlation"
                         + (" + separable FP64-MFMA sums" if have_sep else "") + " + loss gradient (adjoint)",
-            "points": W, "pixels": P, "sums_per_step": sums_per_step,
+            "points": W, "pixels": P, "evaluated_terms_per_step": 2 * terms,
         },
         "paths": {
-            # the step rate counting only the sums whose terms are evaluated one by one
-            # (direct and adjoint; the separable sums are equivalent terms)
-            "step_evaluated_terms_Gterm_s": round(2 * terms / (ms_per_step * 1e-3) / 1e9, 2),
+            # the step rate if the separable call's equivalent terms (W P, not evaluated
+            # one by one) were counted too
+            "step_Gterm_s_with_separable_equivalent": round((3 if have_sep else 2) * terms / (ms_per_step * 1e-3)
+                                                            / 1e9, 2),
             "direct_Gterm_s": round(terms / (t_direct * 1e-3) / 1e9, 2),
             "direct_ms": round(t_direct, 4),
             "direct_kernel_ms": round(kernel_ms["direct_cartesian_kernel"], 4),
@@ -527,6 +644,8 @@ def main():
             "peak": round(PEAK_FP64_VALU / 1e12, 3),
             "unit": "TFLOP/s",
             "frac": round(achieved / (PEAK_FP64_VALU / 1e12), 4),
+            # the same work against the packed FP32 vector peak (the sums run in FP64)
+            "frac_fp32_valu": round(achieved * 1e12 / PEAK_FP32_VALU, 4),
             "traffic": traffic,
             "launch_ms": round(t_kernel, 4),
             "flops_per_launch": FLOPS_PER_TERM * terms,
@@ -537,6 +656,8 @@ def main():
         out["paths"]["batched"] = measure_batched(torch, numag, synth)
         out["paths"]["snapshots"] = measure_snapshots(torch, numag, synth)
         out["paths"]["paper_scale"] = measure_paper_scale(torch, numag, synth)
+        out["paths"]["ensemble_split"] = measure_ensemble_split(torch, numag, synth)
+        out["paths"]["polar"] = polar_only(torch, numag, synth)
 
     if not args.no_cpu_baseline:
         import oracle
@@ -546,6 +667,7 @@ def main():
         t0 = time.perf_counter()
         oracle.amplitudes(cfg["pos"], cfg["nuc"], cfg["mag"], qy[idx], qz[idx])
         dt = time.perf_counter() - t0
+        one = one_core_oracle_rate(cfg, qy[idx[:args.cpu_pixels_1core]], qz[idx[:args.cpu_pixels_1core]])
         out["cpu_baseline"] = {
             "value": round(W * idx.size / dt / 1e9, 5),
             "unit": "Gterm/s",
@@ -553,6 +675,8 @@ def main():
             "kind": "oracle",
             "sample": f"FP64 oracle direct sums of the same 262144 points at {idx.size} random pixels "
                       f"of the 256x256 detector ({W * idx.size:.3g} terms, {dt:.1f} s)",
+            "cpu_model": cpu_model(),
+            "one_core": one,
         }
     print(json.dumps(out))
 

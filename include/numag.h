@@ -154,13 +154,6 @@ size_t numag_workspace_size(const numag_sample *sample, int64_t n_rot, const num
                             int32_t path, int32_t mode);
 
 /*
- * Drops the library's record of planning tables held in `workspace` (see
- * numag_amplitudes, object modes).  Call it before freeing a workspace that an
- * object-mode call used.  Host-only; NULL or an unknown address is a no-op.
- */
-void numag_release_workspace(const void *workspace);
-
-/*
  * Direct Fourier sums, Sec. 3.3 (DSFT and its cos/sin split), per object mode
  * (Sec. 3.3 summation relation and dilute approximation), for n_rot sample
  * rotations (Sec. 3.1; any R in SO(3)).
@@ -182,25 +175,60 @@ void numag_release_workspace(const void *workspace);
  *             a regular-grid sample); SPLIT takes one rotation.  Both run on
  *             either detector kind (Cartesian: one persistent launch over
  *             objects x rotations; polar: per object, groups of rotations in one
- *             launch each, or one direct sum per object in SPLIT mode).  On a
- *             polar detector DILUTE copies the host rotations to the workspace
- *             and waits for `stream` once before enqueuing the sums.
+ *             launch each, or one direct sum per object in SPLIT mode).  These
+ *             modes build a one-off plan (see numag_plan_create) on every call:
+ *             its tables (object offsets, rotations, work items) are copied to
+ *             the start of the workspace from host memory the library frees
+ *             once the stream has passed the copy; the call never waits for the
+ *             stream.  Such a call cannot be captured into a graph
+ *             (NUMAG_E_UNSUPPORTED while `stream` is capturing): capture
+ *             numag_amplitudes_plan instead.
  *   workspace device scratch of at least numag_workspace_size() bytes; its
- *             contents are undefined after the call.  In DILUTE/SPLIT mode on a
- *             Cartesian detector the call keeps its planning tables at the start
- *             of the workspace and a later call on the same workspace with the
- *             same tables skips their upload (so it enqueues only kernels and can
- *             be captured into a graph): the caller must not write to the
- *             workspace between such calls (any numag call on it is fine), and
- *             must call numag_release_workspace() on it before freeing that memory
- *             (the record is kept by address; a new buffer at the same address
- *             would otherwise be taken to hold the tables).
+ *             contents are undefined after the call.
+ * COHERENT mode copies nothing from the host (it enqueues kernels only).
  * Empty samples (W = 0) are valid and give zeros.
  */
 int numag_amplitudes(const numag_sample *sample, int64_t n_rot, const double *rot,
                      const numag_qgrid *grid, int32_t path, int32_t mode, int32_t spec_per_object,
                      double *amp_out, double *spec_out, void *workspace, size_t ws_bytes,
                      void *stream);
+
+/*
+ * Object-mode plans (Sec. 3.3 summation relation and dilute limit, for many
+ * sample rotations): the host-side part of a DILUTE or SPLIT request -- object
+ * offsets, rotations and, on a Cartesian detector, the persistent kernel's
+ * work items -- built once, uploaded once into a caller workspace, then used
+ * by any number of numag_amplitudes_plan calls that enqueue kernels only (so
+ * they can be recorded into a HIP graph and replayed).
+ *   numag_plan_create   validates as numag_amplitudes does (mode DILUTE or
+ *             SPLIT, path DIRECT or DIRECT_HERMITIAN) and copies what it needs
+ *             of the host arguments (rot HOST [n_rot][9] or NULL, the sample's
+ *             HOST object offsets); *plan_out receives the handle.
+ *   numag_plan_workspace_size   bytes of the workspace the plan's calls need.
+ *   numag_plan_upload   enqueues the copy of the plan's tables (held in host
+ *             memory owned by the plan) to the start of `workspace`: the plan
+ *             must not be destroyed before the stream has passed that copy.
+ *   numag_amplitudes_plan   the sums of the plan for `sample`, whose point
+ *             count, object count and object offsets must equal the plan's (its
+ *             device arrays -- positions, weights, object positions -- may
+ *             differ from call to call).  The workspace must hold the plan's
+ *             upload: only its tables region (the start of the workspace) must be
+ *             left untouched between calls; the rest is scratch.  Every table read
+ *             is guarded by a tag unique to the plan, written at the start of its
+ *             upload: a workspace that does not hold this plan's upload (never
+ *             uploaded, overwritten, or another buffer) gives NaN outputs instead
+ *             of reading foreign tables.  Outputs as numag_amplitudes (amp_out
+ *             only in SPLIT mode).
+ *   numag_plan_destroy  frees the handle (NULL is a no-op).
+ */
+typedef struct numag_plan numag_plan;
+int numag_plan_create(const numag_sample *sample, int64_t n_rot, const double *rot, const numag_qgrid *grid,
+                      int32_t path, int32_t mode, int32_t spec_per_object, numag_plan **plan_out);
+size_t numag_plan_workspace_size(const numag_plan *plan);
+int numag_plan_upload(const numag_plan *plan, void *workspace, size_t ws_bytes, void *stream);
+int numag_amplitudes_plan(const numag_plan *plan, const numag_sample *sample, double *amp_out, double *spec_out,
+                          void *workspace, size_t ws_bytes, void *stream);
+void numag_plan_destroy(numag_plan *plan);
 
 /*
  * Loop mode (Sec. 3.1 loop modes; Sec. 3.2: one real-space data set per field,

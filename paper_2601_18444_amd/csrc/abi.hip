@@ -1,8 +1,11 @@
 // C ABI of the numag library: argument validation, workspace layout and dispatch.
 // Host code only; every numerical step runs in the HIP kernels of this library.
+#include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
-#include <algorithm>
+#include <memory>
+#include <random>
 #include <string>
 #include <vector>
 
@@ -130,14 +133,12 @@ bool rot_is_identity(const double *rot)
 
 // Workspace of the coherent direct path for one rotation.
 struct DirectLayout {
-    size_t offsets, points, partial, total;
+    size_t points, partial, total;
 };
 
 DirectLayout direct_layout(const numag_sample *s, const Detector &d)
 {
     DirectLayout L{};
-    const bool need_off = s->n_objects > 1 && s->obj_pos != nullptr;
-    L.offsets = need_off ? align_up((size_t)(s->n_objects + 1) * sizeof(int64_t)) : 0;
     L.points = align_up((size_t)std::max<int64_t>(s->n_points, 1) * sizeof(PointRec));
     // partial sums of the full detector or of its Hermitian half, whichever is larger
     Detector dh = d;
@@ -151,7 +152,7 @@ DirectLayout direct_layout(const numag_sample *s, const Detector &d)
         const DirectPlan p = plan_direct_polar(d, s->n_points), ph = plan_direct_polar(dh, s->n_points);
         L.partial = std::max(align_up(direct_partial_bytes(p, d)), align_up(direct_partial_bytes(ph, dh)));
     }
-    L.total = L.offsets + L.points + L.partial;
+    L.total = L.points + L.partial;
     return L;
 }
 
@@ -162,21 +163,16 @@ int run_direct(const numag_sample *s, const Rot &R, const Detector &d, double *a
 {
     DirectLayout L = direct_layout(s, d);
     Carve cv(ws);
-    int64_t *d_off = (int64_t *)cv.take(L.offsets);
     PointRec *pts = (PointRec *)cv.take(L.points);
     double *part = (double *)cv.take(L.partial);
     const int64_t P = (int64_t)d.n0 * d.n1;
-    if (L.offsets != 0)
-        NUMAG_HIP_CHECK(hipMemcpyAsync(d_off, s->obj_offsets, (size_t)(s->n_objects + 1) * sizeof(int64_t),
-                                       hipMemcpyHostToDevice, st));
     if (s->n_points == 0 || (s->nuc == nullptr && s->mag == nullptr)) {
         return launch_fill(amp, P * 8, 0.0, st);
     }
     // channels summed: a sample without nuclear (magnetic) weights skips those FMAs
     const int channels = s->nuc == nullptr ? 3 : (s->mag == nullptr ? 1 : 4);
-    int rc = launch_prepare_points(s->pos, s->nuc, s->mag, s->n_points, s->regular,
-                                   L.offsets != 0 ? d_off : nullptr, s->n_objects, s->obj_pos, R,
-                                   pts, st);
+    int rc = launch_prepare_points(s->pos, s->nuc, s->mag, 0, s->n_points, s->regular, s->obj_offsets,
+                                   s->n_objects, s->obj_pos, R, pts, st);
     if (rc != NUMAG_OK) return rc;
     if (d.kind == NUMAG_GRID_CARTESIAN) {
         Detector dh = d;
@@ -212,11 +208,12 @@ int run_direct(const numag_sample *s, const Rot &R, const Detector &d, double *a
 // Object modes on the polar detector: each (rotation, object) runs the direct
 // polar path into one amplitude buffer and adds F F^H / n_rot into its spectral
 // matrix (split mode: plus the coherent total of the whole sample).  The
-// direct workspace of the whole sample bounds that of every object.
-size_t polar_objects_ws(const numag_sample *s, const Detector &d, int64_t n_rot)
+// direct workspace of the whole sample bounds that of every object.  Workspace:
+// the plan image (tag, rotations), then the direct-path scratch and one
+// amplitude set.
+size_t polar_objects_rest(const numag_sample *s, const Detector &d)
 {
-    return direct_layout(s, d).total + align_up((size_t)d.n0 * d.n1 * 8 * sizeof(double)) +
-           align_up((size_t)n_rot * 9 * sizeof(double));
+    return direct_layout(s, d).total + align_up((size_t)d.n0 * d.n1 * 8 * sizeof(double));
 }
 
 // Dilute mode on a polar detector: per object, groups of rotations share one
@@ -228,23 +225,15 @@ size_t polar_objects_ws(const numag_sample *s, const Detector &d, int64_t n_rot)
 // partial buffers of the whole sample.
 constexpr int64_t kGroupSplitPoints = 8192;  // measured: 4096 and 16384 about 4 % slower
 
-int run_dilute_polar(const numag_sample *s, const double *rot, int64_t n_rot, const Detector &d,
-                     int32_t spec_per_object, double *spec_out, const DirectLayout &L, void *direct_ws,
-                     double *d_rot, hipStream_t st, bool hermitian)
+int run_dilute_polar(const numag_sample *s, int64_t n_rot, const Detector &d, int32_t spec_per_object,
+                     double *spec_out, const DirectLayout &L, void *direct_ws, const double *d_rot, hipStream_t st,
+                     bool hermitian)
 {
     const int64_t P = (int64_t)d.n0 * d.n1;
     const int64_t K = s->n_objects;
     if (s->nuc == nullptr && s->mag == nullptr) return NUMAG_OK;  // all sums vanish
     const int channels = s->nuc == nullptr ? 3 : (s->mag == nullptr ? 1 : 4);
-    if (rot != nullptr) {
-        NUMAG_HIP_CHECK(hipMemcpyAsync(d_rot, rot, (size_t)n_rot * 9 * sizeof(double), hipMemcpyHostToDevice, st));
-    } else {
-        static const double I3[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
-        NUMAG_HIP_CHECK(hipMemcpyAsync(d_rot, I3, sizeof(I3), hipMemcpyHostToDevice, st));
-    }
-    NUMAG_HIP_CHECK(hipStreamSynchronize(st));  // the host rotations may be pageable
     Carve cv(direct_ws);
-    cv.take(L.offsets);
     PointRec *pts = (PointRec *)cv.take(L.points);
     double *part = (double *)cv.take(L.partial);
     Detector dk = d;
@@ -279,29 +268,28 @@ int run_dilute_polar(const numag_sample *s, const double *rot, int64_t n_rot, co
     return NUMAG_OK;
 }
 
-int run_objects_polar(const numag_sample *s, const double *rot, int64_t n_rot, const Detector &d, int32_t mode,
-                      int32_t spec_per_object, double *spec_out, double *amp_out, void *ws, hipStream_t st,
-                      bool hermitian)
+int run_objects_polar(const ObjPlan &pl, const numag_sample *s, double *spec_out, double *amp_out, void *ws,
+                      hipStream_t st)
 {
+    const Detector &d = pl.d;
+    const bool hermitian = pl.path == NUMAG_PATH_DIRECT_HERMITIAN;
     const int64_t P = (int64_t)d.n0 * d.n1;
     const int64_t K = s->n_objects;
     const DirectLayout L = direct_layout(s, d);
-    Carve cv(ws);
+    char *base = (char *)ws;
+    const double *d_rot = (const double *)(base + pl.o_rot);
+    const double *h_rot = (const double *)(pl.image.data() + pl.o_rot);
+    Carve cv(base + pl.image.size());
     void *direct_ws = cv.take(L.total);
     double *F = (double *)cv.take((size_t)P * 8 * sizeof(double));
-    double *d_rot = (double *)cv.take((size_t)n_rot * 9 * sizeof(double));
-    const int64_t n_spec = spec_per_object ? K : 1;
+    const int64_t n_spec = pl.spec_per_object ? K : 1;
     int rc = launch_fill(spec_out, n_spec * P * 16, 0.0, st);
     if (rc != NUMAG_OK) return rc;
-    if (mode == NUMAG_MODE_DILUTE)
-        return run_dilute_polar(s, rot, n_rot, d, spec_per_object, spec_out, L, direct_ws, d_rot, st, hermitian);
-    if (mode == NUMAG_MODE_SPLIT) {
-        rc = run_direct(s, rot_of(rot, 0), d, amp_out, direct_ws, st, hermitian);
-        if (rc != NUMAG_OK) return rc;
-    }
-    const double scale = 1.0 / (double)n_rot;
-    for (int64_t r = 0; r < n_rot; ++r) {
-        for (int64_t k = 0; k < K; ++k) {
+    if (pl.mode == NUMAG_MODE_DILUTE) {
+        rc = run_dilute_polar(s, pl.n_rot, d, pl.spec_per_object, spec_out, L, direct_ws, d_rot, st, hermitian);
+    } else {
+        rc = run_direct(s, rot_of(h_rot, 0), d, amp_out, direct_ws, st, hermitian);
+        for (int64_t k = 0; k < K && rc == NUMAG_OK; ++k) {
             const int64_t lo = K > 1 ? s->obj_offsets[k] : 0, hi = K > 1 ? s->obj_offsets[k + 1] : s->n_points;
             if (hi == lo) continue;
             numag_sample sk{};
@@ -310,12 +298,79 @@ int run_objects_polar(const numag_sample *s, const double *rot, int64_t n_rot, c
             sk.nuc = s->nuc != nullptr ? s->nuc + lo : nullptr;
             sk.mag = s->mag != nullptr ? s->mag + 3 * lo : nullptr;
             sk.n_objects = 1;
-            rc = run_direct(&sk, rot_of(rot, r), d, F, direct_ws, st, hermitian);
-            if (rc != NUMAG_OK) return rc;
-            rc = launch_spectral_matrix(1, P, F, spec_out + (spec_per_object ? k : 0) * P * 16, st, scale, 1);
-            if (rc != NUMAG_OK) return rc;
+            rc = run_direct(&sk, rot_of(h_rot, 0), d, F, direct_ws, st, hermitian);
+            if (rc == NUMAG_OK)
+                rc = launch_spectral_matrix(1, P, F, spec_out + (pl.spec_per_object ? k : 0) * P * 16, st, 1.0, 1);
         }
     }
+    if (rc != NUMAG_OK) return rc;
+    // a workspace without this plan's image gives NaN
+    rc = launch_tag_guard((const unsigned long long *)base, pl.tag, spec_out, n_spec * P * 16, st);
+    if (rc == NUMAG_OK && amp_out != nullptr) rc = launch_tag_guard((const unsigned long long *)base, pl.tag, amp_out, P * 8, st);
+    return rc;
+}
+
+unsigned long long next_plan_tag()
+{
+    static std::atomic<unsigned long long> counter{0};
+    static const unsigned long long salt = [] {
+        std::random_device rd;
+        return ((unsigned long long)rd() << 32) ^ (unsigned long long)rd();
+    }();
+    // splitmix64 of (salt + counter): distinct for distinct counters, never reused in a process
+    unsigned long long z = salt + 0x9E3779B97F4A7C15ull * (counter.fetch_add(1) + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Object-mode plan of a validated request.  rot may be NULL with n_rot == 1
+// (identity); with rot NULL and n_rot > 1 only the sizes are meaningful.
+std::unique_ptr<ObjPlan> make_plan(const numag_sample *s, int64_t n_rot, const double *rot, const Detector &d,
+                                   int32_t path, int32_t mode, int32_t spec_per_object)
+{
+    auto pl = std::make_unique<ObjPlan>();
+    pl->tag = next_plan_tag();
+    pl->d = d;
+    pl->path = path;
+    pl->mode = mode;
+    pl->spec_per_object = spec_per_object ? 1 : 0;
+    pl->n_rot = n_rot;
+    pl->K = s->n_objects;
+    pl->W = s->n_points;
+    pl->off.resize(s->n_objects + 1);
+    if (s->n_objects == 1 || s->obj_offsets == nullptr) {
+        pl->off[0] = 0;
+        pl->off[1] = s->n_points;
+    } else {
+        std::memcpy(pl->off.data(), s->obj_offsets, sizeof(int64_t) * (s->n_objects + 1));
+    }
+    if (d.kind == NUMAG_GRID_CARTESIAN) {
+        build_objects_plan_cartesian(*pl);
+    } else {
+        pl->o_rot = kPlanTagBytes;
+        pl->image.assign(kPlanTagBytes + align_up((size_t)n_rot * 9 * sizeof(double)), 0);
+        std::memcpy(pl->image.data(), &pl->tag, sizeof(pl->tag));
+        pl->ws_bytes = pl->image.size() + polar_objects_rest(s, d);
+    }
+    double *R = (double *)(pl->image.data() + pl->o_rot);
+    if (rot != nullptr) {
+        std::memcpy(R, rot, sizeof(double) * 9 * n_rot);
+    } else {
+        for (int a = 0; a < 9; ++a) R[a] = (a % 4) == 0 ? 1.0 : 0.0;
+    }
+    return pl;
+}
+
+int run_plan(const ObjPlan &pl, const numag_sample *s, double *amp_out, double *spec_out, void *ws, hipStream_t st)
+{
+    if (pl.d.kind == NUMAG_GRID_CARTESIAN) return launch_objects_plan(pl, *s, spec_out, amp_out, ws, st);
+    return run_objects_polar(pl, s, spec_out, amp_out, ws, st);
+}
+
+int upload_plan(const ObjPlan &pl, void *ws, hipStream_t st)
+{
+    NUMAG_HIP_CHECK(hipMemcpyAsync(ws, pl.image.data(), pl.image.size(), hipMemcpyHostToDevice, st));
     return NUMAG_OK;
 }
 
@@ -325,12 +380,48 @@ size_t amplitudes_ws(const numag_sample *s, int64_t n_rot, const Detector &d, in
     if (path == NUMAG_PATH_SEPARABLE_F64 || path == NUMAG_PATH_SEPARABLE_BF16X3)
         return align_up(separable_workspace_bytes(*s->regular, d, path, 1));
     if (mode == NUMAG_MODE_COHERENT) return direct_layout(s, d).total;
-    if (d.kind == NUMAG_GRID_POLAR) return polar_objects_ws(s, d, n_rot);
-    return align_up(objects_workspace_bytes(objects_detector(d, path == NUMAG_PATH_DIRECT_HERMITIAN), s->obj_offsets,
-                                            s->n_objects, s->n_points, n_rot, mode, spec_per_object));
+    return align_up(make_plan(s, n_rot, nullptr, d, path, mode, spec_per_object)->ws_bytes);
 }
 
+// Validation shared by numag_amplitudes and numag_plan_create.
+int check_amplitudes_request(const numag_sample *sample, int64_t n_rot, const double *rot, const numag_qgrid *grid,
+                             int32_t path, int32_t mode, const char *fn)
+{
+    int rc;
+    if ((rc = check_sample(sample, fn)) != NUMAG_OK) return rc;
+    if ((rc = check_grid(grid, fn)) != NUMAG_OK) return rc;
+    if ((rc = check_rotations(rot, n_rot, fn)) != NUMAG_OK) return rc;
+    const std::string f(fn);
+    if (mode < NUMAG_MODE_COHERENT || mode > NUMAG_MODE_SPLIT) return invalid(f + ": unknown mode");
+    if (path < NUMAG_PATH_DIRECT || path > NUMAG_PATH_DIRECT_HERMITIAN) return invalid(f + ": unknown path");
+    if (path == NUMAG_PATH_DIRECT_HERMITIAN && grid->kind == NUMAG_GRID_POLAR && grid->n1 % 2 != 0)
+        return invalid(f + ": the Hermitian path needs an even n_theta on a polar detector");
+    if (path == NUMAG_PATH_SEPARABLE_F64 || path == NUMAG_PATH_SEPARABLE_BF16X3) {
+        if (sample->regular == nullptr) return invalid(f + ": separable path needs sample->regular");
+        if (!rot_is_identity(rot) || n_rot != 1) return invalid(f + ": separable path needs the identity rotation");
+        if (sample->n_objects != 1) return invalid(f + ": separable path needs one object");
+        if (grid->kind != NUMAG_GRID_CARTESIAN) return invalid(f + ": separable path needs a Cartesian detector");
+        if (mode != NUMAG_MODE_COHERENT) return invalid(f + ": separable path is COHERENT only");
+    }
+    if (mode != NUMAG_MODE_COHERENT) {
+        if (mode == NUMAG_MODE_SPLIT && n_rot != 1) return invalid(f + ": SPLIT mode takes one rotation");
+        if (sample->n_points > 0 && sample->pos == nullptr) {
+            set_error(f + ": DILUTE/SPLIT modes need explicit positions");
+            return NUMAG_E_UNSUPPORTED;
+        }
+        if (n_rot > (int64_t)1 << 30) return invalid(f + ": too many rotations");
+    }
+    return NUMAG_OK;
+}
+
+void delete_plan_cb(void *p) { delete (ObjPlan *)p; }
+
 }  // namespace
+
+// The opaque plan handle of the C ABI.
+struct numag_plan {
+    std::unique_ptr<ObjPlan> p;
+};
 
 extern "C" {
 
@@ -358,7 +449,6 @@ int numag_correlation_2d(const numag_qgrid *grid, const double *f, int32_t n_f, 
         return NUMAG_E_WORKSPACE;
     }
     if (n_f == 0) return NUMAG_OK;
-    forget_workspace(workspace);
     return launch_correlation_2d(d, f, n_f, rd, C_out, workspace, ws_bytes, (hipStream_t)stream);
 }
 
@@ -418,66 +508,51 @@ size_t numag_workspace_size(const numag_sample *sample, int64_t n_rot, const num
     return std::max(amp, grad);
 }
 
-void numag_release_workspace(const void *workspace)
-{
-    if (workspace != nullptr) forget_workspace(workspace);
-}
-
 int numag_amplitudes(const numag_sample *sample, int64_t n_rot, const double *rot, const numag_qgrid *grid,
                      int32_t path, int32_t mode, int32_t spec_per_object, double *amp_out, double *spec_out,
                      void *workspace, size_t ws_bytes, void *stream)
 {
     clear_error();
     int rc;
-    if ((rc = check_sample(sample, "numag_amplitudes")) != NUMAG_OK) return rc;
-    if ((rc = check_grid(grid, "numag_amplitudes")) != NUMAG_OK) return rc;
-    if ((rc = check_rotations(rot, n_rot, "numag_amplitudes")) != NUMAG_OK) return rc;
-    if (mode < NUMAG_MODE_COHERENT || mode > NUMAG_MODE_SPLIT) return invalid("numag_amplitudes: unknown mode");
-    if (path < NUMAG_PATH_DIRECT || path > NUMAG_PATH_DIRECT_HERMITIAN)
-        return invalid("numag_amplitudes: unknown path");
-    if (path == NUMAG_PATH_DIRECT_HERMITIAN) {
-        if (grid->kind == NUMAG_GRID_POLAR && grid->n1 % 2 != 0)
-            return invalid("numag_amplitudes: the Hermitian path needs an even n_theta on a polar detector");
-    }
+    if ((rc = check_amplitudes_request(sample, n_rot, rot, grid, path, mode, "numag_amplitudes")) != NUMAG_OK)
+        return rc;
     if ((mode == NUMAG_MODE_COHERENT || mode == NUMAG_MODE_SPLIT) && amp_out == nullptr)
         return invalid("numag_amplitudes: amp_out required in COHERENT/SPLIT mode");
     if ((mode == NUMAG_MODE_DILUTE || mode == NUMAG_MODE_SPLIT) && spec_out == nullptr)
         return invalid("numag_amplitudes: spec_out required in DILUTE/SPLIT mode");
-    if (path == NUMAG_PATH_SEPARABLE_F64 || path == NUMAG_PATH_SEPARABLE_BF16X3) {
-        if (sample->regular == nullptr) return invalid("numag_amplitudes: separable path needs sample->regular");
-        if (!rot_is_identity(rot) || n_rot != 1)
-            return invalid("numag_amplitudes: separable path needs the identity rotation");
-        if (sample->n_objects != 1) return invalid("numag_amplitudes: separable path needs one object");
-        if (grid->kind != NUMAG_GRID_CARTESIAN)
-            return invalid("numag_amplitudes: separable path needs a Cartesian detector");
-        if (mode != NUMAG_MODE_COHERENT) return invalid("numag_amplitudes: separable path is COHERENT only");
-    }
+    Detector d = make_detector(*grid);
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t P = (int64_t)grid->n0 * grid->n1;
     if (mode != NUMAG_MODE_COHERENT) {
-        if (mode == NUMAG_MODE_SPLIT && n_rot != 1) return invalid("numag_amplitudes: SPLIT mode takes one rotation");
-        if (sample->n_points > 0 && sample->pos == nullptr) {
-            set_error("numag_amplitudes: DILUTE/SPLIT modes need explicit positions");
+        // a one-off plan: its image is uploaded here and freed once the stream has copied it
+        std::unique_ptr<ObjPlan> pl = make_plan(sample, n_rot, rot, d, path, mode, spec_per_object);
+        const size_t need = align_up(pl->ws_bytes);
+        if (ws_bytes < need || workspace == nullptr) {
+            set_error("numag_amplitudes: workspace too small (need " + std::to_string(need) + " bytes)");
+            return NUMAG_E_WORKSPACE;
+        }
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        NUMAG_HIP_CHECK(hipStreamIsCapturing(st, &cap));
+        if (cap != hipStreamCaptureStatusNone) {
+            set_error("numag_amplitudes: DILUTE/SPLIT modes upload their tables on every call; under graph capture "
+                      "create a plan (numag_plan_create), upload it once and capture numag_amplitudes_plan");
             return NUMAG_E_UNSUPPORTED;
         }
-        if (n_rot > (int64_t)1 << 30) return invalid("numag_amplitudes: too many rotations");
+        rc = upload_plan(*pl, workspace, st);
+        if (rc == NUMAG_OK)
+            rc = run_plan(*pl, sample, mode == NUMAG_MODE_SPLIT ? amp_out : nullptr, spec_out, workspace, st);
+        if (rc == NUMAG_OK && hipLaunchHostFunc(st, delete_plan_cb, pl.get()) == hipSuccess) {
+            pl.release();  // deleted by the stream callback
+            return NUMAG_OK;
+        }
+        (void)hipStreamSynchronize(st);  // error path: the copy may still read the image
+        return rc != NUMAG_OK ? rc : NUMAG_E_HIP;
     }
-    Detector d = make_detector(*grid);
-    const size_t need = amplitudes_ws(sample, n_rot, d, path, mode, spec_per_object ? 1 : 0);
+    const size_t need = amplitudes_ws(sample, n_rot, d, path, mode, 0);
     if (ws_bytes < need || (need > 0 && workspace == nullptr)) {
         set_error("numag_amplitudes: workspace too small (need " + std::to_string(need) + " bytes)");
         return NUMAG_E_WORKSPACE;
     }
-    hipStream_t st = (hipStream_t)stream;
-    const int64_t P = (int64_t)grid->n0 * grid->n1;
-
-    if (mode != NUMAG_MODE_COHERENT && grid->kind == NUMAG_GRID_POLAR) {
-        forget_workspace(workspace);
-        return run_objects_polar(sample, rot, n_rot, d, mode, spec_per_object ? 1 : 0, spec_out, amp_out, workspace,
-                                 st, path == NUMAG_PATH_DIRECT_HERMITIAN);
-    }
-    if (mode != NUMAG_MODE_COHERENT)
-        return launch_objects(*sample, rot, n_rot, d, mode, spec_per_object ? 1 : 0, spec_out, amp_out, workspace,
-                              ws_bytes, st, path == NUMAG_PATH_DIRECT_HERMITIAN);
-    forget_workspace(workspace);
     if (path == NUMAG_PATH_SEPARABLE_F64 || path == NUMAG_PATH_SEPARABLE_BF16X3)
         return launch_separable(sample->nuc, sample->mag, *sample->regular, d, path, 1, amp_out, workspace,
                                 ws_bytes, st);
@@ -488,6 +563,77 @@ int numag_amplitudes(const numag_sample *sample, int64_t n_rot, const double *ro
     }
     return NUMAG_OK;
 }
+
+int numag_plan_create(const numag_sample *sample, int64_t n_rot, const double *rot, const numag_qgrid *grid,
+                      int32_t path, int32_t mode, int32_t spec_per_object, numag_plan **plan_out)
+{
+    clear_error();
+    if (plan_out == nullptr) return invalid("numag_plan_create: plan_out is NULL");
+    *plan_out = nullptr;
+    int rc;
+    if ((rc = check_amplitudes_request(sample, n_rot, rot, grid, path, mode, "numag_plan_create")) != NUMAG_OK)
+        return rc;
+    if (mode != NUMAG_MODE_DILUTE && mode != NUMAG_MODE_SPLIT)
+        return invalid("numag_plan_create: plans are for DILUTE and SPLIT modes");
+    if (path != NUMAG_PATH_DIRECT && path != NUMAG_PATH_DIRECT_HERMITIAN)
+        return invalid("numag_plan_create: path must be NUMAG_PATH_DIRECT or NUMAG_PATH_DIRECT_HERMITIAN");
+    auto h = std::make_unique<numag_plan>();
+    h->p = make_plan(sample, n_rot, rot, make_detector(*grid), path, mode, spec_per_object);
+    *plan_out = h.release();
+    return NUMAG_OK;
+}
+
+size_t numag_plan_workspace_size(const numag_plan *plan)
+{
+    clear_error();
+    if (plan == nullptr) {
+        set_error("numag_plan_workspace_size: plan is NULL");
+        return 0;
+    }
+    return align_up(plan->p->ws_bytes);
+}
+
+int numag_plan_upload(const numag_plan *plan, void *workspace, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    if (plan == nullptr) return invalid("numag_plan_upload: plan is NULL");
+    if (workspace == nullptr || ws_bytes < align_up(plan->p->ws_bytes)) {
+        set_error("numag_plan_upload: workspace too small (need " + std::to_string(align_up(plan->p->ws_bytes)) +
+                  " bytes)");
+        return NUMAG_E_WORKSPACE;
+    }
+    return upload_plan(*plan->p, workspace, (hipStream_t)stream);
+}
+
+int numag_amplitudes_plan(const numag_plan *plan, const numag_sample *sample, double *amp_out, double *spec_out,
+                          void *workspace, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    int rc;
+    if (plan == nullptr) return invalid("numag_amplitudes_plan: plan is NULL");
+    const ObjPlan &pl = *plan->p;
+    if ((rc = check_sample(sample, "numag_amplitudes_plan")) != NUMAG_OK) return rc;
+    if (sample->n_points != pl.W || sample->n_objects != pl.K)
+        return invalid("numag_amplitudes_plan: the sample's point or object count differs from the plan's");
+    if (pl.K > 1 && std::memcmp(sample->obj_offsets, pl.off.data(), sizeof(int64_t) * (pl.K + 1)) != 0)
+        return invalid("numag_amplitudes_plan: the sample's object offsets differ from the plan's");
+    if (sample->n_points > 0 && sample->pos == nullptr) {
+        set_error("numag_amplitudes_plan: DILUTE/SPLIT modes need explicit positions");
+        return NUMAG_E_UNSUPPORTED;
+    }
+    if (pl.mode == NUMAG_MODE_SPLIT && amp_out == nullptr)
+        return invalid("numag_amplitudes_plan: amp_out required in SPLIT mode");
+    if (spec_out == nullptr) return invalid("numag_amplitudes_plan: spec_out is NULL");
+    if (workspace == nullptr || ws_bytes < align_up(pl.ws_bytes)) {
+        set_error("numag_amplitudes_plan: workspace too small (need " + std::to_string(align_up(pl.ws_bytes)) +
+                  " bytes)");
+        return NUMAG_E_WORKSPACE;
+    }
+    return run_plan(pl, sample, pl.mode == NUMAG_MODE_SPLIT ? amp_out : nullptr, spec_out, workspace,
+                    (hipStream_t)stream);
+}
+
+void numag_plan_destroy(numag_plan *plan) { delete plan; }
 
 static int check_snapshots(const numag_regular *points, int64_t n_snap, const numag_qgrid *grid, int32_t path,
                            const char *fn)
@@ -532,7 +678,6 @@ int numag_amplitudes_snapshots(const numag_regular *points, int64_t n_snap, cons
         set_error("numag_amplitudes_snapshots: workspace too small (need " + std::to_string(need) + " bytes)");
         return NUMAG_E_WORKSPACE;
     }
-    forget_workspace(workspace);
     return launch_separable(nuc, mag, *points, d, path, n_snap, amp_out, workspace, ws_bytes, (hipStream_t)stream);
 }
 
@@ -639,7 +784,6 @@ int numag_grad_path(const numag_sample *sample, const double *rot, const numag_q
         return NUMAG_E_WORKSPACE;
     }
     hipStream_t st = (hipStream_t)stream;
-    forget_workspace(workspace);
     Carve cv(workspace);
     char *direct_ws = (char *)cv.take(L.total);
     double *amp = (double *)cv.take((size_t)P * 8 * sizeof(double));
@@ -651,19 +795,12 @@ int numag_grad_path(const numag_sample *sample, const double *rot, const numag_q
         amp_in = amp;
     } else {
         // points only
-        Carve c2(direct_ws);
-        int64_t *d_off = (int64_t *)c2.take(L.offsets);
-        PointRec *pts = (PointRec *)c2.take(L.points);
-        if (L.offsets != 0)
-            NUMAG_HIP_CHECK(hipMemcpyAsync(d_off, sample->obj_offsets,
-                                           (size_t)(sample->n_objects + 1) * sizeof(int64_t),
-                                           hipMemcpyHostToDevice, st));
-        rc = launch_prepare_points(sample->pos, sample->nuc, sample->mag, sample->n_points, sample->regular,
-                                   L.offsets != 0 ? d_off : nullptr, sample->n_objects, sample->obj_pos, R,
-                                   pts, st);
+        rc = launch_prepare_points(sample->pos, sample->nuc, sample->mag, 0, sample->n_points, sample->regular,
+                                   sample->obj_offsets, sample->n_objects, sample->obj_pos, R,
+                                   (PointRec *)direct_ws, st);
         if (rc != NUMAG_OK) return rc;
     }
-    const PointRec *pts = (const PointRec *)(direct_ws + L.offsets);
+    const PointRec *pts = (const PointRec *)direct_ws;
     return launch_grad(pts, sample->n_points, d, *consts, amp_in, target, weight, loss_out, dnuc_out, dmag_out,
                        R, gws, grad_workspace_bytes(d, sample->n_points), st, hermitian);
 }

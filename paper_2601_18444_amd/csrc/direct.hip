@@ -13,6 +13,8 @@
 //
 // Work is split over point ranges (split-K); a fixed-order FP64 combine sums
 // the partial results, so results are bitwise reproducible.
+#include <algorithm>
+
 #include "cartesian_sum.h"
 
 namespace numag {
@@ -65,42 +67,50 @@ __device__ __forceinline__ PointRec point_record(const double (&x)[3], const Rot
     return r;
 }
 
+// Objects whose offsets r^k one preparation launch adds: the points
+// [start[0], start[n]) belong to objects k0 .. k0 + n - 1, object k0 + i holding
+// [start[i], start[i + 1]).  Passed by value, so no host-to-device copy is needed.
+constexpr int kObjGroup = 64;
+struct ObjGroup {
+    int n;
+    int64_t k0;
+    int64_t start[kObjGroup + 1];
+};
+
+// Writes out[j - out_base] for the points j in [g.start[0], g.start[g.n]);
+// obj_pos == nullptr: no object offsets.
 __global__ void prepare_points_kernel(const double *__restrict__ pos, const double *__restrict__ nuc,
-                                      const double *__restrict__ mag, int64_t W, int reg,
-                                      numag_regular g, const int64_t *__restrict__ off, int64_t K,
-                                      const double *__restrict__ obj_pos, Rot R,
+                                      const double *__restrict__ mag, int reg, numag_regular rg, ObjGroup g,
+                                      const double *__restrict__ obj_pos, Rot R, int64_t out_base,
                                       PointRec *__restrict__ out)
 {
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= W) return;
+    const int64_t j = g.start[0] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= g.start[g.n]) return;
     double x[3];
     if (reg) {
-        int64_t nyz = (int64_t)g.n[1] * g.n[2];
+        int64_t nyz = (int64_t)rg.n[1] * rg.n[2];
         int64_t ix = j / nyz, rem = j % nyz;
-        int64_t iy = rem / g.n[2], iz = rem % g.n[2];
-        x[0] = g.origin[0] + (double)ix * g.step[0];
-        x[1] = g.origin[1] + (double)iy * g.step[1];
-        x[2] = g.origin[2] + (double)iz * g.step[2];
+        int64_t iy = rem / rg.n[2], iz = rem % rg.n[2];
+        x[0] = rg.origin[0] + (double)ix * rg.step[0];
+        x[1] = rg.origin[1] + (double)iy * rg.step[1];
+        x[2] = rg.origin[2] + (double)iz * rg.step[2];
     } else {
         x[0] = pos[3 * j + 0];
         x[1] = pos[3 * j + 1];
         x[2] = pos[3 * j + 2];
     }
     if (obj_pos != nullptr) {
-        int64_t k = 0;
-        if (K > 1 && off != nullptr) {
-            int64_t lo = 0, hi = K - 1;  // largest k with off[k] <= j
-            while (lo < hi) {
-                int64_t mid = (lo + hi + 1) >> 1;
-                if (off[mid] <= j) lo = mid; else hi = mid - 1;
-            }
-            k = lo;
+        int lo = 0, hi = g.n - 1;  // largest i with start[i] <= j
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (g.start[mid] <= j) lo = mid; else hi = mid - 1;
         }
+        const int64_t k = g.k0 + lo;
         x[0] += obj_pos[3 * k + 0];
         x[1] += obj_pos[3 * k + 1];
         x[2] += obj_pos[3 * k + 2];
     }
-    out[j] = point_record(x, R, nuc, mag, j);
+    out[j - out_base] = point_record(x, R, nuc, mag, j);
 }
 
 // Points of one object (explicit positions, no object offset) under a group of
@@ -131,18 +141,45 @@ int launch_prepare_rotations(const double *pos, const double *nuc, const double 
     return NUMAG_OK;
 }
 
-int launch_prepare_points(const double *pos, const double *nuc, const double *mag, int64_t W,
-                          const numag_regular *regular, const int64_t *d_offsets, int64_t K,
+int launch_prepare_points(const double *pos, const double *nuc, const double *mag, int64_t j_lo, int64_t j_hi,
+                          const numag_regular *regular, const int64_t *h_offsets, int64_t K,
                           const double *obj_pos, const Rot &R, PointRec *out, hipStream_t s)
 {
-    if (W <= 0) return NUMAG_OK;
-    numag_regular g{};
-    if (regular != nullptr) g = *regular;
+    if (j_hi <= j_lo) return NUMAG_OK;
+    numag_regular rg{};
+    if (regular != nullptr) rg = *regular;
     const int tpb = 256;
-    int64_t blocks = (W + tpb - 1) / tpb;
-    hipLaunchKernelGGL(prepare_points_kernel, dim3((unsigned)blocks), dim3(tpb), 0, s, pos, nuc, mag, W,
-                       regular != nullptr ? 1 : 0, g, d_offsets, K, obj_pos, R, out);
-    NUMAG_HIP_CHECK(hipGetLastError());
+    auto launch = [&](const ObjGroup &g) -> int {
+        const int64_t n = g.start[g.n] - g.start[0];
+        if (n <= 0) return NUMAG_OK;
+        hipLaunchKernelGGL(prepare_points_kernel, dim3((unsigned)((n + tpb - 1) / tpb)), dim3(tpb), 0, s, pos, nuc,
+                           mag, regular != nullptr ? 1 : 0, rg, g, obj_pos, R, j_lo, out);
+        NUMAG_HIP_CHECK(hipGetLastError());
+        return NUMAG_OK;
+    };
+    ObjGroup g{};
+    if (obj_pos == nullptr || K <= 1 || h_offsets == nullptr) {
+        g.n = 1;
+        g.k0 = 0;
+        g.start[0] = j_lo;
+        g.start[1] = j_hi;
+        return launch(g);
+    }
+    // first object holding a point >= j_lo: the last k with off[k] <= j_lo among non-empty objects
+    int64_t k = std::upper_bound(h_offsets, h_offsets + K + 1, j_lo) - h_offsets - 1;
+    while (k < K && h_offsets[k + 1] <= j_lo) ++k;
+    while (k < K && h_offsets[k] < j_hi) {
+        g.n = 0;
+        g.k0 = k;
+        while (g.n < kObjGroup && k < K && h_offsets[k] < j_hi) {
+            g.start[g.n] = std::max(h_offsets[k], j_lo);
+            ++g.n;
+            ++k;
+        }
+        g.start[g.n] = std::min(h_offsets[k], j_hi);
+        const int rc = launch(g);
+        if (rc != NUMAG_OK) return rc;
+    }
     return NUMAG_OK;
 }
 
@@ -202,7 +239,7 @@ int target_workgroups()
     return cached;
 }
 
-DirectPlan plan_direct_cartesian(const Detector &d, int64_t W)
+DirectPlan plan_direct_cartesian(const Detector &d, int64_t W, int64_t max_splits)
 {
     DirectPlan p{};
     p.channels = 4;
@@ -216,6 +253,7 @@ DirectPlan plan_direct_cartesian(const Detector &d, int64_t W)
     int64_t max_split = (W + 4 * kChunk - 1) / (4 * kChunk);
     if (max_split < 1) max_split = 1;
     if (want > max_split) want = max_split;
+    if (max_splits > 0 && want > max_splits) want = max_splits;
     if (want > 65535) want = 65535;
     if (want < 1) want = 1;
     int64_t per = (W + want - 1) / want;
@@ -323,7 +361,7 @@ int launch_mirror_cartesian(double *amp, int64_t P, int64_t Ph, hipStream_t s)
 
 // out[i][m] = sum of the splits of part[.][i][m], out[i][m + nh] = its conjugate
 __global__ void combine_polar_half_kernel(const double *__restrict__ part, int nsplit, int n0, int nh,
-                                          double *__restrict__ out)
+                                          double *__restrict__ out, int accumulate)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t Ph = (int64_t)n0 * nh;
@@ -334,16 +372,18 @@ __global__ void combine_polar_half_kernel(const double *__restrict__ part, int n
     for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * Ph * 8 + idx];
     const int64_t i = p / nh, m = p % nh;
     const int64_t full = i * 2 * nh + m;
-    out[full * 8 + v] = s;
-    out[(full + nh) * 8 + v] = (v & 1) ? -s : s;
+    const double sm = (v & 1) ? -s : s;
+    out[full * 8 + v] = accumulate ? out[full * 8 + v] + s : s;
+    out[(full + nh) * 8 + v] = accumulate ? out[(full + nh) * 8 + v] + sm : sm;
 }
 
-int launch_combine_polar_half(const double *part, int nsplit, int n0, int nh, double *out, hipStream_t s)
+int launch_combine_polar_half(const double *part, int nsplit, int n0, int nh, double *out, hipStream_t s,
+                              int accumulate)
 {
     const int64_t n = (int64_t)n0 * nh * 8;
     if (n <= 0) return NUMAG_OK;
     hipLaunchKernelGGL(combine_polar_half_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, nsplit,
-                       n0, nh, out);
+                       n0, nh, out, accumulate);
     NUMAG_HIP_CHECK(hipGetLastError());
     return NUMAG_OK;
 }

@@ -5,7 +5,9 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <memory>
 #include <string>
+#include <vector>
 
 #include "../../include/numag.h"
 #include "types.h"
@@ -51,10 +53,12 @@ Detector make_detector(const numag_qgrid &g);
 // Launchers (each enqueues on `stream`, returns NUMAG_OK or NUMAG_E_HIP).
 // ---------------------------------------------------------------------------
 
-// X_j = R (x_j + r^{k(j)}), w'_j = (n_j, R m_j).  obj_index maps point -> object
-// via device CSR offsets (nullptr when K == 1 or no object positions).
-int launch_prepare_points(const double *pos, const double *nuc, const double *mag, int64_t W,
-                          const numag_regular *regular, const int64_t *d_offsets, int64_t K,
+// X_j = R (x_j + r^{k(j)}), w'_j = (n_j, R m_j) of the points j in [j_lo, j_hi),
+// written to out[j - j_lo].  The object of a point follows from the HOST CSR
+// offsets h_offsets [K+1] (read on the host and passed to the kernels by value,
+// in groups of objects; unused when obj_pos is nullptr or K == 1).
+int launch_prepare_points(const double *pos, const double *nuc, const double *mag, int64_t j_lo, int64_t j_hi,
+                          const numag_regular *regular, const int64_t *h_offsets, int64_t K,
                           const double *obj_pos, const Rot &R, PointRec *out, hipStream_t s);
 
 // direct Cartesian sum.  Writes [nsplit][P][8] partial sums (or the final
@@ -68,11 +72,14 @@ struct DirectPlan {
 };
 // Hermitian completion of a half-detector sum (see direct.hip).
 int launch_mirror_cartesian(double *amp, int64_t P, int64_t Ph, hipStream_t s);
-int launch_combine_polar_half(const double *part, int nsplit, int n0, int nh, double *out, hipStream_t s);
+// accumulate != 0: add into `out` instead of overwriting it
+int launch_combine_polar_half(const double *part, int nsplit, int n0, int nh, double *out, hipStream_t s,
+                              int accumulate = 0);
 
 // Workgroups a direct-sum launch aims for (split-K included).
 int target_workgroups();
-DirectPlan plan_direct_cartesian(const Detector &d, int64_t W);
+// max_splits > 0 caps the point splits (and so the partial-sum buffer).
+DirectPlan plan_direct_cartesian(const Detector &d, int64_t W, int64_t max_splits = 0);
 size_t direct_partial_bytes(const DirectPlan &p, const Detector &d);
 int launch_direct_cartesian(const PointRec *pts, int64_t W, const Detector &d, const DirectPlan &p,
                             double *partial, hipStream_t s);
@@ -110,18 +117,38 @@ struct ObjectsPlan {
     int n_out;      // spectral matrices written (K per object, or 1)
     int64_t n_items;
 };
-size_t objects_workspace_bytes(const Detector &d, const int64_t *h_off, int64_t K, int64_t W, int64_t n_rot,
-                               int mode, int spec_per_object);
+
+// An object-mode (DILUTE / SPLIT) plan: everything the kernels need that depends
+// on the host arguments (object offsets, rotations, work tables), as an image the
+// caller uploads to the start of its workspace.  The image begins with a tag
+// unique to the plan; the kernels compare it with the plan's and write NaN
+// instead of reading tables that another plan, or other data, left there.
+constexpr size_t kPlanTagBytes = 256;
+struct ObjPlanCart;  // Cartesian work tables (objects.hip)
+struct ObjPlan {
+    unsigned long long tag;
+    Detector d;                 // the whole detector
+    int path, mode, spec_per_object;
+    int64_t n_rot, K, W;
+    std::vector<int64_t> off;   // [K+1] host copy of the object offsets
+    std::vector<char> image;    // uploaded to workspace offset 0: the tag, then the tables
+    size_t o_rot = 0;           // rotations [n_rot][9] (doubles) within the image
+    size_t ws_bytes = 0;        // workspace bytes the plan's calls need
+    std::shared_ptr<ObjPlanCart> cart;  // Cartesian detector: the persistent kernel's tables
+};
 // Detector whose rows the object kernel sums: all of d, or with `hermitian` the
 // first ceil(n0 / 2) rows of a Cartesian detector (the rest follow by
-// G(-q) = conj G(q)); size the workspace with it.
+// G(-q) = conj G(q)).
 Detector objects_detector(const Detector &d, bool hermitian);
-int launch_objects(const numag_sample &s, const double *h_rot, int64_t n_rot, const Detector &d, int mode,
-                   int spec_per_object, double *spec_out, double *amp_out, void *ws, size_t ws_bytes,
-                   hipStream_t st, bool hermitian = false);
-// Drops the record of tables uploaded into `ws` (any other use of a workspace
-// overwrites them).
-void forget_workspace(const void *ws);
+// Fills pl.cart, pl.image (rotations excepted), pl.o_rot and pl.ws_bytes of a plan on a
+// Cartesian detector whose other fields are set.
+void build_objects_plan_cartesian(ObjPlan &pl);
+// out[i] = NaN (i < n) when the tag at tag_ptr is not `tag`.
+int launch_tag_guard(const unsigned long long *tag_ptr, unsigned long long tag, double *out, int64_t n,
+                     hipStream_t st);
+// Enqueues the sums of a Cartesian plan whose image is in `ws` (kernels only).
+int launch_objects_plan(const ObjPlan &pl, const numag_sample &s, double *spec_out, double *amp_out, void *ws,
+                        hipStream_t st);
 
 // cross sections from amplitudes ([n_sets][P][8]) or spectra ([n_sets][P][16]).
 int launch_cross_section(const Detector &d, int64_t n_sets, const double *amp, const double *spec,

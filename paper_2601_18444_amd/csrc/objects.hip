@@ -21,8 +21,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
-#include <mutex>
-#include <unordered_map>
+#include <memory>
 #include <vector>
 
 #include "cartesian_sum.h"
@@ -54,6 +53,8 @@ struct RawLoader {
 };
 
 struct ObjArgs {
+    const unsigned long long *tag_ptr;  // the plan tag at the start of the workspace
+    unsigned long long tag;             // the tag of the plan these tables belong to
     const double *pos, *nuc, *mag;
     const int64_t *off;      // [K+1]
     const double *obj_pos;   // [K][3] or null
@@ -74,6 +75,7 @@ __global__ __launch_bounds__(cart::kThreads, 2) void objects_kernel(ObjArgs a, D
     __shared__ int s_item;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t P = (int64_t)d.n0 * d.n1;
+    if (*a.tag_ptr != a.tag) return;  // the workspace does not hold this plan's tables
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
         __syncthreads();
@@ -149,16 +151,29 @@ __global__ void fill_i32_kernel(int *p, int n, int v)
 
 // out[s][p][v] = scale * sum of the slots of output s (slot_off CSR, ascending);
 // slots hold P pixels, out rows are P_out >= P pixels apart (the first P filled)
-__global__ void spec_reduce_kernel(const double *__restrict__ slots, const int *__restrict__ slot_off, int n_out,
+// A workspace that does not hold the plan's tables (tag mismatch) gives NaN.
+__global__ void spec_reduce_kernel(const unsigned long long *tag_ptr, unsigned long long tag,
+                                   const double *__restrict__ slots, const int *__restrict__ slot_off, int n_out,
                                    int64_t P, int64_t P_out, double scale, double *__restrict__ out)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)n_out * P * 16) return;
     const int s = (int)(idx / (P * 16));
     const int64_t pv = idx % (P * 16);
+    if (*tag_ptr != tag) {
+        out[(int64_t)s * P_out * 16 + pv] = __builtin_nan("");
+        return;
+    }
     double acc = 0.0;
     for (int sl = slot_off[s]; sl < slot_off[s + 1]; ++sl) acc += slots[(int64_t)sl * P * 16 + pv];
     out[(int64_t)s * P_out * 16 + pv] = scale * acc;
+}
+
+// out[i] = NaN for i < n when the workspace tag is not the plan's.
+__global__ void tag_guard_kernel(const unsigned long long *tag_ptr, unsigned long long tag, double *out, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && *tag_ptr != tag) out[i] = __builtin_nan("");
 }
 
 // Hermitian completion of spectral matrices on a centro-symmetric Cartesian
@@ -179,11 +194,16 @@ __global__ void mirror_spec_kernel(double *__restrict__ out, int n_out, int64_t 
     o[q * 16 + v] = (v >= 5 && (v & 1)) ? -o[p * 16 + v] : o[p * 16 + v];
 }
 
-__global__ void amp_reduce_kernel(const double *__restrict__ slots, int n_slots, int64_t P,
+__global__ void amp_reduce_kernel(const unsigned long long *tag_ptr, unsigned long long tag,
+                                  const double *__restrict__ slots, int n_slots, int64_t P,
                                   double *__restrict__ out)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= P * 8) return;
+    if (*tag_ptr != tag) {
+        out[idx] = __builtin_nan("");
+        return;
+    }
     double s = 0.0;
     for (int sl = 0; sl < n_slots; ++sl) s += slots[(int64_t)sl * P * 8 + idx];
     out[idx] = s;
@@ -201,24 +221,15 @@ int device_cus()
     return cus;
 }
 
-// Host-side record of the tables last uploaded into a workspace, so that a
-// repeated call (e.g. one recorded into a HIP graph) enqueues no host copy.
-struct Upload {
-    std::vector<char> bytes;
-};
-std::mutex g_upload_mu;
-std::unordered_map<const void *, Upload> g_uploads;
-
 // The full host-side plan: object groups, slots and sorted items.
 struct Tables {
     ObjectsPlan p;
-    std::vector<int64_t> off;     // [K+1]
     std::vector<int4> slots;      // (object lo, hi, rotation lo, hi)
     std::vector<int> slot_off;    // outputs -> slots (CSR)
     std::vector<int2> items;      // (slot, block), by decreasing cost
 };
 
-Tables make_tables(const Detector &d, const int64_t *h_off, int64_t K, int64_t W, int64_t n_rot, int mode,
+Tables make_tables(const Detector &d, const std::vector<int64_t> &off, int64_t K, int64_t W, int64_t n_rot, int mode,
                    int spec_per_object)
 {
     Tables T;
@@ -228,14 +239,6 @@ Tables make_tables(const Detector &d, const int64_t *h_off, int64_t K, int64_t W
     p.col_blocks = (d.n1 + cols - 1) / cols;
     p.row_blocks = (d.n0 + rows - 1) / rows;
     const int64_t nblocks = (int64_t)p.col_blocks * p.row_blocks;
-    T.off.resize(K + 1);
-    if (K == 1 || h_off == nullptr) {
-        T.off[0] = 0;
-        T.off[1] = W;
-    } else {
-        std::memcpy(T.off.data(), h_off, sizeof(int64_t) * (K + 1));
-    }
-    const std::vector<int64_t> &off = T.off;
     // slot groups wanted (each spans all pixel blocks)
     const int64_t want = std::max<int64_t>(1, (kTarget + nblocks - 1) / nblocks);
     // object groups: single objects, or contiguous groups of roughly equal point counts
@@ -287,27 +290,20 @@ size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
 
 }  // namespace
 
-void forget_workspace(const void *ws)
-{
-    std::lock_guard<std::mutex> lk(g_upload_mu);
-    g_uploads.erase(ws);
-}
+// Cartesian part of an object-mode plan: the work tables and where they and the
+// accumulators sit in the workspace.
+struct ObjPlanCart {
+    Tables T;
+    Detector dk;  // the rows that are summed
+    size_t o_off, o_items, o_slots, o_slot_off, o_counter, o_spec, o_amp;
+};
 
-size_t objects_workspace_bytes(const Detector &d, const int64_t *h_off, int64_t K, int64_t W, int64_t n_rot,
-                               int mode, int spec_per_object)
+int launch_tag_guard(const unsigned long long *tag_ptr, unsigned long long tag, double *out, int64_t n, hipStream_t st)
 {
-    const Tables T = make_tables(d, h_off, K, W, n_rot, mode, spec_per_object);
-    const size_t P = (size_t)d.n0 * d.n1;
-    size_t b = 0;
-    b += al((size_t)(K + 1) * sizeof(int64_t));
-    b += al((size_t)n_rot * 9 * sizeof(double));
-    b += al(T.items.size() * sizeof(int2));
-    b += al(T.slots.size() * sizeof(int4));
-    b += al(T.slot_off.size() * sizeof(int));
-    b += al(sizeof(int) * 64);
-    b += al((size_t)T.p.n_slots * P * 16 * sizeof(double));
-    if (mode == NUMAG_MODE_SPLIT) b += al((size_t)T.p.n_slots * P * 8 * sizeof(double));
-    return b;
+    if (n <= 0) return NUMAG_OK;
+    hipLaunchKernelGGL(tag_guard_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, tag_ptr, tag, out, n);
+    NUMAG_HIP_CHECK(hipGetLastError());
+    return NUMAG_OK;
 }
 
 Detector objects_detector(const Detector &d, bool hermitian)
@@ -317,67 +313,54 @@ Detector objects_detector(const Detector &d, bool hermitian)
     return dk;
 }
 
-int launch_objects(const numag_sample &s, const double *h_rot, int64_t n_rot, const Detector &d_full, int mode,
-                   int spec_per_object, double *spec_out, double *amp_out, void *ws, size_t ws_bytes,
-                   hipStream_t st, bool hermitian)
+void build_objects_plan_cartesian(ObjPlan &pl)
 {
-    const int64_t K = s.n_objects;
-    const Detector d = objects_detector(d_full, hermitian);  // the rows that are summed
-    const int64_t P = (int64_t)d.n0 * d.n1;
-    const int64_t P_full = (int64_t)d_full.n0 * d_full.n1;
-    const Tables T = make_tables(d, s.obj_offsets, K, s.n_points, n_rot, mode, spec_per_object);
-    const ObjectsPlan &p = T.p;
-
-    // workspace layout
-    char *base = (char *)ws;
-    size_t used = 0;
+    auto c = std::make_shared<ObjPlanCart>();
+    c->dk = objects_detector(pl.d, pl.path == NUMAG_PATH_DIRECT_HERMITIAN);
+    c->T = make_tables(c->dk, pl.off, pl.K, pl.W, pl.n_rot, pl.mode, pl.spec_per_object);
+    const Tables &T = c->T;
+    const size_t P = (size_t)c->dk.n0 * c->dk.n1;
+    size_t used = kPlanTagBytes;
     auto take = [&](size_t bytes) {
-        char *r = base + used;
+        const size_t r = used;
         used += al(bytes);
         return r;
     };
-    char *tables = base;
-    int64_t *d_off = (int64_t *)take(sizeof(int64_t) * (K + 1));
-    double *d_rot = (double *)take(sizeof(double) * 9 * n_rot);
-    int2 *d_items = (int2 *)take(sizeof(int2) * T.items.size());
-    int4 *d_slots = (int4 *)take(sizeof(int4) * T.slots.size());
-    int *d_slot_off = (int *)take(sizeof(int) * T.slot_off.size());
-    const size_t table_bytes = used;
-    int *d_counter = (int *)take(sizeof(int) * 64);
-    double *d_spec = (double *)take(sizeof(double) * 16 * (size_t)p.n_slots * P);
-    double *d_amp = mode == NUMAG_MODE_SPLIT ? (double *)take(sizeof(double) * 8 * (size_t)p.n_slots * P) : nullptr;
-    if (used > ws_bytes) {
-        set_error("numag_amplitudes: workspace too small for the object path");
-        return NUMAG_E_WORKSPACE;
-    }
+    c->o_off = take(sizeof(int64_t) * (pl.K + 1));
+    pl.o_rot = take(sizeof(double) * 9 * pl.n_rot);
+    c->o_items = take(sizeof(int2) * T.items.size());
+    c->o_slots = take(sizeof(int4) * T.slots.size());
+    c->o_slot_off = take(sizeof(int) * T.slot_off.size());
+    const size_t image_bytes = used;
+    c->o_counter = take(sizeof(int) * 64);
+    c->o_spec = take(sizeof(double) * 16 * (size_t)T.p.n_slots * P);
+    c->o_amp = pl.mode == NUMAG_MODE_SPLIT ? take(sizeof(double) * 8 * (size_t)T.p.n_slots * P) : 0;
+    pl.ws_bytes = used;
+    // host image of the tag and the tables (rotations are filled by the caller)
+    pl.image.assign(image_bytes, 0);
+    std::memcpy(pl.image.data(), &pl.tag, sizeof(pl.tag));
+    std::memcpy(pl.image.data() + c->o_off, pl.off.data(), sizeof(int64_t) * (pl.K + 1));
+    std::memcpy(pl.image.data() + c->o_items, T.items.data(), sizeof(int2) * T.items.size());
+    std::memcpy(pl.image.data() + c->o_slots, T.slots.data(), sizeof(int4) * T.slots.size());
+    std::memcpy(pl.image.data() + c->o_slot_off, T.slot_off.data(), sizeof(int) * T.slot_off.size());
+    pl.cart = c;
+}
 
-    // host image of the tables
-    std::vector<char> img(table_bytes, 0);
-    auto put = [&](const void *dst, const void *src, size_t n) {
-        std::memcpy(img.data() + ((const char *)dst - tables), src, n);
-    };
-    put(d_off, T.off.data(), sizeof(int64_t) * (K + 1));
-    if (h_rot != nullptr) {
-        put(d_rot, h_rot, sizeof(double) * 9 * n_rot);
-    } else {
-        const double I3[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
-        put(d_rot, I3, sizeof(I3));
-    }
-    put(d_items, T.items.data(), sizeof(int2) * T.items.size());
-    put(d_slots, T.slots.data(), sizeof(int4) * T.slots.size());
-    put(d_slot_off, T.slot_off.data(), sizeof(int) * T.slot_off.size());
-    bool upload = true;
-    {
-        std::lock_guard<std::mutex> lk(g_upload_mu);
-        auto itr = g_uploads.find(ws);
-        if (itr != g_uploads.end() && itr->second.bytes == img) upload = false;
-    }
-    if (upload) {
-        NUMAG_HIP_CHECK(hipMemcpyAsync(tables, img.data(), img.size(), hipMemcpyHostToDevice, st));
-        NUMAG_HIP_CHECK(hipStreamSynchronize(st));  // the host image goes out of scope
-        std::lock_guard<std::mutex> lk(g_upload_mu);
-        g_uploads[ws].bytes = img;
-    }
+int launch_objects_plan(const ObjPlan &pl, const numag_sample &s, double *spec_out, double *amp_out, void *ws,
+                        hipStream_t st)
+{
+    const ObjPlanCart &c = *pl.cart;
+    const ObjectsPlan &p = c.T.p;
+    const Detector &d = c.dk;
+    const bool hermitian = pl.path == NUMAG_PATH_DIRECT_HERMITIAN;
+    const int64_t P = (int64_t)d.n0 * d.n1;
+    const int64_t P_full = (int64_t)pl.d.n0 * pl.d.n1;
+    char *base = (char *)ws;
+    const unsigned long long *tag_ptr = (const unsigned long long *)base;
+    const unsigned long long tag = pl.tag;
+    int *d_counter = (int *)(base + c.o_counter);
+    double *d_spec = (double *)(base + c.o_spec);
+    double *d_amp = pl.mode == NUMAG_MODE_SPLIT ? (double *)(base + c.o_amp) : nullptr;
 
     // zero the accumulators and the counter (kernels, so the sequence can be captured)
     int rc = launch_fill(d_spec, 16 * (int64_t)p.n_slots * P, 0.0, st);
@@ -387,14 +370,16 @@ int launch_objects(const numag_sample &s, const double *h_rot, int64_t n_rot, co
     NUMAG_HIP_CHECK(hipGetLastError());
 
     ObjArgs args{};
+    args.tag_ptr = tag_ptr;
+    args.tag = tag;
     args.pos = s.pos;
     args.nuc = s.nuc;
     args.mag = s.mag;
-    args.off = d_off;
+    args.off = (const int64_t *)(base + c.o_off);
     args.obj_pos = s.obj_pos;
-    args.rot = d_rot;
-    args.items = d_items;
-    args.slots = d_slots;
+    args.rot = (const double *)(base + pl.o_rot);
+    args.items = (const int2 *)(base + c.o_items);
+    args.slots = (const int4 *)(base + c.o_slots);
     args.n_items = (int)p.n_items;
     args.col_blocks = p.col_blocks;
     args.counter = d_counter;
@@ -413,12 +398,13 @@ int launch_objects(const numag_sample &s, const double *h_rot, int64_t n_rot, co
     NUMAG_HIP_CHECK(hipGetLastError());
 
     const int64_t n_spec = (int64_t)p.n_out * P * 16;
-    hipLaunchKernelGGL(spec_reduce_kernel, dim3((unsigned)((n_spec + 255) / 256)), dim3(256), 0, st, d_spec, d_slot_off,
-                       p.n_out, P, P_full, 1.0 / (double)n_rot, spec_out);
+    hipLaunchKernelGGL(spec_reduce_kernel, dim3((unsigned)((n_spec + 255) / 256)), dim3(256), 0, st, tag_ptr, tag,
+                       d_spec, (const int *)(base + c.o_slot_off), p.n_out, P, P_full, 1.0 / (double)pl.n_rot,
+                       spec_out);
     NUMAG_HIP_CHECK(hipGetLastError());
     if (d_amp != nullptr) {
-        hipLaunchKernelGGL(amp_reduce_kernel, dim3((unsigned)((P * 8 + 255) / 256)), dim3(256), 0, st, d_amp,
-                           p.n_slots, P, amp_out);
+        hipLaunchKernelGGL(amp_reduce_kernel, dim3((unsigned)((P * 8 + 255) / 256)), dim3(256), 0, st, tag_ptr, tag,
+                           d_amp, p.n_slots, P, amp_out);
         NUMAG_HIP_CHECK(hipGetLastError());
     }
     if (hermitian) {

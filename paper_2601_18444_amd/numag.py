@@ -70,7 +70,11 @@ def _load():
         "numag_correlation": (ctypes.c_int, [P, P, i32, i32, P, i32, d, P, P, P]),
         "numag_grad": (ctypes.c_int, [P, P, P, P, P, P, P, P, P, P, P, sz, P]),
         "numag_grad_path": (ctypes.c_int, [P, P, P, i32, P, P, P, P, P, P, P, P, sz, P]),
-        "numag_release_workspace": (None, [P]),
+        "numag_plan_create": (ctypes.c_int, [P, i64, P, P, i32, i32, i32, P]),
+        "numag_plan_workspace_size": (sz, [P]),
+        "numag_plan_upload": (ctypes.c_int, [P, P, sz, P]),
+        "numag_amplitudes_plan": (ctypes.c_int, [P, P, P, P, P, sz, P]),
+        "numag_plan_destroy": (None, [P]),
         "numag_correlation_2d_workspace_size": (sz, [P, P]),
         "numag_correlation_2d": (ctypes.c_int, [P, P, i32, P, P, P, sz, P]),
         "numag_angular_spectrum": (ctypes.c_int, [P, P, i32, i32, P, P, P, P, P]),
@@ -153,24 +157,14 @@ def workspace(nbytes: int, device) -> torch.Tensor:
     key = str(torch.device(device))
     buf = _ws_cache.get(key)
     if buf is None or buf.numel() < nbytes:
-        if buf is not None:
-            release_workspace(buf)  # its memory may be reused by anything from here on
         buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
         _ws_cache[key] = buf
     return buf
 
 
 def clear_workspace_cache() -> None:
-    """Release and drop the cached workspaces (the next call allocates exactly what it needs)."""
-    for buf in _ws_cache.values():
-        release_workspace(buf)
+    """Drop the cached workspaces (the next call allocates exactly what it needs)."""
     _ws_cache.clear()
-
-
-def release_workspace(ws: torch.Tensor) -> None:
-    """numag_release_workspace: forget planning tables kept in `ws` before it is freed."""
-    if ws is not None and _lib is not None:
-        _lib.numag_release_workspace(_ptr(ws))
 
 
 def qgrid(kind: int, n0: int, n1: int, qmax: float) -> QGrid:
@@ -295,48 +289,90 @@ def amplitudes_snapshots(points: Regular, grid: QGrid, nuc=None, mag=None, path=
     return amp
 
 
+class Plan:
+    """numag_plan_*: an object-mode (DILUTE / SPLIT) plan of a sample's object
+    offsets and a set of rotations, uploaded once into its own workspace; calls
+    then enqueue kernels only.  The sample's device arrays are read at call time."""
+
+    def __init__(self, sample: Sample, grid: QGrid, rotations=None, mode: int = MODE_DILUTE,
+                 spec_per_object: bool = True, path: int = PATH_DIRECT):
+        r, n_rot = _rot_array(rotations)
+        self.sample, self.grid, self.mode, self.n_rot = sample, grid, mode, n_rot
+        self.spec_per_object = spec_per_object
+        self._rot = r
+        h = ctypes.c_void_p()
+        rc = _lib.numag_plan_create(sample.c, n_rot, r.ctypes.data_as(ctypes.c_void_p) if r is not None else None,
+                                    ctypes.byref(grid), int(path), int(mode), int(bool(spec_per_object)),
+                                    ctypes.byref(h))
+        _check("numag_plan_create", rc)
+        self._h = h
+        nws = _lib.numag_plan_workspace_size(self._h)
+        self.ws = torch.empty(max(int(nws), 256), dtype=torch.uint8, device=sample.device)
+
+    def upload(self, ws: Optional[torch.Tensor] = None) -> None:
+        """Enqueue the copy of the plan's tables into `ws` (default: its own workspace)."""
+        w = self.ws if ws is None else ws
+        _check("numag_plan_upload", _lib.numag_plan_upload(self._h, _ptr(w), w.numel(), _stream()))
+
+    def __call__(self, sample: Optional[Sample] = None, spec_out=None, amp_out=None,
+                 ws: Optional[torch.Tensor] = None):
+        """numag_amplitudes_plan: returns (amp [1, P, 4, 2] or None, spec [n_spec, P, 16])."""
+        s = self.sample if sample is None else sample
+        w = self.ws if ws is None else ws
+        P = self.grid.n_pixels
+        n_spec = s.n_objects if self.spec_per_object else 1
+        spec = spec_out if spec_out is not None else torch.empty((n_spec, P, 16), dtype=torch.float64,
+                                                                 device=s.device)
+        amp = None
+        if self.mode == MODE_SPLIT:
+            amp = amp_out if amp_out is not None else torch.empty((1, P, 4, 2), dtype=torch.float64, device=s.device)
+        rc = _lib.numag_amplitudes_plan(self._h, s.c, _ptr(amp), _ptr(spec), _ptr(w), w.numel(), _stream())
+        _check("numag_amplitudes_plan", rc)
+        return amp, spec
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            try:
+                torch.cuda.synchronize()  # an upload may still read the plan's host tables
+            except Exception:  # interpreter shutdown
+                pass
+            _lib.numag_plan_destroy(h)
+            self._h = None
+
+
 class BatchedOrientations:
     """Orientational average of a dilute sample (Sec. 3.3 dilute limit) over many
-    sample rotations: one persistent launch over (object, rotation group, pixel
-    block) work items, recorded once into a HIP graph and replayed.
+    sample rotations, recorded once into a HIP graph and replayed.  A plan holds
+    the rotations and object offsets; its tables are uploaded once, and the graph
+    records the plan's kernels (Cartesian detector: one persistent launch over
+    (object, rotation range, pixel block) work items; polar detector: per object,
+    groups of rotations on the polar direct kernel).
 
     The graph reads the sample's device arrays at replay time, so weights may
     be updated in place between replays; rotations and object offsets are fixed
-    at construction.  The dedicated workspace must not be shared.
-    path=PATH_DIRECT_HERMITIAN sums half of a centro-symmetric detector and
-    completes the spectral matrices by G(-q) = conj G(q)."""
+    at construction.  path=PATH_DIRECT_HERMITIAN sums half of a symmetric
+    detector and completes the spectral matrices by G(-q) = conj G(q)."""
 
     def __init__(self, sample: Sample, grid: QGrid, rotations, spec_per_object: bool = True, path: int = PATH_DIRECT):
-        if grid.kind != 0:
-            raise ValueError("BatchedOrientations records the persistent object kernel of a Cartesian detector; "
-                             "on a polar detector call amplitudes(..., mode=MODE_DILUTE) directly")
         self.sample, self.grid, self.path = sample, grid, path
-        self.rot = np.ascontiguousarray(np.asarray(rotations, dtype=np.float64).reshape(-1, 9))
-        self.spec_per_object = spec_per_object
+        self.plan = Plan(sample, grid, rotations, mode=MODE_DILUTE, spec_per_object=spec_per_object, path=path)
         dev = sample.device
         n_spec = sample.n_objects if spec_per_object else 1
         self.spec = torch.empty((n_spec, grid.n_pixels, 16), dtype=torch.float64, device=dev)
-        nws = workspace_size(sample, grid, self.rot.shape[0], path, MODE_DILUTE)
-        self.ws = torch.empty(max(nws, 256), dtype=torch.uint8, device=dev)
-        self._call()  # uploads the work tables into the dedicated workspace
+        self.plan.upload()
+        self._call()
         torch.cuda.synchronize()
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
             self._call()
 
     def _call(self):
-        amplitudes(self.sample, self.grid, rot=self.rot, path=self.path, mode=MODE_DILUTE,
-                   spec_per_object=self.spec_per_object, spec_out=self.spec, ws=self.ws)
+        self.plan(spec_out=self.spec)
 
     def eager(self) -> torch.Tensor:
         self._call()
         return self.spec
-
-    def __del__(self):
-        try:
-            release_workspace(getattr(self, "ws", None))
-        except Exception:  # interpreter shutdown: the library may be gone already
-            pass
 
     def replay(self) -> torch.Tensor:
         self.graph.replay()

@@ -198,8 +198,45 @@ def test_binding_refuses_to_import_without_the_library(tmp_path):
     assert "ImportError" in r.stderr and "is not built" in r.stderr
 
 
-def test_batched_orientations_refuses_a_polar_detector():
-    """The graph-recorded orientation batch is the Cartesian persistent kernel; a
-    polar detector is refused before anything is allocated or launched."""
-    with pytest.raises(ValueError, match="Cartesian"):
-        numag.BatchedOrientations(None, numag.qgrid(1, 8, 8, 1.0), np.eye(3).reshape(1, 9))
+def test_object_plans_validate_and_size_on_the_host():
+    """numag_plan_create validates like numag_amplitudes (object modes only) and
+    needs no device; numag_amplitudes_plan refuses a sample whose point count,
+    object count or offsets differ from the plan's, and a short workspace, before
+    any GPU work."""
+    off = np.array([0, 4, 4, 10], dtype=np.int64)
+    s = _cpu_sample(W=10, K=3, offsets=off)
+    rots = np.stack([np.eye(3).reshape(9)] * 5)
+    rp = rots.ctypes.data_as(ctypes.c_void_p)
+    h = ctypes.c_void_p()
+    for kind in (0, 1):
+        grid = numag.qgrid(kind, 20, 24, 1.0)
+        # coherent mode and the separable paths have no plan
+        assert numag._lib.numag_plan_create(ctypes.byref(s), 5, rp, ctypes.byref(grid), 0, numag.MODE_COHERENT, 1,
+                                            ctypes.byref(h)) == numag.E_INVALID
+        assert numag._lib.numag_plan_create(ctypes.byref(s), 5, rp, ctypes.byref(grid), 1, numag.MODE_DILUTE, 1,
+                                            ctypes.byref(h)) == numag.E_INVALID
+        assert numag._lib.numag_plan_create(ctypes.byref(s), 5, rp, ctypes.byref(grid), 0, numag.MODE_SPLIT, 1,
+                                            ctypes.byref(h)) == numag.E_INVALID  # SPLIT takes one rotation
+        assert numag._lib.numag_plan_create(ctypes.byref(s), 5, rp, ctypes.byref(grid), 0, numag.MODE_DILUTE, 1,
+                                            None) == numag.E_INVALID
+        for path in (numag.PATH_DIRECT, numag.PATH_DIRECT_HERMITIAN):
+            assert numag._lib.numag_plan_create(ctypes.byref(s), 5, rp, ctypes.byref(grid), path, numag.MODE_DILUTE,
+                                                1, ctypes.byref(h)) == numag.OK, numag.last_error()
+            nws = numag._lib.numag_plan_workspace_size(h)
+            assert nws > 0 and nws % 256 == 0
+            spec = ctypes.c_void_p(0x4000)
+            ws = ctypes.c_void_p(0x8000)
+            other = _cpu_sample(W=10, K=3, offsets=np.array([0, 5, 5, 10], dtype=np.int64))
+            assert numag._lib.numag_amplitudes_plan(h, ctypes.byref(other), None, spec, ws, nws,
+                                                    None) == numag.E_INVALID
+            fewer = _cpu_sample(W=9, K=3, offsets=np.array([0, 4, 4, 9], dtype=np.int64))
+            assert numag._lib.numag_amplitudes_plan(h, ctypes.byref(fewer), None, spec, ws, nws,
+                                                    None) == numag.E_INVALID
+            assert numag._lib.numag_amplitudes_plan(h, ctypes.byref(s), None, None, ws, nws, None) == numag.E_INVALID
+            assert numag._lib.numag_amplitudes_plan(h, ctypes.byref(s), None, spec, ws, nws - 256,
+                                                    None) == numag.E_WORKSPACE
+            assert numag._lib.numag_plan_upload(h, ws, nws - 256, None) == numag.E_WORKSPACE
+            numag._lib.numag_plan_destroy(h)
+    numag._lib.numag_plan_destroy(None)
+    assert numag._lib.numag_plan_workspace_size(None) == 0
+

@@ -302,28 +302,58 @@ def test_hermitian_object_modes(orc, kind, n0, n1, mode):
         assert max_norm_err(spec.cpu().numpy(), specf.cpu().numpy()) <= 1e-11
 
 
-def test_released_workspace_tables_are_uploaded_again():
-    """The planning tables of the object modes are kept in the workspace and a
-    repeated call skips their upload; numag_release_workspace drops that record.
-    After a release the memory is overwritten (zeros stand in for other data and
-    keep every table index in bounds) and the same call must upload the tables
-    again and give the same result bit for bit."""
+def test_workspace_reuse_never_reads_stale_tables():
+    """Object modes take their tables from the start of the workspace.  A plain
+    call uploads them on every call, so a workspace freed and allocated again at
+    the same address with foreign bytes in it gives the right result for another
+    sample.  A plan's calls read the tables its upload left there, guarded by the
+    plan's tag: a workspace whose tables were overwritten, or that holds another
+    plan's upload, gives NaN; uploading again restores the result bit for bit."""
     cfg = _objects(52, [40, 90, 15], spread=0.0)
     rots = synth.uniform_rotations(4, np.random.default_rng(53))
     grid = numag.qgrid(0, 20, 28, 1.0)
     s = _sample(cfg)
     nws = numag.workspace_size(s, grid, len(rots), numag.PATH_DIRECT, numag.MODE_DILUTE)
     ws = torch.empty(nws, dtype=torch.uint8, device=DEV)
-    _, a = numag.amplitudes(s, grid, rot=rots, mode=numag.MODE_DILUTE, spec_per_object=True, ws=ws)
-    ref = a.clone()
-    _, a2 = numag.amplitudes(s, grid, rot=rots, mode=numag.MODE_DILUTE, spec_per_object=True, ws=ws)
-    assert torch.equal(a2, ref)  # tables reused
-    numag.release_workspace(ws)
-    ws.zero_()
-    _, b = numag.amplitudes(s, grid, rot=rots, mode=numag.MODE_DILUTE, spec_per_object=True, ws=ws)
+    _, ref = numag.amplitudes(s, grid, rot=rots, mode=numag.MODE_DILUTE, spec_per_object=True, ws=ws)
+    ref = ref.clone()
     torch.cuda.synchronize()
-    assert torch.equal(b, ref)
-    assert float(ref.abs().max()) > 0.0
+    addr = ws.data_ptr()
+    del ws
+    # another sample (other offsets) on a buffer allocated after the free, full of foreign bytes
+    cfg2 = _objects(54, [70, 5, 60], spread=0.0)
+    s2 = _sample(cfg2)
+    ws2 = torch.full((nws,), 0xFF, dtype=torch.uint8, device=DEV)
+    print("workspace reallocated at the same address:", ws2.data_ptr() == addr, flush=True)
+    _, got2 = numag.amplitudes(s2, grid, rot=rots, mode=numag.MODE_DILUTE, spec_per_object=True, ws=ws2)
+    _, want2 = numag.amplitudes(s2, grid, rot=rots, mode=numag.MODE_DILUTE, spec_per_object=True,
+                                ws=torch.empty(nws, dtype=torch.uint8, device=DEV))
+    torch.cuda.synchronize()
+    assert torch.equal(got2, want2)
+    # plans: one upload, many calls; overwritten or foreign tables give NaN
+    for kind in (0, 1):
+        g = numag.qgrid(kind, 20, 28, 1.0)
+        pa = numag.Plan(s, g, rots, mode=numag.MODE_DILUTE, spec_per_object=True)
+        pb = numag.Plan(s, g, rots[::-1].copy(), mode=numag.MODE_DILUTE, spec_per_object=True)
+        pa.upload()
+        _, a1 = pa()
+        _, a2 = pa()
+        a1 = a1.clone()
+        torch.cuda.synchronize()
+        assert torch.equal(a1, a2) and float(a1.abs().max()) > 0.0
+        _, direct = numag.amplitudes(s, g, rot=rots, mode=numag.MODE_DILUTE, spec_per_object=True)
+        assert max_norm_err(a1.cpu().numpy(), direct.cpu().numpy()) <= 1e-12
+        pa.ws.zero_()
+        _, z = pa()
+        torch.cuda.synchronize()
+        assert torch.isnan(z).all(), kind
+        pa.upload()
+        _, a3 = pa()
+        torch.cuda.synchronize()
+        assert torch.equal(a3, a1)
+        _, f = pb(ws=pa.ws)  # pa's tables, pb's tag
+        torch.cuda.synchronize()
+        assert torch.isnan(f).all(), kind
 
 
 @pytest.mark.parametrize("nq,nt,path", [(24, 30, 0), (40, 36, 0), (40, 36, 3), (130, 20, 0), (130, 20, 3)])
@@ -354,3 +384,29 @@ def test_dilute_polar_rotation_groups(orc, nq, nt, path):
     # summed over objects
     _, tot = numag.amplitudes(_sample(cfg), grid, rot=rots, path=path, mode=numag.MODE_DILUTE)
     assert max_norm_err(tot[0].cpu().numpy(), spec.sum(axis=0)) <= 1e-12
+
+
+@pytest.mark.parametrize("path", [0, 3])
+def test_batched_orientations_graph_replay_polar(orc, path):
+    """The orientation batch on a polar detector: the plan's kernels (rotation
+    groups on the polar direct kernel) recorded into a HIP graph; every replay,
+    with eager work in between, equals the eager result bit for bit, and one
+    object's average equals the oracle's."""
+    cfg = _objects(66, [5, 200, 3000, 0, 40], spread=0.0)
+    rots = synth.uniform_rotations(12, np.random.default_rng(67))
+    qmax = 1.1
+    grid = numag.qgrid(1, 40, 36, qmax)
+    b = numag.BatchedOrientations(_sample(cfg), grid, rots, spec_per_object=True, path=path)
+    ref = b.eager().clone()
+    torch.cuda.synchronize()
+    for _ in range(3):
+        out = b.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
+        _ = torch.ones(1000, device=DEV).sum().item()  # eager work between replays
+    off = cfg["obj_offsets"]
+    k = 2
+    sl = slice(off[k], off[k + 1])
+    qy, qz, _ = orc.pixels(1, 40, 36, qmax)
+    Fs = [orc.amplitudes(cfg["pos"][sl], cfg["nuc"][sl], cfg["mag"][sl], qy, qz, R=R) for R in rots]
+    _check_spec(ref[k].cpu().numpy(), orc.spectral(np.stack(Fs)) / len(rots))
