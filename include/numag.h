@@ -194,6 +194,32 @@ int numag_amplitudes(const numag_sample *sample, int64_t n_rot, const double *ro
                      void *stream);
 
 /*
+ * Allocation-free coherent sums, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): numag_amplitudes in COHERENT mode on NUMAG_PATH_DIRECT or
+ * NUMAG_PATH_DIRECT_HERMITIAN, same arguments and outputs (amp_out [n_rot][P][4]
+ * complex, device) but no workspace.
+ *   Scratch: the point records and split partial sums live in one static device
+ *   array of NUMAG_NOALLOC_SCRATCH_BYTES that the library holds on every device
+ *   it runs on until the process ends; its device address is looked up on the
+ *   first call on a device.  Points go through in chunks, so any W fits; the
+ *   partial sums of the evaluated pixels (64 bytes each: the whole detector, or
+ *   the half that the Hermitian path sums) must fit in half of the array, at
+ *   most 1,048,576 evaluated pixels, else NUMAG_E_UNSUPPORTED with a message.
+ *   Calls on one device share the array: calls that may overlap in time on one
+ *   device (streams not ordered with each other, or other host threads) race
+ *   and give wrong results; calls ordered on one stream are safe.  Nothing in
+ *   the array has to start at zero (a call writes every byte it reads).
+ *   The call enqueues kernels only: no hipMalloc, hipFree or host-to-device
+ *   copy, and no wait for the stream (with the kernel timer disabled, since it
+ *   creates events on demand).  The sums equal numag_amplitudes' up to rounding
+ *   (the points may be split differently).
+ */
+#define NUMAG_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int numag_amplitudes_noalloc(const numag_sample *sample, int64_t n_rot, const double *rot,
+                             const numag_qgrid *grid, int32_t path, double *amp_out, void *stream);
+
+/*
  * Object-mode plans (Sec. 3.3 summation relation and dilute limit, for many
  * sample rotations): the host-side part of a DILUTE or SPLIT request -- object
  * offsets, rotations and, on a Cartesian detector, the persistent kernel's

@@ -418,6 +418,12 @@ void delete_plan_cb(void *p) { delete (ObjPlan *)p; }
 
 }  // namespace
 
+int numag::validate_amplitudes_request(const numag_sample *sample, int64_t n_rot, const double *rot,
+                                       const numag_qgrid *grid, int32_t path, int32_t mode, const char *fn)
+{
+    return check_amplitudes_request(sample, n_rot, rot, grid, path, mode, fn);
+}
+
 // The opaque plan handle of the C ABI.
 struct numag_plan {
     std::unique_ptr<ObjPlan> p;

@@ -49,6 +49,11 @@ struct TimedLaunch {
 
 Detector make_detector(const numag_qgrid &g);
 
+// Validation of a numag_amplitudes request (sample, detector, rotations, path and
+// mode); `fn` prefixes the error message.  NUMAG_OK or the status to return.
+int validate_amplitudes_request(const numag_sample *sample, int64_t n_rot, const double *rot,
+                                const numag_qgrid *grid, int32_t path, int32_t mode, const char *fn);
+
 // ---------------------------------------------------------------------------
 // Launchers (each enqueues on `stream`, returns NUMAG_OK or NUMAG_E_HIP).
 // ---------------------------------------------------------------------------

@@ -70,6 +70,7 @@ def _load():
         "numag_correlation": (ctypes.c_int, [P, P, i32, i32, P, i32, d, P, P, P]),
         "numag_grad": (ctypes.c_int, [P, P, P, P, P, P, P, P, P, P, P, sz, P]),
         "numag_grad_path": (ctypes.c_int, [P, P, P, i32, P, P, P, P, P, P, P, P, sz, P]),
+        "numag_amplitudes_noalloc": (ctypes.c_int, [P, i64, P, P, i32, P, P]),
         "numag_plan_create": (ctypes.c_int, [P, i64, P, P, i32, i32, i32, P]),
         "numag_plan_workspace_size": (sz, [P]),
         "numag_plan_upload": (ctypes.c_int, [P, P, sz, P]),
@@ -257,6 +258,18 @@ def amplitudes(sample: Sample, grid: QGrid, rot=None, path=PATH_DIRECT, mode=MOD
                                _ptr(amp), _ptr(spec), _ptr(ws), ws.numel(), _stream())
     _check("numag_amplitudes", rc)
     return amp, spec
+
+
+def amplitudes_noalloc(sample: Sample, grid: QGrid, rot=None, path=PATH_DIRECT, out=None):
+    """numag_amplitudes_noalloc: the coherent sums with the library's static scratch
+    (no workspace, nothing allocated by the library).  Returns amp [n_rot, P, 4, 2]."""
+    r, n_rot = _rot_array(rot)
+    amp = out if out is not None else torch.empty((n_rot, grid.n_pixels, 4, 2), dtype=torch.float64,
+                                                  device=sample.device)
+    rc = _lib.numag_amplitudes_noalloc(sample.c, n_rot, r.ctypes.data_as(ctypes.c_void_p) if r is not None else None,
+                                       ctypes.byref(grid), int(path), _ptr(amp), _stream())
+    _check("numag_amplitudes_noalloc", rc)
+    return amp
 
 
 def regular_grid(n, origin, step) -> Regular:

@@ -240,3 +240,35 @@ def test_object_plans_validate_and_size_on_the_host():
     numag._lib.numag_plan_destroy(None)
     assert numag._lib.numag_plan_workspace_size(None) == 0
 
+
+
+def test_noalloc_entry_rejects_before_any_gpu_work():
+    """numag_amplitudes_noalloc validates like numag_amplitudes and refuses detectors
+    whose partial sums exceed half of its static scratch (no GPU needed: every case
+    returns before a HIP call)."""
+    lib = numag._lib
+    s = _cpu_sample()
+    amp = ctypes.c_void_p(0x2000)
+    grid = numag.qgrid(0, 8, 8, 1.0)
+    assert lib.numag_amplitudes_noalloc(ctypes.byref(s), 1, None, ctypes.byref(grid), numag.PATH_SEPARABLE_F64,
+                                        amp, None) == numag.E_INVALID
+    assert "path" in numag.last_error()
+    assert lib.numag_amplitudes_noalloc(ctypes.byref(s), 1, None, ctypes.byref(grid), 0, None, None) == numag.E_INVALID
+    assert lib.numag_amplitudes_noalloc(None, 1, None, ctypes.byref(grid), 0, amp, None) == numag.E_INVALID
+    assert lib.numag_amplitudes_noalloc(ctypes.byref(s), 2, None, ctypes.byref(grid), 0, amp, None) == numag.E_INVALID
+    bad = np.eye(3).reshape(9) * 2.0
+    assert lib.numag_amplitudes_noalloc(ctypes.byref(s), 1, bad.ctypes.data_as(ctypes.c_void_p), ctypes.byref(grid),
+                                        0, amp, None) == numag.E_INVALID
+    odd = numag.qgrid(1, 8, 7, 1.0)
+    assert lib.numag_amplitudes_noalloc(ctypes.byref(s), 1, None, ctypes.byref(odd), numag.PATH_DIRECT_HERMITIAN,
+                                        amp, None) == numag.E_INVALID
+    # partial sums of 64 bytes per evaluated pixel must fit in half of the scratch
+    cap = 128 << 20
+    limit = cap // 2 // 64
+    big = numag.qgrid(0, 1025, 1024, 1.0)  # 1,049,600 > limit pixels
+    assert 1025 * 1024 > limit
+    assert lib.numag_amplitudes_noalloc(ctypes.byref(s), 1, None, ctypes.byref(big), 0, amp, None) == \
+        numag.E_UNSUPPORTED
+    assert "static scratch" in numag.last_error()
+    text = open(HEADER).read()
+    assert "#define NUMAG_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)" in text

@@ -1,0 +1,71 @@
+"""The allocation-free entry point (numag_amplitudes_noalloc, through the C ABI)
+against numag_amplitudes on the same inputs: the same coherent sums (Sec. 3.3
+DSFT) up to rounding, since only the point split differs.
+
+Two calls in a row share the static scratch: first 1.2 million points on a
+256 x 256 Cartesian detector (the point records do not fit beside the partial
+sums in one piece, so they go through in two chunks), then a smaller input
+(5,000 points, two rotations, a 70 q x 90 theta polar detector), then the
+half-detector (Hermitian) path of each.  Tolerances: the accuracy gate (relative
+error <= 1e-5 at pixels >= 1e-6 of the maximum) and, tighter, 1e-11 of the
+largest sum in the max norm (the two are FP64 sums of the same terms).
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2601_18444_amd import numag, synth  # noqa: E402
+from tests.helpers import amp_to_complex, gated_rel_err, max_norm_err  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _compare(sample, grid, rot, path):
+    ref, _ = numag.amplitudes(sample, grid, rot=rot, path=path)
+    got = numag.amplitudes_noalloc(sample, grid, rot=rot, path=path)
+    torch.cuda.synchronize()
+    a, b = amp_to_complex(got), amp_to_complex(ref)
+    assert np.all(np.isfinite(a))
+    assert max_norm_err(a, b) <= 1e-11
+    for c in range(4):
+        assert gated_rel_err(a[..., c], b[..., c]) <= 1e-5
+
+
+def test_noalloc_matches_workspace_entry_point_two_calls_in_a_row():
+    big = synth.random_cloud(1_200_000, 60.0, seed=11)
+    s1 = numag.Sample(pos=big["pos"], nuc=big["nuc"], mag=big["mag"], device=DEV)
+    g1 = numag.qgrid(0, 256, 256, 1.0)
+    R1 = synth.sample_rotation(20.0, 35.0)
+    print("noalloc: 1.2e6 points, 256 x 256 Cartesian, one rotation", flush=True)
+    _compare(s1, g1, R1, numag.PATH_DIRECT)
+    small = synth.random_cloud(5000, 12.0, seed=12)
+    s2 = numag.Sample(pos=small["pos"], nuc=small["nuc"], mag=small["mag"], device=DEV)
+    g2 = numag.qgrid(1, 70, 90, 1.4)
+    rots = synth.uniform_rotations(2, np.random.default_rng(13))
+    print("noalloc: 5000 points, 70 x 90 polar, two rotations", flush=True)
+    _compare(s2, g2, rots, numag.PATH_DIRECT)
+    print("noalloc: half-detector path on both", flush=True)
+    _compare(s1, g1, R1, numag.PATH_DIRECT_HERMITIAN)
+    _compare(s2, g2, rots, numag.PATH_DIRECT_HERMITIAN)
+
+
+def test_noalloc_objects_channels_and_empty_sample():
+    """Object offsets (coherent total of several objects), a magnetic-only sample
+    and an empty one through the static scratch."""
+    cl = synth.random_cloud(3000, 10.0, seed=14)
+    off = np.array([0, 700, 700, 1900, 3000], dtype=np.int64)
+    opos = np.random.default_rng(15).uniform(-40.0, 40.0, (4, 3))
+    s = numag.Sample(pos=cl["pos"], nuc=cl["nuc"], mag=cl["mag"], obj_offsets=off, obj_pos=opos, device=DEV)
+    g = numag.qgrid(0, 61, 47, 1.1)
+    _compare(s, g, synth.sample_rotation(10.0, 80.0), numag.PATH_DIRECT)
+    sm = numag.Sample(pos=cl["pos"], mag=cl["mag"], device=DEV)
+    _compare(sm, g, None, numag.PATH_DIRECT)
+    e = numag.Sample(pos=np.zeros((0, 3)), nuc=np.zeros(0), device=DEV)
+    got = numag.amplitudes_noalloc(e, g)
+    torch.cuda.synchronize()
+    assert float(got.abs().max()) == 0.0
