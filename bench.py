@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10,
                     help="untimed steps; the engine clock needs about 35 ms of this load to settle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="time the step under the library's default launch shapes (the tuning report is still made)")
     ap.add_argument("--cpu-pixels", type=int, default=49152,
                     help="pixels of the oracle's bounded sample")
     ap.add_argument("--cpu-pixels-1core", type=int, default=1024,
@@ -79,6 +81,36 @@ def parse():
     ap.add_argument("--ensemble", action="store_true",
                     help="only run the 512-sphere split-mode measurement (512 x 512 detector)")
     return ap.parse_args()
+
+
+def kernel_ms(torch, numag, kid, fn, n=3, warm=1):
+    """Average duration (ms) of the library's `kid` kernel launches over n calls of fn."""
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    numag.kernel_timer(True)
+    for _ in range(n):
+        fn()
+    torch.cuda.synchronize()
+    t, k = numag.kernel_timer_read(kid)
+    numag.kernel_timer(False)
+    return t / k if k else float("nan")
+
+
+def tuned_vs_default(torch, numag, kernel, kid, sample, grid, fn, rot=None, max_points=0, n=3, warm=1):
+    """Kernel time under the library's default launch shape, then numag_autotune on the
+    same inputs and the kernel time under the shape it keeps (left in the table for
+    the rest of the run)."""
+    W = sample.n_points
+    numag.tune_set(kernel, grid, W, None)
+    default, _, _ = numag.tune_get(kernel, grid, W)
+    t_def = kernel_ms(torch, numag, kid, fn, n, warm)
+    t0 = time.perf_counter()
+    chosen = numag.autotune(sample, grid, kernel, rot=rot, max_points=max_points)
+    t_tune = time.perf_counter() - t0
+    t_tuned = kernel_ms(torch, numag, kid, fn, n, warm)
+    return {"default_shape": list(default), "tuned_shape": list(chosen), "default_kernel_ms": round(t_def, 4),
+            "tuned_kernel_ms": round(t_tuned, 4), "tuning_s": round(t_tune, 2)}
 
 
 def polar_only(torch, numag, synth, launches=5, warmup=3):
@@ -141,6 +173,11 @@ def measure_batched(torch, numag, synth):
     grid = numag.qgrid(g["kind"], g["n0"], g["n1"], g["qmax"])
     s = numag.Sample(pos=cfg["pos"], nuc=cfg["nuc"], mag=cfg["mag"], obj_offsets=cfg["obj_offsets"], device=dev)
     rots = cfg["rotations"]
+    tuning = tuned_vs_default(
+        torch, numag, numag.TUNE_OBJECTS, numag.KERNEL_OBJECTS, s, grid,
+        lambda: numag.amplitudes(s, grid, rot=rots[:32], mode=numag.MODE_DILUTE, spec_per_object=True),
+        rot=rots[:32], n=2)
+    tuning["sample"] = "first 32 rotations, dilute per-particle average"
     b = numag.BatchedOrientations(s, grid, rots, spec_per_object=True)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -204,6 +241,7 @@ def measure_batched(torch, numag, synth):
         "polar_dilute_Gterm_s": round(polar_terms / t_polar / 1e9, 2),
         "polar_dilute_sample": "same particles, first 50 rotations, 128 q x 128 theta polar detector, dilute "
                                "per-particle average (rotation groups on the polar direct kernel)",
+        "tuning": tuning,
     }
 
 
@@ -268,6 +306,9 @@ def measure_paper_scale(torch, numag, synth):
     rgrid = numag.qgrid(1, 1000, 1000, 100.0)
     s = numag.Sample(pos=cfg["pos"], nuc=cfg["nuc"], mag=cfg["mag"], device=dev)
     amp = torch.empty((1, grid.n_pixels, 4, 2), dtype=torch.float64, device=dev)
+    tuning = tuned_vs_default(torch, numag, numag.TUNE_DIRECT, numag.KERNEL_DIRECT, s, grid,
+                              lambda: numag.amplitudes(s, grid, out=amp), max_points=262144, n=1, warm=0)
+    tuning["sample"] = "candidate shapes timed on the first 262144 points"
     torch.cuda.synchronize()
     e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     e[0].record()
@@ -299,6 +340,7 @@ def measure_paper_scale(torch, numag, synth):
         "corr2d_Gterm_s_effective": round(grid.n_pixels * rgrid.n_pixels / t_corr / 1e9, 1),
         "paper_context": "the paper reports about 60 s on one RTX 3090 for a 3.38e6-cell ensemble with every "
                          "output enabled on grids of this size (not the same workload or outputs)",
+        "tuning": tuning,
     }
 
 
@@ -490,6 +532,16 @@ def main():
         have_sep = False
     torch.cuda.synchronize()
 
+    # launch shapes: the library default, then the autotuner's choice on this workload
+    tuning = {
+        "direct": tuned_vs_default(torch, numag, numag.TUNE_DIRECT, numag.KERNEL_DIRECT, sample, grid,
+                                   lambda: numag.amplitudes(sample, grid, out=amp)),
+        "adjoint": tuned_vs_default(torch, numag, numag.TUNE_ADJOINT, numag.KERNEL_ADJOINT, sample, grid,
+                                    lambda: numag.grad(sample, grid, k, weight=w, target=T, amp=amp[0])),
+    }
+    if args.no_tune:
+        numag.tune_clear()
+
     ev = {"direct": [], "adjoint": [], "separable": []}
 
     def step(record):
@@ -608,7 +660,9 @@ def main():
                         "direct sums + 13 cross sections + azimuthal average + correlation"
                         + (" + separable FP64-MFMA sums" if have_sep else "") + " + loss gradient (adjoint)",
             "points": W, "pixels": P, "evaluated_terms_per_step": 2 * terms,
+            "launch_shapes": "default" if args.no_tune else "autotuned",
         },
+        "tuning": tuning,
         "paths": {
             # the step rate if the separable call's equivalent terms (W P, not evaluated
             # one by one) were counted too

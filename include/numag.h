@@ -385,6 +385,58 @@ int numag_angular_spectrum(const numag_qgrid *grid, const double *f, int32_t n_f
                            double *Ic_out, double *As_out, double *Ac_out, void *stream);
 
 /*
+ * Launch shapes and their autotuner (the paper's runtime scales over three
+ * decades of point counts, Sec. 4.4, so no single launch shape suits every
+ * workload).  A shape cuts a kernel's work into workgroups and point splits; it
+ * never changes what is summed, so sums under different shapes agree to
+ * rounding.  Shapes are kept in a process-wide table keyed by (kernel, detector
+ * kind and the size of the part a path evaluates, the point count's half-octave
+ * class floor(2 log2 W), GPU architecture); a kernel without an entry uses the
+ * library default.  With NUMAG_AUTOTUNE_CACHE naming a file, the table is read
+ * from it on the first lookup and rewritten after every numag_autotune (one
+ * text line per entry).
+ *   kernel    NUMAG_TUNE_DIRECT (direct sums; the detector kind selects the
+ *             Cartesian or the polar kernel), NUMAG_TUNE_ADJOINT (the gradient's
+ *             adjoint sums), NUMAG_TUNE_OBJECTS (the persistent object kernel of
+ *             DILUTE / SPLIT modes on a Cartesian detector).
+ *   shape     Cartesian direct and objects: lanes per detector row (8, 16, 32,
+ *             64); polar direct: workgroup shape 0-4 (0: 64 q rows x 64 theta
+ *             columns; 1: 32 x 64, only for at most 32 q rows; 2: 128 x 32;
+ *             3: 256 x 16 with chunks of 16 points; 4: 256 x 16 with
+ *             double-buffered chunks of 8 points); adjoint: 0.
+ *   target    workgroups a launch aims for (objects: work items); 0 = default.
+ *   path      NUMAG_PATH_DIRECT or NUMAG_PATH_DIRECT_HERMITIAN (which part of
+ *             the detector is evaluated).
+ * numag_tune_get writes the default and the shape in use (either pointer may be
+ * NULL) and returns 1 if the table holds an entry in use, 0 if the default is
+ * used, or a negative status.  numag_tune_set stores a shape (NULL removes the
+ * entry; NUMAG_E_INVALID for a shape the kernel cannot take on this detector).
+ * numag_autotune times the candidate shapes of `kernel` on the caller's sample
+ * and detector (the direct and adjoint kernels on the first max_points points
+ * as one object when max_points > 0; the object kernel on the first 64 of the
+ * rotations, all objects), keeps the fastest in the table (the default unless
+ * another is more than 1 % faster), writes it to *chosen_out (may be NULL) and
+ * saves the cache file if one is named.  It allocates its own trial buffers,
+ * waits for the stream and cannot run under graph capture; call it when no
+ * other call of this library is in flight (workspace sizes follow the table:
+ * query them again after tuning).
+ */
+typedef struct {
+    int32_t shape;
+    int32_t target;
+} numag_tune_shape;
+#define NUMAG_TUNE_DIRECT  0
+#define NUMAG_TUNE_ADJOINT 1
+#define NUMAG_TUNE_OBJECTS 2
+int numag_tune_get(int32_t kernel, const numag_qgrid *grid, int32_t path, int64_t n_points,
+                   numag_tune_shape *default_out, numag_tune_shape *current_out);
+int numag_tune_set(int32_t kernel, const numag_qgrid *grid, int32_t path, int64_t n_points,
+                   const numag_tune_shape *shape);
+int numag_tune_clear(void);
+int numag_autotune(const numag_sample *sample, int64_t n_rot, const double *rot, const numag_qgrid *grid,
+                   int32_t path, int32_t kernel, int64_t max_points, numag_tune_shape *chosen_out, void *stream);
+
+/*
  * Kernel timer, for measurement harnesses.  While enabled, the library records
  * a HIP event pair on the caller's stream around every launch of its sum
  * kernels (the events are enqueued like the kernels: nothing blocks).  Leave

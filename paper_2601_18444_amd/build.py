@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnumag.so")
 SOURCES = ["abi.hip", "direct.hip", "polar.hip", "objects.hip", "observables.hip", "adjoint.hip", "separable.hip", "timing.hip",
-           "noalloc.hip", "correlation2d.hip"]
+           "noalloc.hip", "tune.hip",
+           "correlation2d.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

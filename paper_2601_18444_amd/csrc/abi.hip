@@ -416,6 +416,92 @@ int check_amplitudes_request(const numag_sample *sample, int64_t n_rot, const do
 
 void delete_plan_cb(void *p) { delete (ObjPlan *)p; }
 
+// The detector part a kernel evaluates on `path`: the whole detector, or the half
+// of the Hermitian path (Cartesian rows [0, ceil(n0 / 2)), polar columns
+// [0, n_theta / 2)).
+Detector evaluated_detector(const Detector &d, int32_t path)
+{
+    Detector dh = d;
+    if (path == NUMAG_PATH_DIRECT_HERMITIAN) {
+        if (d.kind == NUMAG_GRID_CARTESIAN) dh.n0 = (d.n0 + 1) / 2;
+        else dh.n1 = d.n1 / 2;
+    }
+    return dh;
+}
+
+// Device buffers the tuner allocates for its trial runs (freed on scope exit).
+struct DeviceBuffers {
+    std::vector<void *> bufs;
+    ~DeviceBuffers()
+    {
+        for (void *b : bufs) (void)hipFree(b);
+    }
+    void *get(size_t bytes)
+    {
+        void *p = nullptr;
+        if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess) return nullptr;
+        bufs.push_back(p);
+        return p;
+    }
+};
+
+// Shortest time (ms) of `reps` runs of f() on st after one untimed run; < 0 on error.
+template <class F>
+double time_runs(F &&f, hipStream_t st, int reps)
+{
+    if (f() != NUMAG_OK) return -1.0;
+    std::vector<hipEvent_t> ev(2 * (size_t)reps, nullptr);
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) e = nullptr;
+    double best = -1.0;
+    bool ok = true;
+    for (int r = 0; r < reps && ok; ++r) {
+        ok = ev[2 * r] != nullptr && ev[2 * r + 1] != nullptr && hipEventRecord(ev[2 * r], st) == hipSuccess &&
+             f() == NUMAG_OK && hipEventRecord(ev[2 * r + 1], st) == hipSuccess;
+    }
+    if (ok && hipStreamSynchronize(st) == hipSuccess) {
+        for (int r = 0; r < reps; ++r) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, ev[2 * r], ev[2 * r + 1]) != hipSuccess) {
+                best = -1.0;
+                break;
+            }
+            if (best < 0.0 || ms < best) best = ms;
+        }
+    }
+    for (auto &e : ev)
+        if (e != nullptr) (void)hipEventDestroy(e);
+    return best;
+}
+
+// Candidate shapes of a kernel on the evaluated detector d.
+std::vector<TuneShape> tune_candidates(int kernel, const Detector &d, int64_t W)
+{
+    std::vector<TuneShape> c;
+    const TuneShape def = default_tune_shape(kernel, d, W);
+    if (kernel == kTuneDirect && d.kind == NUMAG_GRID_POLAR) {
+        const std::vector<int> shapes = d.n0 <= 32 ? std::vector<int>{1, 0} : std::vector<int>{0, 2, 3, 4};
+        for (int sh : shapes)
+            for (int t : {256, 512, 1024}) c.push_back(TuneShape{sh, t * 8 / polar_shape_waves(sh)});
+    } else if (kernel == kTuneDirect || kernel == kTuneObjects) {
+        const int l0 = def.shape;
+        std::vector<int> lanes{l0};
+        if (l0 > 8) lanes.push_back(l0 / 2);
+        if (l0 < 64) lanes.push_back(l0 * 2);
+        const std::vector<int> targets = kernel == kTuneDirect ? std::vector<int>{1024, 2048, 3072, 4096}
+                                                               : std::vector<int>{1024, 2048, 4096};
+        for (int l : lanes)
+            for (int t : targets) c.push_back(TuneShape{l, t});
+    } else {
+        for (int t : {2048, 4096, 8192}) c.push_back(TuneShape{0, t});
+    }
+    // the default first (it is kept unless another shape is clearly faster)
+    std::vector<TuneShape> out{def};
+    for (const TuneShape &s : c)
+        if (s.shape != def.shape || s.target != def.target) out.push_back(s);
+    return out;
+}
+
 }  // namespace
 
 int numag::validate_amplitudes_request(const numag_sample *sample, int64_t n_rot, const double *rot,
@@ -809,6 +895,203 @@ int numag_grad_path(const numag_sample *sample, const double *rot, const numag_q
     const PointRec *pts = (const PointRec *)direct_ws;
     return launch_grad(pts, sample->n_points, d, *consts, amp_in, target, weight, loss_out, dnuc_out, dmag_out,
                        R, gws, grad_workspace_bytes(d, sample->n_points), st, hermitian);
+}
+
+int numag_tune_get(int32_t kernel, const numag_qgrid *grid, int32_t path, int64_t n_points,
+                   numag_tune_shape *default_out, numag_tune_shape *current_out)
+{
+    clear_error();
+    int rc;
+    if ((rc = check_grid(grid, "numag_tune_get")) != NUMAG_OK) return rc;
+    if (kernel < 0 || kernel >= kTuneKernelCount) return invalid("numag_tune_get: unknown kernel");
+    if (path != NUMAG_PATH_DIRECT && path != NUMAG_PATH_DIRECT_HERMITIAN)
+        return invalid("numag_tune_get: path must be NUMAG_PATH_DIRECT or NUMAG_PATH_DIRECT_HERMITIAN");
+    if (n_points < 0) return invalid("numag_tune_get: n_points < 0");
+    const Detector d = evaluated_detector(make_detector(*grid), path);
+    const TuneShape def = default_tune_shape(kernel, d, n_points), cur = current_tune_shape(kernel, d, n_points);
+    if (default_out != nullptr) *default_out = numag_tune_shape{def.shape, def.target};
+    if (current_out != nullptr) *current_out = numag_tune_shape{cur.shape, cur.target};
+    TuneShape t{};
+    return tuned_shape(kernel, d, n_points, &t) && valid_tune_shape(kernel, d, t) ? 1 : 0;
+}
+
+int numag_tune_set(int32_t kernel, const numag_qgrid *grid, int32_t path, int64_t n_points,
+                   const numag_tune_shape *shape)
+{
+    clear_error();
+    int rc;
+    if ((rc = check_grid(grid, "numag_tune_set")) != NUMAG_OK) return rc;
+    if (kernel < 0 || kernel >= kTuneKernelCount) return invalid("numag_tune_set: unknown kernel");
+    if (path != NUMAG_PATH_DIRECT && path != NUMAG_PATH_DIRECT_HERMITIAN)
+        return invalid("numag_tune_set: path must be NUMAG_PATH_DIRECT or NUMAG_PATH_DIRECT_HERMITIAN");
+    if (n_points < 0) return invalid("numag_tune_set: n_points < 0");
+    const Detector d = evaluated_detector(make_detector(*grid), path);
+    if (shape == nullptr) {
+        tune_erase(kernel, d, n_points);
+        return NUMAG_OK;
+    }
+    const TuneShape s{shape->shape, shape->target};
+    if (!valid_tune_shape(kernel, d, s)) return invalid("numag_tune_set: shape not valid for this kernel and detector");
+    tune_store(kernel, d, n_points, s, 0.0, 0.0);
+    return NUMAG_OK;
+}
+
+int numag_tune_clear(void)
+{
+    clear_error();
+    tune_clear();
+    return NUMAG_OK;
+}
+
+int numag_autotune(const numag_sample *sample, int64_t n_rot, const double *rot, const numag_qgrid *grid,
+                   int32_t path, int32_t kernel, int64_t max_points, numag_tune_shape *chosen_out, void *stream)
+{
+    clear_error();
+    int rc;
+    const char *fn = "numag_autotune";
+    if (kernel < 0 || kernel >= kTuneKernelCount) return invalid("numag_autotune: unknown kernel");
+    if (path != NUMAG_PATH_DIRECT && path != NUMAG_PATH_DIRECT_HERMITIAN)
+        return invalid("numag_autotune: path must be NUMAG_PATH_DIRECT or NUMAG_PATH_DIRECT_HERMITIAN");
+    const int32_t mode = kernel == kTuneObjects ? NUMAG_MODE_DILUTE : NUMAG_MODE_COHERENT;
+    if ((rc = check_amplitudes_request(sample, n_rot, rot, grid, path, mode, fn)) != NUMAG_OK) return rc;
+    if (max_points < 0) return invalid("numag_autotune: max_points < 0");
+    if (kernel == kTuneObjects && grid->kind != NUMAG_GRID_CARTESIAN)
+        return invalid("numag_autotune: the persistent object kernel runs on Cartesian detectors");
+    hipStream_t st = (hipStream_t)stream;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    NUMAG_HIP_CHECK(hipStreamIsCapturing(st, &cap));
+    if (cap != hipStreamCaptureStatusNone) {
+        set_error("numag_autotune: waits for the stream and allocates; not under graph capture");
+        return NUMAG_E_UNSUPPORTED;
+    }
+    const Detector dfull = make_detector(*grid);
+    const Detector d = kernel == kTuneObjects ? objects_detector(dfull, path == NUMAG_PATH_DIRECT_HERMITIAN)
+                                              : evaluated_detector(dfull, path);
+    const int64_t W = sample->n_points;
+    const int64_t P = (int64_t)grid->n0 * grid->n1;
+    // the trial sample: coherent kernels time the first max_points points as one
+    // object (object offsets move points, they do not change the work)
+    numag_sample ts = *sample;
+    if (kernel != kTuneObjects) {
+        ts.n_objects = 1;
+        ts.obj_offsets = nullptr;
+        ts.obj_pos = nullptr;
+        if (max_points > 0 && max_points < W && ts.regular == nullptr) ts.n_points = max_points;
+    }
+    const int64_t n_rot_t = kernel == kTuneObjects ? std::min<int64_t>(n_rot, 64) : 1;
+    const std::vector<TuneShape> cands = tune_candidates(kernel, d, W);
+    // buffers: outputs, and a workspace large enough for every candidate
+    DeviceBuffers mem;
+    double *amp = (double *)mem.get((size_t)P * 8 * sizeof(double));
+    double *spec = nullptr, *target = nullptr, *weight = nullptr, *loss = nullptr, *dn = nullptr, *dm = nullptr;
+    if (kernel == kTuneObjects) spec = (double *)mem.get((size_t)P * 16 * sizeof(double) *
+                                                         (size_t)std::max<int64_t>(1, sample->n_objects));
+    if (kernel == kTuneAdjoint) {
+        target = (double *)mem.get((size_t)P * sizeof(double));
+        weight = (double *)mem.get((size_t)P * sizeof(double));
+        loss = (double *)mem.get(sizeof(double));
+        dn = (double *)mem.get((size_t)ts.n_points * sizeof(double));
+        dm = (double *)mem.get((size_t)ts.n_points * 3 * sizeof(double));
+        if (target == nullptr || weight == nullptr || loss == nullptr || dn == nullptr || dm == nullptr) {
+            set_error("numag_autotune: hipMalloc failed");
+            return NUMAG_E_HIP;
+        }
+        if ((rc = launch_fill(target, P, 0.0, st)) != NUMAG_OK) return rc;
+        if ((rc = launch_fill(weight, P, 1.0, st)) != NUMAG_OK) return rc;
+    }
+    if (amp == nullptr || (kernel == kTuneObjects && spec == nullptr)) {
+        set_error("numag_autotune: hipMalloc failed");
+        return NUMAG_E_HIP;
+    }
+    // trial runs read their shape from the table under the trial point count Wt;
+    // the result is stored under the sample's W.  An entry already held under Wt
+    // is put back afterwards (or if tuning fails).
+    const int64_t Wt = ts.n_points;
+    TuneShape prev{};
+    const bool had_prev = tuned_shape(kernel, d, Wt, &prev);
+    auto restore = [&]() {
+        if (had_prev) tune_store(kernel, d, Wt, prev, 0.0, 0.0);
+        else tune_erase(kernel, d, Wt);
+    };
+    size_t ws_need = 0;
+    for (const TuneShape &c : cands) {
+        tune_store(kernel, d, Wt, c, 0.0, 0.0);
+        size_t need = 0;
+        if (kernel == kTuneObjects) {
+            need = make_plan(sample, n_rot_t, nullptr, dfull, path, NUMAG_MODE_DILUTE, 1)->ws_bytes;
+        } else {
+            const Detector &dd = dfull;
+            need = direct_layout(&ts, dd).total + align_up((size_t)P * 8 * sizeof(double)) +
+                   align_up(grad_workspace_bytes(dd, ts.n_points));
+        }
+        ws_need = std::max(ws_need, align_up(need));
+    }
+    void *ws = mem.get(ws_need);
+    if (ws == nullptr) {
+        restore();
+        set_error("numag_autotune: hipMalloc of the trial workspace failed");
+        return NUMAG_E_HIP;
+    }
+    const bool herm = path == NUMAG_PATH_DIRECT_HERMITIAN;
+    const Rot R = rot_of(rot, 0);
+    if (kernel == kTuneAdjoint) {  // the sums the residual weights are formed from
+        if ((rc = run_direct(&ts, R, dfull, amp, ws, st, herm)) != NUMAG_OK) {
+            restore();
+            return rc;
+        }
+    }
+    double best_ms = -1.0, default_ms = -1.0;
+    TuneShape best = cands[0];
+    for (size_t i = 0; i < cands.size(); ++i) {
+        const TuneShape &c = cands[i];
+        tune_store(kernel, d, Wt, c, 0.0, 0.0);
+        std::unique_ptr<ObjPlan> pl;
+        if (kernel == kTuneObjects) {
+            pl = make_plan(sample, n_rot_t, rot, dfull, path, NUMAG_MODE_DILUTE, 1);
+            rc = upload_plan(*pl, ws, st);
+            if (rc == NUMAG_OK && hipStreamSynchronize(st) != hipSuccess) rc = NUMAG_E_HIP;
+            if (rc != NUMAG_OK) {
+                restore();
+                return rc;
+            }
+        }
+        auto run = [&]() -> int {
+            if (kernel == kTuneObjects) return run_plan(*pl, sample, nullptr, spec, ws, st);
+            if (kernel == kTuneDirect) return run_direct(&ts, R, dfull, amp, ws, st, herm);
+            const DirectLayout L = direct_layout(&ts, dfull);
+            char *base = (char *)ws;
+            const int r1 = launch_prepare_points(ts.pos, ts.nuc, ts.mag, 0, ts.n_points, ts.regular, nullptr, 1,
+                                                 nullptr, R, (PointRec *)base, st);
+            if (r1 != NUMAG_OK) return r1;
+            numag_consts k{1.0, 1.0, 1.0, {0.0, 0.0, 1.0}};
+            return launch_grad((const PointRec *)base, ts.n_points, dfull, k, amp, target, weight, loss, dn, dm, R,
+                               base + L.total + align_up((size_t)P * 8 * sizeof(double)),
+                               grad_workspace_bytes(dfull, ts.n_points), st, herm);
+        };
+        // one trial run to size the repetitions: about 0.3 s of timed work per candidate
+        const double t1 = time_runs(run, st, 1);
+        if (t1 < 0.0) {
+            restore();
+            if (numag_last_error()[0] == 0) set_error("numag_autotune: a trial run failed");
+            return NUMAG_E_HIP;
+        }
+        const int reps = (int)std::max(1.0, std::min(5.0, 300.0 / std::max(t1, 1e-3)));
+        const double t = reps > 1 ? std::min(t1, time_runs(run, st, reps)) : t1;
+        if (i == 0) default_ms = t;
+        if (best_ms < 0.0 || t < best_ms) {
+            best_ms = t;
+            best = c;
+        }
+    }
+    // keep the default unless another shape is faster by more than 1 %
+    if (best_ms > 0.99 * default_ms) {
+        best = cands[0];
+        best_ms = default_ms;
+    }
+    if (Wt != W) restore();
+    tune_store(kernel, d, W, best, best_ms, default_ms);
+    if (chosen_out != nullptr) *chosen_out = numag_tune_shape{best.shape, best.target};
+    return tune_save();
 }
 
 }  // extern "C"

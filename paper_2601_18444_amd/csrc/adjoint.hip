@@ -376,9 +376,8 @@ static int adjoint_row_splits(const Detector &d, int64_t W)
 {
     int64_t pblocks = (W + kAdjThreads * kAdjNPL - 1) / (kAdjThreads * kAdjNPL);
     if (pblocks < 1) pblocks = 1;
-    // twice the direct path's workgroups (measured about 2 % faster than the same
-    // count: shorter row ranges balance better across the CUs)
-    int64_t want = (2 * (int64_t)target_workgroups() + pblocks - 1) / pblocks;
+    const int64_t target = current_tune_shape(kTuneAdjoint, d, W).target;
+    int64_t want = (target + pblocks - 1) / pblocks;
     const int extent = d.kind == NUMAG_GRID_CARTESIAN ? d.n0 : d.n1;
     if (want > extent) want = extent;
     if (want < 1) want = 1;

@@ -69,7 +69,8 @@ int launch_prepare_points(const double *pos, const double *nuc, const double *ma
 // direct Cartesian sum.  Writes [nsplit][P][8] partial sums (or the final
 // [P][8] sums when nsplit == 1) for points [0, W).
 struct DirectPlan {
-    int lanes;       // lanes per detector row (Cartesian) or 64 (polar)
+    int lanes;       // lanes per detector row (Cartesian) or theta columns per workgroup (polar)
+    int shape;       // polar: workgroup shape (index into the polar kernel's shapes)
     int channels;    // channels summed: 4 (N, M), 3 (M only) or 1 (N only); the rest are written as 0
     int nsplit;      // point ranges summed by different workgroups
     int64_t per;     // points per split (multiple of the chunk)
@@ -83,6 +84,27 @@ int launch_combine_polar_half(const double *part, int nsplit, int n0, int nh, do
 
 // Workgroups a direct-sum launch aims for (split-K included).
 int target_workgroups();
+
+// ---------------------------------------------------------------------------
+// Launch-shape table (tune.hip): tuned shapes keyed by kernel, the evaluated
+// detector and the point-count class; plans fall back to the defaults below.
+// ---------------------------------------------------------------------------
+enum { kTuneDirect = 0, kTuneAdjoint = 1, kTuneObjects = 2, kTuneKernelCount = 3 };
+struct TuneShape {
+    int shape;   // Cartesian direct / objects: lanes per row; polar direct: workgroup shape; adjoint: 0
+    int target;  // workgroups (objects: work items) a launch aims for
+};
+int tune_wclass(int64_t W);
+bool tuned_shape(int kernel, const Detector &d, int64_t W, TuneShape *out);
+void tune_store(int kernel, const Detector &d, int64_t W, const TuneShape &s, double ms, double default_ms);
+void tune_erase(int kernel, const Detector &d, int64_t W);
+int tune_save();
+void tune_clear();
+bool valid_tune_shape(int kernel, const Detector &d, const TuneShape &s);
+// The library's untuned shape for a kernel on detector d (evaluated part) and W points.
+TuneShape default_tune_shape(int kernel, const Detector &d, int64_t W);
+// The shape in use: the tuned one if the table holds it, else the default.
+TuneShape current_tune_shape(int kernel, const Detector &d, int64_t W);
 // max_splits > 0 caps the point splits (and so the partial-sum buffer).
 DirectPlan plan_direct_cartesian(const Detector &d, int64_t W, int64_t max_splits = 0);
 size_t direct_partial_bytes(const DirectPlan &p, const Detector &d);
@@ -90,8 +112,16 @@ int launch_direct_cartesian(const PointRec *pts, int64_t W, const Detector &d, c
                             double *partial, hipStream_t s);
 
 // Polar detector direct sum: [nsplit][P][8] partials.
-// max_splits > 0 caps the point splits (rotation groups trade splits for rotations).
-DirectPlan plan_direct_polar(const Detector &d, int64_t W, int64_t max_splits = 0);
+// max_splits > 0 caps the point splits (rotation groups trade splits for rotations);
+// shape >= 0 picks a workgroup shape (else the default for the detector) and
+// target_wgs > 0 the workgroups aimed for (else the library default).
+constexpr int kPolarShapeCount = 5;
+int default_polar_shape(const Detector &d);
+int polar_shape_rows(int shape);
+int polar_shape_cols(int shape);
+int polar_shape_waves(int shape);
+DirectPlan plan_direct_polar(const Detector &d, int64_t W, int64_t max_splits = 0, int shape = -1,
+                             int target_wgs = 0);
 // n_rot > 1: pts holds n_rot consecutive copies of W points (one per rotation of a
 // group) and the partials are [n_rot][p.nsplit][P][8].
 int launch_direct_polar(const PointRec *pts, int64_t W, const Detector &d, const DirectPlan &p,

@@ -30,8 +30,6 @@ namespace numag {
 
 namespace {
 
-constexpr int kTarget = 2048;  // work items aimed for
-
 struct RawLoader {
     const double *pos, *nuc, *mag;
     const double *R;  // row-major 3x3, wave-uniform
@@ -234,13 +232,14 @@ Tables make_tables(const Detector &d, const std::vector<int64_t> &off, int64_t K
 {
     Tables T;
     ObjectsPlan &p = T.p;
-    p.lanes = cart::choose_lanes(d.n1);
+    const TuneShape ts = current_tune_shape(kTuneObjects, d, W);
+    p.lanes = ts.shape;
     const int cols = p.lanes * cart::kB, rows = cart::kThreads / p.lanes;
     p.col_blocks = (d.n1 + cols - 1) / cols;
     p.row_blocks = (d.n0 + rows - 1) / rows;
     const int64_t nblocks = (int64_t)p.col_blocks * p.row_blocks;
     // slot groups wanted (each spans all pixel blocks)
-    const int64_t want = std::max<int64_t>(1, (kTarget + nblocks - 1) / nblocks);
+    const int64_t want = std::max<int64_t>(1, (ts.target + nblocks - 1) / nblocks);
     // object groups: single objects, or contiguous groups of roughly equal point counts
     std::vector<int2> groups;
     if (spec_per_object) {

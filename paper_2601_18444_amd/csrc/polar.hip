@@ -7,33 +7,41 @@ namespace numag {
 
 // ---------------------------------------------------------------------------
 // Polar direct sum.  The phase q_i u_m with u_m = Y sin(theta_m) + Z cos(theta_m)
-// does not separate, but along q it is a geometric sequence: lanes own theta
-// columns and each walks 8 q rows, the first by the row-group start, the second
-// by one step exp(-i dq u), the rest by the two-term recurrence
-// p_{r+1} = 2 cos(dq u) p_r - p_{r-1}.  A workgroup of WV waves covers 8 WV rows,
-// so the per-(point, column) generation (u, one sincos for the step, the block
-// start exp(-i q(row0) u) as a power of the step, the wave starts by the same
-// recurrence with step^8) is shared by 8 WV rows.
+// does not separate, but along q it is a geometric sequence: a lane owns one theta
+// column and walks 8 q rows, the first from its row group's start phasor, the
+// second by one step exp(-i dq u), the rest by the two-term recurrence
+// p_{r+1} = 2 cos(dq u) p_r - p_{r-1}.
+//
+// Workgroup shapes (PolarShape): WV waves, CW theta columns; a wave covers its CW
+// columns with 64 / CW row groups of 8 rows, so the workgroup covers
+// ROWS = 8 WV 64 / CW q rows.  The per-(point, column) generation -- u, one sincos
+// for the step, the block start exp(-i q(row0) u) as a power of the step, the row
+// groups' starts by the same recurrence in step^8 -- is done once per workgroup
+// and shared by its ROWS rows: narrower column blocks share it over more rows (and
+// do fewer generations per workgroup) at the price of padding on detectors with
+// fewer rows.
 // ---------------------------------------------------------------------------
-constexpr int kPolarChunk = 8;
-constexpr int kPolarB = 8;
+constexpr int kPolarB = 8;  // q rows per lane
 
-// Operands of point jj for this lane: ez = the wave's start phasor, dz = the q step
-// (the recurrence coefficient 2 Re dz is formed where it is used).
-template <int WV, int R>
-__device__ __forceinline__ cart::Operands polar_operands(const double2 (&s_start)[R][WV][64],
-                                                         const double2 (&s_step)[R][64],
-                                                         const double (&s_w)[R][4], int jj, int lane,
-                                                         int wave)
+// The workgroup shapes the launcher instantiates (index = DirectPlan::shape).
+struct PolarShapeDesc {
+    int waves, cols, chunk, buffers;
+};
+constexpr PolarShapeDesc kPolarShapes[kPolarShapeCount] = {
+    {8, 64, 8, 2},   // 0: 64 rows x 64 columns, double-buffered chunks of 8 points
+    {4, 64, 8, 1},   // 1: 32 rows x 64 columns (detectors of at most 32 q rows), two per CU
+    {8, 32, 8, 2},   // 2: 128 rows x 32 columns, double-buffered
+    {8, 16, 16, 1},  // 3: 256 rows x 16 columns, single-buffered chunks of 16 points
+    {8, 16, 8, 2},   // 4: 256 rows x 16 columns, double-buffered chunks of 8 points
+};
+
+int polar_shape_rows(int shape)
 {
-    cart::Operands o;
-    o.ez = s_start[jj][wave][lane];
-    o.dz = s_step[jj][lane];
-    o.k = 0.0;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) o.w[v] = s_w[jj][v];
-    return o;
+    const PolarShapeDesc &s = kPolarShapes[shape];
+    return kPolarB * s.waves * (64 / s.cols);
 }
+int polar_shape_cols(int shape) { return kPolarShapes[shape].cols; }
+int polar_shape_waves(int shape) { return kPolarShapes[shape].waves; }
 
 // Adds one point to the lane's B q rows: start, one step, then the recurrence.
 template <int B, int CH>
@@ -53,38 +61,35 @@ __device__ __forceinline__ void polar_point(const cart::Operands &o, double (&ac
     }
 }
 
-// LDS buffers of the polar kernel: two at WV = 8 (the next chunk is generated into
-// one while the other is summed, one barrier per chunk, 149 KB), one at WV = 4
-// (two workgroups per CU).
-template <int WV>
-constexpr int polar_buffers()
-{
-    return WV == 8 ? 2 : 1;
-}
-
 // grid.z = rotation r of a group x split sp (nsp splits per rotation); the points of
 // rotation r are pts[r wrot, (r + 1) wrot).  One rotation: wrot = W, nsp = grid.z.
-template <int WV, int CH>
+template <int WV, int CW, int CHK, int NB, int CH>
 __global__ __launch_bounds__(64 * WV, 8 / WV) void direct_polar_kernel(const PointRec *__restrict__ pts,
                                                                       int64_t wrot, int64_t per, int nsp, Detector d,
                                                                       double *__restrict__ out)
 {
     constexpr int B = kPolarB;
-    constexpr int ROWS = WV * B;
-    constexpr int CHK = kPolarChunk;
-    constexpr int NB = polar_buffers<WV>();
+    constexpr int NT = 64 * WV;        // threads
+    constexpr int LPC = 64 / CW;       // row groups per wave
+    constexpr int G = WV * LPC;        // row groups per workgroup
+    constexpr int ROWS = B * G;
+    constexpr int GEN = CHK * CW;      // (point, column) generations per chunk
+    constexpr int GPT = (GEN + NT - 1) / NT;  // generations per thread
+    static_assert(CW == 64 || CW == 32 || CW == 16, "columns per workgroup");
+    static_assert(GEN % 64 == 0, "generation is wave-uniform");
+    static_assert(4 * CHK <= NT, "one weight component per thread");
     // one row per point of a chunk; single-buffered, plus one the pipelined loop
     // may read past the end (double-buffered, that read is clamped instead)
     constexpr int R = NB == 2 ? CHK : CHK + 1;
-    __shared__ double2 s_start[NB][R][WV][64];
-    __shared__ double2 s_step[NB][R][64];
+    __shared__ double2 s_start[NB][R][G][CW];  // start phasor of each row group and column
+    __shared__ double2 s_step[NB][R][CW];      // q step of each column
     __shared__ double s_w[NB][R][4];
-    __shared__ double2 s_trig[64];  // (sin, cos) of the lane's column angle
+    __shared__ double2 s_trig[CW];             // (sin, cos) of the column angles
 
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int wave = t >> 6;
-    const int col0 = blockIdx.x * 64;
+    const int col0 = blockIdx.x * CW;
     const int row0 = blockIdx.y * ROWS;
     const int64_t rbase = (int64_t)(blockIdx.z / nsp) * wrot;
     const int64_t jbeg = rbase + (int64_t)(blockIdx.z % nsp) * per;
@@ -96,46 +101,47 @@ __global__ __launch_bounds__(64 * WV, 8 / WV) void direct_polar_kernel(const Poi
 #pragma unroll
         for (int v = 0; v < 2 * CH; ++v) acc[r][v] = 0.0;
 
-    // generation role: thread t handles column (t & 63) for points wave, wave + WV, ...
-    const int gcol = col0 + lane;
-    if (wave == 0) {
-        const double theta = (2.0 * 3.141592653589793 * (double)gcol) / (double)d.n_theta;
+    if (t < CW) {
+        const double theta = (2.0 * 3.141592653589793 * (double)(col0 + t)) / (double)d.n_theta;
         double sth, cth;
         sincos(theta, &sth, &cth);
-        s_trig[lane] = make_double2(sth, cth);
+        s_trig[t] = make_double2(sth, cth);
     }
     __syncthreads();
     const double qrow0 = axis_value(d.origin0, row0, d.step0);
 
-    // point data of a chunk, loaded one chunk ahead of its generation: (Y, Z) of
-    // the points wave + WV i that this wave generates, and weight component t % 4
-    // of point t / 4 for t < 4 CHK
-    constexpr int GPW = CHK / WV;  // points generated per wave
-    static_assert(GPW * WV == CHK, "chunk and waves");
+    // generation e = t + NT i of a chunk (e < GEN): point e / CW, column e % CW.
+    // Point data of a chunk is loaded one chunk ahead of its generation: (Y, Z) of
+    // the thread's generation points, and weight component t % 4 of point t / 4
+    // for t < 4 CHK.
     const int wj = t >> 2, wc = t & 3;
-    double nY[GPW], nZ[GPW], nW = 0.0;
+    double nY[GPT], nZ[GPT], nW = 0.0;
     auto fetch = [&](int64_t j1) {
 #pragma unroll
-        for (int i = 0; i < GPW; ++i) {
-            const int64_t j = j1 + wave + WV * i;
-            nY[i] = j < jend ? pts[j].Y : 0.0;
-            nZ[i] = j < jend ? pts[j].Z : 0.0;
+        for (int i = 0; i < GPT; ++i) {
+            const int e = t + NT * i;
+            const int64_t j = j1 + e / CW;
+            const bool ok = e < GEN && j < jend;
+            nY[i] = ok ? pts[j].Y : 0.0;
+            nZ[i] = ok ? pts[j].Z : 0.0;
         }
         nW = (wj < CHK && j1 + wj < jend) ? pts[j1 + wj].w[wc] : 0.0;
     };
     // twiddles of the fetched chunk into LDS buffer b (zeros past the end)
     auto generate = [&](int b) {
 #pragma unroll
-        for (int i = 0; i < GPW; ++i) {
-            const int jj = wave + WV * i;
-            const double2 tr = s_trig[lane];
+        for (int i = 0; i < GPT; ++i) {
+            const int e = t + NT * i;
+            if (e >= GEN) break;  // wave-uniform
+            const int jj = e / CW, c = e % CW;
+            const double2 tr = s_trig[c];
             const double u = nY[i] * tr.x + nZ[i] * tr.y;
             const double2 step = twiddle(d.step0 * u);
-            double2 sb = cmul(step, step);  // step^8: from one wave's rows to the next
+            double2 sb = cmul(step, step);  // step^8: from one row group to the next
             sb = cmul(sb, sb);
             sb = cmul(sb, sb);
             // start of the block exp(-i q(row0) u): with q rows from zero it is
-            // step^row0 = (step^(8 WV))^blockIdx.y by binary powering (uniform over
+            // step^row0 = (step^ROWS)^blockIdx.y by binary powering (uniform over
             // the workgroup; the rounding of dq u is carried row0 times, a few
             // times the error of a sincos of q(row0) u, and each squaring adds one
             // rounding)
@@ -143,44 +149,56 @@ __global__ __launch_bounds__(64 * WV, 8 / WV) void direct_polar_kernel(const Poi
             if (d.origin0 == 0.0) {
                 double2 base = sb;
 #pragma unroll
-                for (int w = 1; w < WV; w += w) base = cmul(base, base);
+                for (int g = 1; g < G; g += g) base = cmul(base, base);
                 st = make_double2(1.0, 0.0);
-                for (unsigned e = blockIdx.y; e != 0; e >>= 1) {
-                    if (e & 1) st = cmul(st, base);
-                    if (e > 1) base = cmul(base, base);
+                for (unsigned ex = blockIdx.y; ex != 0; ex >>= 1) {
+                    if (ex & 1) st = cmul(st, base);
+                    if (ex > 1) base = cmul(base, base);
                 }
             } else {
                 st = twiddle(qrow0 * u);
             }
-            s_step[b][jj][lane] = step;
-            // wave starts st sb^w by the two-term recurrence in w (7 steps: the error
-            // grows at most linearly in w)
+            s_step[b][jj][c] = step;
+            // row-group starts st sb^g by the two-term recurrence in g (G - 1 steps:
+            // the error grows at most linearly in g)
             const double k8 = sb.x + sb.x;
             double2 pm = st, pc = cmul(st, sb);
-            s_start[b][jj][0][lane] = pm;
-            s_start[b][jj][1][lane] = pc;
+            s_start[b][jj][0][c] = pm;
+            s_start[b][jj][1][c] = pc;
 #pragma unroll
-            for (int w = 2; w < WV; ++w) {
+            for (int g = 2; g < G; ++g) {
                 const double2 pn = make_double2(fma(k8, pc.x, -pm.x), fma(k8, pc.y, -pm.y));
-                s_start[b][jj][w][lane] = pn;
+                s_start[b][jj][g][c] = pn;
                 pm = pc;
                 pc = pn;
             }
         }
         if (wj < CHK) s_w[b][wj][wc] = nW;
     };
+    // this lane's column and row group
+    const int lc = lane % CW;
+    const int lg = wave * LPC + lane / CW;
+    auto operands = [&](int b, int jj) {
+        cart::Operands o;
+        o.ez = s_start[b][jj][lg][lc];
+        o.dz = s_step[b][jj][lc];
+        o.k = 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) o.w[v] = s_w[b][jj][v];
+        return o;
+    };
     // sums of the nk points in buffer b; the operands of the next point are
     // requested before the current point is accumulated (as in the Cartesian loop)
     auto sum = [&](int b, int nk) {
-        cart::Operands opa = polar_operands<WV, R>(s_start[b], s_step[b], s_w[b], 0, lane, wave);
+        cart::Operands opa = operands(b, 0);
         int jj = 0;
         for (; jj + 1 < nk; jj += 2) {
-            const cart::Operands opb = polar_operands<WV, R>(s_start[b], s_step[b], s_w[b], jj + 1, lane, wave);
+            const cart::Operands opb = operands(b, jj + 1);
             __builtin_amdgcn_sched_barrier(0);
             polar_point<B, CH>(opa, acc);
             __builtin_amdgcn_sched_barrier(0);
             const int nxt = NB == 2 ? min(jj + 2, CHK - 1) : jj + 2;  // past the end: discarded
-            opa = polar_operands<WV, R>(s_start[b], s_step[b], s_w[b], nxt, lane, wave);
+            opa = operands(b, nxt);
             __builtin_amdgcn_sched_barrier(0);
             polar_point<B, CH>(opb, acc);
             __builtin_amdgcn_sched_barrier(0);
@@ -216,9 +234,10 @@ __global__ __launch_bounds__(64 * WV, 8 / WV) void direct_polar_kernel(const Poi
     }
     const int64_t P = (int64_t)d.n0 * d.n1;
     double *dst = out + (int64_t)blockIdx.z * P * 8;
+    const int gcol = col0 + lc;
 #pragma unroll
     for (int r = 0; r < B; ++r) {
-        const int row = row0 + wave * B + r;
+        const int row = row0 + lg * B + r;
         if (row < d.n0 && gcol < d.n1) {
             double *o = dst + ((int64_t)row * d.n1 + gcol) * 8;
 #pragma unroll
@@ -227,31 +246,55 @@ __global__ __launch_bounds__(64 * WV, 8 / WV) void direct_polar_kernel(const Poi
     }
 }
 
-// Waves per workgroup of the polar kernel: 8 (64 rows) unless the detector has
-// at most 32 q rows.
-static int polar_waves(const Detector &d) { return d.n0 > 4 * kPolarB ? 8 : 4; }
+// Default workgroup shape: 32 rows on detectors of at most 32 q rows; otherwise,
+// among the double-buffered shapes, the one with the fewest estimated VALU
+// instructions per (point, theta column): the sums (about 10.3 per term over the
+// padded rows) plus one generation per row block (about 150 for the sincos,
+// powers and stores, plus 2 per row group).  Measured on 262,144 points: 256 x 256
+// and 1000 x 1000 detectors take shape 4 (0.72 and 0.68 of the FP64 peak, against
+// 0.59 and 0.57 for shape 0), 128 x 128 takes shape 2 (0.68 against 0.63).
+int default_polar_shape(const Detector &d)
+{
+    if (d.n0 <= 32) return 1;
+    int best = 0;
+    double best_cost = 0.0;
+    for (int sh : {0, 2, 4}) {
+        const int rows = polar_shape_rows(sh), cols = polar_shape_cols(sh);
+        const double rb = (double)((d.n0 + rows - 1) / rows);
+        const double cpad = (double)(((d.n1 + cols - 1) / cols) * cols) / (double)d.n1;
+        const double cost = cpad * rb * (10.3 * rows + 150.0 + 2.0 * rows / kPolarB);
+        if (sh == 0 || cost < best_cost) {
+            best = sh;
+            best_cost = cost;
+        }
+    }
+    return best;
+}
 
-DirectPlan plan_direct_polar(const Detector &d, int64_t W, int64_t max_splits)
+DirectPlan plan_direct_polar(const Detector &d, int64_t W, int64_t max_splits, int shape, int target_wgs)
 {
     DirectPlan p{};
     p.channels = 4;
-    p.lanes = 64;
-    const int rows = polar_waves(d) * kPolarB;
-    p.col_blocks = (d.n1 + 63) / 64;
+    const TuneShape ts = current_tune_shape(kTuneDirect, d, W);
+    p.shape = shape >= 0 && shape < kPolarShapeCount ? shape : ts.shape;
+    if (d.n0 > 32 && p.shape == 1) p.shape = 0;  // the 4-wave shape serves short detectors only
+    const PolarShapeDesc &sd = kPolarShapes[p.shape];
+    p.lanes = sd.cols;
+    const int rows = polar_shape_rows(p.shape);
+    p.col_blocks = (d.n1 + sd.cols - 1) / sd.cols;
     p.row_blocks = (d.n0 + rows - 1) / rows;
     int64_t blocks = (int64_t)p.col_blocks * p.row_blocks;
-    // half the Cartesian path's wave count: a polar workgroup holds its CU alone, and
-    // two rounds of them over the chip measured faster than four (fewer partials too)
-    int64_t want = (target_workgroups() * 2 / polar_waves(d) + blocks - 1) / blocks;
-    int64_t max_split = (W + 8 * kPolarChunk - 1) / (8 * kPolarChunk);
+    const int tw = target_wgs > 0 ? target_wgs : ts.target;
+    int64_t want = (tw + blocks - 1) / blocks;
+    int64_t max_split = (W + 8 * sd.chunk - 1) / (8 * sd.chunk);
     if (max_split < 1) max_split = 1;
     if (want > max_split) want = max_split;
     if (max_splits > 0 && want > max_splits) want = max_splits;
     if (want > 65535) want = 65535;
     if (want < 1) want = 1;
     int64_t per = (W + want - 1) / want;
-    per = ((per + kPolarChunk - 1) / kPolarChunk) * kPolarChunk;
-    if (per < kPolarChunk) per = kPolarChunk;
+    per = ((per + sd.chunk - 1) / sd.chunk) * sd.chunk;
+    if (per < sd.chunk) per = sd.chunk;
     p.per = per;
     p.nsplit = (int)((W + per - 1) / per);
     if (p.nsplit < 1) p.nsplit = 1;
@@ -262,24 +305,29 @@ int launch_direct_polar(const PointRec *pts, int64_t W, const Detector &d, const
                         double *partial, hipStream_t s, int n_rot)
 {
     if ((int64_t)p.nsplit * n_rot > 65535) return NUMAG_E_INVALID;
+    if (p.shape < 0 || p.shape >= kPolarShapeCount) return NUMAG_E_INVALID;
+    const PolarShapeDesc &sd = kPolarShapes[p.shape];
     dim3 grid(p.col_blocks, p.row_blocks, p.nsplit * n_rot);
     TimedLaunch timed(NUMAG_KERNEL_DIRECT, s);
-#define NUMAG_LAUNCH_POLAR(WV, CH)                                                                          \
-    hipLaunchKernelGGL((direct_polar_kernel<WV, CH>), grid, dim3(64 * WV), 0, s, pts, W, p.per, p.nsplit, d, \
-                       partial)
-#define NUMAG_LAUNCH_POLAR_CH(WV)                  \
-    switch (p.channels) {                          \
-        case 1: NUMAG_LAUNCH_POLAR(WV, 1); break;  \
-        case 3: NUMAG_LAUNCH_POLAR(WV, 3); break;  \
-        default: NUMAG_LAUNCH_POLAR(WV, 4); break; \
+#define NUMAG_LAUNCH_POLAR(WV, CW, CHK, NB, CH)                                                                   \
+    hipLaunchKernelGGL((direct_polar_kernel<WV, CW, CHK, NB, CH>), grid, dim3(64 * WV), 0, s, pts, W, p.per, \
+                       p.nsplit, d, partial)
+#define NUMAG_LAUNCH_POLAR_CH(WV, CW, CHK, NB)                  \
+    switch (p.channels) {                                       \
+        case 1: NUMAG_LAUNCH_POLAR(WV, CW, CHK, NB, 1); break;  \
+        case 3: NUMAG_LAUNCH_POLAR(WV, CW, CHK, NB, 3); break;  \
+        default: NUMAG_LAUNCH_POLAR(WV, CW, CHK, NB, 4); break; \
     }
-    if (polar_waves(d) == 8) {
-        NUMAG_LAUNCH_POLAR_CH(8);
-    } else {
-        NUMAG_LAUNCH_POLAR_CH(4);
+    switch (p.shape) {
+        case 0: NUMAG_LAUNCH_POLAR_CH(8, 64, 8, 2); break;
+        case 1: NUMAG_LAUNCH_POLAR_CH(4, 64, 8, 1); break;
+        case 2: NUMAG_LAUNCH_POLAR_CH(8, 32, 8, 2); break;
+        case 3: NUMAG_LAUNCH_POLAR_CH(8, 16, 16, 1); break;
+        default: NUMAG_LAUNCH_POLAR_CH(8, 16, 8, 2); break;
     }
 #undef NUMAG_LAUNCH_POLAR_CH
 #undef NUMAG_LAUNCH_POLAR
+    (void)sd;
     NUMAG_HIP_CHECK(hipGetLastError());
     return NUMAG_OK;
 }

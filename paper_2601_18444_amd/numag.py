@@ -82,6 +82,10 @@ def _load():
         "numag_spectral_matrix": (ctypes.c_int, [P, i64, P, P, P]),
         "numag_snapshots_workspace_size": (sz, [P, i64, P, i32]),
         "numag_amplitudes_snapshots": (ctypes.c_int, [P, i64, P, P, P, i32, P, P, sz, P]),
+        "numag_tune_get": (ctypes.c_int, [i32, P, i32, i64, P, P]),
+        "numag_tune_set": (ctypes.c_int, [i32, P, i32, i64, P]),
+        "numag_tune_clear": (ctypes.c_int, []),
+        "numag_autotune": (ctypes.c_int, [P, i64, P, P, i32, i32, i64, P, P]),
         "numag_kernel_timer": (ctypes.c_int, [i32]),
         "numag_kernel_timer_read": (ctypes.c_int, [i32, P, P]),
         "numag_last_error": (ctypes.c_char_p, []),
@@ -270,6 +274,47 @@ def amplitudes_noalloc(sample: Sample, grid: QGrid, rot=None, path=PATH_DIRECT, 
                                        ctypes.byref(grid), int(path), _ptr(amp), _stream())
     _check("numag_amplitudes_noalloc", rc)
     return amp
+
+
+TUNE_DIRECT, TUNE_ADJOINT, TUNE_OBJECTS = 0, 1, 2
+
+
+class TuneShape(ctypes.Structure):
+    _fields_ = [("shape", ctypes.c_int32), ("target", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return int(self.shape), int(self.target)
+
+
+def tune_get(kernel: int, grid: QGrid, n_points: int, path=PATH_DIRECT):
+    """(default (shape, target), shape in use (shape, target), tuned entry in use?)"""
+    d, c = TuneShape(), TuneShape()
+    rc = _lib.numag_tune_get(int(kernel), ctypes.byref(grid), int(path), int(n_points), ctypes.byref(d),
+                             ctypes.byref(c))
+    if rc < 0:
+        raise NumagError("numag_tune_get", rc, last_error())
+    return d.as_tuple(), c.as_tuple(), rc == 1
+
+
+def tune_set(kernel: int, grid: QGrid, n_points: int, shape=None, path=PATH_DIRECT) -> None:
+    """Store (shape, target) for the kernel, detector and point-count class; None removes it."""
+    s = None if shape is None else ctypes.byref(TuneShape(int(shape[0]), int(shape[1])))
+    _check("numag_tune_set", _lib.numag_tune_set(int(kernel), ctypes.byref(grid), int(path), int(n_points), s))
+
+
+def tune_clear() -> None:
+    _check("numag_tune_clear", _lib.numag_tune_clear())
+
+
+def autotune(sample: Sample, grid: QGrid, kernel: int = TUNE_DIRECT, rot=None, path=PATH_DIRECT, max_points: int = 0):
+    """numag_autotune: time the candidate shapes of `kernel` on this sample and keep the
+    fastest.  Returns the chosen (shape, target)."""
+    r, n_rot = _rot_array(rot)
+    ch = TuneShape()
+    rc = _lib.numag_autotune(sample.c, n_rot, r.ctypes.data_as(ctypes.c_void_p) if r is not None else None,
+                             ctypes.byref(grid), int(path), int(kernel), int(max_points), ctypes.byref(ch), _stream())
+    _check("numag_autotune", rc)
+    return ch.as_tuple()
 
 
 def regular_grid(n, origin, step) -> Regular:
