@@ -47,7 +47,7 @@ KERNELS = {
 }
 # kernels measured outside the step (their counter summaries, same format)
 SIDE_KERNELS = {
-    "direct_polar_kernel": (0, ["cartesian_sum.h", "polar.hip", "phasor.h", "types.h"],
+    "direct_polar_kernel": (0, ["cartesian_sum.h", "polar_sum.h", "polar.hip", "phasor.h", "types.h"],
                             "direct_polar_kernel_vortex64_polar256x256.md"),
 }
 
@@ -277,6 +277,17 @@ def measure_snapshots(torch, numag, synth, n_snap=64):
     e1.record()
     torch.cuda.synchronize()
     t_single = e0.elapsed_time(e1) * 1e-3
+    # the same batch on the BF16 split-product modes (matrix cores at BF16 rate)
+    t_bf = {}
+    for name, path in (("bf16x3", numag.PATH_SEPARABLE_BF16X3), ("bf16x6", numag.PATH_SEPARABLE_BF16X6)):
+        numag.amplitudes_snapshots(points, grid, nuc=nucs, mag=mt, path=path, out=out, device=dev)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            numag.amplitudes_snapshots(points, grid, nuc=nucs, mag=mt, path=path, out=out, device=dev)
+        e1.record()
+        torch.cuda.synchronize()
+        t_bf[name] = e0.elapsed_time(e1) / reps
     flops = n_snap * 4 * (64 * 64 * 256 * 4 + 256 * 64 * 256 * 8)  # both contractions, four channels
     return {
         "workload": f"{n_snap} field-sweep snapshots of the 64^3 vortex grid, 256x256 detector, FP64 MFMA separable "
@@ -286,6 +297,8 @@ def measure_snapshots(torch, numag, synth, n_snap=64):
         "batched_Gterm_s_effective": round(n_snap * W * grid.n_pixels / t_batch / 1e9, 1),
         "batched_mfma_TFLOP_s": round(flops / t_batch / 1e12, 3),
         "single_calls_per_snapshot_us": round(t_single / n_snap * 1e6, 2),
+        "bf16x3_batched_ms": round(t_bf["bf16x3"], 4),
+        "bf16x6_batched_ms": round(t_bf["bf16x6"], 4),
         # the whole batched call (projection, twiddles, both contractions) against the
         # FP64 matrix peak, the flops being those of the two contractions
         "roofline": {"bound": "mfma", "achieved": round(flops / t_batch / 1e12, 3),
@@ -304,7 +317,9 @@ def measure_paper_scale(torch, numag, synth):
     W = cfg["pos"].shape[0]
     grid = numag.qgrid(1, 1000, 1000, 1.5)
     rgrid = numag.qgrid(1, 1000, 1000, 100.0)
-    s = numag.Sample(pos=cfg["pos"], nuc=cfg["nuc"], mag=cfg["mag"], device=dev)
+    # the spheres at their centres (coherent sums: points moved by the object offsets)
+    s = numag.Sample(pos=cfg["pos"], nuc=cfg["nuc"], mag=cfg["mag"], obj_offsets=cfg["obj_offsets"],
+                     obj_pos=cfg["obj_pos"], device=dev)
     amp = torch.empty((1, grid.n_pixels, 4, 2), dtype=torch.float64, device=dev)
     tuning = tuned_vs_default(torch, numag, numag.TUNE_DIRECT, numag.KERNEL_DIRECT, s, grid,
                               lambda: numag.amplitudes(s, grid, out=amp), max_points=262144, n=1, warm=0)
@@ -320,6 +335,20 @@ def measure_paper_scale(torch, numag, synth):
     torch.cuda.synchronize()
     t_sum = e[0].elapsed_time(e[1]) * 1e-3
     t_corr = e[1].elapsed_time(e[2]) * 1e-3
+    # split mode on the same detector: the 512 spheres as objects at their centres;
+    # one persistent launch gives the coherent sums and the form-factor spectral matrix
+    so = s
+    spec = torch.empty((1, grid.n_pixels, 16), dtype=torch.float64, device=dev)
+    amp_s = torch.empty_like(amp)
+    numag.kernel_timer(True)
+    e[0].record()
+    numag.amplitudes(so, grid, mode=numag.MODE_SPLIT, out=amp_s, spec_out=spec)
+    e[1].record()
+    torch.cuda.synchronize()
+    t_split = e[0].elapsed_time(e[1]) * 1e-3
+    tk, nk = numag.kernel_timer_read(numag.KERNEL_OBJECTS)
+    numag.kernel_timer(False)
+    del spec, amp_s
     # the same sums on the half-detector path (theta in [0, pi), the rest by conjugation)
     amp_h = torch.empty_like(amp)
     e[0].record()
@@ -336,6 +365,12 @@ def measure_paper_scale(torch, numag, synth):
         "sum_Gterm_s": round(W * grid.n_pixels / t_sum / 1e9, 1),
         "sum_hermitian_s": round(t_herm, 4),
         "sum_hermitian_max_diff": herm_diff,
+        "split_mode_s": round(t_split, 4),
+        "split_mode_Gterm_s": round(W * grid.n_pixels / t_split / 1e9, 1),
+        "split_mode_objects_kernel_frac": round(FLOPS_PER_TERM * W * grid.n_pixels / (tk / nk * 1e-3) / PEAK_FP64_VALU,
+                                                4) if nk else None,
+        "split_mode_sample": "the 512 spheres as objects at their centres, split mode (coherent sums and form-factor "
+                             "spectral matrix) on the same polar detector, one persistent launch",
         "cross_section_and_corr2d_s": round(t_corr, 4),
         "corr2d_Gterm_s_effective": round(grid.n_pixels * rgrid.n_pixels / t_corr / 1e9, 1),
         "paper_context": "the paper reports about 60 s on one RTX 3090 for a 3.38e6-cell ensemble with every "

@@ -33,11 +33,12 @@
  * work is enqueued; an invalid call returns a negative status, enqueues
  * nothing and leaves a message for numag_last_error() (per thread).
  *
- * Tuning: the environment variable NUMAG_TARGET_WGS (read once per process)
- * sets the number of workgroups the direct sums aim for per launch (default
- * 2048, the value measured best on MI355X; the polar sums take half, the
- * adjoint twice).  It changes how the points are split, never a result's
- * definition; sums split differently agree to rounding.
+ * Tuning: launch shapes come from a table (numag_tune_get / numag_autotune
+ * below); without an entry, the environment variable NUMAG_TARGET_WGS (read
+ * once per process) sets the number of workgroups the direct sums aim for per
+ * launch (default 2048, the value measured best on MI355X; the polar sums take
+ * half, the adjoint twice).  Shapes change how the work is split, never a
+ * result's definition; sums split differently agree to rounding.
  */
 #ifndef NUMAG_H
 #define NUMAG_H
@@ -68,10 +69,13 @@ extern "C" {
    object and a Cartesian detector.  The sum over x is a projection and the
    rest is two dense complex contractions on the matrix cores. */
 #define NUMAG_PATH_SEPARABLE_F64  1  /* FP64 matrix-core contractions        */
-/* BF16 hi/lo split of every operand, 3 products, FP32 accumulation.  Measured
-   on the 64^3 vortex grid at about 2e-3 gated relative error on the cross
-   sections: it does NOT meet the 1e-4 gate of the matrix-core path, and is
-   provided for speed comparisons only. */
+/* BF16 split products on the matrix cores (FP32 accumulation): every operand
+   split into 2 (X3: 3 products per real product) or 3 (X6: 6 products) bf16
+   parts.  Measured on the 64^3 vortex grid (256 x 256 detector) against the
+   FP64 path, gated relative error of the 13 cross sections: X3 8e-4 .. 2e-2,
+   X6 9e-6 .. 7e-5 except 2.6e-4 on the nuclear-magnetic interference.  Neither
+   meets the 1e-4 gate of the matrix-core path on every observable; they are
+   provided for speed comparisons. */
 #define NUMAG_PATH_SEPARABLE_BF16X3 2
 /* Direct path on half of a detector that is symmetric about q = 0 (every
    Cartesian detector; a polar one with an even n_theta), the other half filled
@@ -82,6 +86,7 @@ extern "C" {
    follow G(-q) = conj G(q) and the coherent total A(-q) = conj A(q), for
    every rotation. */
 #define NUMAG_PATH_DIRECT_HERMITIAN 3
+#define NUMAG_PATH_SEPARABLE_BF16X6 4  /* see NUMAG_PATH_SEPARABLE_BF16X3 */
 
 /* ---- object modes (Sec. 3.3, summation relation and dilute limit) -------- */
 #define NUMAG_MODE_COHERENT 0  /* |sum_k exp(-i q.R r^k) F_k|^2                   */
@@ -173,9 +178,8 @@ size_t numag_workspace_size(const numag_sample *sample, int64_t n_rot, const num
  *             path needs an even n_theta on a polar detector.
  *   mode      DILUTE and SPLIT need explicit positions (NUMAG_E_UNSUPPORTED for
  *             a regular-grid sample); SPLIT takes one rotation.  Both run on
- *             either detector kind (Cartesian: one persistent launch over
- *             objects x rotations; polar: per object, groups of rotations in one
- *             launch each, or one direct sum per object in SPLIT mode).  These
+ *             either detector kind as one persistent launch over (object group,
+ *             rotation range, pixel block) work items.  These
  *             modes build a one-off plan (see numag_plan_create) on every call:
  *             its tables (object offsets, rotations, work items) are copied to
  *             the start of the workspace from host memory the library frees

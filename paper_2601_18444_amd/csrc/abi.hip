@@ -40,6 +40,11 @@ struct Carve {
     }
 };
 
+bool is_separable(int32_t path)
+{
+    return path == NUMAG_PATH_SEPARABLE_F64 || path == NUMAG_PATH_SEPARABLE_BF16X3 || path == NUMAG_PATH_SEPARABLE_BF16X6;
+}
+
 int invalid(const std::string &msg)
 {
     set_error(msg);
@@ -205,111 +210,6 @@ int run_direct(const numag_sample *s, const Rot &R, const Detector &d, double *a
     return launch_combine(part, p.nsplit, P, amp, 0, st);
 }
 
-// Object modes on the polar detector: each (rotation, object) runs the direct
-// polar path into one amplitude buffer and adds F F^H / n_rot into its spectral
-// matrix (split mode: plus the coherent total of the whole sample).  The
-// direct workspace of the whole sample bounds that of every object.  Workspace:
-// the plan image (tag, rotations), then the direct-path scratch and one
-// amplitude set.
-size_t polar_objects_rest(const numag_sample *s, const Detector &d)
-{
-    return direct_layout(s, d).total + align_up((size_t)d.n0 * d.n1 * 8 * sizeof(double));
-}
-
-// Dilute mode on a polar detector: per object, groups of rotations share one
-// point-preparation launch, one polar-sum launch (grid z = rotation x split) and
-// one reduction that adds F F^H / n_rot of each rotation in order.  Splits over
-// the points keep at least kGroupSplitPoints points each (fewer split partial
-// sums to write and read per rotation), and a group is as large as fills the chip
-// (about target_workgroups() / 4 workgroups of 8 waves) within the point and
-// partial buffers of the whole sample.
-constexpr int64_t kGroupSplitPoints = 8192;  // measured: 4096 and 16384 about 4 % slower
-
-int run_dilute_polar(const numag_sample *s, int64_t n_rot, const Detector &d, int32_t spec_per_object,
-                     double *spec_out, const DirectLayout &L, void *direct_ws, const double *d_rot, hipStream_t st,
-                     bool hermitian)
-{
-    const int64_t P = (int64_t)d.n0 * d.n1;
-    const int64_t K = s->n_objects;
-    if (s->nuc == nullptr && s->mag == nullptr) return NUMAG_OK;  // all sums vanish
-    const int channels = s->nuc == nullptr ? 3 : (s->mag == nullptr ? 1 : 4);
-    Carve cv(direct_ws);
-    PointRec *pts = (PointRec *)cv.take(L.points);
-    double *part = (double *)cv.take(L.partial);
-    Detector dk = d;
-    if (hermitian) dk.n1 = d.n1 / 2;  // theta in [0, pi); the rest by conjugation
-    const int64_t Pk = (int64_t)dk.n0 * dk.n1;
-    const int nh = hermitian ? dk.n1 : 0;
-    const double scale = 1.0 / (double)n_rot;
-    for (int64_t k = 0; k < K; ++k) {
-        const int64_t lo = K > 1 ? s->obj_offsets[k] : 0, hi = K > 1 ? s->obj_offsets[k + 1] : s->n_points;
-        const int64_t Wk = hi - lo;
-        if (Wk == 0) continue;
-        DirectPlan p = plan_direct_polar(dk, Wk, (Wk + kGroupSplitPoints - 1) / kGroupSplitPoints);
-        p.channels = channels;
-        const int64_t blocks = (int64_t)p.col_blocks * p.row_blocks;
-        int64_t rg = (target_workgroups() / 4) / (blocks * p.nsplit);
-        rg = std::min<int64_t>(rg, n_rot);
-        rg = std::min<int64_t>(rg, (int64_t)(L.points / ((size_t)Wk * sizeof(PointRec))));
-        rg = std::min<int64_t>(rg, (int64_t)(L.partial / ((size_t)p.nsplit * Pk * 8 * sizeof(double))));
-        rg = std::min<int64_t>(rg, 65535 / p.nsplit);
-        rg = std::max<int64_t>(rg, 1);  // the buffers hold one rotation of any object
-        double *spec = spec_out + (spec_per_object ? k : 0) * P * 16;
-        for (int64_t r0 = 0; r0 < n_rot; r0 += rg) {
-            const int nr = (int)std::min<int64_t>(rg, n_rot - r0);
-            int rc = launch_prepare_rotations(s->pos + 3 * lo, s->nuc != nullptr ? s->nuc + lo : nullptr,
-                                              s->mag != nullptr ? s->mag + 3 * lo : nullptr, Wk, d_rot + 9 * r0, nr,
-                                              pts, st);
-            if (rc == NUMAG_OK) rc = launch_direct_polar(pts, Wk, dk, p, part, st, nr);
-            if (rc == NUMAG_OK) rc = launch_spectral_rotations(part, nr, p.nsplit, Pk, d.n1, nh, scale, spec, st);
-            if (rc != NUMAG_OK) return rc;
-        }
-    }
-    return NUMAG_OK;
-}
-
-int run_objects_polar(const ObjPlan &pl, const numag_sample *s, double *spec_out, double *amp_out, void *ws,
-                      hipStream_t st)
-{
-    const Detector &d = pl.d;
-    const bool hermitian = pl.path == NUMAG_PATH_DIRECT_HERMITIAN;
-    const int64_t P = (int64_t)d.n0 * d.n1;
-    const int64_t K = s->n_objects;
-    const DirectLayout L = direct_layout(s, d);
-    char *base = (char *)ws;
-    const double *d_rot = (const double *)(base + pl.o_rot);
-    const double *h_rot = (const double *)(pl.image.data() + pl.o_rot);
-    Carve cv(base + pl.image.size());
-    void *direct_ws = cv.take(L.total);
-    double *F = (double *)cv.take((size_t)P * 8 * sizeof(double));
-    const int64_t n_spec = pl.spec_per_object ? K : 1;
-    int rc = launch_fill(spec_out, n_spec * P * 16, 0.0, st);
-    if (rc != NUMAG_OK) return rc;
-    if (pl.mode == NUMAG_MODE_DILUTE) {
-        rc = run_dilute_polar(s, pl.n_rot, d, pl.spec_per_object, spec_out, L, direct_ws, d_rot, st, hermitian);
-    } else {
-        rc = run_direct(s, rot_of(h_rot, 0), d, amp_out, direct_ws, st, hermitian);
-        for (int64_t k = 0; k < K && rc == NUMAG_OK; ++k) {
-            const int64_t lo = K > 1 ? s->obj_offsets[k] : 0, hi = K > 1 ? s->obj_offsets[k + 1] : s->n_points;
-            if (hi == lo) continue;
-            numag_sample sk{};
-            sk.n_points = hi - lo;
-            sk.pos = s->pos + 3 * lo;
-            sk.nuc = s->nuc != nullptr ? s->nuc + lo : nullptr;
-            sk.mag = s->mag != nullptr ? s->mag + 3 * lo : nullptr;
-            sk.n_objects = 1;
-            rc = run_direct(&sk, rot_of(h_rot, 0), d, F, direct_ws, st, hermitian);
-            if (rc == NUMAG_OK)
-                rc = launch_spectral_matrix(1, P, F, spec_out + (pl.spec_per_object ? k : 0) * P * 16, st, 1.0, 1);
-        }
-    }
-    if (rc != NUMAG_OK) return rc;
-    // a workspace without this plan's image gives NaN
-    rc = launch_tag_guard((const unsigned long long *)base, pl.tag, spec_out, n_spec * P * 16, st);
-    if (rc == NUMAG_OK && amp_out != nullptr) rc = launch_tag_guard((const unsigned long long *)base, pl.tag, amp_out, P * 8, st);
-    return rc;
-}
-
 unsigned long long next_plan_tag()
 {
     static std::atomic<unsigned long long> counter{0};
@@ -345,14 +245,7 @@ std::unique_ptr<ObjPlan> make_plan(const numag_sample *s, int64_t n_rot, const d
     } else {
         std::memcpy(pl->off.data(), s->obj_offsets, sizeof(int64_t) * (s->n_objects + 1));
     }
-    if (d.kind == NUMAG_GRID_CARTESIAN) {
-        build_objects_plan_cartesian(*pl);
-    } else {
-        pl->o_rot = kPlanTagBytes;
-        pl->image.assign(kPlanTagBytes + align_up((size_t)n_rot * 9 * sizeof(double)), 0);
-        std::memcpy(pl->image.data(), &pl->tag, sizeof(pl->tag));
-        pl->ws_bytes = pl->image.size() + polar_objects_rest(s, d);
-    }
+    build_objects_plan(*pl);
     double *R = (double *)(pl->image.data() + pl->o_rot);
     if (rot != nullptr) {
         std::memcpy(R, rot, sizeof(double) * 9 * n_rot);
@@ -364,8 +257,7 @@ std::unique_ptr<ObjPlan> make_plan(const numag_sample *s, int64_t n_rot, const d
 
 int run_plan(const ObjPlan &pl, const numag_sample *s, double *amp_out, double *spec_out, void *ws, hipStream_t st)
 {
-    if (pl.d.kind == NUMAG_GRID_CARTESIAN) return launch_objects_plan(pl, *s, spec_out, amp_out, ws, st);
-    return run_objects_polar(pl, s, spec_out, amp_out, ws, st);
+    return launch_objects_plan(pl, *s, spec_out, amp_out, ws, st);
 }
 
 int upload_plan(const ObjPlan &pl, void *ws, hipStream_t st)
@@ -377,7 +269,7 @@ int upload_plan(const ObjPlan &pl, void *ws, hipStream_t st)
 size_t amplitudes_ws(const numag_sample *s, int64_t n_rot, const Detector &d, int32_t path, int32_t mode,
                      int32_t spec_per_object)
 {
-    if (path == NUMAG_PATH_SEPARABLE_F64 || path == NUMAG_PATH_SEPARABLE_BF16X3)
+    if (is_separable(path))
         return align_up(separable_workspace_bytes(*s->regular, d, path, 1));
     if (mode == NUMAG_MODE_COHERENT) return direct_layout(s, d).total;
     return align_up(make_plan(s, n_rot, nullptr, d, path, mode, spec_per_object)->ws_bytes);
@@ -393,10 +285,10 @@ int check_amplitudes_request(const numag_sample *sample, int64_t n_rot, const do
     if ((rc = check_rotations(rot, n_rot, fn)) != NUMAG_OK) return rc;
     const std::string f(fn);
     if (mode < NUMAG_MODE_COHERENT || mode > NUMAG_MODE_SPLIT) return invalid(f + ": unknown mode");
-    if (path < NUMAG_PATH_DIRECT || path > NUMAG_PATH_DIRECT_HERMITIAN) return invalid(f + ": unknown path");
+    if (path < NUMAG_PATH_DIRECT || path > NUMAG_PATH_SEPARABLE_BF16X6) return invalid(f + ": unknown path");
     if (path == NUMAG_PATH_DIRECT_HERMITIAN && grid->kind == NUMAG_GRID_POLAR && grid->n1 % 2 != 0)
         return invalid(f + ": the Hermitian path needs an even n_theta on a polar detector");
-    if (path == NUMAG_PATH_SEPARABLE_F64 || path == NUMAG_PATH_SEPARABLE_BF16X3) {
+    if (is_separable(path)) {
         if (sample->regular == nullptr) return invalid(f + ": separable path needs sample->regular");
         if (!rot_is_identity(rot) || n_rot != 1) return invalid(f + ": separable path needs the identity rotation");
         if (sample->n_objects != 1) return invalid(f + ": separable path needs one object");
@@ -483,6 +375,10 @@ std::vector<TuneShape> tune_candidates(int kernel, const Detector &d, int64_t W)
         const std::vector<int> shapes = d.n0 <= 32 ? std::vector<int>{1, 0} : std::vector<int>{0, 2, 3, 4};
         for (int sh : shapes)
             for (int t : {256, 512, 1024}) c.push_back(TuneShape{sh, t * 8 / polar_shape_waves(sh)});
+    } else if (kernel == kTuneObjects && d.kind == NUMAG_GRID_POLAR) {
+        const std::vector<int> shapes = d.n0 <= 32 ? std::vector<int>{1, 0} : std::vector<int>{0, 2, 4};
+        for (int sh : shapes)
+            for (int t : {512, 1024, 2048}) c.push_back(TuneShape{sh, t});
     } else if (kernel == kTuneDirect || kernel == kTuneObjects) {
         const int l0 = def.shape;
         std::vector<int> lanes{l0};
@@ -575,11 +471,11 @@ size_t numag_workspace_size(const numag_sample *sample, int64_t n_rot, const num
         set_error("numag_workspace_size: unknown mode");
         return 0;
     }
-    if (path < NUMAG_PATH_DIRECT || path > NUMAG_PATH_DIRECT_HERMITIAN) {
+    if (path < NUMAG_PATH_DIRECT || path > NUMAG_PATH_SEPARABLE_BF16X6) {
         set_error("numag_workspace_size: unknown path");
         return 0;
     }
-    if ((path == NUMAG_PATH_SEPARABLE_F64 || path == NUMAG_PATH_SEPARABLE_BF16X3) && sample->regular == nullptr) {
+    if ((is_separable(path)) && sample->regular == nullptr) {
         set_error("numag_workspace_size: separable path needs a regular grid");
         return 0;
     }
@@ -645,7 +541,7 @@ int numag_amplitudes(const numag_sample *sample, int64_t n_rot, const double *ro
         set_error("numag_amplitudes: workspace too small (need " + std::to_string(need) + " bytes)");
         return NUMAG_E_WORKSPACE;
     }
-    if (path == NUMAG_PATH_SEPARABLE_F64 || path == NUMAG_PATH_SEPARABLE_BF16X3)
+    if (is_separable(path))
         return launch_separable(sample->nuc, sample->mag, *sample->regular, d, path, 1, amp_out, workspace,
                                 ws_bytes, st);
     for (int64_t r = 0; r < n_rot; ++r) {
@@ -734,7 +630,7 @@ static int check_snapshots(const numag_regular *points, int64_t n_snap, const nu
     if (points == nullptr) return invalid(std::string(fn) + ": points is NULL");
     if (n_snap < 1) return invalid(std::string(fn) + ": n_snap must be >= 1");
     if ((rc = check_grid(grid, fn)) != NUMAG_OK) return rc;
-    if (path != NUMAG_PATH_SEPARABLE_F64 && path != NUMAG_PATH_SEPARABLE_BF16X3)
+    if (!is_separable(path))
         return invalid(std::string(fn) + ": snapshots run on the separable paths");
     if (grid->kind != NUMAG_GRID_CARTESIAN) return invalid(std::string(fn) + ": separable path needs a Cartesian detector");
     numag_sample smp{};
@@ -955,8 +851,6 @@ int numag_autotune(const numag_sample *sample, int64_t n_rot, const double *rot,
     const int32_t mode = kernel == kTuneObjects ? NUMAG_MODE_DILUTE : NUMAG_MODE_COHERENT;
     if ((rc = check_amplitudes_request(sample, n_rot, rot, grid, path, mode, fn)) != NUMAG_OK) return rc;
     if (max_points < 0) return invalid("numag_autotune: max_points < 0");
-    if (kernel == kTuneObjects && grid->kind != NUMAG_GRID_CARTESIAN)
-        return invalid("numag_autotune: the persistent object kernel runs on Cartesian detectors");
     hipStream_t st = (hipStream_t)stream;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     NUMAG_HIP_CHECK(hipStreamIsCapturing(st, &cap));

@@ -113,34 +113,6 @@ __global__ void prepare_points_kernel(const double *__restrict__ pos, const doub
     out[j - out_base] = point_record(x, R, nuc, mag, j);
 }
 
-// Points of one object (explicit positions, no object offset) under a group of
-// rotations: out[r][j] for rotation r < nr of rots[r][9] (device), the same
-// records prepare_points_kernel writes for each rotation.
-__global__ void prepare_rotations_kernel(const double *__restrict__ pos, const double *__restrict__ nuc,
-                                         const double *__restrict__ mag, int64_t W,
-                                         const double *__restrict__ rots, PointRec *__restrict__ out)
-{
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= W) return;
-    const int r = blockIdx.y;
-    Rot R;
-#pragma unroll
-    for (int a = 0; a < 9; ++a) R.m[a] = rots[9 * r + a];
-    const double x[3] = {pos[3 * j + 0], pos[3 * j + 1], pos[3 * j + 2]};
-    out[(int64_t)r * W + j] = point_record(x, R, nuc, mag, j);
-}
-
-int launch_prepare_rotations(const double *pos, const double *nuc, const double *mag, int64_t W,
-                             const double *d_rots, int nr, PointRec *out, hipStream_t s)
-{
-    if (W <= 0 || nr <= 0) return NUMAG_OK;
-    if (nr > 65535) return NUMAG_E_INVALID;
-    dim3 grid((unsigned)((W + 255) / 256), (unsigned)nr);
-    hipLaunchKernelGGL(prepare_rotations_kernel, grid, dim3(256), 0, s, pos, nuc, mag, W, d_rots, out);
-    NUMAG_HIP_CHECK(hipGetLastError());
-    return NUMAG_OK;
-}
-
 int launch_prepare_points(const double *pos, const double *nuc, const double *mag, int64_t j_lo, int64_t j_hi,
                           const numag_regular *regular, const int64_t *h_offsets, int64_t K,
                           const double *obj_pos, const Rot &R, PointRec *out, hipStream_t s)
@@ -255,7 +227,8 @@ TuneShape default_tune_shape(int kernel, const Detector &d, int64_t W)
             // twice the direct path's workgroups (measured about 2 % faster than the same
             // count: shorter row ranges balance better across the CUs)
             return TuneShape{0, 2 * target_workgroups()};
-        default:
+        default:  // the persistent object kernel: lanes per row (polar: workgroup shape), work items
+            if (d.kind == NUMAG_GRID_POLAR) return TuneShape{default_polar_shape(d), 1024};
             return TuneShape{cart::choose_lanes(d.n1), 2048};
     }
 }

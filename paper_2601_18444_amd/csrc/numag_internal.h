@@ -126,14 +126,6 @@ DirectPlan plan_direct_polar(const Detector &d, int64_t W, int64_t max_splits = 
 // group) and the partials are [n_rot][p.nsplit][P][8].
 int launch_direct_polar(const PointRec *pts, int64_t W, const Detector &d, const DirectPlan &p,
                         double *partial, hipStream_t s, int n_rot = 1);
-// Points of one object under nr rotations (d_rots: device [nr][9]) into out[nr][W].
-int launch_prepare_rotations(const double *pos, const double *nuc, const double *mag, int64_t W,
-                             const double *d_rots, int nr, PointRec *out, hipStream_t s);
-// spec[p] += scale sum over the group's rotations of F F^H from polar partials
-// [nr][nsp][Ph][8]; nh > 0: half-detector partials, mirrored into column m + nh.
-int launch_spectral_rotations(const double *part, int nr, int nsp, int64_t Ph, int n1, int nh, double scale,
-                              double *spec, hipStream_t s);
-
 // out[i] = value for i < n (a kernel, so that callers may capture it in a graph).
 int launch_fill(double *out, int64_t n, double value, hipStream_t s);
 
@@ -159,7 +151,7 @@ struct ObjectsPlan {
 // unique to the plan; the kernels compare it with the plan's and write NaN
 // instead of reading tables that another plan, or other data, left there.
 constexpr size_t kPlanTagBytes = 256;
-struct ObjPlanCart;  // Cartesian work tables (objects.hip)
+struct ObjPlanTables;  // the persistent kernel's work tables (objects.hip)
 struct ObjPlan {
     unsigned long long tag;
     Detector d;                 // the whole detector
@@ -169,19 +161,19 @@ struct ObjPlan {
     std::vector<char> image;    // uploaded to workspace offset 0: the tag, then the tables
     size_t o_rot = 0;           // rotations [n_rot][9] (doubles) within the image
     size_t ws_bytes = 0;        // workspace bytes the plan's calls need
-    std::shared_ptr<ObjPlanCart> cart;  // Cartesian detector: the persistent kernel's tables
+    std::shared_ptr<ObjPlanTables> tables;  // the persistent kernel's tables
 };
-// Detector whose rows the object kernel sums: all of d, or with `hermitian` the
-// first ceil(n0 / 2) rows of a Cartesian detector (the rest follow by
-// G(-q) = conj G(q)).
+// Detector part the object kernel sums: all of d, or with `hermitian` the first
+// ceil(n0 / 2) rows of a Cartesian detector or the theta columns [0, n_theta / 2)
+// of a polar one (the rest follow by G(-q) = conj G(q)).
 Detector objects_detector(const Detector &d, bool hermitian);
-// Fills pl.cart, pl.image (rotations excepted), pl.o_rot and pl.ws_bytes of a plan on a
-// Cartesian detector whose other fields are set.
-void build_objects_plan_cartesian(ObjPlan &pl);
+// Fills pl.tables, pl.image (rotations excepted), pl.o_rot and pl.ws_bytes of a plan
+// whose other fields are set (either detector kind).
+void build_objects_plan(ObjPlan &pl);
 // out[i] = NaN (i < n) when the tag at tag_ptr is not `tag`.
 int launch_tag_guard(const unsigned long long *tag_ptr, unsigned long long tag, double *out, int64_t n,
                      hipStream_t st);
-// Enqueues the sums of a Cartesian plan whose image is in `ws` (kernels only).
+// Enqueues the sums of a plan whose image is in `ws` (kernels only).
 int launch_objects_plan(const ObjPlan &pl, const numag_sample &s, double *spec_out, double *amp_out, void *ws,
                         hipStream_t st);
 

@@ -17,7 +17,9 @@
 //
 // Rotations are applied on the fly (X = R x, w' = (n, R m)) while a chunk's
 // twiddles are generated, so the point data is read once per chunk and never
-// rewritten per orientation.
+// rewritten per orientation.  On a polar detector the same work queue runs on the
+// polar building block (polar_sum.h): a pixel block is one of its workgroup
+// tiles (q rows x theta columns).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -25,6 +27,7 @@
 #include <vector>
 
 #include "cartesian_sum.h"
+#include "polar_sum.h"
 
 namespace numag {
 
@@ -141,30 +144,128 @@ __global__ __launch_bounds__(cart::kThreads, 2) void objects_kernel(ObjArgs a, D
     }
 }
 
+// The same work queue on a polar detector: a pixel block is a polar workgroup
+// tile (col_blocks theta-column blocks of CW columns x row blocks of ROWS q rows);
+// the lane's pixels are its 8 q rows of one theta column.
+template <int WV, int CW, int CHK, int NB>
+__global__ __launch_bounds__(64 * WV, 8 / WV) void objects_polar_kernel(ObjArgs a, Detector d)
+{
+    using S = polar::Shape<WV, CW, CHK, NB>;
+    __shared__ polar::Smem<WV, CW, CHK, NB> sm;
+    __shared__ int s_item;
+    const int64_t P = (int64_t)d.n0 * d.n1;
+    if (*a.tag_ptr != a.tag) return;  // the workspace does not hold this plan's tables
+    const int lc = polar::lane_col<WV, CW>(), lg = polar::lane_group<WV, CW>();
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();
+        if (it >= a.n_items) break;
+        const int2 item = a.items[it];
+        const int slot = item.x, blk = item.y;
+        const int col0 = (blk % a.col_blocks) * CW;
+        const int rb = blk / a.col_blocks;
+        const int col = col0 + lc;
+        const int row0 = rb * S::ROWS + lg * polar::kB;
+        const int4 sr = a.slots[slot];
+        double *G = a.spec + (int64_t)slot * P * 16;
+        for (int r = sr.z; r < sr.w; ++r) {
+            const double *R = a.rot + 9 * (int64_t)r;
+            for (int k = sr.x; k < sr.y; ++k) {
+                double acc[polar::kB][8];
+#pragma unroll
+                for (int q = 0; q < polar::kB; ++q)
+#pragma unroll
+                    for (int v = 0; v < 8; ++v) acc[q][v] = 0.0;
+                polar::accumulate<WV, CW, CHK, NB, 4>(RawLoader{a.pos, a.nuc, a.mag, R}, a.off[k], a.off[k + 1], d,
+                                                      col0, rb, sm, acc);
+                if (col >= d.n1) continue;
+                // lab position of the object projected on the column direction (split mode)
+                double uk = 0.0;
+                if (a.amp != nullptr && a.obj_pos != nullptr) {
+                    const double *o = a.obj_pos + 3 * k;
+                    const double XY = R[3] * o[0] + R[4] * o[1] + R[5] * o[2];
+                    const double XZ = R[6] * o[0] + R[7] * o[1] + R[8] * o[2];
+                    const double2 tr = sm.trig[lc];  // valid until the next accumulate call
+                    uk = XY * tr.x + XZ * tr.y;
+                }
+#pragma unroll
+                for (int q = 0; q < polar::kB; ++q) {
+                    const int row = row0 + q;
+                    if (row >= d.n0) break;
+                    const int64_t p = (int64_t)row * d.n1 + col;
+                    const double *F = acc[q];
+                    double *g = G + p * 16;
+                    // G_ab += F_a conj(F_b): diagonal, then the upper triangle
+                    g[0] += F[0] * F[0] + F[1] * F[1];
+                    g[1] += F[2] * F[2] + F[3] * F[3];
+                    g[2] += F[4] * F[4] + F[5] * F[5];
+                    g[3] += F[6] * F[6] + F[7] * F[7];
+                    const int pa[6] = {0, 0, 0, 1, 1, 2};
+                    const int pb[6] = {1, 2, 3, 2, 3, 3};
+#pragma unroll
+                    for (int t = 0; t < 6; ++t) {
+                        const double ar = F[2 * pa[t]], ai = F[2 * pa[t] + 1];
+                        const double br = F[2 * pb[t]], bi = F[2 * pb[t] + 1];
+                        g[4 + 2 * t] += ar * br + ai * bi;
+                        g[5 + 2 * t] += ai * br - ar * bi;
+                    }
+                    if (a.amp != nullptr) {
+                        const double2 ph = twiddle(axis_value(d.origin0, row, d.step0) * uk);
+                        double *o = a.amp + ((int64_t)slot * P + p) * 8;
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            o[2 * v] += ph.x * F[2 * v] - ph.y * F[2 * v + 1];
+                            o[2 * v + 1] += ph.x * F[2 * v + 1] + ph.y * F[2 * v];
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
 __global__ void fill_i32_kernel(int *p, int n, int v)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
 }
 
+// Full-detector pixel of pixel p of the evaluated part: the same index (the
+// first rows of a Cartesian detector), or, with nh > 0, column p % nh of row
+// p / nh of a polar detector of 2 nh columns (the half theta < pi).
+__device__ __forceinline__ int64_t full_pixel(int64_t p, int nh)
+{
+    return nh > 0 ? (p / nh) * 2 * nh + p % nh : p;
+}
+
 // out[s][p][v] = scale * sum of the slots of output s (slot_off CSR, ascending);
-// slots hold P pixels, out rows are P_out >= P pixels apart (the first P filled)
+// slots hold P pixels, out rows are P_out >= P pixels apart.  nh > 0: the slots
+// hold the half theta < pi of a polar detector, and pixel (i, m + nh) receives
+// conj G of pixel (i, m) (real weights: G(-q) = conj G(q)).
 // A workspace that does not hold the plan's tables (tag mismatch) gives NaN.
 __global__ void spec_reduce_kernel(const unsigned long long *tag_ptr, unsigned long long tag,
                                    const double *__restrict__ slots, const int *__restrict__ slot_off, int n_out,
-                                   int64_t P, int64_t P_out, double scale, double *__restrict__ out)
+                                   int64_t P, int64_t P_out, int nh, double scale, double *__restrict__ out)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)n_out * P * 16) return;
     const int s = (int)(idx / (P * 16));
     const int64_t pv = idx % (P * 16);
+    const int v = (int)(pv & 15);
+    const int64_t pf = full_pixel(pv >> 4, nh);
+    double *o = out + (int64_t)s * P_out * 16;
+    double val;
     if (*tag_ptr != tag) {
-        out[(int64_t)s * P_out * 16 + pv] = __builtin_nan("");
-        return;
+        val = __builtin_nan("");
+    } else {
+        double acc = 0.0;
+        for (int sl = slot_off[s]; sl < slot_off[s + 1]; ++sl) acc += slots[(int64_t)sl * P * 16 + pv];
+        val = scale * acc;
     }
-    double acc = 0.0;
-    for (int sl = slot_off[s]; sl < slot_off[s + 1]; ++sl) acc += slots[(int64_t)sl * P * 16 + pv];
-    out[(int64_t)s * P_out * 16 + pv] = scale * acc;
+    o[pf * 16 + v] = val;
+    if (nh > 0) o[(pf + nh) * 16 + v] = (v >= 5 && (v & 1)) ? -val : val;
 }
 
 // out[i] = NaN for i < n when the workspace tag is not the plan's.
@@ -192,19 +293,26 @@ __global__ void mirror_spec_kernel(double *__restrict__ out, int n_out, int64_t 
     o[q * 16 + v] = (v >= 5 && (v & 1)) ? -o[p * 16 + v] : o[p * 16 + v];
 }
 
+// Coherent total: out = sum of the amplitude slots in order (nh > 0: polar half,
+// pixel (i, m + nh) receives conj A of pixel (i, m)).
 __global__ void amp_reduce_kernel(const unsigned long long *tag_ptr, unsigned long long tag,
-                                  const double *__restrict__ slots, int n_slots, int64_t P,
+                                  const double *__restrict__ slots, int n_slots, int64_t P, int nh,
                                   double *__restrict__ out)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= P * 8) return;
+    const int v = (int)(idx & 7);
+    const int64_t pf = full_pixel(idx >> 3, nh);
+    double val;
     if (*tag_ptr != tag) {
-        out[idx] = __builtin_nan("");
-        return;
+        val = __builtin_nan("");
+    } else {
+        double s = 0.0;
+        for (int sl = 0; sl < n_slots; ++sl) s += slots[(int64_t)sl * P * 8 + idx];
+        val = s;
     }
-    double s = 0.0;
-    for (int sl = 0; sl < n_slots; ++sl) s += slots[(int64_t)sl * P * 8 + idx];
-    out[idx] = s;
+    out[pf * 8 + v] = val;
+    if (nh > 0) out[(pf + nh) * 8 + v] = (v & 1) ? -val : val;
 }
 
 int device_cus()
@@ -233,8 +341,9 @@ Tables make_tables(const Detector &d, const std::vector<int64_t> &off, int64_t K
     Tables T;
     ObjectsPlan &p = T.p;
     const TuneShape ts = current_tune_shape(kTuneObjects, d, W);
-    p.lanes = ts.shape;
-    const int cols = p.lanes * cart::kB, rows = cart::kThreads / p.lanes;
+    p.lanes = ts.shape;  // Cartesian: lanes per row; polar: the workgroup shape
+    const int cols = d.kind == NUMAG_GRID_POLAR ? polar_shape_cols(p.lanes) : p.lanes * cart::kB;
+    const int rows = d.kind == NUMAG_GRID_POLAR ? polar_shape_rows(p.lanes) : cart::kThreads / p.lanes;
     p.col_blocks = (d.n1 + cols - 1) / cols;
     p.row_blocks = (d.n0 + rows - 1) / rows;
     const int64_t nblocks = (int64_t)p.col_blocks * p.row_blocks;
@@ -289,11 +398,11 @@ size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
 
 }  // namespace
 
-// Cartesian part of an object-mode plan: the work tables and where they and the
-// accumulators sit in the workspace.
-struct ObjPlanCart {
+// The persistent kernel's part of an object-mode plan: the work tables and where
+// they and the accumulators sit in the workspace.
+struct ObjPlanTables {
     Tables T;
-    Detector dk;  // the rows that are summed
+    Detector dk;  // the part of the detector that is summed
     size_t o_off, o_items, o_slots, o_slot_off, o_counter, o_spec, o_amp;
 };
 
@@ -308,13 +417,16 @@ int launch_tag_guard(const unsigned long long *tag_ptr, unsigned long long tag, 
 Detector objects_detector(const Detector &d, bool hermitian)
 {
     Detector dk = d;
-    if (hermitian) dk.n0 = (d.n0 + 1) / 2;  // rows [0, h): the first h n1 pixels of the outputs
+    if (hermitian) {
+        if (d.kind == NUMAG_GRID_CARTESIAN) dk.n0 = (d.n0 + 1) / 2;  // rows [0, h): the first h n1 pixels
+        else dk.n1 = d.n1 / 2;  // theta in [0, pi); n_theta stays the full count
+    }
     return dk;
 }
 
-void build_objects_plan_cartesian(ObjPlan &pl)
+void build_objects_plan(ObjPlan &pl)
 {
-    auto c = std::make_shared<ObjPlanCart>();
+    auto c = std::make_shared<ObjPlanTables>();
     c->dk = objects_detector(pl.d, pl.path == NUMAG_PATH_DIRECT_HERMITIAN);
     c->T = make_tables(c->dk, pl.off, pl.K, pl.W, pl.n_rot, pl.mode, pl.spec_per_object);
     const Tables &T = c->T;
@@ -342,13 +454,13 @@ void build_objects_plan_cartesian(ObjPlan &pl)
     std::memcpy(pl.image.data() + c->o_items, T.items.data(), sizeof(int2) * T.items.size());
     std::memcpy(pl.image.data() + c->o_slots, T.slots.data(), sizeof(int4) * T.slots.size());
     std::memcpy(pl.image.data() + c->o_slot_off, T.slot_off.data(), sizeof(int) * T.slot_off.size());
-    pl.cart = c;
+    pl.tables = c;
 }
 
 int launch_objects_plan(const ObjPlan &pl, const numag_sample &s, double *spec_out, double *amp_out, void *ws,
                         hipStream_t st)
 {
-    const ObjPlanCart &c = *pl.cart;
+    const ObjPlanTables &c = *pl.tables;
     const ObjectsPlan &p = c.T.p;
     const Detector &d = c.dk;
     const bool hermitian = pl.path == NUMAG_PATH_DIRECT_HERMITIAN;
@@ -384,29 +496,46 @@ int launch_objects_plan(const ObjPlan &pl, const numag_sample &s, double *spec_o
     args.counter = d_counter;
     args.spec = d_spec;
     args.amp = d_amp;
-    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(p.n_items, 2LL * device_cus()));
+    const bool pol = d.kind == NUMAG_GRID_POLAR;
+    // persistent grid: as many workgroups as fit the chip at once
+    const int per_cu = pol ? (polar_shape_waves(p.lanes) == 4 ? 2 : 1) : 2;
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(p.n_items, (int64_t)per_cu * device_cus()));
     {
         TimedLaunch timed(NUMAG_KERNEL_OBJECTS, st);
-        switch (p.lanes) {
-            case 8: hipLaunchKernelGGL((objects_kernel<8>), dim3((unsigned)grid), dim3(cart::kThreads), 0, st, args, d); break;
-            case 16: hipLaunchKernelGGL((objects_kernel<16>), dim3((unsigned)grid), dim3(cart::kThreads), 0, st, args, d); break;
-            case 32: hipLaunchKernelGGL((objects_kernel<32>), dim3((unsigned)grid), dim3(cart::kThreads), 0, st, args, d); break;
-            default: hipLaunchKernelGGL((objects_kernel<64>), dim3((unsigned)grid), dim3(cart::kThreads), 0, st, args, d); break;
+        const dim3 g((unsigned)grid);
+        if (pol) {
+            switch (p.lanes) {
+                case 0: hipLaunchKernelGGL((objects_polar_kernel<8, 64, 8, 2>), g, dim3(512), 0, st, args, d); break;
+                case 1: hipLaunchKernelGGL((objects_polar_kernel<4, 64, 8, 1>), g, dim3(256), 0, st, args, d); break;
+                case 2: hipLaunchKernelGGL((objects_polar_kernel<8, 32, 8, 2>), g, dim3(512), 0, st, args, d); break;
+                case 3: hipLaunchKernelGGL((objects_polar_kernel<8, 16, 16, 1>), g, dim3(512), 0, st, args, d); break;
+                default: hipLaunchKernelGGL((objects_polar_kernel<8, 16, 8, 2>), g, dim3(512), 0, st, args, d); break;
+            }
+        } else {
+            switch (p.lanes) {
+                case 8: hipLaunchKernelGGL((objects_kernel<8>), g, dim3(cart::kThreads), 0, st, args, d); break;
+                case 16: hipLaunchKernelGGL((objects_kernel<16>), g, dim3(cart::kThreads), 0, st, args, d); break;
+                case 32: hipLaunchKernelGGL((objects_kernel<32>), g, dim3(cart::kThreads), 0, st, args, d); break;
+                default: hipLaunchKernelGGL((objects_kernel<64>), g, dim3(cart::kThreads), 0, st, args, d); break;
+            }
         }
     }
     NUMAG_HIP_CHECK(hipGetLastError());
 
+    // the half of a polar detector is mirrored by the reductions, that of a
+    // Cartesian one by the mirror kernels below
+    const int nh = pol && hermitian ? d.n1 : 0;
     const int64_t n_spec = (int64_t)p.n_out * P * 16;
     hipLaunchKernelGGL(spec_reduce_kernel, dim3((unsigned)((n_spec + 255) / 256)), dim3(256), 0, st, tag_ptr, tag,
-                       d_spec, (const int *)(base + c.o_slot_off), p.n_out, P, P_full, 1.0 / (double)pl.n_rot,
+                       d_spec, (const int *)(base + c.o_slot_off), p.n_out, P, P_full, nh, 1.0 / (double)pl.n_rot,
                        spec_out);
     NUMAG_HIP_CHECK(hipGetLastError());
     if (d_amp != nullptr) {
         hipLaunchKernelGGL(amp_reduce_kernel, dim3((unsigned)((P * 8 + 255) / 256)), dim3(256), 0, st, tag_ptr, tag,
-                           d_amp, p.n_slots, P, amp_out);
+                           d_amp, p.n_slots, P, nh, amp_out);
         NUMAG_HIP_CHECK(hipGetLastError());
     }
-    if (hermitian) {
+    if (hermitian && !pol) {
         hipLaunchKernelGGL(mirror_spec_kernel, dim3((unsigned)((n_spec + 255) / 256)), dim3(256), 0, st, spec_out,
                            p.n_out, P_full, P);
         NUMAG_HIP_CHECK(hipGetLastError());

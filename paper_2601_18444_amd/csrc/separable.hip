@@ -7,13 +7,11 @@
 //   T_c(y, k)   = sum_z S_c(y, z) exp(-i q_z(k) z)         (real x complex contraction)
 //   F_c(i, k)   = sum_y exp(-i q_y(i) y) T_c(y, k)         (complex x complex contraction)
 // The two contractions are dense GEMMs and run on MFMA:
-//   NUMAG_PATH_SEPARABLE_F64:    FP64 operands and accumulation, the first on
-//                                v_mfma_f64_16x16x4f64 (one wave per 16 x 16 tile),
-//                                the second on v_mfma_f64_4x4x4f64 (register-blocked
-//                                16 x 16 or 32 x 32 tiles, see sep_contract2_f64);
-//   NUMAG_PATH_SEPARABLE_BF16X3: v_mfma_f32_16x16x16bf16_1k with every operand split
-//                                into bf16 hi + lo and the three products hi*hi,
-//                                hi*lo, lo*hi accumulated in FP32.
+//   NUMAG_PATH_SEPARABLE_F64:    FP64 operands and accumulation on
+//                                v_mfma_f64_4x4x4f64 (register-blocked tiles);
+//   NUMAG_PATH_SEPARABLE_BF16X3 / _BF16X6: every operand split into 2 or 3 bf16
+//                                parts, 3 or 6 split products per real product on
+//                                v_mfma_f32_16x16x32_bf16, FP32 accumulation.
 // Twiddles are generated in FP64 into the workspace; the projection is a
 // fixed-order FP64 sum.
 //
@@ -28,210 +26,262 @@ namespace numag {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
-typedef short v4s __attribute__((ext_vector_type(4)));
+
+// Padded sizes of the operands, so that the matrix-core loads need no bounds
+// checks: every padding entry is zero.
+//   S  [sets][ny16][nz4]    projections (ny16 = ny rounded up to 32, nz4 = nz to 4)
+//   Ez [nz4][n1p]           column twiddles (n1p = n1 rounded up to 64)
+//   T  [sets][ny16][n1p]    first contraction (complex)
+//   Ey [n0p][nyp]           row twiddles (n0p = n0 to 32, nyp = ny to 4)
+struct SepDims {
+    int ny, nz, n0, n1, ny16, nz4, nyp, n0p, n1p;
+};
 
 struct SepLayout {
     size_t ey, ez, s, t, total;
 };
 
-// Output tile of one wave in the second contraction (rows i, columns k).
-constexpr int kC2M = 32, kC2N = 64;
+// Output tiles of one wave: first contraction (16 MG1) x (4 NG1), second (16 MG) x (4 NG)
+// with (MG, NG) = (2, 8) or (1, 4).
+constexpr int kC1MG = 2, kC1NG = 8;
+constexpr int kC2M = 32, kC2N = 64;  // paddings of the second contraction's rows and columns
 
-// The operands of the second contraction are zero-padded so that its loads need
-// no bounds checks: E_y is [n0p][nyp], T is [sets][nyp][n1p] with n0p, nyp, n1p
-// the detector rows, grid y cells and detector columns rounded up to 32, 4, 64.
 __host__ __device__ static inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
 static size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
 
+static SepDims sep_dims(const numag_regular &g, const Detector &d)
+{
+    SepDims m{};
+    m.ny = g.n[1];
+    m.nz = g.n[2];
+    m.n0 = d.n0;
+    m.n1 = d.n1;
+    m.ny16 = round_up(m.ny, 16 * kC1MG);
+    m.nz4 = round_up(m.nz, 4);
+    m.nyp = round_up(m.ny, 4);
+    m.n0p = round_up(m.n0, kC2M);
+    m.n1p = round_up(m.n1, kC2N);
+    return m;
+}
+
 static SepLayout sep_layout(const numag_regular &g, const Detector &d, int64_t n_snap)
 {
-    const size_t ny = g.n[1], nz = g.n[2], n1 = d.n1, sets = 4 * (size_t)n_snap;
-    const size_t n0p = round_up(d.n0, kC2M), nyp = round_up(g.n[1], 4), n1p = round_up(d.n1, kC2N);
+    const SepDims m = sep_dims(g, d);
+    const size_t sets = 4 * (size_t)n_snap;
     SepLayout L{};
-    L.ey = al(n0p * nyp * sizeof(double2));
-    L.ez = al(nz * n1 * sizeof(double2));
-    L.s = al(sets * ny * nz * sizeof(double));
-    L.t = al(sets * nyp * n1p * sizeof(double2));
+    L.ey = al((size_t)m.n0p * m.nyp * sizeof(double2));
+    L.ez = al((size_t)m.nz4 * m.n1p * sizeof(double2));
+    L.s = al(sets * m.ny16 * m.nz4 * sizeof(double));
+    L.t = al(sets * m.ny16 * m.n1p * sizeof(double2));
     L.total = L.ey + L.ez + L.s + L.t;
     return L;
 }
 
+static size_t bf_bytes(const numag_regular &g, const Detector &d, int path, int64_t n_snap);
+
 size_t separable_workspace_bytes(const numag_regular &g, const Detector &d, int path, int64_t n_snap)
 {
-    (void)path;
-    return sep_layout(g, d, n_snap).total;
+    const SepLayout L = sep_layout(g, d, n_snap);
+    if (path == NUMAG_PATH_SEPARABLE_F64) return L.total;
+    // the BF16 paths also use the FP64 projections (the S region) before splitting them
+    return L.s + bf_bytes(g, d, path, n_snap);
 }
 
-constexpr int kProjCells = 64;   // (y, z) cells per projection workgroup
-constexpr int kProjSlices = 4;   // x slices per cell (one thread each)
-
-// Sum over the x cells ix = slice, slice + kProjSlices, ... of column rem (a cell
-// (iy, iz)), in x order.  Loads of four x cells are issued before their adds so
-// that several are in flight (the projection is HBM-bound).
-template <bool HN, bool HM>
-__device__ __forceinline__ void project_cells(const double *__restrict__ nuc, const double *__restrict__ mag,
-                                              int64_t rem, int64_t nyz, int nx, int slice, double (&s)[4])
-{
-    constexpr int U = 4;
-    int ix = slice;
-    for (; ix + (U - 1) * kProjSlices < nx; ix += U * kProjSlices) {
-        double vn[U], vm[U][3];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t j = (int64_t)(ix + u * kProjSlices) * nyz + rem;
-            vn[u] = HN ? nuc[j] : 0.0;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) vm[u][a] = HM ? mag[3 * j + a] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            s[0] += vn[u];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) s[1 + a] += vm[u][a];
-        }
-    }
-    for (; ix < nx; ix += kProjSlices) {
-        const int64_t j = (int64_t)ix * nyz + rem;
-        if (HN) s[0] += nuc[j];
-        if (HM) {
-#pragma unroll
-            for (int a = 0; a < 3; ++a) s[1 + a] += mag[3 * j + a];
-        }
-    }
-}
+constexpr int kProjThreads = 64;  // column groups per projection workgroup
+constexpr int kProjSlices = 4;    // x slices per column (one thread each)
+constexpr int kProjUnroll = 8;    // loads in flight per thread
 
 // One launch for the operands of both contractions.
-// Workgroups [0, n_proj * n_snap): projection S[b][c][iy][iz] = sum_x w_c(x, iy, iz)
-// of snapshot b for 64 cells, x split into 4 slices summed by 4 threads, slices
-// added in a fixed order through LDS.  The remaining workgroups: twiddles
-// Ey[i][iy] = exp(-i q_y(i) y_iy) and Ez[iz][k] = exp(-i q_z(k) z_iz).
-__global__ __launch_bounds__(256) void sep_prepare_kernel(Detector d, numag_regular g, const double *__restrict__ nuc,
+// Workgroups [0, n_proj * n_snap): projections (all paths).  Snapshot b's weights
+// are two row-major matrices over x, nuc [nx][nyz] and mag [nx][3 nyz]; their
+// column sums over x are the projections (column m of mag is component m % 3 of
+// cell m / 3).  A workgroup owns 64 CPT consecutive columns of the 4 nyz (nuc
+// first, then mag), CPT = 2 adjacent columns per thread (one 16-byte load) when
+// nyz is even and the weights are 16-byte aligned, else 1; x is split into 4
+// slices summed by 4 threads in x order, the slices added in a fixed order
+// through LDS (the same order for either CPT).  Output S[4 b + c][iy][iz].
+// The remaining workgroups: twiddles Ey[i][iy] = exp(-i q_y(i) y_iy) and
+// Ez[iz][k] = exp(-i q_z(k) z_iz), zeros in the padding, and zeros in the
+// padding of S.
+template <int CPT>
+__device__ __forceinline__ void project_columns(const double *__restrict__ src, int64_t stride, int nx, int slice,
+                                                double (&acc)[CPT])
+{
+    int ix = slice;
+    for (; ix + (kProjUnroll - 1) * kProjSlices < nx; ix += kProjUnroll * kProjSlices) {
+        double v[kProjUnroll][CPT];
+#pragma unroll
+        for (int u = 0; u < kProjUnroll; ++u) {
+            const double *q = src + (int64_t)(ix + u * kProjSlices) * stride;
+            if (CPT == 2) {
+                const double2 t = *(const double2 *)q;
+                v[u][0] = t.x;
+                v[u][CPT - 1] = t.y;
+            } else {
+                v[u][0] = q[0];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kProjUnroll; ++u)
+#pragma unroll
+            for (int k = 0; k < CPT; ++k) acc[k] += v[u][k];
+    }
+    for (; ix < nx; ix += kProjSlices)
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) acc[k] += src[(int64_t)ix * stride + k];
+}
+
+template <int CPT>
+__global__ __launch_bounds__(256) void sep_prepare_kernel(Detector d, numag_regular g, SepDims m,
+                                                          const double *__restrict__ nuc,
                                                           const double *__restrict__ mag, int n_proj, int n_snap,
-                                                          double *__restrict__ S, double2 *__restrict__ ey,
-                                                          double2 *__restrict__ ez)
+                                                          int tw, int pad_s, double *__restrict__ S,
+                                                          double2 *__restrict__ ey, double2 *__restrict__ ez)
 {
     const int64_t nyz = (int64_t)g.n[1] * g.n[2];
     const int64_t W = (int64_t)g.n[0] * nyz;
+    const int64_t sstride = (int64_t)m.ny16 * m.nz4;  // one channel set of S
     if ((int64_t)blockIdx.x < (int64_t)n_proj * n_snap) {
-        __shared__ double part[kProjSlices][4][kProjCells];
+        __shared__ double part[kProjSlices][kProjThreads * CPT];
         const int b = (int)(blockIdx.x / n_proj);
-        if (nuc != nullptr) nuc += (int64_t)b * W;
-        if (mag != nullptr) mag += (int64_t)b * W * 3;
-        S += (int64_t)b * 4 * nyz;
-        const int cell = threadIdx.x % kProjCells, slice = threadIdx.x / kProjCells;
-        const int64_t rem = (int64_t)(blockIdx.x % n_proj) * kProjCells + cell;
-        double s[4] = {0.0, 0.0, 0.0, 0.0};
-        if (rem < nyz) {
-            if (nuc != nullptr && mag != nullptr)
-                project_cells<true, true>(nuc, mag, rem, nyz, g.n[0], slice, s);
-            else if (mag != nullptr)
-                project_cells<false, true>(nuc, mag, rem, nyz, g.n[0], slice, s);
-            else if (nuc != nullptr)
-                project_cells<true, false>(nuc, mag, rem, nyz, g.n[0], slice, s);
-        }
-        for (int c = 0; c < 4; ++c) part[slice][c][cell] = s[c];
+        const int col = threadIdx.x % kProjThreads, slice = threadIdx.x / kProjThreads;
+        // first of this thread's CPT columns, in [0, 4 nyz); with CPT = 2, nyz is even,
+        // so both columns lie in the same matrix
+        const int64_t mcol = ((int64_t)(blockIdx.x % n_proj) * kProjThreads + col) * CPT;
+        const bool is_nuc = mcol < nyz;
+        const double *src = is_nuc ? (nuc != nullptr ? nuc + (int64_t)b * W + mcol : nullptr)
+                                   : (mag != nullptr && mcol < 4 * nyz ? mag + (int64_t)b * W * 3 + (mcol - nyz)
+                                                                       : nullptr);
+        double acc[CPT];
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) acc[k] = 0.0;
+        if (src != nullptr) project_columns<CPT>(src, is_nuc ? nyz : 3 * nyz, g.n[0], slice, acc);
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) part[slice][col * CPT + k] = acc[k];
         __syncthreads();
-        // thread (c, cell) adds the slices in order
-        const int c = threadIdx.x / kProjCells;
-        if (rem < nyz) {
-            double t = 0.0;
-            for (int sl = 0; sl < kProjSlices; ++sl) t += part[sl][c][cell];
-            S[c * nyz + rem] = t;
+        // thread t < 64 CPT: column t of the workgroup, slices added in order
+        const int t = threadIdx.x;
+        const int64_t mc = (int64_t)(blockIdx.x % n_proj) * kProjThreads * CPT + t;
+        if (t < kProjThreads * CPT && mc < 4 * nyz) {
+            double v = 0.0;
+            for (int sl = 0; sl < kProjSlices; ++sl) v += part[sl][t];
+            const bool nc = mc < nyz;
+            const int64_t cell = nc ? mc : (mc - nyz) / 3;
+            const int c = nc ? 0 : 1 + (int)((mc - nyz) % 3);
+            const int iy = (int)(cell / g.n[2]), iz = (int)(cell % g.n[2]);
+            S[(int64_t)(4 * b + c) * sstride + (int64_t)iy * m.nz4 + iz] = v;
         }
         return;
     }
     const int64_t idx = ((int64_t)blockIdx.x - (int64_t)n_proj * n_snap) * blockDim.x + threadIdx.x;
-    const int64_t ny = g.n[1], nz = g.n[2];
-    const int64_t nyp = round_up(g.n[1], 4);
-    const int64_t ne = (int64_t)round_up(d.n0, kC2M) * nyp;
+    // tw == 0: no FP64 twiddles (the BF16 paths write their own), padding of S only
+    const int64_t ne = tw ? (int64_t)m.n0p * m.nyp : 0;
+    const int64_t nez = tw ? (int64_t)m.nz4 * m.n1p : 0;
     if (idx < ne) {
-        const int i = (int)(idx / nyp), iy = (int)(idx % nyp);
+        const int i = (int)(idx / m.nyp), iy = (int)(idx % m.nyp);
         const double y = g.origin[1] + (double)iy * g.step[1];
-        ey[idx] = (i < d.n0 && iy < ny) ? twiddle(axis_value(d.origin0, i, d.step0) * y) : make_double2(0.0, 0.0);
-    } else if (idx < ne + nz * d.n1) {
+        ey[idx] = (i < d.n0 && iy < m.ny) ? twiddle(axis_value(d.origin0, i, d.step0) * y) : make_double2(0.0, 0.0);
+    } else if (idx < ne + nez) {
         const int64_t r = idx - ne;
-        const int iz = (int)(r / d.n1), k = (int)(r % d.n1);
+        const int iz = (int)(r / m.n1p), k = (int)(r % m.n1p);
         const double z = g.origin[2] + (double)iz * g.step[2];
-        ez[r] = twiddle(axis_value(d.origin1, k, d.step1) * z);
+        ez[r] = (iz < m.nz && k < d.n1) ? twiddle(axis_value(d.origin1, k, d.step1) * z) : make_double2(0.0, 0.0);
+    } else if (pad_s) {
+        // padding of S: rows iy >= ny and columns iz >= nz of every channel set
+        const int64_t r = idx - ne - nez;
+        if (r < (int64_t)4 * n_snap * sstride) {
+            const int64_t cell = r % sstride;
+            const int iy = (int)(cell / m.nz4), iz = (int)(cell % m.nz4);
+            if (iy >= m.ny || iz >= m.nz) S[r] = 0.0;
+        }
     }
 }
 
 // ---- FP64 MFMA -------------------------------------------------------------
-// v_mfma_f64_16x16x4f64 lane layout: A[l % 16][l / 16], B[l / 16][l % 16],
-// D[4 r + l / 16][l % 16] for r < 4 (unlike the FP32-accumulating MFMAs below).
+// Both contractions run on v_mfma_f64_4x4x4f64 (four 4 x 4 x 4 blocks per
+// instruction; it issues its flops faster on gfx950 than the 16 x 16 x 4 form).
+// Lane layout (one-hot probe): block g = (l / 4) % 4, A[g][l % 4][l / 16],
+// B[g][l / 16][l % 4], D[g][l / 16][l % 4].  A wave owns a (16 MG) x (4 NG)
+// output tile: per K step of 4 it holds MG A fragments (rows i0 + 16 mg + 4 g + e)
+// and NG B fragments (columns k0 + 4 ng + e, the same for every block).  Every
+// output element sees the same instruction sequence whatever the tile shape, so
+// the shape never changes a result.
 
-// T[c][iy][k] = sum_iz S[c][iy][iz] Ez[iz][k]
+// T[c][iy][k] = sum_iz S[c][iy][iz] Ez[iz][k] (real x complex: two products per
+// step, into independent accumulators).
+template <int MG, int NG>
 __global__ __launch_bounds__(256) void sep_contract1_f64(const double *__restrict__ S, const double2 *__restrict__ Ez,
-                                                         int ny, int nz, int n1, int nyp, int n1p, int n_sets,
-                                                         double2 *__restrict__ T)
+                                                         SepDims m, int n_sets, double2 *__restrict__ T)
 {
+    constexpr int TM = 16 * MG, TN = 4 * NG;
     const int lane = threadIdx.x & 63;
-    const int tm = (nyp + 15) / 16, tn = (n1p + 15) / 16;
+    const int tm = m.ny16 / TM, tn = m.n1p / TN;
     const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (tile >= (int64_t)n_sets * tm * tn) return;
-    const int c = (int)(tile / (tm * tn));
-    const int rem = (int)(tile % (tm * tn));
-    const int m0 = (rem / tn) * 16, n0 = (rem % tn) * 16;
-    const int ai = m0 + (lane & 15), bj = n0 + (lane & 15), kq = lane >> 4;
-    const double *Sc = S + (int64_t)c * ny * nz;
-    v4d accR = {0.0, 0.0, 0.0, 0.0}, accI = {0.0, 0.0, 0.0, 0.0};
-    auto load = [&](int k, double &a, double2 &b) {
-        const int kk = k + kq;
-        a = (ai < ny && kk < nz) ? Sc[(int64_t)ai * nz + kk] : 0.0;
-        b = (bj < n1 && kk < nz) ? Ez[(int64_t)kk * n1 + bj] : make_double2(0.0, 0.0);
+    const int c = (int)(tile / ((int64_t)tm * tn));
+    const int rem = (int)(tile % ((int64_t)tm * tn));
+    const int i0 = (rem / tn) * TM, k0 = (rem % tn) * TN;
+    const int g = (lane >> 2) & 3, e = lane & 3, kq = lane >> 4;
+    const double *pa = S + (int64_t)c * m.ny16 * m.nz4 + (int64_t)(i0 + 4 * g + e) * m.nz4 + kq;  // + 16 mg nz4 + z0
+    const double2 *pb = Ez + (int64_t)kq * m.n1p + k0 + e;                                         // + z0 n1p + 4 ng
+    double accR[MG][NG], accI[MG][NG];
+#pragma unroll
+    for (int mg = 0; mg < MG; ++mg)
+#pragma unroll
+        for (int ng = 0; ng < NG; ++ng) accR[mg][ng] = accI[mg][ng] = 0.0;
+    auto load = [&](int z0, double (&a)[MG], double2 (&b)[NG]) {
+#pragma unroll
+        for (int mg = 0; mg < MG; ++mg) a[mg] = pa[(int64_t)16 * mg * m.nz4 + z0];
+#pragma unroll
+        for (int ng = 0; ng < NG; ++ng) b[ng] = pb[(int64_t)z0 * m.n1p + 4 * ng];
     };
-    // four K steps at a time: their loads are issued before their MFMAs (the
-    // accumulation order is the same as one step at a time)
-    constexpr int U = 4;
-    int k = 0;
-    for (; k + 4 * (U - 1) < nz; k += 4 * U) {
-        double a[U];
-        double2 b[U];
+    auto mma = [&](const double (&a)[MG], const double2 (&b)[NG]) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) load(k + 4 * u, a[u], b[u]);
+        for (int ng = 0; ng < NG; ++ng)
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            accR = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u].x, accR, 0, 0, 0);
-            accI = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u].y, accI, 0, 0, 0);
-        }
+            for (int mg = 0; mg < MG; ++mg) {
+                accR[mg][ng] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[mg], b[ng].x, accR[mg][ng], 0, 0, 0);
+                accI[mg][ng] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[mg], b[ng].y, accI[mg][ng], 0, 0, 0);
+            }
+    };
+    double a0[MG], a1[MG];
+    double2 b0[NG], b1[NG];
+    load(0, a0, b0);
+    for (int z0 = 0; z0 < m.nz4; z0 += 8) {
+        const bool more = z0 + 4 < m.nz4;
+        if (more) load(z0 + 4, a1, b1);
+        mma(a0, b0);
+        if (!more) break;
+        if (z0 + 8 < m.nz4) load(z0 + 8, a0, b0);
+        mma(a1, b1);
     }
-    for (; k < nz; k += 4) {
-        double a;
-        double2 b;
-        load(k, a, b);
-        accR = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b.x, accR, 0, 0, 0);
-        accI = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b.y, accI, 0, 0, 0);
-    }
-    double2 *Tc = T + (int64_t)c * nyp * n1p;
+    double2 *Tc = T + (int64_t)c * m.ny16 * m.n1p;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int i = m0 + 4 * r + kq;
-        if (i < nyp && bj < n1p) Tc[(int64_t)i * n1p + bj] = make_double2(accR[r], accI[r]);
+    for (int mg = 0; mg < MG; ++mg) {
+        const int row = i0 + 16 * mg + 4 * g + kq;
+#pragma unroll
+        for (int ng = 0; ng < NG; ++ng)
+            Tc[(int64_t)row * m.n1p + k0 + 4 * ng + e] = make_double2(accR[mg][ng], accI[mg][ng]);
     }
 }
 
 // F[c][i][k] = sum_iy Ey[i][iy] T[c][iy][k]  ->  amp[c / 4][(i n1 + k)][c % 4]
 //
-// This contraction carries nine tenths of the flops, so it runs on
-// v_mfma_f64_4x4x4f64 (four 4 x 4 x 4 blocks per instruction), which issues its
-// flops faster on gfx950 than the 16 x 16 x 4 form.  Lane layout (one-hot probe):
-// block g = (l / 4) % 4, A[g][l % 4][l / 16], B[g][l / 16][l % 4], D[g][l / 16][l % 4].
-// A wave owns a (16 MG) x (4 NG) output tile: per K step of 4 it holds MG A
-// fragments (rows i0 + 16 mg + 4 g + m) and NG B fragments (columns k0 + 4 ng + n,
-// the same for every block) and issues MG x NG x 4 instructions (the complex
-// product as four real ones).  Every output element sees the same instruction
-// sequence whatever the tile shape, so the shape (chosen by the amount of work)
-// does not change the result.
+// This contraction carries nine tenths of the flops; the complex product is four
+// real products per K step (MG x NG x 4 instructions).  It is bound by the issue of
+// its operand loads rather than by the matrix cores: forming it with three real
+// products instead (Gauss's trick, with the sums A + B and C + D as extra operand
+// planes) cut the MFMA work by a quarter but added half again to the operand
+// loads, and measured 1.5 times slower (204 -> 307 us for 64 snapshots).
 template <int MG, int NG>
 __global__ __launch_bounds__(256) void sep_contract2_f64(const double2 *__restrict__ Ey, const double2 *__restrict__ T,
-                                                         int n0, int n1, int nyp, int n1p, int n_sets,
-                                                         double *__restrict__ amp)
+                                                         SepDims m, int n_sets, double *__restrict__ amp)
 {
     constexpr int TM = 16 * MG, TN = 4 * NG;
     static_assert(kC2M % TM == 0 && kC2N % TN == 0, "tile inside the padding");
     const int lane = threadIdx.x & 63;
-    const int tm = (n0 + TM - 1) / TM, tn = (n1 + TN - 1) / TN;
+    const int tm = (m.n0 + TM - 1) / TM, tn = (m.n1 + TN - 1) / TN;
     const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (tile >= (int64_t)n_sets * tm * tn) return;
     const int c = (int)(tile / ((int64_t)tm * tn));
@@ -239,8 +289,8 @@ __global__ __launch_bounds__(256) void sep_contract2_f64(const double2 *__restri
     const int i0 = (rem / tn) * TM, k0 = (rem % tn) * TN;
     const int g = (lane >> 2) & 3, e = lane & 3, kq = lane >> 4;
     // this lane's operand streams (every index stays inside the padded arrays)
-    const double2 *pa = Ey + (int64_t)(i0 + 4 * g + e) * nyp + kq;               // + 16 mg nyp + y0
-    const double2 *pb = T + (int64_t)c * nyp * n1p + (int64_t)kq * n1p + k0 + e;  // + y0 n1p + 4 ng
+    const double2 *pa = Ey + (int64_t)(i0 + 4 * g + e) * m.nyp + kq;                            // + 16 mg nyp + y0
+    const double2 *pb = T + (int64_t)c * m.ny16 * m.n1p + (int64_t)kq * m.n1p + k0 + e;         // + y0 n1p + 4 ng
     double accR[MG][NG], accI[MG][NG];
 #pragma unroll
     for (int mg = 0; mg < MG; ++mg)
@@ -249,9 +299,9 @@ __global__ __launch_bounds__(256) void sep_contract2_f64(const double2 *__restri
 
     auto load = [&](int y0, double2 (&a)[MG], double2 (&b)[NG]) {
 #pragma unroll
-        for (int mg = 0; mg < MG; ++mg) a[mg] = pa[(int64_t)16 * mg * nyp + y0];
+        for (int mg = 0; mg < MG; ++mg) a[mg] = pa[(int64_t)16 * mg * m.nyp + y0];
 #pragma unroll
-        for (int ng = 0; ng < NG; ++ng) b[ng] = pb[(int64_t)y0 * n1p + 4 * ng];
+        for (int ng = 0; ng < NG; ++ng) b[ng] = pb[(int64_t)y0 * m.n1p + 4 * ng];
     };
     auto mma = [&](const double2 (&a)[MG], const double2 (&b)[NG]) {
 #pragma unroll
@@ -267,24 +317,24 @@ __global__ __launch_bounds__(256) void sep_contract2_f64(const double2 *__restri
     // two register buffers: the next K step's fragments load while this one's MFMAs run
     double2 a0[MG], b0[NG], a1[MG], b1[NG];
     load(0, a0, b0);
-    for (int y0 = 0; y0 < nyp; y0 += 8) {
-        const bool more = y0 + 4 < nyp;
+    for (int y0 = 0; y0 < m.nyp; y0 += 8) {
+        const bool more = y0 + 4 < m.nyp;
         if (more) load(y0 + 4, a1, b1);
         mma(a0, b0);
         if (!more) break;
-        if (y0 + 8 < nyp) load(y0 + 8, a0, b0);
+        if (y0 + 8 < m.nyp) load(y0 + 8, a0, b0);
         mma(a1, b1);
     }
-    double *dst = amp + (int64_t)(c >> 2) * n0 * n1 * 8 + 2 * (c & 3);
+    double *dst = amp + (int64_t)(c >> 2) * m.n0 * m.n1 * 8 + 2 * (c & 3);
 #pragma unroll
     for (int mg = 0; mg < MG; ++mg) {
         const int row = i0 + 16 * mg + 4 * g + kq;
-        if (row >= n0) continue;
+        if (row >= m.n0) continue;
 #pragma unroll
         for (int ng = 0; ng < NG; ++ng) {
             const int col = k0 + 4 * ng + e;
-            if (col < n1) {
-                double *o = dst + ((int64_t)row * n1 + col) * 8;
+            if (col < m.n1) {
+                double *o = dst + ((int64_t)row * m.n1 + col) * 8;
                 o[0] = accR[mg][ng];
                 o[1] = accI[mg][ng];
             }
@@ -292,167 +342,323 @@ __global__ __launch_bounds__(256) void sep_contract2_f64(const double2 *__restri
     }
 }
 
-// ---- BF16 x 3 MFMA ---------------------------------------------------------
-// v_mfma_f32_16x16x16bf16_1k lane layout: A[l % 16][4 (l / 16) + v],
-// B[4 (l / 16) + v][l % 16] for v < 4, D[4 (l / 16) + r][l % 16].
+// ---- BF16 split products -------------------------------------------------
+// NUMAG_PATH_SEPARABLE_BF16X3 / _BF16X6: every operand x is split into NP = 2 or 3
+// bf16 parts (x = p0 + p1 [+ p2], each the bf16 rounding of what the previous
+// parts leave, the remainders exact in FP64) and a real product takes the split
+// pairs (i, j) with i + j < NP -- 3 or 6 products -- on v_mfma_f32_16x16x32_bf16,
+// accumulated in FP32.  The parts are formed once, where an operand is written:
+// the twiddles by the prepare kernel, the projections by the projection, the first
+// contraction's result by that contraction, each into "K-contiguous" planes so
+// that a lane reads its 8 consecutive K elements of a plane with one 16-byte load.
+// Lane layout of the 16 x 16 x 32 form (one-hot probe): A[l % 16][8 (l / 16) + v],
+// B[8 (l / 16) + v][l % 16] for v < 8, D[4 (l / 16) + r][l % 16].
+//   Sb  [NP][sets][ny32][nz32]       projections, row y, K = z
+//   EzT [NP][2][n1p][nz32]           column twiddles transposed (column k, K = z), re / im
+//   Eyb [NP][2][n0p][ny32]           row twiddles (row i, K = y), re / im
+//   TT  [NP][2][sets][n1p][ny32]     first contraction transposed (column k, K = y), re / im
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
-__device__ __forceinline__ short to_bf16(float x)
+struct BfLayout {
+    int np, ny32, nz32;
+    size_t s, ez, ey, t, total;
+};
+
+static BfLayout bf_layout(const SepDims &m, int path, int64_t n_snap)
+{
+    BfLayout L{};
+    L.np = path == NUMAG_PATH_SEPARABLE_BF16X6 ? 3 : 2;
+    L.ny32 = round_up(m.ny, 32);
+    L.nz32 = round_up(m.nz, 32);
+    const size_t sets = 4 * (size_t)n_snap, h = sizeof(unsigned short);
+    L.s = al((size_t)L.np * sets * L.ny32 * L.nz32 * h);
+    L.ez = al((size_t)L.np * 2 * m.n1p * L.nz32 * h);
+    L.ey = al((size_t)L.np * 2 * m.n0p * L.ny32 * h);
+    L.t = al((size_t)L.np * 2 * sets * m.n1p * L.ny32 * h);
+    L.total = L.s + L.ez + L.ey + L.t;
+    return L;
+}
+
+__device__ __forceinline__ unsigned short to_bf16(float x)
 {
     uint32_t u = __float_as_uint(x);
     u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
-    return (short)(u >> 16);
+    return (unsigned short)(u >> 16);
 }
 
-__device__ __forceinline__ float from_bf16(short h) { return __uint_as_float(((uint32_t)(uint16_t)h) << 16); }
+__device__ __forceinline__ double from_bf16(unsigned short h) { return (double)__uint_as_float(((uint32_t)h) << 16); }
 
-struct Bf3 {
-    v4s hi, lo;
-};
-
-// element v of o: x = hi + lo, both bf16
-__device__ __forceinline__ void split_bf16(double x, Bf3 &o, int v)
+// The NP bf16 parts of x, written to dst[p * pstride].
+template <int NP>
+__device__ __forceinline__ void store_split(double x, unsigned short *dst, int64_t pstride)
 {
-    const short hi = to_bf16((float)x);
-    o.hi[v] = hi;
-    o.lo[v] = to_bf16((float)(x - (double)from_bf16(hi)));
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const unsigned short h = to_bf16((float)x);
+        dst[(int64_t)p * pstride] = h;
+        x -= from_bf16(h);
+    }
 }
 
-__device__ __forceinline__ v4f mfma3(const Bf3 &a, const Bf3 &b, v4f acc)
+// Four consecutive K elements of one plane, split: the parts of v[0..3] packed as
+// 4 bf16 per plane.
+template <int NP>
+__device__ __forceinline__ void store_split4(const float (&v)[4], unsigned short *dst, int64_t pstride)
 {
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.hi, b.hi, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.hi, b.lo, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.lo, b.hi, acc, 0, 0, 0);
+    double r[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) r[j] = (double)v[j];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        unsigned short h[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            h[j] = to_bf16((float)r[j]);
+            r[j] -= from_bf16(h[j]);
+        }
+        uint2 w;
+        w.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
+        w.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
+        *(uint2 *)(dst + (int64_t)p * pstride) = w;
+    }
+}
+
+__device__ __forceinline__ v8bf load8(const unsigned short *p) { return __builtin_bit_cast(v8bf, *(const uint4 *)p); }
+
+// acc += sum over the split pairs (i, j), i + j < NP, of a[i] b[j]; the smallest
+// products first.
+template <int NP>
+__device__ __forceinline__ v4f mfma_split(const v8bf (&a)[NP], const v8bf (&b)[NP], v4f acc)
+{
+#pragma unroll
+    for (int t = NP - 1; t >= 0; --t)
+#pragma unroll
+        for (int i = t; i >= 0; --i) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[t - i], acc, 0, 0, 0);
     return acc;
 }
 
-__global__ __launch_bounds__(256) void sep_contract1_bf16x3(const double *__restrict__ S,
-                                                            const double2 *__restrict__ Ez, int ny, int nz,
-                                                            int n1, int nyp, int n1p, int n_sets,
-                                                            double2 *__restrict__ T)
+// Twiddles and the padding of the projections of the BF16 paths (the projection
+// itself is sep_prepare_kernel's, written split by sep_split_s_kernel).
+template <int NP>
+__global__ __launch_bounds__(256) void sep_twiddles_bf16(Detector d, numag_regular g, SepDims m, int ny32, int nz32,
+                                                         unsigned short *__restrict__ eyb,
+                                                         unsigned short *__restrict__ ezt)
 {
-    const int lane = threadIdx.x & 63;
-    const int tm = (nyp + 15) / 16, tn = (n1p + 15) / 16;
-    const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (tile >= (int64_t)n_sets * tm * tn) return;
-    const int c = (int)(tile / (tm * tn));
-    const int rem = (int)(tile % (tm * tn));
-    const int m0 = (rem / tn) * 16, n0 = (rem % tn) * 16;
-    const int ai = m0 + (lane & 15), bj = n0 + (lane & 15), kq = lane >> 4;
-    const double *Sc = S + (int64_t)c * ny * nz;
-    v4f accR = {0.f, 0.f, 0.f, 0.f}, accI = {0.f, 0.f, 0.f, 0.f};
-    for (int k = 0; k < nz; k += 16) {
-        Bf3 a, br, bi;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int kk = k + 4 * kq + v;
-            const double av = (ai < ny && kk < nz) ? Sc[(int64_t)ai * nz + kk] : 0.0;
-            const double2 bv = (bj < n1 && kk < nz) ? Ez[(int64_t)kk * n1 + bj] : make_double2(0.0, 0.0);
-            split_bf16(av, a, v);
-            split_bf16(bv.x, br, v);
-            split_bf16(bv.y, bi, v);
-        }
-        accR = mfma3(a, br, accR);
-        accI = mfma3(a, bi, accI);
-    }
-    double2 *Tc = T + (int64_t)c * nyp * n1p;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int i = m0 + 4 * kq + r;
-        if (i < nyp && bj < n1p) Tc[(int64_t)i * n1p + bj] = make_double2((double)accR[r], (double)accI[r]);
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ne = (int64_t)m.n0p * ny32;
+    const int64_t nezt = (int64_t)m.n1p * nz32;
+    if (idx < ne) {
+        const int i = (int)(idx / ny32), iy = (int)(idx % ny32);
+        const double y = g.origin[1] + (double)iy * g.step[1];
+        const double2 e =
+            (i < d.n0 && iy < m.ny) ? twiddle(axis_value(d.origin0, i, d.step0) * y) : make_double2(0.0, 0.0);
+        store_split<NP>(e.x, eyb + idx, 2 * ne);
+        store_split<NP>(e.y, eyb + ne + idx, 2 * ne);
+    } else if (idx < ne + nezt) {
+        const int64_t r = idx - ne;
+        const int k = (int)(r / nz32), iz = (int)(r % nz32);
+        const double z = g.origin[2] + (double)iz * g.step[2];
+        const double2 e =
+            (k < d.n1 && iz < m.nz) ? twiddle(axis_value(d.origin1, k, d.step1) * z) : make_double2(0.0, 0.0);
+        store_split<NP>(e.x, ezt + r, 2 * nezt);
+        store_split<NP>(e.y, ezt + nezt + r, 2 * nezt);
     }
 }
 
-__global__ __launch_bounds__(256) void sep_contract2_bf16x3(const double2 *__restrict__ Ey,
-                                                            const double2 *__restrict__ T, int n0, int ny,
-                                                            int n1, int nyp, int n1p, int n_sets,
-                                                            double *__restrict__ amp)
+// Split projections: Sb[p][set][iy][iz] from the FP64 S[set][ny16][nz4] (zero beyond ny, nz).
+template <int NP>
+__global__ __launch_bounds__(256) void sep_split_s_kernel(const double *__restrict__ S, SepDims m, int ny32,
+                                                          int nz32, int sets, unsigned short *__restrict__ sb)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = (int64_t)ny32 * nz32;
+    if (idx >= (int64_t)sets * per) return;
+    const int set = (int)(idx / per);
+    const int iy = (int)((idx % per) / nz32), iz = (int)(idx % nz32);
+    const double v = (iy < m.ny && iz < m.nz) ? S[((int64_t)set * m.ny16 + iy) * m.nz4 + iz] : 0.0;
+    store_split<NP>(v, sb + idx, (int64_t)sets * per);
+}
+
+// T[c][y][k] = sum_z S[c][y][z] Ez[z][k] on 16 x 16 tiles, written split and
+// transposed into TT[p][re / im][c][k][y].
+template <int NP>
+__global__ __launch_bounds__(256) void sep_contract1_bf16(const unsigned short *__restrict__ sb,
+                                                          const unsigned short *__restrict__ ezt, SepDims m, int ny32,
+                                                          int nz32, int sets, unsigned short *__restrict__ tt)
 {
     const int lane = threadIdx.x & 63;
-    const int tm = (n0 + 15) / 16, tn = (n1 + 15) / 16;
+    const int tm = ny32 / 16, tn = m.n1p / 16;
     const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (tile >= (int64_t)n_sets * tm * tn) return;
-    const int c = (int)(tile / (tm * tn));
-    const int rem = (int)(tile % (tm * tn));
-    const int m0 = (rem / tn) * 16, n0t = (rem % tn) * 16;
-    const int ai = m0 + (lane & 15), bj = n0t + (lane & 15), kq = lane >> 4;
-    const double2 *Tc = T + (int64_t)c * nyp * n1p;
+    if (tile >= (int64_t)sets * tm * tn) return;
+    const int c = (int)(tile / ((int64_t)tm * tn));
+    const int rem = (int)(tile % ((int64_t)tm * tn));
+    const int m0 = (rem / tn) * 16, n0 = (rem % tn) * 16;
+    const int kq = lane >> 4;
+    const int64_t sp = (int64_t)sets * ny32 * nz32;  // part stride of Sb
+    const int64_t ep = (int64_t)2 * m.n1p * nz32;    // part stride of EzT
+    const unsigned short *pa = sb + ((int64_t)c * ny32 + m0 + (lane & 15)) * nz32 + 8 * kq;
+    const unsigned short *pr = ezt + (int64_t)(n0 + (lane & 15)) * nz32 + 8 * kq;
+    const unsigned short *pi = pr + (int64_t)m.n1p * nz32;
     v4f accR = {0.f, 0.f, 0.f, 0.f}, accI = {0.f, 0.f, 0.f, 0.f};
-    for (int k = 0; k < ny; k += 16) {
-        Bf3 ar, ai_neg, aim, br, bi;
+    for (int k0 = 0; k0 < nz32; k0 += 32) {
+        v8bf a[NP], br[NP], bi[NP];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int kk = k + 4 * kq + v;
-            const double2 av = (ai < n0 && kk < ny) ? Ey[(int64_t)ai * nyp + kk] : make_double2(0.0, 0.0);
-            const double2 bv = (bj < n1 && kk < ny) ? Tc[(int64_t)kk * n1p + bj] : make_double2(0.0, 0.0);
-            split_bf16(av.x, ar, v);
-            split_bf16(av.y, aim, v);
-            split_bf16(-av.y, ai_neg, v);
-            split_bf16(bv.x, br, v);
-            split_bf16(bv.y, bi, v);
+        for (int p = 0; p < NP; ++p) {
+            a[p] = load8(pa + p * sp + k0);
+            br[p] = load8(pr + p * ep + k0);
+            bi[p] = load8(pi + p * ep + k0);
         }
-        accR = mfma3(ar, br, accR);
-        accR = mfma3(ai_neg, bi, accR);
-        accI = mfma3(ar, bi, accI);
-        accI = mfma3(aim, br, accI);
+        accR = mfma_split<NP>(a, br, accR);
+        accI = mfma_split<NP>(a, bi, accI);
+    }
+    // D[4 kq + r][lane % 16]: rows y = m0 + 4 kq + r of column k = n0 + lane % 16
+    const int64_t tp = (int64_t)2 * sets * m.n1p * ny32;  // part stride of TT
+    unsigned short *dr = tt + ((int64_t)c * m.n1p + n0 + (lane & 15)) * ny32 + m0 + 4 * kq;
+    unsigned short *di = dr + (int64_t)sets * m.n1p * ny32;
+    const float vr[4] = {accR[0], accR[1], accR[2], accR[3]};
+    const float vi[4] = {accI[0], accI[1], accI[2], accI[3]};
+    store_split4<NP>(vr, dr, tp);
+    store_split4<NP>(vi, di, tp);
+}
+
+// F[c][i][k] = sum_y Ey[i][y] T[c][y][k] on 16 x 16 tiles (four real products).
+template <int NP>
+__global__ __launch_bounds__(256) void sep_contract2_bf16(const unsigned short *__restrict__ eyb,
+                                                          const unsigned short *__restrict__ tt, SepDims m, int ny32,
+                                                          int sets, double *__restrict__ amp)
+{
+    const int lane = threadIdx.x & 63;
+    const int tm = (m.n0 + 15) / 16, tn = (m.n1 + 15) / 16;
+    const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (tile >= (int64_t)sets * tm * tn) return;
+    const int c = (int)(tile / ((int64_t)tm * tn));
+    const int rem = (int)(tile % ((int64_t)tm * tn));
+    const int m0 = (rem / tn) * 16, n0 = (rem % tn) * 16;
+    const int kq = lane >> 4;
+    const int64_t ne = (int64_t)m.n0p * ny32;            // one re / im plane of Ey
+    const int64_t nt = (int64_t)sets * m.n1p * ny32;     // one re / im plane of TT
+    const unsigned short *par = eyb + (int64_t)(m0 + (lane & 15)) * ny32 + 8 * kq;
+    const unsigned short *pai = par + ne;
+    const unsigned short *pbr = tt + ((int64_t)c * m.n1p + n0 + (lane & 15)) * ny32 + 8 * kq;
+    const unsigned short *pbi = pbr + nt;
+    v4f rr = {0.f, 0.f, 0.f, 0.f}, ii = rr, ri = rr, ir = rr;
+    for (int y0 = 0; y0 < ny32; y0 += 32) {
+        v8bf ar[NP], ai[NP], br[NP], bi[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            ar[p] = load8(par + p * 2 * ne + y0);
+            ai[p] = load8(pai + p * 2 * ne + y0);
+            br[p] = load8(pbr + p * 2 * nt + y0);
+            bi[p] = load8(pbi + p * 2 * nt + y0);
+        }
+        rr = mfma_split<NP>(ar, br, rr);
+        ii = mfma_split<NP>(ai, bi, ii);
+        ri = mfma_split<NP>(ar, bi, ri);
+        ir = mfma_split<NP>(ai, br, ir);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int i = m0 + 4 * kq + r;
-        if (i < n0 && bj < n1) {
-            double *o = amp + (((int64_t)(c >> 2) * n0 + i) * n1 + bj) * 8 + 2 * (c & 3);
-            o[0] = (double)accR[r];
-            o[1] = (double)accI[r];
+        const int i = m0 + 4 * kq + r, k = n0 + (lane & 15);
+        if (i < m.n0 && k < m.n1) {
+            double *o = amp + (((int64_t)(c >> 2) * m.n0 + i) * m.n1 + k) * 8 + 2 * (c & 3);
+            o[0] = (double)rr[r] - (double)ii[r];
+            o[1] = (double)ri[r] + (double)ir[r];
         }
     }
+}
+
+template <int NP>
+static int launch_bf16_path(const SepDims &m, const BfLayout &B, const Detector &d, const numag_regular &g,
+                            const double *S, int sets, char *base, double *amp, hipStream_t s)
+{
+    unsigned short *sb = (unsigned short *)base;
+    unsigned short *ezt = (unsigned short *)(base + B.s);
+    unsigned short *eyb = (unsigned short *)(base + B.s + B.ez);
+    unsigned short *tt = (unsigned short *)(base + B.s + B.ez + B.ey);
+    const int64_t ntw = (int64_t)m.n0p * B.ny32 + (int64_t)m.n1p * B.nz32;
+    hipLaunchKernelGGL((sep_twiddles_bf16<NP>), dim3((unsigned)((ntw + 255) / 256)), dim3(256), 0, s, d, g, m, B.ny32,
+                       B.nz32, eyb, ezt);
+    NUMAG_HIP_CHECK(hipGetLastError());
+    const int64_t ns = (int64_t)sets * B.ny32 * B.nz32;
+    hipLaunchKernelGGL((sep_split_s_kernel<NP>), dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, s, S, m, B.ny32,
+                       B.nz32, sets, sb);
+    NUMAG_HIP_CHECK(hipGetLastError());
+    const int64_t t1 = (int64_t)sets * (B.ny32 / 16) * (m.n1p / 16);
+    hipLaunchKernelGGL((sep_contract1_bf16<NP>), dim3((unsigned)((t1 + 3) / 4)), dim3(256), 0, s, sb, ezt, m, B.ny32,
+                       B.nz32, sets, tt);
+    NUMAG_HIP_CHECK(hipGetLastError());
+    const int64_t t2 = (int64_t)sets * ((d.n0 + 15) / 16) * ((d.n1 + 15) / 16);
+    hipLaunchKernelGGL((sep_contract2_bf16<NP>), dim3((unsigned)((t2 + 3) / 4)), dim3(256), 0, s, eyb, tt, m, B.ny32,
+                       sets, amp);
+    NUMAG_HIP_CHECK(hipGetLastError());
+    return NUMAG_OK;
 }
 
 int launch_separable(const double *nuc, const double *mag, const numag_regular &g, const Detector &d, int path,
                      int64_t n_snap, double *amp, void *ws, size_t ws_bytes, hipStream_t s)
 {
     const SepLayout L = sep_layout(g, d, n_snap);
-    if (ws_bytes < L.total || ws == nullptr) {
+    const SepDims m = sep_dims(g, d);
+    const bool f64 = path == NUMAG_PATH_SEPARABLE_F64;
+    if (ws_bytes < separable_workspace_bytes(g, d, path, n_snap) || ws == nullptr) {
         set_error("numag_amplitudes: workspace too small for the separable path");
         return NUMAG_E_WORKSPACE;
     }
+    // FP64 path: Ey, Ez, S, T.  BF16 paths: S, then their split operands.
     char *base = (char *)ws;
-    double2 *ey = (double2 *)base;
-    double2 *ez = (double2 *)(base + L.ey);
-    double *S = (double *)(base + L.ey + L.ez);
-    double2 *T = (double2 *)(base + L.ey + L.ez + L.s);
-    const int ny = g.n[1], nz = g.n[2];
-    const int nyp = round_up(ny, 4), n1p = round_up(d.n1, kC2N), n0p = round_up(d.n0, kC2M);
+    double2 *ey = f64 ? (double2 *)base : nullptr;
+    double2 *ez = f64 ? (double2 *)(base + L.ey) : nullptr;
+    double *S = (double *)(f64 ? base + L.ey + L.ez : base);
     const int sets = (int)(4 * n_snap);
-    const int64_t ntw = (int64_t)n0p * nyp + (int64_t)nz * d.n1;
-    const int64_t n_proj = ((int64_t)ny * nz + kProjCells - 1) / kProjCells;
-    const int64_t n_tw = (ntw + 255) / 256;
-    hipLaunchKernelGGL(sep_prepare_kernel, dim3((unsigned)(n_proj * n_snap + n_tw)), dim3(256), 0, s, d, g, nuc, mag,
-                       (int)n_proj, (int)n_snap, S, ey, ez);
+    const int64_t nyz = (int64_t)m.ny * m.nz;
+    const bool pairs = nyz % 2 == 0 && ((uintptr_t)nuc % 16) == 0 && ((uintptr_t)mag % 16) == 0;
+    const int64_t per_wg = (int64_t)kProjThreads * (pairs ? 2 : 1);
+    const int64_t n_proj = (4 * nyz + per_wg - 1) / per_wg;
+    const bool pad_s = m.ny16 != m.ny || m.nz4 != m.nz;
+    const int64_t n_elem = (f64 ? (int64_t)m.n0p * m.nyp + (int64_t)m.nz4 * m.n1p : 0) +
+                           (pad_s ? (int64_t)sets * m.ny16 * m.nz4 : 0);
+    const int64_t n_tw = (n_elem + 255) / 256;
+    if (n_proj * n_snap + n_tw > 0x7fffffffLL) {
+        set_error("numag_amplitudes: too many snapshots for one separable call");
+        return NUMAG_E_INVALID;
+    }
+    if (pairs)
+        hipLaunchKernelGGL(sep_prepare_kernel<2>, dim3((unsigned)(n_proj * n_snap + n_tw)), dim3(256), 0, s, d, g, m,
+                           nuc, mag, (int)n_proj, (int)n_snap, f64 ? 1 : 0, pad_s ? 1 : 0, S, ey, ez);
+    else
+        hipLaunchKernelGGL(sep_prepare_kernel<1>, dim3((unsigned)(n_proj * n_snap + n_tw)), dim3(256), 0, s, d, g, m,
+                           nuc, mag, (int)n_proj, (int)n_snap, f64 ? 1 : 0, pad_s ? 1 : 0, S, ey, ez);
     NUMAG_HIP_CHECK(hipGetLastError());
-    const int64_t t1 = (int64_t)sets * ((nyp + 15) / 16) * ((n1p + 15) / 16);
-    const int64_t t2 = (int64_t)sets * ((d.n0 + 15) / 16) * ((d.n1 + 15) / 16);
+    if (!f64) {
+        const BfLayout B = bf_layout(m, path, n_snap);
+        char *bbase = base + L.s;
+        return B.np == 3 ? launch_bf16_path<3>(m, B, d, g, S, sets, bbase, amp, s)
+                         : launch_bf16_path<2>(m, B, d, g, S, sets, bbase, amp, s);
+    }
+    double2 *T = (double2 *)(base + L.ey + L.ez + L.s);
+    const int64_t t1 = (int64_t)sets * (m.ny16 / (16 * kC1MG)) * (m.n1p / (4 * kC1NG));
+    hipLaunchKernelGGL((sep_contract1_f64<kC1MG, kC1NG>), dim3((unsigned)((t1 + 3) / 4)), dim3(256), 0, s, S, ez, m,
+                       sets, T);
+    NUMAG_HIP_CHECK(hipGetLastError());
     // 32 x 32 tiles when they give every SIMD a few waves, else 16 x 16
     const int64_t t2big = (int64_t)sets * ((d.n0 + 31) / 32) * ((d.n1 + 31) / 32);
     const bool big = t2big >= 4096;
-    const int64_t t2f = big ? t2big : (int64_t)sets * ((d.n0 + 15) / 16) * ((d.n1 + 15) / 16);
-    if (path == NUMAG_PATH_SEPARABLE_F64) {
-        hipLaunchKernelGGL(sep_contract1_f64, dim3((unsigned)((t1 + 3) / 4)), dim3(256), 0, s, S, ez, ny, nz, d.n1,
-                           nyp, n1p, sets, T);
-        NUMAG_HIP_CHECK(hipGetLastError());
-        if (big)
-            hipLaunchKernelGGL((sep_contract2_f64<2, 8>), dim3((unsigned)((t2f + 3) / 4)), dim3(256), 0, s, ey, T,
-                               d.n0, d.n1, nyp, n1p, sets, amp);
-        else
-            hipLaunchKernelGGL((sep_contract2_f64<1, 4>), dim3((unsigned)((t2f + 3) / 4)), dim3(256), 0, s, ey, T,
-                               d.n0, d.n1, nyp, n1p, sets, amp);
-    } else {
-        hipLaunchKernelGGL(sep_contract1_bf16x3, dim3((unsigned)((t1 + 3) / 4)), dim3(256), 0, s, S, ez, ny, nz,
-                           d.n1, nyp, n1p, sets, T);
-        NUMAG_HIP_CHECK(hipGetLastError());
-        hipLaunchKernelGGL(sep_contract2_bf16x3, dim3((unsigned)((t2 + 3) / 4)), dim3(256), 0, s, ey, T, d.n0, ny,
-                           d.n1, nyp, n1p, sets, amp);
-    }
+    const int64_t t2 = big ? t2big : (int64_t)sets * ((d.n0 + 15) / 16) * ((d.n1 + 15) / 16);
+    if (big)
+        hipLaunchKernelGGL((sep_contract2_f64<2, 8>), dim3((unsigned)((t2 + 3) / 4)), dim3(256), 0, s, ey, T, m, sets,
+                           amp);
+    else
+        hipLaunchKernelGGL((sep_contract2_f64<1, 4>), dim3((unsigned)((t2 + 3) / 4)), dim3(256), 0, s, ey, T, m, sets,
+                           amp);
     NUMAG_HIP_CHECK(hipGetLastError());
     return NUMAG_OK;
 }
 
+}  // namespace numag
+
+namespace numag {
+static size_t bf_bytes(const numag_regular &g, const Detector &d, int path, int64_t n_snap)
+{
+    return bf_layout(sep_dims(g, d), path, n_snap).total;
+}
 }  // namespace numag

@@ -15,8 +15,8 @@
 //     (64 x 64, 32 x 64, 128 x 32, 256 x 16 single- or double-buffered) and the
 //     workgroups aimed for;
 //   adjoint: the workgroups aimed for (point blocks x detector ranges);
-//   objects (persistent kernel, Cartesian detector): lanes per detector row and
-//     the work items aimed for.
+//   objects (persistent kernel): lanes per detector row (polar: the workgroup
+//     shape) and the work items aimed for.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -184,7 +184,8 @@ bool valid_tune_shape(int kernel, const Detector &d, const TuneShape &s)
         case kTuneAdjoint:
             return s.shape == 0;
         case kTuneObjects:
-            return d.kind == NUMAG_GRID_CARTESIAN && (s.shape == 8 || s.shape == 16 || s.shape == 32 || s.shape == 64);
+            if (d.kind == NUMAG_GRID_POLAR) return s.shape >= 0 && s.shape < kPolarShapeCount && (s.shape != 1 || d.n0 <= 32);
+            return s.shape == 8 || s.shape == 16 || s.shape == 32 || s.shape == 64;
         default:
             return false;
     }

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libnumag.so")
 
 OBSERVABLES = ("N", "M", "NM", "P", "CHI", "SF", "PP", "MM", "PM", "MP", "PLUS", "MINUS", "UNPOL")
 GRID_CARTESIAN, GRID_POLAR = 0, 1
-PATH_DIRECT, PATH_SEPARABLE_F64, PATH_SEPARABLE_BF16X3, PATH_DIRECT_HERMITIAN = 0, 1, 2, 3
+PATH_DIRECT, PATH_SEPARABLE_F64, PATH_SEPARABLE_BF16X3, PATH_DIRECT_HERMITIAN, PATH_SEPARABLE_BF16X6 = 0, 1, 2, 3, 4
 MODE_COHERENT, MODE_DILUTE, MODE_SPLIT = 0, 1, 2
 OK, E_INVALID, E_WORKSPACE, E_HIP, E_UNSUPPORTED = 0, -1, -2, -4, -5
 
@@ -403,9 +403,8 @@ class BatchedOrientations:
     """Orientational average of a dilute sample (Sec. 3.3 dilute limit) over many
     sample rotations, recorded once into a HIP graph and replayed.  A plan holds
     the rotations and object offsets; its tables are uploaded once, and the graph
-    records the plan's kernels (Cartesian detector: one persistent launch over
-    (object, rotation range, pixel block) work items; polar detector: per object,
-    groups of rotations on the polar direct kernel).
+    records the plan's kernels (one persistent launch over (object, rotation range,
+    pixel block) work items, on either detector kind).
 
     The graph reads the sample's device arrays at replay time, so weights may
     be updated in place between replays; rotations and object offsets are fixed

@@ -293,7 +293,7 @@ def test_separable_f64_ragged_grid(orc):
 def test_separable_paths_c2_full_size(orc):
     """64^3 vortex grid, 256 x 256 detector: the FP64 separable path meets the
     1e-5 gate against the oracle (sampled pixels) and matches the direct path
-    everywhere; the BF16x3 path's gated error is measured and reported."""
+    everywhere; the BF16 split-product paths' gated errors are measured and reported."""
     cfg = synth.vortex_grid()
     g = cfg["grid"]
     grid = _grid(g)
@@ -309,18 +309,24 @@ def test_separable_paths_c2_full_size(orc):
     idx = np.sort(rng.choice(qy.size, 128, replace=False))
     ref = _oracle_amp(orc, cfg, qy[idx], qz[idx])
     _check_amp(a64[idx], ref)
-    abf, _ = numag.amplitudes(s, grid, path=numag.PATH_SEPARABLE_BF16X3)
-    abf = amp_to_complex(abf[0])
-    # gated error of the unpolarized cross section, against the FP64 path over all pixels
+    # the BF16 split-product modes: gated error of all 13 cross sections against the
+    # FP64 path (which meets the gate against the oracle) over every pixel, q = 0 excluded
     x64 = numag.cross_section(grid, amp=torch.as_tensor(np.stack([a64.real, a64.imag], -1)[None], device=DEV),
-                              obs=("N", "M", "UNPOL"))[0].cpu().numpy()
-    xbf = numag.cross_section(grid, amp=torch.as_tensor(np.stack([abf.real, abf.imag], -1)[None], device=DEV),
-                              obs=("N", "M", "UNPOL"))[0].cpu().numpy()
-    errs = [gated_rel_err(xbf[i], x64[i]) for i in range(3)]
-    print(f"BF16x3 separable gated rel err N/M/unpol: {errs}")
-    # measured about 2e-3: the BF16x3 split misses the 1e-4 matrix-core gate, and this
-    # bound only guards against a regression of that level
-    assert max(errs) < 5e-3
+                              obs=numag.OBSERVABLES)[0].cpu().numpy()
+    worst = {}
+    for name, path in (("BF16x3", numag.PATH_SEPARABLE_BF16X3), ("BF16x6", numag.PATH_SEPARABLE_BF16X6)):
+        abf, _ = numag.amplitudes(s, grid, path=path)
+        xbf = numag.cross_section(grid, amp=abf, obs=numag.OBSERVABLES)[0].cpu().numpy()
+        errs = {o: gated_rel_err(xbf[i], x64[i]) for i, o in enumerate(numag.OBSERVABLES)}
+        print(f"{name} separable gated rel err per observable: " +
+              ", ".join(f"{o} {e:.2e}" for o, e in errs.items()))
+        worst[name] = max(errs.values())
+    # regression bounds at the measured levels: BF16x3 reaches about 2e-2 (the
+    # nuclear-magnetic interference) and BF16x6 about 2.6e-4 (the same term; 1e-5 to
+    # 7e-5 on the others): neither meets the 1e-4 matrix-core gate on every
+    # observable, and the FP64 matrix-core mode is the one that does
+    assert worst["BF16x3"] < 5e-2
+    assert worst["BF16x6"] < 1e-3
 
 
 @pytest.mark.parametrize("n0,n1", [(13, 50), (11, 100), (9, 200), (7, 300), (5, 700)])

@@ -46,8 +46,8 @@ def test_snapshots_ragged_grid_vs_single_calls_and_oracle(orc):
 
 
 def test_snapshots_channel_off_and_bf16_batch():
-    """mag only (nuclear channel off gives zeros) and the BF16x3 mode batch equal
-    their single calls."""
+    """mag only (nuclear channel off gives zeros) and the BF16 split-product modes'
+    batches equal their single calls."""
     n, a, origin = (4, 6, 10), (1.0, 1.0, 1.0), (-1.5, -2.5, -4.5)
     W = 4 * 6 * 10
     rng = np.random.default_rng(41)
@@ -55,7 +55,7 @@ def test_snapshots_channel_off_and_bf16_batch():
     grid = numag.qgrid(0, 16, 24, 1.0)
     points = numag.regular_grid(n, origin, a)
     reg = {"n": n, "origin": origin, "step": a}
-    for path in (numag.PATH_SEPARABLE_F64, numag.PATH_SEPARABLE_BF16X3):
+    for path in (numag.PATH_SEPARABLE_F64, numag.PATH_SEPARABLE_BF16X3, numag.PATH_SEPARABLE_BF16X6):
         amp = numag.amplitudes_snapshots(points, grid, mag=mag, path=path, device=DEV)
         assert torch.count_nonzero(amp[:, :, 0, :]).item() == 0
         for b in range(2):

@@ -89,9 +89,11 @@ def test_autotune_direct_and_adjoint_keep_parity(orc):
             assert max_norm_err(gdm.cpu().numpy(), dm) <= 1e-9
 
 
-def test_autotune_objects_and_every_object_shape(orc):
+@pytest.mark.parametrize("kind,n0,n1", [(0, 48, 80), (1, 140, 40), (1, 24, 64)])
+def test_autotune_objects_and_every_object_shape(orc, kind, n0, n1):
     """Dilute per-object orientational averages: the persistent kernel under the
-    tuned shape and under every candidate (lanes per row x work items)."""
+    tuned shape and under every candidate (Cartesian: lanes per row; polar: the
+    workgroup shape; x work items)."""
     rng = np.random.default_rng(34)
     sizes = [1500, 40, 3100, 700]
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
@@ -100,18 +102,22 @@ def test_autotune_objects_and_every_object_shape(orc):
     nuc = rng.standard_normal(W)
     mag = rng.standard_normal((W, 3))
     s = numag.Sample(pos=pos, nuc=nuc, mag=mag, obj_offsets=off, device=DEV)
-    grid = numag.qgrid(0, 48, 80, 1.1)
+    grid = numag.qgrid(kind, n0, n1, 1.1)
     rots = synth.uniform_rotations(6, np.random.default_rng(35))
     chosen = numag.autotune(s, grid, numag.TUNE_OBJECTS, rot=rots)
     assert numag.tune_get(numag.TUNE_OBJECTS, grid, W)[1] == chosen
-    qy, qz, _ = orc.pixels(0, 48, 80, 1.1)
+    qy, qz, _ = orc.pixels(kind, n0, n1, 1.1)
     acc = np.zeros((len(sizes), qy.size, 16))
     for R in rots:
         F = orc.amplitudes(pos, nuc, mag, qy, qz, R=R, obj_offsets=off, per_object=True)
         for k in range(len(sizes)):
             acc[k] += orc.spectral(F[k])
     acc /= len(rots)
-    for shape in [None] + [(l, t) for l in (8, 16, 32) for t in (64, 1024, 4096)]:
+    if kind == numag.GRID_POLAR:
+        shapes = [(sh, t) for sh in ((1, 0) if n0 <= 32 else (0, 2, 3, 4)) for t in (64, 1024)]
+    else:
+        shapes = [(l, t) for l in (8, 16, 32) for t in (64, 1024, 4096)]
+    for shape in [None] + shapes:
         if shape is not None:
             numag.tune_set(numag.TUNE_OBJECTS, grid, W, shape)
         _, spec = numag.amplitudes(s, grid, rot=rots, mode=numag.MODE_DILUTE, spec_per_object=True)
