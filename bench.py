@@ -60,7 +60,8 @@ def parse():
                     help="untimed steps; the engine clock needs about 35 ms of this load to settle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
-                    help="time the step under the library's default launch shapes (the tuning report is still made)")
+                    help="no autotuning: launch shapes come from the table as it stands (the file named by "
+                         "NUMAG_AUTOTUNE_CACHE, else the library defaults); for profiler runs")
     ap.add_argument("--cpu-pixels", type=int, default=49152,
                     help="pixels of the oracle's bounded sample")
     ap.add_argument("--cpu-pixels-1core", type=int, default=1024,
@@ -97,11 +98,18 @@ def kernel_ms(torch, numag, kid, fn, n=3, warm=1):
     return t / k if k else float("nan")
 
 
+TUNE = True  # False (--no-tune): no autotuning; shapes come from the table as it is
+
+
 def tuned_vs_default(torch, numag, kernel, kid, sample, grid, fn, rot=None, max_points=0, n=3, warm=1):
     """Kernel time under the library's default launch shape, then numag_autotune on the
     same inputs and the kernel time under the shape it keeps (left in the table for
-    the rest of the run)."""
+    the rest of the run).  With --no-tune: only the shape in use, from the table."""
     W = sample.n_points
+    if not TUNE:
+        default, current, tuned = numag.tune_get(kernel, grid, W)
+        return {"default_shape": list(default), "shape_in_use": list(current),
+                "from": "NUMAG_AUTOTUNE_CACHE" if tuned else "library default"}
     numag.tune_set(kernel, grid, W, None)
     default, _, _ = numag.tune_get(kernel, grid, W)
     t_def = kernel_ms(torch, numag, kid, fn, n, warm)
@@ -219,6 +227,11 @@ def measure_batched(torch, numag, synth):
     # rotations: rotation groups on the polar direct kernel
     pgrid = numag.qgrid(1, g["n0"], g["n1"], g["qmax"])
     prots = rots[:50]
+    polar_tuning = tuned_vs_default(
+        torch, numag, numag.TUNE_OBJECTS, numag.KERNEL_OBJECTS, s, pgrid,
+        lambda: numag.amplitudes(s, pgrid, rot=prots[:16], mode=numag.MODE_DILUTE, spec_per_object=True),
+        rot=prots[:16], n=2)
+    polar_tuning["sample"] = "first 16 rotations, dilute per-particle average, polar detector"
     numag.amplitudes(s, pgrid, rot=prots[:2], mode=numag.MODE_DILUTE, spec_per_object=True)  # warm-up
     torch.cuda.synchronize()
     e0.record()
@@ -239,9 +252,11 @@ def measure_batched(torch, numag, synth):
         "plain_direct_sample": "same particles, first 8 rotations, one coherent direct call per (particle, rotation)",
         "polar_dilute_s": round(t_polar, 4),
         "polar_dilute_Gterm_s": round(polar_terms / t_polar / 1e9, 2),
+        "polar_dilute_frac": round(FLOPS_PER_TERM * polar_terms / t_polar / PEAK_FP64_VALU, 4),
         "polar_dilute_sample": "same particles, first 50 rotations, 128 q x 128 theta polar detector, dilute "
-                               "per-particle average (rotation groups on the polar direct kernel)",
+                               "per-particle average (persistent polar object kernel)",
         "tuning": tuning,
+        "polar_tuning": polar_tuning,
     }
 
 
@@ -441,19 +456,23 @@ def sources_sha256(names):
     return h.hexdigest()
 
 
-def traffic_per_launch(kernel):
+def traffic_per_launch(kernel, shape=None):
     """HBM bytes per launch of `kernel` from its committed counter summary, or None
-    when there is none or the kernel's sources changed since it was taken."""
+    when there is none, the kernel's sources changed since it was taken, or (with
+    `shape`) the summary was taken under another launch shape."""
     _, srcs, name = {**KERNELS, **SIDE_KERNELS}[kernel]
     path = os.path.join(PROFILES, name)
     if not os.path.exists(path):
         return None
     vals = {}
     for line in open(path):
-        m = re.match(r"^\s*-?\s*`?([a-z_0-9]+)`?\s*:\s*`?([0-9a-f.e+]+)`?\s*$", line.strip())
+        m = re.match(r"^\s*-?\s*`?([a-z_0-9]+)`?\s*:\s*`?([0-9a-f.e+ ]+?)`?\s*$", line.strip())
         if m:
             vals[m.group(1)] = m.group(2)
     if vals.get("sources_sha256") != sources_sha256(srcs):
+        return None
+    if shape is not None and vals.get("launch_shape") is not None and \
+            [int(v) for v in vals["launch_shape"].split()] != list(shape):
         return None
     try:
         return int(float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"]))
@@ -506,7 +525,9 @@ def calibrate_copy(torch):
 
 
 def main():
+    global TUNE
     args = parse()
+    TUNE = not args.no_tune
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 "
                                    "(splitting a job over several GPUs is not implemented)"}))
@@ -574,8 +595,6 @@ def main():
         "adjoint": tuned_vs_default(torch, numag, numag.TUNE_ADJOINT, numag.KERNEL_ADJOINT, sample, grid,
                                     lambda: numag.grad(sample, grid, k, weight=w, target=T, amp=amp[0])),
     }
-    if args.no_tune:
-        numag.tune_clear()
 
     ev = {"direct": [], "adjoint": [], "separable": []}
 
@@ -676,7 +695,9 @@ def main():
     dominant = max(kernel_ms, key=lambda k: kernel_ms[k])
     t_kernel = kernel_ms[dominant]
     achieved = FLOPS_PER_TERM * terms / (t_kernel * 1e-3) / 1e12
-    traffic = traffic_per_launch(dominant)
+    shapes = {"direct_cartesian_kernel": numag.tune_get(numag.TUNE_DIRECT, grid, W)[1],
+              "adjoint_cartesian_kernel": numag.tune_get(numag.TUNE_ADJOINT, grid, W)[1]}
+    traffic = traffic_per_launch(dominant, shapes[dominant])
     out = {
         "metric": "point*q-pixel terms/s (G/s), direct vs batched vs MFMA at rel err <= 1e-5",
         "value": round(value, 3),
@@ -695,7 +716,8 @@ def main():
                         "direct sums + 13 cross sections + azimuthal average + correlation"
                         + (" + separable FP64-MFMA sums" if have_sep else "") + " + loss gradient (adjoint)",
             "points": W, "pixels": P, "evaluated_terms_per_step": 2 * terms,
-            "launch_shapes": "default" if args.no_tune else "autotuned",
+            "launch_shapes": "autotuned" if TUNE else ("from NUMAG_AUTOTUNE_CACHE" if os.environ.get(
+                "NUMAG_AUTOTUNE_CACHE") else "library defaults"),
         },
         "tuning": tuning,
         "paths": {
@@ -717,7 +739,7 @@ def main():
                 "achieved": round(FLOPS_PER_TERM * terms / (kernel_ms["adjoint_cartesian_kernel"] * 1e-3) / 1e12, 3),
                 "frac": round(FLOPS_PER_TERM * terms / (kernel_ms["adjoint_cartesian_kernel"] * 1e-3)
                               / PEAK_FP64_VALU, 4),
-                "traffic": traffic_per_launch("adjoint_cartesian_kernel"),
+                "traffic": traffic_per_launch("adjoint_cartesian_kernel", shapes["adjoint_cartesian_kernel"]),
             },
             "adjoint_hermitian_ms": round(t_adj_herm, 4) if t_adj_herm else None,
             "adjoint_hermitian_Gterm_s_effective": round(terms / (t_adj_herm * 1e-3) / 1e9, 2) if t_adj_herm else None,
@@ -736,6 +758,7 @@ def main():
             # the same work against the packed FP32 vector peak (the sums run in FP64)
             "frac_fp32_valu": round(achieved * 1e12 / PEAK_FP32_VALU, 4),
             "traffic": traffic,
+            "launch_shape": list(shapes[dominant]),
             "launch_ms": round(t_kernel, 4),
             "flops_per_launch": FLOPS_PER_TERM * terms,
         },

@@ -243,12 +243,13 @@ __global__ __launch_bounds__(kAdjThreads, 2) void adjoint_cartesian_kernel(
 // owns kAdjNPL points; per theta column it forms u, the q step exp(-i dq u) (one
 // sincos) and walks the q rows with the two-term recurrence, restarted from a
 // fresh sincos every kPolRestart rows (the error growth of the recurrence stays
-// below kPolRestart^2 / 2 ulp).  The residual weights are column-major
+// below kPolRestart^2 / 2 ulp, 2^15 ulp or 7e-12 relative; the first segment starts
+// at q = 0, whose phasor is 1 without a sincos).  The residual weights are column-major
 // [theta][q][8] and are walked as segments of kPolRestart rows of one column,
 // double-buffered in LDS like the Cartesian kernel's: the next segment is held
 // in registers while the current one is summed.
 // grid.x: point blocks of kAdjThreads * kAdjNPL; grid.y: theta-column ranges.
-constexpr int kPolRestart = 128;
+constexpr int kPolRestart = 256;
 constexpr int kPolPer = kPolRestart * 8 / kAdjThreads;  // doubles per thread per segment
 static_assert(kPolPer * kAdjThreads == kPolRestart * 8, "segment split over the threads");
 
@@ -318,7 +319,7 @@ __global__ __launch_bounds__(kAdjThreads, 2) void adjoint_polar_kernel(
         double2 pc[kAdjNPL], pm[kAdjNPL];
 #pragma unroll
         for (int u = 0; u < kAdjNPL; ++u) {
-            pc[u] = twiddle(q0 * uu[u]);
+            pc[u] = r0 == 0 ? make_double2(1.0, 0.0) : twiddle(q0 * uu[u]);
             pm[u] = cmul(pc[u], stc[u]);
         }
         const double *sa = s_a[buf];
