@@ -17,6 +17,8 @@
   covers the largest particle, whose work is cut into many rotation ranges), and
   every particle under 4 seeded rotations on more pixels.
 """
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import pytest
 
@@ -116,12 +118,18 @@ def test_orientational_average_every_particle_full_rotation_set(orc):
     # all 1000 rotations, every particle, on 4 pixels
     idx = np.sort(np.random.default_rng(46).choice(qy.size, 4, replace=False))
     print("C4: oracle, 64 particles x 1000 rotations x 4 pixels", flush=True)
+    # The oracle parallelises over pixels, so with 4 pixels it uses 4 threads: the
+    # rotations run concurrently from a thread pool (the library call releases the
+    # interpreter lock) and are accumulated in rotation order.
+    def one_rotation(R):
+        return orc.amplitudes(cfg["pos"], cfg["nuc"], cfg["mag"], qy[idx], qz[idx], R=R, obj_offsets=off,
+                              per_object=True)
+
     acc = np.zeros((K, idx.size, 16))
-    for R in rots:
-        F = orc.amplitudes(cfg["pos"], cfg["nuc"], cfg["mag"], qy[idx], qz[idx], R=R, obj_offsets=off,
-                           per_object=True)
-        for kk in range(K):
-            acc[kk] += orc.spectral(F[kk])
+    with ThreadPoolExecutor(max_workers=4) as pool:
+        for F in pool.map(one_rotation, rots):
+            for kk in range(K):
+                acc[kk] += orc.spectral(F[kk])
     acc /= len(rots)
     for kk in range(K):
         _check_spec(spec[kk][idx], acc[kk])

@@ -69,3 +69,32 @@ def test_noalloc_objects_channels_and_empty_sample():
     got = numag.amplitudes_noalloc(e, g)
     torch.cuda.synchronize()
     assert float(got.abs().max()) == 0.0
+
+
+def test_noalloc_graph_capture_replays():
+    """The allocation-free call recorded into a HIP graph (it enqueues kernels only:
+    no allocation, no copy, no memset) and replayed three times, with eager work and
+    synchronisations between the replays: every replay equals the eager call bit for
+    bit."""
+    cl = synth.random_cloud(20000, 15.0, seed=16)
+    s = numag.Sample(pos=cl["pos"], nuc=cl["nuc"], mag=cl["mag"], device=DEV)
+    g = numag.qgrid(1, 96, 80, 1.3)
+    R = synth.sample_rotation(40.0, 15.0)
+    eager = numag.amplitudes_noalloc(s, g, rot=R)  # first call on the device: scratch address lookup
+    out = torch.empty_like(eager)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        numag.amplitudes_noalloc(s, g, rot=R, out=out)  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        numag.amplitudes_noalloc(s, g, rot=R, out=out)
+    for _ in range(3):
+        out.fill_(-1.0)
+        numag.amplitudes(s, g, rot=R)  # other eager work between replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager)
