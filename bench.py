@@ -292,9 +292,11 @@ def measure_snapshots(torch, numag, synth, n_snap=64):
     e1.record()
     torch.cuda.synchronize()
     t_single = e0.elapsed_time(e1) * 1e-3
-    # the same batch on the BF16 split-product modes (matrix cores at BF16 rate)
+    # the same batch on the Hermitian FP64 variant (second contraction on half of the
+    # detector rows) and the BF16 split-product modes (matrix cores at BF16 rate)
     t_bf = {}
-    for name, path in (("bf16x3", numag.PATH_SEPARABLE_BF16X3), ("bf16x6", numag.PATH_SEPARABLE_BF16X6)):
+    for name, path in (("hermitian", numag.PATH_SEPARABLE_F64_HERMITIAN), ("bf16x3", numag.PATH_SEPARABLE_BF16X3),
+                       ("bf16x6", numag.PATH_SEPARABLE_BF16X6)):
         numag.amplitudes_snapshots(points, grid, nuc=nucs, mag=mt, path=path, out=out, device=dev)
         torch.cuda.synchronize()
         e0.record()
@@ -304,6 +306,7 @@ def measure_snapshots(torch, numag, synth, n_snap=64):
         torch.cuda.synchronize()
         t_bf[name] = e0.elapsed_time(e1) / reps
     flops = n_snap * 4 * (64 * 64 * 256 * 4 + 256 * 64 * 256 * 8)  # both contractions, four channels
+    flops_h = n_snap * 4 * (64 * 64 * 256 * 4 + 128 * 64 * 256 * 8)  # the Hermitian variant's executed flops
     return {
         "workload": f"{n_snap} field-sweep snapshots of the 64^3 vortex grid, 256x256 detector, FP64 MFMA separable "
                     "path, one batched call",
@@ -312,6 +315,8 @@ def measure_snapshots(torch, numag, synth, n_snap=64):
         "batched_Gterm_s_effective": round(n_snap * W * grid.n_pixels / t_batch / 1e9, 1),
         "batched_mfma_TFLOP_s": round(flops / t_batch / 1e12, 3),
         "single_calls_per_snapshot_us": round(t_single / n_snap * 1e6, 2),
+        "hermitian_batched_ms": round(t_bf["hermitian"], 4),
+        "hermitian_mfma_TFLOP_s_executed": round(flops_h / (t_bf["hermitian"] * 1e-3) / 1e12, 3),
         "bf16x3_batched_ms": round(t_bf["bf16x3"], 4),
         "bf16x6_batched_ms": round(t_bf["bf16x6"], 4),
         # the whole batched call (projection, twiddles, both contractions) against the

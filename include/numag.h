@@ -87,6 +87,14 @@ extern "C" {
    every rotation. */
 #define NUMAG_PATH_DIRECT_HERMITIAN 3
 #define NUMAG_PATH_SEPARABLE_BF16X6 4  /* see NUMAG_PATH_SEPARABLE_BF16X3 */
+/* FP64 separable path on half of the (symmetric) Cartesian detector: the second
+   contraction runs on rows [0, ceil(n0 / 2)) only and writes each pixel's
+   conjugate at the mirrored pixel, S(-q) = conj S(q) for real weights -- half of
+   the dominant contraction's work.  The computed rows equal the full path's bit
+   for bit; a mirrored pixel takes its partner's conjugate instead of a sum over
+   its own q (which differs from -q by at most an ulp).  Same arguments,
+   workspace and outputs as NUMAG_PATH_SEPARABLE_F64. */
+#define NUMAG_PATH_SEPARABLE_F64_HERMITIAN 5
 
 /* ---- object modes (Sec. 3.3, summation relation and dilute limit) -------- */
 #define NUMAG_MODE_COHERENT 0  /* |sum_k exp(-i q.R r^k) F_k|^2                   */

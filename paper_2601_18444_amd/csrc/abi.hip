@@ -42,7 +42,8 @@ struct Carve {
 
 bool is_separable(int32_t path)
 {
-    return path == NUMAG_PATH_SEPARABLE_F64 || path == NUMAG_PATH_SEPARABLE_BF16X3 || path == NUMAG_PATH_SEPARABLE_BF16X6;
+    return path == NUMAG_PATH_SEPARABLE_F64 || path == NUMAG_PATH_SEPARABLE_BF16X3 ||
+           path == NUMAG_PATH_SEPARABLE_BF16X6 || path == NUMAG_PATH_SEPARABLE_F64_HERMITIAN;
 }
 
 int invalid(const std::string &msg)
@@ -285,7 +286,7 @@ int check_amplitudes_request(const numag_sample *sample, int64_t n_rot, const do
     if ((rc = check_rotations(rot, n_rot, fn)) != NUMAG_OK) return rc;
     const std::string f(fn);
     if (mode < NUMAG_MODE_COHERENT || mode > NUMAG_MODE_SPLIT) return invalid(f + ": unknown mode");
-    if (path < NUMAG_PATH_DIRECT || path > NUMAG_PATH_SEPARABLE_BF16X6) return invalid(f + ": unknown path");
+    if (path < NUMAG_PATH_DIRECT || path > NUMAG_PATH_SEPARABLE_F64_HERMITIAN) return invalid(f + ": unknown path");
     if (path == NUMAG_PATH_DIRECT_HERMITIAN && grid->kind == NUMAG_GRID_POLAR && grid->n1 % 2 != 0)
         return invalid(f + ": the Hermitian path needs an even n_theta on a polar detector");
     if (is_separable(path)) {
@@ -471,7 +472,7 @@ size_t numag_workspace_size(const numag_sample *sample, int64_t n_rot, const num
         set_error("numag_workspace_size: unknown mode");
         return 0;
     }
-    if (path < NUMAG_PATH_DIRECT || path > NUMAG_PATH_SEPARABLE_BF16X6) {
+    if (path < NUMAG_PATH_DIRECT || path > NUMAG_PATH_SEPARABLE_F64_HERMITIAN) {
         set_error("numag_workspace_size: unknown path");
         return 0;
     }

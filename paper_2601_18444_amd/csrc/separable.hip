@@ -8,7 +8,9 @@
 //   F_c(i, k)   = sum_y exp(-i q_y(i) y) T_c(y, k)         (complex x complex contraction)
 // The two contractions are dense GEMMs and run on MFMA:
 //   NUMAG_PATH_SEPARABLE_F64:    FP64 operands and accumulation on
-//                                v_mfma_f64_4x4x4f64 (register-blocked tiles);
+//                                v_mfma_f64_16x16x4f64 (_HERMITIAN: the second
+//                                contraction on half of the detector rows, the
+//                                rest mirrored by S(-q) = conj S(q));
 //   NUMAG_PATH_SEPARABLE_BF16X3 / _BF16X6: every operand split into 2 or 3 bf16
 //                                parts, 3 or 6 split products per real product on
 //                                v_mfma_f32_16x16x32_bf16, FP32 accumulation.
@@ -29,22 +31,29 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 
 // Padded sizes of the operands, so that the matrix-core loads need no bounds
 // checks: every padding entry is zero.
-//   S  [sets][ny16][nz4]    projections (ny16 = ny rounded up to 32, nz4 = nz to 4)
-//   Ez [nz4][n1p]           column twiddles (n1p = n1 rounded up to 64)
+//   S  [sets][ny16][nzk]    projections (ny16 = ny rounded up to 32, nzk = nz to 16)
+//   Ez [nzk][n1p]           column twiddles (n1p = n1 rounded up to 64)
 //   T  [sets][ny16][n1p]    first contraction (complex)
-//   Ey [n0p][nyp]           row twiddles (n0p = n0 to 32, nyp = ny to 4)
+//   Ey [n0p][nyk]           row twiddles (n0p = n0 to 32, nyk = ny to 16)
+// nzk and nyk are the contraction depths, multiples of 16 so that the FP64
+// kernels' loops (four or two K steps of 4 per iteration) need no remainder.
 struct SepDims {
-    int ny, nz, n0, n1, ny16, nz4, nyp, n0p, n1p;
+    int ny, nz, n0, n1, ny16, nzk, nyk, n0p, n1p;
 };
 
 struct SepLayout {
     size_t ey, ez, s, t, total;
 };
 
-// Output tiles of one wave: first contraction (16 MG1) x (4 NG1), second (16 MG) x (4 NG)
-// with (MG, NG) = (2, 8) or (1, 4).
-constexpr int kC1MG = 2, kC1NG = 8;
-constexpr int kC2M = 32, kC2N = 64;  // paddings of the second contraction's rows and columns
+// Paddings: rows of S and T (ny16) to the first contraction's 32-row wave tiles,
+// detector rows and columns to 32 and 64 (the BF16 paths' tiles; the FP64 tiles
+// are 16 x 16).
+constexpr int kC1M = 32;
+constexpr int kC2M = 32, kC2N = 64;
+constexpr int kKStep = 16;  // padding of the contraction depths
+// K steps of 4 per loop iteration of the first contraction (all their fragments
+// loaded first, then the MFMAs).
+constexpr int kC1Steps = 4;
 
 __host__ __device__ static inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
@@ -57,9 +66,9 @@ static SepDims sep_dims(const numag_regular &g, const Detector &d)
     m.nz = g.n[2];
     m.n0 = d.n0;
     m.n1 = d.n1;
-    m.ny16 = round_up(m.ny, 16 * kC1MG);
-    m.nz4 = round_up(m.nz, 4);
-    m.nyp = round_up(m.ny, 4);
+    m.ny16 = round_up(m.ny, kC1M);
+    m.nzk = round_up(m.nz, kKStep);
+    m.nyk = round_up(m.ny, kKStep);
     m.n0p = round_up(m.n0, kC2M);
     m.n1p = round_up(m.n1, kC2N);
     return m;
@@ -70,9 +79,9 @@ static SepLayout sep_layout(const numag_regular &g, const Detector &d, int64_t n
     const SepDims m = sep_dims(g, d);
     const size_t sets = 4 * (size_t)n_snap;
     SepLayout L{};
-    L.ey = al((size_t)m.n0p * m.nyp * sizeof(double2));
-    L.ez = al((size_t)m.nz4 * m.n1p * sizeof(double2));
-    L.s = al(sets * m.ny16 * m.nz4 * sizeof(double));
+    L.ey = al((size_t)m.n0p * m.nyk * sizeof(double2));
+    L.ez = al((size_t)m.nzk * m.n1p * sizeof(double2));
+    L.s = al(sets * m.ny16 * m.nzk * sizeof(double));
     L.t = al(sets * m.ny16 * m.n1p * sizeof(double2));
     L.total = L.ey + L.ez + L.s + L.t;
     return L;
@@ -83,7 +92,7 @@ static size_t bf_bytes(const numag_regular &g, const Detector &d, int path, int6
 size_t separable_workspace_bytes(const numag_regular &g, const Detector &d, int path, int64_t n_snap)
 {
     const SepLayout L = sep_layout(g, d, n_snap);
-    if (path == NUMAG_PATH_SEPARABLE_F64) return L.total;
+    if (path == NUMAG_PATH_SEPARABLE_F64 || path == NUMAG_PATH_SEPARABLE_F64_HERMITIAN) return L.total;
     // the BF16 paths also use the FP64 projections (the S region) before splitting them
     return L.s + bf_bytes(g, d, path, n_snap);
 }
@@ -145,7 +154,7 @@ __global__ __launch_bounds__(256) void sep_prepare_kernel(Detector d, numag_regu
 {
     const int64_t nyz = (int64_t)g.n[1] * g.n[2];
     const int64_t W = (int64_t)g.n[0] * nyz;
-    const int64_t sstride = (int64_t)m.ny16 * m.nz4;  // one channel set of S
+    const int64_t sstride = (int64_t)m.ny16 * m.nzk;  // one channel set of S
     if ((int64_t)blockIdx.x < (int64_t)n_proj * n_snap) {
         __shared__ double part[kProjSlices][kProjThreads * CPT];
         const int b = (int)(blockIdx.x / n_proj);
@@ -174,16 +183,16 @@ __global__ __launch_bounds__(256) void sep_prepare_kernel(Detector d, numag_regu
             const int64_t cell = nc ? mc : (mc - nyz) / 3;
             const int c = nc ? 0 : 1 + (int)((mc - nyz) % 3);
             const int iy = (int)(cell / g.n[2]), iz = (int)(cell % g.n[2]);
-            S[(int64_t)(4 * b + c) * sstride + (int64_t)iy * m.nz4 + iz] = v;
+            S[(int64_t)(4 * b + c) * sstride + (int64_t)iy * m.nzk + iz] = v;
         }
         return;
     }
     const int64_t idx = ((int64_t)blockIdx.x - (int64_t)n_proj * n_snap) * blockDim.x + threadIdx.x;
     // tw == 0: no FP64 twiddles (the BF16 paths write their own), padding of S only
-    const int64_t ne = tw ? (int64_t)m.n0p * m.nyp : 0;
-    const int64_t nez = tw ? (int64_t)m.nz4 * m.n1p : 0;
+    const int64_t ne = tw ? (int64_t)m.n0p * m.nyk : 0;
+    const int64_t nez = tw ? (int64_t)m.nzk * m.n1p : 0;
     if (idx < ne) {
-        const int i = (int)(idx / m.nyp), iy = (int)(idx % m.nyp);
+        const int i = (int)(idx / m.nyk), iy = (int)(idx % m.nyk);
         const double y = g.origin[1] + (double)iy * g.step[1];
         ey[idx] = (i < d.n0 && iy < m.ny) ? twiddle(axis_value(d.origin0, i, d.step0) * y) : make_double2(0.0, 0.0);
     } else if (idx < ne + nez) {
@@ -196,29 +205,32 @@ __global__ __launch_bounds__(256) void sep_prepare_kernel(Detector d, numag_regu
         const int64_t r = idx - ne - nez;
         if (r < (int64_t)4 * n_snap * sstride) {
             const int64_t cell = r % sstride;
-            const int iy = (int)(cell / m.nz4), iz = (int)(cell % m.nz4);
+            const int iy = (int)(cell / m.nzk), iz = (int)(cell % m.nzk);
             if (iy >= m.ny || iz >= m.nz) S[r] = 0.0;
         }
     }
 }
 
 // ---- FP64 MFMA -------------------------------------------------------------
-// Both contractions run on v_mfma_f64_4x4x4f64 (four 4 x 4 x 4 blocks per
-// instruction; it issues its flops faster on gfx950 than the 16 x 16 x 4 form).
-// Lane layout (one-hot probe): block g = (l / 4) % 4, A[g][l % 4][l / 16],
-// B[g][l / 16][l % 4], D[g][l / 16][l % 4].  A wave owns a (16 MG) x (4 NG)
-// output tile: per K step of 4 it holds MG A fragments (rows i0 + 16 mg + 4 g + e)
-// and NG B fragments (columns k0 + 4 ng + e, the same for every block).  Every
-// output element sees the same instruction sequence whatever the tile shape, so
-// the shape never changes a result.
+// Both contractions run on v_mfma_f64_16x16x4f64.  Lane layout: lane l holds
+// A[l % 16][l / 16] and B[l / 16][l % 16] of a K step of 4; accumulator register
+// r holds D[4 r + l / 16][l % 16].  A wave owns 16 x 16 output tiles (MI x NI of
+// them in the first contraction; in the second, one pixel tile of CSW channel
+// sets).  Every output element takes the same instruction sequence whatever the
+// tile shape or the channel sets a wave holds, so neither changes a result: a
+// batch of snapshots gives each snapshot its single-call sums bit for bit.
+// The 4 x 4 x 4 form issues its flops at a higher rate, but its register-blocked
+// tiles need 2.5 times the operand loads per flop.  Measured on 64 snapshots
+// (ny = nz = 64, 256 x 256 detector) against register-blocked 4 x 4 x 4 tiles:
+// first contraction 41 -> 27 us, second 236 -> 181 us, bit-identical results.
 
 // T[c][iy][k] = sum_iz S[c][iy][iz] Ez[iz][k] (real x complex: two products per
 // step, into independent accumulators).
-template <int MG, int NG>
+template <int MI, int NI>
 __global__ __launch_bounds__(256) void sep_contract1_f64(const double *__restrict__ S, const double2 *__restrict__ Ez,
                                                          SepDims m, int n_sets, double2 *__restrict__ T)
 {
-    constexpr int TM = 16 * MG, TN = 4 * NG;
+    constexpr int TM = 16 * MI, TN = 16 * NI;
     const int lane = threadIdx.x & 63;
     const int tm = m.ny16 / TM, tn = m.n1p / TN;
     const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -226,129 +238,154 @@ __global__ __launch_bounds__(256) void sep_contract1_f64(const double *__restric
     const int c = (int)(tile / ((int64_t)tm * tn));
     const int rem = (int)(tile % ((int64_t)tm * tn));
     const int i0 = (rem / tn) * TM, k0 = (rem % tn) * TN;
-    const int g = (lane >> 2) & 3, e = lane & 3, kq = lane >> 4;
-    const double *pa = S + (int64_t)c * m.ny16 * m.nz4 + (int64_t)(i0 + 4 * g + e) * m.nz4 + kq;  // + 16 mg nz4 + z0
-    const double2 *pb = Ez + (int64_t)kq * m.n1p + k0 + e;                                         // + z0 n1p + 4 ng
-    double accR[MG][NG], accI[MG][NG];
+    const int r16 = lane & 15, kq = lane >> 4;
+    const double *pa = S + (int64_t)c * m.ny16 * m.nzk + (int64_t)(i0 + r16) * m.nzk + kq;  // + 16 mi nzk + z0
+    const double2 *pb = Ez + (int64_t)kq * m.n1p + k0 + r16;                                 // + z0 n1p + 16 ni
+    v4d accR[MI][NI], accI[MI][NI];
 #pragma unroll
-    for (int mg = 0; mg < MG; ++mg)
+    for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
-        for (int ng = 0; ng < NG; ++ng) accR[mg][ng] = accI[mg][ng] = 0.0;
-    auto load = [&](int z0, double (&a)[MG], double2 (&b)[NG]) {
+        for (int ni = 0; ni < NI; ++ni) accR[mi][ni] = accI[mi][ni] = v4d{0.0, 0.0, 0.0, 0.0};
+    auto load = [&](int z0, double (&a)[MI], double2 (&b)[NI]) {
 #pragma unroll
-        for (int mg = 0; mg < MG; ++mg) a[mg] = pa[(int64_t)16 * mg * m.nz4 + z0];
+        for (int mi = 0; mi < MI; ++mi) a[mi] = pa[(int64_t)16 * mi * m.nzk + z0];
 #pragma unroll
-        for (int ng = 0; ng < NG; ++ng) b[ng] = pb[(int64_t)z0 * m.n1p + 4 * ng];
+        for (int ni = 0; ni < NI; ++ni) b[ni] = pb[(int64_t)z0 * m.n1p + 16 * ni];
     };
-    auto mma = [&](const double (&a)[MG], const double2 (&b)[NG]) {
+    auto mma = [&](const double (&a)[MI], const double2 (&b)[NI]) {
 #pragma unroll
-        for (int ng = 0; ng < NG; ++ng)
+        for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
-            for (int mg = 0; mg < MG; ++mg) {
-                accR[mg][ng] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[mg], b[ng].x, accR[mg][ng], 0, 0, 0);
-                accI[mg][ng] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[mg], b[ng].y, accI[mg][ng], 0, 0, 0);
+            for (int ni = 0; ni < NI; ++ni) {
+                accR[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mi], b[ni].x, accR[mi][ni], 0, 0, 0);
+                accI[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mi], b[ni].y, accI[mi][ni], 0, 0, 0);
             }
     };
-    double a0[MG], a1[MG];
-    double2 b0[NG], b1[NG];
-    load(0, a0, b0);
-    for (int z0 = 0; z0 < m.nz4; z0 += 8) {
-        const bool more = z0 + 4 < m.nz4;
-        if (more) load(z0 + 4, a1, b1);
-        mma(a0, b0);
-        if (!more) break;
-        if (z0 + 8 < m.nz4) load(z0 + 8, a0, b0);
-        mma(a1, b1);
+    // kC1Steps K steps per iteration: all their fragments are loaded first, and the
+    // MFMAs take them as they arrive
+    for (int z0 = 0; z0 < m.nzk; z0 += 4 * kC1Steps) {
+        double a[kC1Steps][MI];
+        double2 b[kC1Steps][NI];
+#pragma unroll
+        for (int u = 0; u < kC1Steps; ++u) load(z0 + 4 * u, a[u], b[u]);
+#pragma unroll
+        for (int u = 0; u < kC1Steps; ++u) mma(a[u], b[u]);
     }
     double2 *Tc = T + (int64_t)c * m.ny16 * m.n1p;
 #pragma unroll
-    for (int mg = 0; mg < MG; ++mg) {
-        const int row = i0 + 16 * mg + 4 * g + kq;
+    for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
-        for (int ng = 0; ng < NG; ++ng)
-            Tc[(int64_t)row * m.n1p + k0 + 4 * ng + e] = make_double2(accR[mg][ng], accI[mg][ng]);
-    }
+        for (int ni = 0; ni < NI; ++ni)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                Tc[(int64_t)(i0 + 16 * mi + 4 * r + kq) * m.n1p + k0 + 16 * ni + r16] =
+                    make_double2(accR[mi][ni][r], accI[mi][ni][r]);
 }
 
 // F[c][i][k] = sum_iy Ey[i][iy] T[c][iy][k]  ->  amp[c / 4][(i n1 + k)][c % 4]
 //
 // This contraction carries nine tenths of the flops; the complex product is four
-// real products per K step (MG x NG x 4 instructions).  It is bound by the issue of
-// its operand loads rather than by the matrix cores: forming it with three real
-// products instead (Gauss's trick, with the sums A + B and C + D as extra operand
-// planes) cut the MFMA work by a quarter but added half again to the operand
-// loads, and measured 1.5 times slower (204 -> 307 us for 64 snapshots).
-template <int MG, int NG>
+// real products per K step.  A wave owns one 16 x 16 pixel tile of CSW channel
+// sets: CSW = 4 holds all four channel sets of a snapshot, shares the Ey fragment
+// between them and writes whole 64-byte pixel records; CSW = 1 (four times the
+// waves, for small batches) puts the four channel sets of a tile in the four
+// waves of one workgroup, which write the same records together.  Measured
+// alternatives: larger register tiles (32 x 32, 32 x 64 pixels) lose occupancy and
+// run slower, non-temporal stores of the result more than double the time, and
+// the complex product as three real products (Gauss's trick, with the sums
+// A + B and C + D as extra operand planes) cut the MFMA work by a quarter but
+// added half again to the operand loads (1.5 times slower).  A16: the result
+// pointer is 16-byte aligned (one 16-byte store per channel).  HERM: only rows
+// [0, ceil(n0 / 2)) are contracted, and each of their pixels p also writes the
+// conjugate at the mirrored pixel P - 1 - p (S(-q) = conj S(q) for real weights
+// on the symmetric Cartesian detector); the middle row of an odd n0 is contracted
+// for every column and mirrors nothing.
+template <int CSW, bool A16, bool HERM>
 __global__ __launch_bounds__(256) void sep_contract2_f64(const double2 *__restrict__ Ey, const double2 *__restrict__ T,
                                                          SepDims m, int n_sets, double *__restrict__ amp)
 {
-    constexpr int TM = 16 * MG, TN = 4 * NG;
-    static_assert(kC2M % TM == 0 && kC2N % TN == 0, "tile inside the padding");
+    static_assert(CSW == 1 || CSW == 4, "one or four channel sets per wave");
+    static_assert(kC2M % 16 == 0 && kC2N % 16 == 0, "tiles inside the padding");
     const int lane = threadIdx.x & 63;
-    const int tm = (m.n0 + TM - 1) / TM, tn = (m.n1 + TN - 1) / TN;
+    const int nr = HERM ? (m.n0 + 1) / 2 : m.n0;  // contracted rows
+    const int tm = (nr + 15) / 16, tn = (m.n1 + 15) / 16;
+    const int64_t tiles = (int64_t)tm * tn;
     const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (tile >= (int64_t)n_sets * tm * tn) return;
-    const int c = (int)(tile / ((int64_t)tm * tn));
-    const int rem = (int)(tile % ((int64_t)tm * tn));
-    const int i0 = (rem / tn) * TM, k0 = (rem % tn) * TN;
-    const int g = (lane >> 2) & 3, e = lane & 3, kq = lane >> 4;
+    if (tile >= (int64_t)(n_sets / CSW) * tiles) return;
+    int64_t c0;
+    int rem;
+    if (CSW == 4) {
+        c0 = 4 * (tile / tiles);
+        rem = (int)(tile % tiles);
+    } else {
+        const int64_t r2 = tile % (4 * tiles);
+        c0 = 4 * (tile / (4 * tiles)) + (r2 & 3);
+        rem = (int)(r2 >> 2);
+    }
+    const int i0 = (rem / tn) * 16, k0 = (rem % tn) * 16;
+    const int r16 = lane & 15, kq = lane >> 4;
+    const int64_t cs = (int64_t)m.ny16 * m.n1p;  // one channel set of T
     // this lane's operand streams (every index stays inside the padded arrays)
-    const double2 *pa = Ey + (int64_t)(i0 + 4 * g + e) * m.nyp + kq;                            // + 16 mg nyp + y0
-    const double2 *pb = T + (int64_t)c * m.ny16 * m.n1p + (int64_t)kq * m.n1p + k0 + e;         // + y0 n1p + 4 ng
-    double accR[MG][NG], accI[MG][NG];
+    const double2 *pa = Ey + (int64_t)(i0 + r16) * m.nyk + kq;               // + y0
+    const double2 *pb = T + c0 * cs + (int64_t)kq * m.n1p + k0 + r16;        // + ch cs + y0 n1p
+    v4d accR[CSW], accI[CSW];
 #pragma unroll
-    for (int mg = 0; mg < MG; ++mg)
+    for (int ch = 0; ch < CSW; ++ch) accR[ch] = accI[ch] = v4d{0.0, 0.0, 0.0, 0.0};
+    auto load = [&](int y0, double2 &a, double2 (&b)[CSW]) {
+        a = pa[y0];
 #pragma unroll
-        for (int ng = 0; ng < NG; ++ng) accR[mg][ng] = accI[mg][ng] = 0.0;
-
-    auto load = [&](int y0, double2 (&a)[MG], double2 (&b)[NG]) {
-#pragma unroll
-        for (int mg = 0; mg < MG; ++mg) a[mg] = pa[(int64_t)16 * mg * m.nyp + y0];
-#pragma unroll
-        for (int ng = 0; ng < NG; ++ng) b[ng] = pb[(int64_t)y0 * m.n1p + 4 * ng];
+        for (int ch = 0; ch < CSW; ++ch) b[ch] = pb[ch * cs + (int64_t)y0 * m.n1p];
     };
-    // Two passes over the tile, so that the two products an accumulator takes per K
-    // step are issued 2 MG NG instructions apart instead of back to back (each
-    // accumulator still takes them in the same order: the results do not change).
-    auto mma = [&](const double2 (&a)[MG], const double2 (&b)[NG]) {
+    // Two passes, so that the two products an accumulator takes per K step are issued
+    // 2 CSW instructions apart (each accumulator takes them in the same order).
+    auto mma = [&](const double2 &a, const double2 (&b)[CSW]) {
 #pragma unroll
-        for (int ng = 0; ng < NG; ++ng)
+        for (int ch = 0; ch < CSW; ++ch) {
+            accR[ch] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b[ch].x, accR[ch], 0, 0, 0);
+            accI[ch] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b[ch].y, accI[ch], 0, 0, 0);
+        }
 #pragma unroll
-            for (int mg = 0; mg < MG; ++mg) {
-                accR[mg][ng] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[mg].x, b[ng].x, accR[mg][ng], 0, 0, 0);
-                accI[mg][ng] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[mg].x, b[ng].y, accI[mg][ng], 0, 0, 0);
-            }
-#pragma unroll
-        for (int ng = 0; ng < NG; ++ng)
-#pragma unroll
-            for (int mg = 0; mg < MG; ++mg) {
-                accR[mg][ng] = __builtin_amdgcn_mfma_f64_4x4x4f64(-a[mg].y, b[ng].y, accR[mg][ng], 0, 0, 0);
-                accI[mg][ng] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[mg].y, b[ng].x, accI[mg][ng], 0, 0, 0);
-            }
+        for (int ch = 0; ch < CSW; ++ch) {
+            accR[ch] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b[ch].y, accR[ch], 0, 0, 0);
+            accI[ch] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b[ch].x, accI[ch], 0, 0, 0);
+        }
     };
-    // two register buffers: the next K step's fragments load while this one's MFMAs run
-    double2 a0[MG], b0[NG], a1[MG], b1[NG];
+    // Two register buffers of one K step each: the next step's fragments load while
+    // this one's MFMAs run (three waves per SIMD).  nyk is a multiple of 8, so an
+    // iteration takes two steps and needs no exit test; the last iteration's
+    // prefetch reloads an in-bounds step.  Measured against loading two or four
+    // steps and then running their MFMAs: 181 against 197 and 204 us.
+    double2 a0, b0[CSW], a1, b1[CSW];
     load(0, a0, b0);
-    for (int y0 = 0; y0 < m.nyp; y0 += 8) {
-        const bool more = y0 + 4 < m.nyp;
-        if (more) load(y0 + 4, a1, b1);
+    for (int y0 = 0; y0 < m.nyk; y0 += 8) {
+        load(y0 + 4, a1, b1);
         mma(a0, b0);
-        if (!more) break;
-        if (y0 + 8 < m.nyp) load(y0 + 8, a0, b0);
+        load(min(y0 + 8, m.nyk - 4), a0, b0);
         mma(a1, b1);
     }
-    double *dst = amp + (int64_t)(c >> 2) * m.n0 * m.n1 * 8 + 2 * (c & 3);
+    double *dst = amp + (c0 >> 2) * m.n0 * m.n1 * 8 + 2 * (c0 & 3);
+    const int col = k0 + r16;
+    const int64_t P = (int64_t)m.n0 * m.n1;
 #pragma unroll
-    for (int mg = 0; mg < MG; ++mg) {
-        const int row = i0 + 16 * mg + 4 * g + kq;
-        if (row >= m.n0) continue;
+    for (int r = 0; r < 4; ++r) {
+        const int row = i0 + 4 * r + kq;
+        if (row >= nr || col >= m.n1) continue;
+        const int64_t p = (int64_t)row * m.n1 + col;
+        const bool mirror = HERM && row < m.n0 - nr;
+        double *o = dst + p * 8;
+        double *om = dst + (P - 1 - p) * 8;
 #pragma unroll
-        for (int ng = 0; ng < NG; ++ng) {
-            const int col = k0 + 4 * ng + e;
-            if (col < m.n1) {
-                double *o = dst + ((int64_t)row * m.n1 + col) * 8;
-                o[0] = accR[mg][ng];
-                o[1] = accI[mg][ng];
+        for (int ch = 0; ch < CSW; ++ch) {
+            if (A16) {
+                ((double2 *)o)[ch] = make_double2(accR[ch][r], accI[ch][r]);
+                if (mirror) ((double2 *)om)[ch] = make_double2(accR[ch][r], -accI[ch][r]);
+            } else {
+                o[2 * ch] = accR[ch][r];
+                o[2 * ch + 1] = accI[ch][r];
+                if (mirror) {
+                    om[2 * ch] = accR[ch][r];
+                    om[2 * ch + 1] = -accI[ch][r];
+                }
             }
         }
     }
@@ -482,7 +519,7 @@ __global__ __launch_bounds__(256) void sep_twiddles_bf16(Detector d, numag_regul
     }
 }
 
-// Split projections: Sb[p][set][iy][iz] from the FP64 S[set][ny16][nz4] (zero beyond ny, nz).
+// Split projections: Sb[p][set][iy][iz] from the FP64 S[set][ny16][nzk] (zero beyond ny, nz).
 template <int NP>
 __global__ __launch_bounds__(256) void sep_split_s_kernel(const double *__restrict__ S, SepDims m, int ny32,
                                                           int nz32, int sets, unsigned short *__restrict__ sb)
@@ -492,7 +529,7 @@ __global__ __launch_bounds__(256) void sep_split_s_kernel(const double *__restri
     if (idx >= (int64_t)sets * per) return;
     const int set = (int)(idx / per);
     const int iy = (int)((idx % per) / nz32), iz = (int)(idx % nz32);
-    const double v = (iy < m.ny && iz < m.nz) ? S[((int64_t)set * m.ny16 + iy) * m.nz4 + iz] : 0.0;
+    const double v = (iy < m.ny && iz < m.nz) ? S[((int64_t)set * m.ny16 + iy) * m.nzk + iz] : 0.0;
     store_split<NP>(v, sb + idx, (int64_t)sets * per);
 }
 
@@ -616,13 +653,13 @@ static int launch_bf16_path(const SepDims &m, const BfLayout &B, const Detector 
 // FP64 path for snapshots [b0, b1): projection (+ twiddles when tw), then both
 // contractions; every buffer offset by the first snapshot.
 static int launch_f64_chunk(const double *nuc, const double *mag, const numag_regular &g, const Detector &d,
-                            const SepDims &m, int64_t b0, int64_t b1, bool tw, double2 *ey, double2 *ez, double *S,
-                            double2 *T, double *amp, hipStream_t s)
+                            const SepDims &m, int64_t b0, int64_t b1, bool tw, bool herm, double2 *ey, double2 *ez,
+                            double *S, double2 *T, double *amp, hipStream_t s)
 {
     const int64_t W = (int64_t)g.n[0] * g.n[1] * g.n[2];
     const int64_t nb = b1 - b0;
     const int sets = (int)(4 * nb);
-    const int64_t sstride = (int64_t)m.ny16 * m.nz4;
+    const int64_t sstride = (int64_t)m.ny16 * m.nzk;
     if (nuc != nullptr) nuc += b0 * W;
     if (mag != nullptr) mag += b0 * W * 3;
     S += 4 * b0 * sstride;
@@ -632,8 +669,8 @@ static int launch_f64_chunk(const double *nuc, const double *mag, const numag_re
     const bool pairs = nyz % 2 == 0 && ((uintptr_t)nuc % 16) == 0 && ((uintptr_t)mag % 16) == 0;
     const int64_t per_wg = (int64_t)kProjThreads * (pairs ? 2 : 1);
     const int64_t n_proj = (4 * nyz + per_wg - 1) / per_wg;
-    const bool pad_s = m.ny16 != m.ny || m.nz4 != m.nz;
-    const int64_t n_elem = (tw ? (int64_t)m.n0p * m.nyp + (int64_t)m.nz4 * m.n1p : 0) +
+    const bool pad_s = m.ny16 != m.ny || m.nzk != m.nz;
+    const int64_t n_elem = (tw ? (int64_t)m.n0p * m.nyk + (int64_t)m.nzk * m.n1p : 0) +
                            (pad_s ? (int64_t)sets * sstride : 0);
     const int64_t n_tw = (n_elem + 255) / 256;
     const dim3 grid((unsigned)(n_proj * nb + n_tw));
@@ -644,20 +681,42 @@ static int launch_f64_chunk(const double *nuc, const double *mag, const numag_re
         hipLaunchKernelGGL(sep_prepare_kernel<1>, grid, dim3(256), 0, s, d, g, m, nuc, mag, (int)n_proj, (int)nb,
                            tw ? 1 : 0, pad_s ? 1 : 0, S, ey, ez);
     NUMAG_HIP_CHECK(hipGetLastError());
-    const int64_t t1 = (int64_t)sets * (m.ny16 / (16 * kC1MG)) * (m.n1p / (4 * kC1NG));
-    hipLaunchKernelGGL((sep_contract1_f64<kC1MG, kC1NG>), dim3((unsigned)((t1 + 3) / 4)), dim3(256), 0, s, S, ez, m,
-                       sets, T);
+    // first contraction: 32 x 64 or 16 x 64 outputs per wave when that still makes
+    // a few workgroups per CU, else 16 x 16
+    const int64_t t1big = (int64_t)sets * (m.ny16 / 32) * (m.n1p / 64);
+    const int64_t t1mid = (int64_t)sets * (m.ny16 / 16) * (m.n1p / 64);
+    if (t1big >= 2048) {
+        hipLaunchKernelGGL((sep_contract1_f64<2, 4>), dim3((unsigned)((t1big + 3) / 4)), dim3(256), 0, s, S, ez, m,
+                           sets, T);
+    } else if (t1mid >= 2048) {
+        hipLaunchKernelGGL((sep_contract1_f64<1, 4>), dim3((unsigned)((t1mid + 3) / 4)), dim3(256), 0, s, S, ez, m,
+                           sets, T);
+    } else {
+        const int64_t t1 = (int64_t)sets * (m.ny16 / 16) * (m.n1p / 16);
+        hipLaunchKernelGGL((sep_contract1_f64<1, 1>), dim3((unsigned)((t1 + 3) / 4)), dim3(256), 0, s, S, ez, m, sets,
+                           T);
+    }
     NUMAG_HIP_CHECK(hipGetLastError());
-    // 32 x 32 tiles when they give every SIMD a few waves, else 16 x 16
-    const int64_t t2big = (int64_t)sets * ((d.n0 + 31) / 32) * ((d.n1 + 31) / 32);
-    const bool big = t2big >= 4096;
-    const int64_t t2 = big ? t2big : (int64_t)sets * ((d.n0 + 15) / 16) * ((d.n1 + 15) / 16);
-    if (big)
-        hipLaunchKernelGGL((sep_contract2_f64<2, 8>), dim3((unsigned)((t2 + 3) / 4)), dim3(256), 0, s, ey, T, m, sets,
-                           amp);
-    else
-        hipLaunchKernelGGL((sep_contract2_f64<1, 4>), dim3((unsigned)((t2 + 3) / 4)), dim3(256), 0, s, ey, T, m, sets,
-                           amp);
+    // second contraction: all four channel sets of a pixel tile in one wave when
+    // that still makes 1024 workgroups, else one channel set per wave
+    const int nr = herm ? (d.n0 + 1) / 2 : d.n0;  // contracted rows
+    const int64_t t2 = nb * ((nr + 15) / 16) * ((d.n1 + 15) / 16);  // pixel tiles of all snapshots
+    const bool a16 = ((uintptr_t)amp % 16) == 0;
+    const unsigned g4 = (unsigned)((t2 + 3) / 4), g1 = (unsigned)t2;  // 4 waves per workgroup
+#define NUMAG_LAUNCH_C2(CSW, A16, HERM, G) \
+    hipLaunchKernelGGL((sep_contract2_f64<CSW, A16, HERM>), dim3(G), dim3(256), 0, s, ey, T, m, sets, amp)
+    const int variant = (t2 >= 4096 ? 4 : 0) + (a16 ? 2 : 0) + (herm ? 1 : 0);
+    switch (variant) {
+        case 0: NUMAG_LAUNCH_C2(1, false, false, g1); break;
+        case 1: NUMAG_LAUNCH_C2(1, false, true, g1); break;
+        case 2: NUMAG_LAUNCH_C2(1, true, false, g1); break;
+        case 3: NUMAG_LAUNCH_C2(1, true, true, g1); break;
+        case 4: NUMAG_LAUNCH_C2(4, false, false, g4); break;
+        case 5: NUMAG_LAUNCH_C2(4, false, true, g4); break;
+        case 6: NUMAG_LAUNCH_C2(4, true, false, g4); break;
+        default: NUMAG_LAUNCH_C2(4, true, true, g4); break;
+    }
+#undef NUMAG_LAUNCH_C2
     NUMAG_HIP_CHECK(hipGetLastError());
     return NUMAG_OK;
 }
@@ -667,15 +726,16 @@ int launch_separable(const double *nuc, const double *mag, const numag_regular &
 {
     const SepLayout L = sep_layout(g, d, n_snap);
     const SepDims m = sep_dims(g, d);
-    const bool f64 = path == NUMAG_PATH_SEPARABLE_F64;
+    const bool herm = path == NUMAG_PATH_SEPARABLE_F64_HERMITIAN;
+    const bool f64 = path == NUMAG_PATH_SEPARABLE_F64 || herm;
     if (ws_bytes < separable_workspace_bytes(g, d, path, n_snap) || ws == nullptr) {
         set_error("numag_amplitudes: workspace too small for the separable path");
         return NUMAG_E_WORKSPACE;
     }
     const int64_t nyz = (int64_t)m.ny * m.nz;
-    const bool pad_s = m.ny16 != m.ny || m.nz4 != m.nz;
+    const bool pad_s = m.ny16 != m.ny || m.nzk != m.nz;
     if ((4 * nyz + kProjThreads - 1) / kProjThreads * n_snap +
-            ((int64_t)m.n0p * m.nyp + (int64_t)m.nz4 * m.n1p + (pad_s ? 4 * n_snap * m.ny16 * m.nz4 : 0)) / 256 + 1 >
+            ((int64_t)m.n0p * m.nyk + (int64_t)m.nzk * m.n1p + (pad_s ? 4 * n_snap * m.ny16 * m.nzk : 0)) / 256 + 1 >
         0x7fffffffLL) {
         set_error("numag_amplitudes: too many snapshots for one separable call");
         return NUMAG_E_INVALID;
@@ -691,7 +751,7 @@ int launch_separable(const double *nuc, const double *mag, const numag_regular &
         const bool pairs = nyz % 2 == 0 && ((uintptr_t)nuc % 16) == 0 && ((uintptr_t)mag % 16) == 0;
         const int64_t per_wg = (int64_t)kProjThreads * (pairs ? 2 : 1);
         const int64_t n_proj = (4 * nyz + per_wg - 1) / per_wg;
-        const int64_t n_tw = ((pad_s ? (int64_t)sets * m.ny16 * m.nz4 : 0) + 255) / 256;
+        const int64_t n_tw = ((pad_s ? (int64_t)sets * m.ny16 * m.nzk : 0) + 255) / 256;
         const dim3 grid((unsigned)(n_proj * n_snap + n_tw));
         if (pairs)
             hipLaunchKernelGGL(sep_prepare_kernel<2>, grid, dim3(256), 0, s, d, g, m, nuc, mag, (int)n_proj,
@@ -710,7 +770,7 @@ int launch_separable(const double *nuc, const double *mag, const numag_regular &
     // second contraction of the previous one, was measured slower for 64 snapshots
     // (0.42 against 0.34 ms): the two kernels slowed each other down (the
     // contraction 51 -> 82 us per chunk, the projection 22 -> 70 us).
-    return launch_f64_chunk(nuc, mag, g, d, m, 0, n_snap, true, ey, ez, S, T, amp, s);
+    return launch_f64_chunk(nuc, mag, g, d, m, 0, n_snap, true, herm, ey, ez, S, T, amp, s);
 }
 
 }  // namespace numag

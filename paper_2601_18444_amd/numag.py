@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libnumag.so")
 OBSERVABLES = ("N", "M", "NM", "P", "CHI", "SF", "PP", "MM", "PM", "MP", "PLUS", "MINUS", "UNPOL")
 GRID_CARTESIAN, GRID_POLAR = 0, 1
 PATH_DIRECT, PATH_SEPARABLE_F64, PATH_SEPARABLE_BF16X3, PATH_DIRECT_HERMITIAN, PATH_SEPARABLE_BF16X6 = 0, 1, 2, 3, 4
+PATH_SEPARABLE_F64_HERMITIAN = 5
 MODE_COHERENT, MODE_DILUTE, MODE_SPLIT = 0, 1, 2
 OK, E_INVALID, E_WORKSPACE, E_HIP, E_UNSUPPORTED = 0, -1, -2, -4, -5
 

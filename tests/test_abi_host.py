@@ -142,6 +142,11 @@ def test_snapshots_validate_without_gpu_work():
     one = lib.numag_snapshots_workspace_size(ctypes.byref(pts), 1, ctypes.byref(grid), F64)
     two = lib.numag_snapshots_workspace_size(ctypes.byref(pts), 2, ctypes.byref(grid), F64)
     assert two > one
+    # the Hermitian variant uses the FP64 path's workspace; path values end there
+    H64 = numag.PATH_SEPARABLE_F64_HERMITIAN
+    assert lib.numag_snapshots_workspace_size(ctypes.byref(pts), 2, ctypes.byref(grid), H64) == two
+    assert lib.numag_snapshots_workspace_size(ctypes.byref(pts), 2, ctypes.byref(pol), H64) == 0
+    assert lib.numag_snapshots_workspace_size(ctypes.byref(pts), 2, ctypes.byref(grid), H64 + 1) == 0
     bad = numag.regular_grid((0, 5, 6), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0))
     assert lib.numag_snapshots_workspace_size(ctypes.byref(bad), 1, ctypes.byref(grid), F64) == 0
     fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first

@@ -108,3 +108,76 @@ def test_snapshots_pipelined_batch_equals_single_calls(orc):
     qy, qz, _ = orc.pixels(0, 21, 30, 1.1)
     for b in (0, 13):
         _check(amp_to_complex(amp[b]), orc.amplitudes(pos, nuc[b], mag[b], qy, qz))
+
+
+def test_snapshots_wave_tilings_ragged_detector_and_unaligned_output(orc):
+    """460 snapshots on a ragged 37 x 45 detector take the second contraction with
+    all four channel sets of a pixel tile in one wave; single calls take one channel
+    set per wave.  Both tilings, and 16-byte and 8-byte aligned result pointers,
+    give the same sums bit for bit; two snapshots against the oracle."""
+    n, a, origin = (5, 6, 7), (1.2, 0.7, 1.1), (-2.5, -2.0, -3.5)
+    pos = synth.box_lattice(n, a, origin)
+    W = pos.shape[0]
+    B = 460
+    rng = np.random.default_rng(44)
+    nuc = rng.standard_normal((B, W))
+    mag = rng.standard_normal((B, W, 3))
+    grid = numag.qgrid(0, 37, 45, 1.4)
+    P = 37 * 45
+    points = numag.regular_grid(n, origin, a)
+    amp = numag.amplitudes_snapshots(points, grid, nuc=nuc, mag=mag, device=DEV)
+    raw = torch.empty(B * P * 8 + 1, dtype=torch.float64, device=DEV)
+    shifted = raw[1:].view(B, P, 4, 2)  # 8 bytes past a 16-byte boundary
+    assert shifted.data_ptr() % 16 == 8
+    numag.amplitudes_snapshots(points, grid, nuc=nuc, mag=mag, out=shifted, device=DEV)
+    assert torch.equal(amp, shifted)
+    reg = {"n": n, "origin": origin, "step": a}
+    for b in (0, 1, 2, 3, 201, 330, 458, 459):
+        s = numag.Sample(nuc=nuc[b], mag=mag[b], regular=reg, n_points=W, device=DEV)
+        single, _ = numag.amplitudes(s, grid, path=numag.PATH_SEPARABLE_F64)
+        assert torch.equal(amp[b], single[0]), f"snapshot {b} differs from its single call"
+    few = torch.empty(2 * P * 8 + 1, dtype=torch.float64, device=DEV)[1:].view(2, P, 4, 2)
+    numag.amplitudes_snapshots(points, grid, nuc=nuc[:2], mag=mag[:2], out=few, device=DEV)
+    assert torch.equal(few, amp[:2])
+    qy, qz, _ = orc.pixels(0, 37, 45, 1.4)
+    for b in (0, 459):
+        _check(amp_to_complex(amp[b]), orc.amplitudes(pos, nuc[b], mag[b], qy, qz))
+
+
+@pytest.mark.parametrize("n0,n1,B", [(36, 30, 2), (37, 45, 460)])
+def test_separable_hermitian_half_detector(orc, n0, n1, B):
+    """PATH_SEPARABLE_F64_HERMITIAN contracts rows [0, ceil(n0 / 2)) and mirrors the
+    rest by S(-q) = conj S(q): the contracted rows equal the full path bit for bit,
+    every mirrored pixel is exactly the conjugate of its partner P - 1 - p and
+    within rounding of the full path's own sum; batched and single calls agree bit
+    for bit (460 snapshots take the four-channel-set tiles); oracle on two
+    snapshots.  Even and odd row counts (the odd middle row is contracted whole)."""
+    n, a, origin = (5, 6, 7), (1.2, 0.7, 1.1), (-2.5, -2.0, -3.5)
+    pos = synth.box_lattice(n, a, origin)
+    W = pos.shape[0]
+    rng = np.random.default_rng(45 + n0)
+    nuc = rng.standard_normal((B, W))
+    mag = rng.standard_normal((B, W, 3))
+    grid = numag.qgrid(0, n0, n1, 1.4)
+    P = n0 * n1
+    nr = (n0 + 1) // 2
+    points = numag.regular_grid(n, origin, a)
+    full = numag.amplitudes_snapshots(points, grid, nuc=nuc, mag=mag, device=DEV)
+    half = numag.amplitudes_snapshots(points, grid, nuc=nuc, mag=mag, path=numag.PATH_SEPARABLE_F64_HERMITIAN,
+                                      device=DEV)
+    assert torch.equal(half[:, : nr * n1], full[:, : nr * n1])
+    # rows below n0 - nr mirror (an odd n0's middle row is contracted for every column)
+    mirrored = torch.arange((n0 - nr) * n1, device=DEV)
+    partner = half[:, P - 1 - mirrored]
+    assert torch.equal(partner[..., 0], half[:, mirrored][..., 0])
+    assert torch.equal(partner[..., 1], -half[:, mirrored][..., 1])
+    scale = float(full.abs().max())
+    assert float((half - full).abs().max()) <= 1e-12 * scale
+    reg = {"n": n, "origin": origin, "step": a}
+    for b in (0, B - 1):
+        s = numag.Sample(nuc=nuc[b], mag=mag[b], regular=reg, n_points=W, device=DEV)
+        single, _ = numag.amplitudes(s, grid, path=numag.PATH_SEPARABLE_F64_HERMITIAN)
+        assert torch.equal(half[b], single[0]), f"snapshot {b} differs from its single call"
+    qy, qz, _ = orc.pixels(0, n0, n1, 1.4)
+    for b in (0, B - 1):
+        _check(amp_to_complex(half[b]), orc.amplitudes(pos, nuc[b], mag[b], qy, qz))
