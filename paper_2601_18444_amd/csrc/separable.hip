@@ -286,12 +286,18 @@ __global__ __launch_bounds__(256) void sep_contract1_f64(const double *__restric
 //
 // This contraction carries nine tenths of the flops; the complex product is four
 // real products per K step.  A wave owns one 16 x 16 pixel tile of CSW channel
-// sets: CSW = 4 holds all four channel sets of a snapshot, shares the Ey fragment
-// between them and writes whole 64-byte pixel records; CSW = 1 (four times the
-// waves, for small batches) puts the four channel sets of a tile in the four
-// waves of one workgroup, which write the same records together.  Measured
-// alternatives: larger register tiles (32 x 32, 32 x 64 pixels) lose occupancy and
-// run slower, non-temporal stores of the result more than double the time, and
+// sets: CSW = 4 holds all four channel sets of a snapshot and shares the Ey
+// fragment between them; CSW = 1 (four times the waves, for small batches) puts
+// the four channel sets of a tile in the four waves of one workgroup, which write
+// the same records together.  With CSW = 4 the result leaves through LDS: a lane
+// holds four rows of one column, so a direct store instruction would scatter 16
+// bytes into each of 64 pixel records; staged by rows, every store instruction
+// writes 16 whole records (1 KB) of one row (170 against 190 us for 64 snapshots;
+// 123 against 154 us on the Hermitian half).  Measured alternatives: larger
+// register tiles (32 x 32, 32 x 64 pixels) lose occupancy and run slower, a
+// deeper prefetch ring (four one-step buffers) gains without LDS stores but loses
+// with them, a persistent grid-stride loop over tiles gains nothing, non-temporal
+// stores of the result more than double the time, and
 // the complex product as three real products (Gauss's trick, with the sums
 // A + B and C + D as extra operand planes) cut the MFMA work by a quarter but
 // added half again to the operand loads (1.5 times slower).  A16: the result
@@ -310,8 +316,11 @@ __global__ __launch_bounds__(256) void sep_contract2_f64(const double2 *__restri
     const int nr = HERM ? (m.n0 + 1) / 2 : m.n0;  // contracted rows
     const int tm = (nr + 15) / 16, tn = (m.n1 + 15) / 16;
     const int64_t tiles = (int64_t)tm * tn;
-    const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (tile >= (int64_t)(n_sets / CSW) * tiles) return;
+    // a wave past the last tile works on tile 0 and stores nothing (the LDS store
+    // path has workgroup barriers)
+    const int64_t tile_w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const bool active = tile_w < (int64_t)(n_sets / CSW) * tiles;
+    const int64_t tile = active ? tile_w : 0;
     int64_t c0;
     int rem;
     if (CSW == 4) {
@@ -363,9 +372,51 @@ __global__ __launch_bounds__(256) void sep_contract2_f64(const double2 *__restri
         load(min(y0 + 8, m.nyk - 4), a0, b0);
         mma(a1, b1);
     }
-    double *dst = amp + (c0 >> 2) * m.n0 * m.n1 * 8 + 2 * (c0 & 3);
     const int col = k0 + r16;
     const int64_t P = (int64_t)m.n0 * m.n1;
+    if (CSW == 4) {
+        __shared__ double2 stage[4][4][16][4];  // [wave][row of the group][column][channel]
+        const int w = threadIdx.x >> 6;
+        const int px = lane >> 2, chl = lane & 3;  // the record part this lane stores
+        double *dst = amp + (c0 >> 2) * P * 8 + 2 * chl;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+#pragma unroll
+            for (int ch = 0; ch < CSW; ++ch) stage[w][kq][r16][ch] = make_double2(accR[ch][r], accI[ch][r]);
+            __syncthreads();
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int row = i0 + 4 * r + s;
+                if (!active || row >= nr) continue;
+                if (k0 + px < m.n1) {
+                    const double2 v = stage[w][s][px][chl];
+                    double *o = dst + ((int64_t)row * m.n1 + k0 + px) * 8;
+                    if (A16) {
+                        *(double2 *)o = v;
+                    } else {
+                        o[0] = v.x;
+                        o[1] = v.y;
+                    }
+                }
+                // mirrored pixels of this row segment, P - 1 - p, ascending in px
+                const int cm = k0 + 15 - px;
+                if (HERM && row < m.n0 - nr && cm < m.n1) {
+                    const double2 v = stage[w][s][15 - px][chl];
+                    double *o = dst + (P - 1 - ((int64_t)row * m.n1 + cm)) * 8;
+                    if (A16) {
+                        *(double2 *)o = make_double2(v.x, -v.y);
+                    } else {
+                        o[0] = v.x;
+                        o[1] = -v.y;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        return;
+    }
+    if (!active) return;
+    double *dst = amp + (c0 >> 2) * P * 8 + 2 * (c0 & 3);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int row = i0 + 4 * r + kq;
@@ -374,18 +425,15 @@ __global__ __launch_bounds__(256) void sep_contract2_f64(const double2 *__restri
         const bool mirror = HERM && row < m.n0 - nr;
         double *o = dst + p * 8;
         double *om = dst + (P - 1 - p) * 8;
-#pragma unroll
-        for (int ch = 0; ch < CSW; ++ch) {
-            if (A16) {
-                ((double2 *)o)[ch] = make_double2(accR[ch][r], accI[ch][r]);
-                if (mirror) ((double2 *)om)[ch] = make_double2(accR[ch][r], -accI[ch][r]);
-            } else {
-                o[2 * ch] = accR[ch][r];
-                o[2 * ch + 1] = accI[ch][r];
-                if (mirror) {
-                    om[2 * ch] = accR[ch][r];
-                    om[2 * ch + 1] = -accI[ch][r];
-                }
+        if (A16) {
+            ((double2 *)o)[0] = make_double2(accR[0][r], accI[0][r]);
+            if (mirror) ((double2 *)om)[0] = make_double2(accR[0][r], -accI[0][r]);
+        } else {
+            o[0] = accR[0][r];
+            o[1] = accI[0][r];
+            if (mirror) {
+                om[0] = accR[0][r];
+                om[1] = -accI[0][r];
             }
         }
     }
