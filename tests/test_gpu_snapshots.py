@@ -181,3 +181,28 @@ def test_separable_hermitian_half_detector(orc, n0, n1, B):
     qy, qz, _ = orc.pixels(0, n0, n1, 1.4)
     for b in (0, B - 1):
         _check(amp_to_complex(half[b]), orc.amplitudes(pos, nuc[b], mag[b], qy, qz))
+
+
+@pytest.mark.parametrize("n,n0,n1", [((1, 1, 1), 1, 1), ((3, 1, 5), 2, 7), ((2, 5, 1), 5, 1), ((4, 3, 2), 1, 33),
+                                     ((3, 17, 33), 2, 2), ((2, 70, 9), 19, 16)])
+def test_separable_degenerate_shapes(orc, n, n0, n1):
+    """Separable paths on single cells, single grid rows or columns, 1-pixel, 1-row and
+    1-column detectors, and a grid deeper than one 64-row contraction: the FP64 path
+    against the oracle, the Hermitian variant against the FP64 path (rows it
+    contracts bit for bit, the rest within rounding)."""
+    a, origin = (0.9, 1.1, 0.8), (-1.0, -2.0, -3.0)
+    pos = synth.box_lattice(n, a, origin)
+    W = pos.shape[0]
+    rng = np.random.default_rng(60 + n0 * n1)
+    nuc = rng.standard_normal(W)
+    mag = rng.standard_normal((W, 3))
+    grid = numag.qgrid(0, n0, n1, 1.3)
+    s = numag.Sample(nuc=nuc, mag=mag, regular={"n": n, "origin": origin, "step": a}, n_points=W, device=DEV)
+    full, _ = numag.amplitudes(s, grid, path=numag.PATH_SEPARABLE_F64)
+    half, _ = numag.amplitudes(s, grid, path=numag.PATH_SEPARABLE_F64_HERMITIAN)
+    qy, qz, _ = orc.pixels(0, n0, n1, 1.3)
+    _check(amp_to_complex(full[0]), orc.amplitudes(pos, nuc, mag, qy, qz))
+    nr = (n0 + 1) // 2
+    assert torch.equal(half[0, : nr * n1], full[0, : nr * n1])
+    scale = max(float(full.abs().max()), 1e-300)
+    assert float((half - full).abs().max()) <= 1e-12 * scale
