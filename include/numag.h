@@ -182,8 +182,9 @@ size_t numag_workspace_size(const numag_sample *sample, int64_t n_rot, const num
  *             spec_per_object != 0 (one matrix per object, averaged over the
  *             rotations), else 1 (summed over objects).  NULL in COHERENT mode.
  *   path      NUMAG_PATH_*; the separable paths need sample->regular, rot NULL,
- *             K = 1, a Cartesian detector and COHERENT mode; the Hermitian
- *             path needs an even n_theta on a polar detector.
+ *             K = 1, a Cartesian detector and COHERENT mode;
+ *             NUMAG_PATH_DIRECT_HERMITIAN needs an even n_theta on a polar
+ *             detector.
  *   mode      DILUTE and SPLIT need explicit positions (NUMAG_E_UNSUPPORTED for
  *             a regular-grid sample); SPLIT takes one rotation.  Both run on
  *             either detector kind as one persistent launch over (object group,
@@ -272,13 +273,15 @@ void numag_plan_destroy(numag_plan *plan);
  * Loop mode (Sec. 3.1 loop modes; Sec. 3.2: one real-space data set per field,
  * temperature or time value): the raw sums of n_snap weight snapshots given on
  * one regular grid, unrotated, one object, on a Cartesian detector, by a
- * separable path (NUMAG_PATH_SEPARABLE_F64 or _BF16X3) in one batched call.
+ * separable path (NUMAG_PATH_SEPARABLE_F64, _F64_HERMITIAN, _BF16X3 or _BF16X6) in
+ * one batched call.
  *   points    HOST regular grid of the W = n[0] n[1] n[2] points (as numag_sample.regular)
  *   nuc       [n_snap][W] or NULL (channel off);  mag [n_snap][W][3] or NULL
  *   amp_out   [n_snap][P][4] complex: snapshot b equals numag_amplitudes of
  *             snapshot b alone on the same path.
  *   workspace at least numag_snapshots_workspace_size() bytes (it grows with
- *             n_snap: 4 n_snap (ny nz + 2 ny n1) doubles plus the twiddles).
+ *             n_snap: 4 n_snap (ny nz + 2 ny n1) doubles plus the twiddles, each
+ *             dimension padded to the matrix-core tiles).
  * Returns NUMAG_E_INVALID for n_snap < 1, a non-separable path, a polar
  * detector or a bad grid; numag_snapshots_workspace_size returns 0 then.
  */
