@@ -159,11 +159,14 @@ _ws_cache: dict = {}
 
 
 def workspace(nbytes: int, device) -> torch.Tensor:
-    """A cached device workspace of at least nbytes (reused across calls)."""
-    key = str(torch.device(device))
+    """A cached device workspace of at least nbytes, one per (device, stream): calls
+    on one stream run in order and may share it, calls on different streams may
+    overlap and must not."""
+    dev = torch.device(device)
+    key = (str(dev), torch.cuda.current_stream(dev).cuda_stream)
     buf = _ws_cache.get(key)
     if buf is None or buf.numel() < nbytes:
-        buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+        buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=dev)
         _ws_cache[key] = buf
     return buf
 

@@ -206,3 +206,30 @@ def test_separable_degenerate_shapes(orc, n, n0, n1):
     assert torch.equal(half[0, : nr * n1], full[0, : nr * n1])
     scale = max(float(full.abs().max()), 1e-300)
     assert float((half - full).abs().max()) <= 1e-12 * scale
+
+
+def test_concurrent_streams_use_separate_workspaces():
+    """Calls on two streams may overlap: the binding keeps one workspace per stream,
+    so chunks of a batch computed alternately on two streams equal one batched call
+    bit for bit (with a single shared workspace they raced and did not)."""
+    n, a, origin = (8, 24, 20), (1.0, 0.9, 1.1), (-4.0, -10.0, -9.0)
+    W = n[0] * n[1] * n[2]
+    B = 16
+    rng = np.random.default_rng(70)
+    nuc = torch.as_tensor(rng.standard_normal((B, W)), device=DEV)
+    mag = torch.as_tensor(rng.standard_normal((B, W, 3)), device=DEV)
+    grid = numag.qgrid(0, 96, 80, 1.2)
+    points = numag.regular_grid(n, origin, a)
+    ref = numag.amplitudes_snapshots(points, grid, nuc=nuc, mag=mag, device=DEV)
+    out = torch.full_like(ref, -1.0)
+    main = torch.cuda.current_stream()
+    side = torch.cuda.Stream()
+    side.wait_stream(main)
+    torch.cuda.synchronize()
+    for k in range(4):
+        with torch.cuda.stream(main if k % 2 == 0 else side):
+            sl = slice(4 * k, 4 * k + 4)
+            numag.amplitudes_snapshots(points, grid, nuc=nuc[sl], mag=mag[sl], out=out[sl], device=DEV)
+    main.wait_stream(side)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
