@@ -297,10 +297,10 @@ __global__ __launch_bounds__(256) void sep_contract1_f64(const double *__restric
 // register tiles (32 x 32, 32 x 64 pixels) lose occupancy and run slower, a
 // deeper prefetch ring (four one-step buffers) gains without LDS stores but loses
 // with them, a persistent grid-stride loop over tiles gains nothing, non-temporal
-// stores of the result more than double the time, and
-// the complex product as three real products (Gauss's trick, with the sums
-// A + B and C + D as extra operand planes) cut the MFMA work by a quarter but
-// added half again to the operand loads (1.5 times slower).  A16: the result
+// stores of the result more than double the time, and the complex product as
+// three real products (Gauss's trick, with the sums A + B and C + D as extra
+// operand planes) cut the MFMA work by a quarter but added half again to the
+// operand loads (1.5 times slower, with the earlier tiles).  A16: the result
 // pointer is 16-byte aligned (one 16-byte store per channel).  HERM: only rows
 // [0, ceil(n0 / 2)) are contracted, and each of their pixels p also writes the
 // conjugate at the mirrored pixel P - 1 - p (S(-q) = conj S(q) for real weights

@@ -354,7 +354,9 @@ def amplitudes_snapshots(points: Regular, grid: QGrid, nuc=None, mag=None, path=
 class Plan:
     """numag_plan_*: an object-mode (DILUTE / SPLIT) plan of a sample's object
     offsets and a set of rotations, uploaded once into its own workspace; calls
-    then enqueue kernels only.  The sample's device arrays are read at call time."""
+    then enqueue kernels only.  The sample's device arrays are read at call time.
+    Calls that may overlap (on different streams) each need a workspace of their
+    own: upload(ws) into it and pass ws= to the call."""
 
     def __init__(self, sample: Sample, grid: QGrid, rotations=None, mode: int = MODE_DILUTE,
                  spec_per_object: bool = True, path: int = PATH_DIRECT):
