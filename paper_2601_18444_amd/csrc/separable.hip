@@ -97,7 +97,7 @@ size_t separable_workspace_bytes(const numag_regular &g, const Detector &d, int 
     return L.s + bf_bytes(g, d, path, n_snap);
 }
 
-constexpr int kProjThreads = 64;  // column groups per projection workgroup
+constexpr int kProjThreads = 64;  // columns per projection workgroup
 constexpr int kProjSlices = 4;    // x slices per column (one thread each)
 constexpr int kProjUnroll = 8;    // loads in flight per thread
 
@@ -105,47 +105,32 @@ constexpr int kProjUnroll = 8;    // loads in flight per thread
 // Workgroups [0, n_proj * n_snap): projections (all paths).  Snapshot b's weights
 // are two row-major matrices over x, nuc [nx][nyz] and mag [nx][3 nyz]; their
 // column sums over x are the projections (column m of mag is component m % 3 of
-// cell m / 3).  A workgroup owns 64 CPT consecutive columns of the 4 nyz (nuc
-// first, then mag), CPT = 2 adjacent columns per thread (one 16-byte load) when
-// nyz is even and the weights are 16-byte aligned, else 1; x is split into 4
-// slices summed by 4 threads in x order, the slices added in a fixed order
-// through LDS (the same order for either CPT).  Output S[4 b + c][iy][iz].
+// cell m / 3).  A workgroup owns 64 consecutive columns of the 4 nyz (nuc first,
+// then mag), one per thread of a slice; x is split into 4 slices summed by 4
+// threads in x order, the slices added in a fixed order through LDS.  Output
+// S[4 b + c][iy][iz].
 // The remaining workgroups: twiddles Ey[i][iy] = exp(-i q_y(i) y_iy) and
 // Ez[iz][k] = exp(-i q_z(k) z_iz), zeros in the padding, and zeros in the
 // padding of S.
-// The weights are read once: non-temporal loads (measured on a 537 MB column-sum
-// pattern: 6.9 TB/s against 6.1 TB/s with ordinary loads).
-typedef double v2d __attribute__((ext_vector_type(2)));
-
-template <int CPT>
-__device__ __forceinline__ void project_columns(const double *__restrict__ src, int64_t stride, int nx, int slice,
-                                                double (&acc)[CPT])
+// The weights are read once, with 8-byte non-temporal loads: measured on the
+// 537 MB of 64 snapshots of a 64^3 grid in this layout, 77 us (7.0 TB/s) against
+// 82 us with 16-byte loads of two adjacent columns per thread, and 88 us with
+// ordinary loads; 2 or 8 slices, or 16 loads in flight, were no faster.
+__device__ __forceinline__ double project_column(const double *__restrict__ src, int64_t stride, int nx, int slice)
 {
+    double acc = 0.0;
     int ix = slice;
     for (; ix + (kProjUnroll - 1) * kProjSlices < nx; ix += kProjUnroll * kProjSlices) {
-        double v[kProjUnroll][CPT];
+        double v[kProjUnroll];
 #pragma unroll
-        for (int u = 0; u < kProjUnroll; ++u) {
-            const double *q = src + (int64_t)(ix + u * kProjSlices) * stride;
-            if (CPT == 2) {
-                const v2d t = __builtin_nontemporal_load((const v2d *)q);
-                v[u][0] = t.x;
-                v[u][CPT - 1] = t.y;
-            } else {
-                v[u][0] = __builtin_nontemporal_load(q);
-            }
-        }
+        for (int u = 0; u < kProjUnroll; ++u) v[u] = __builtin_nontemporal_load(src + (int64_t)(ix + u * kProjSlices) * stride);
 #pragma unroll
-        for (int u = 0; u < kProjUnroll; ++u)
-#pragma unroll
-            for (int k = 0; k < CPT; ++k) acc[k] += v[u][k];
+        for (int u = 0; u < kProjUnroll; ++u) acc += v[u];
     }
-    for (; ix < nx; ix += kProjSlices)
-#pragma unroll
-        for (int k = 0; k < CPT; ++k) acc[k] += src[(int64_t)ix * stride + k];
+    for (; ix < nx; ix += kProjSlices) acc += src[(int64_t)ix * stride];
+    return acc;
 }
 
-template <int CPT>
 __global__ __launch_bounds__(256) void sep_prepare_kernel(Detector d, numag_regular g, SepDims m,
                                                           const double *__restrict__ nuc,
                                                           const double *__restrict__ mag, int n_proj, int n_snap,
@@ -156,27 +141,20 @@ __global__ __launch_bounds__(256) void sep_prepare_kernel(Detector d, numag_regu
     const int64_t W = (int64_t)g.n[0] * nyz;
     const int64_t sstride = (int64_t)m.ny16 * m.nzk;  // one channel set of S
     if ((int64_t)blockIdx.x < (int64_t)n_proj * n_snap) {
-        __shared__ double part[kProjSlices][kProjThreads * CPT];
+        __shared__ double part[kProjSlices][kProjThreads];
         const int b = (int)(blockIdx.x / n_proj);
         const int col = threadIdx.x % kProjThreads, slice = threadIdx.x / kProjThreads;
-        // first of this thread's CPT columns, in [0, 4 nyz); with CPT = 2, nyz is even,
-        // so both columns lie in the same matrix
-        const int64_t mcol = ((int64_t)(blockIdx.x % n_proj) * kProjThreads + col) * CPT;
+        const int64_t mcol = (int64_t)(blockIdx.x % n_proj) * kProjThreads + col;  // in [0, 4 nyz)
         const bool is_nuc = mcol < nyz;
         const double *src = is_nuc ? (nuc != nullptr ? nuc + (int64_t)b * W + mcol : nullptr)
                                    : (mag != nullptr && mcol < 4 * nyz ? mag + (int64_t)b * W * 3 + (mcol - nyz)
                                                                        : nullptr);
-        double acc[CPT];
-#pragma unroll
-        for (int k = 0; k < CPT; ++k) acc[k] = 0.0;
-        if (src != nullptr) project_columns<CPT>(src, is_nuc ? nyz : 3 * nyz, g.n[0], slice, acc);
-#pragma unroll
-        for (int k = 0; k < CPT; ++k) part[slice][col * CPT + k] = acc[k];
+        part[slice][col] = src != nullptr ? project_column(src, is_nuc ? nyz : 3 * nyz, g.n[0], slice) : 0.0;
         __syncthreads();
-        // thread t < 64 CPT: column t of the workgroup, slices added in order
+        // thread t < 64: column t of the workgroup, slices added in order
         const int t = threadIdx.x;
-        const int64_t mc = (int64_t)(blockIdx.x % n_proj) * kProjThreads * CPT + t;
-        if (t < kProjThreads * CPT && mc < 4 * nyz) {
+        const int64_t mc = (int64_t)(blockIdx.x % n_proj) * kProjThreads + t;
+        if (t < kProjThreads && mc < 4 * nyz) {
             double v = 0.0;
             for (int sl = 0; sl < kProjSlices; ++sl) v += part[sl][t];
             const bool nc = mc < nyz;
@@ -714,20 +692,13 @@ static int launch_f64_chunk(const double *nuc, const double *mag, const numag_re
     T += 4 * b0 * (int64_t)m.ny16 * m.n1p;
     amp += b0 * (int64_t)d.n0 * d.n1 * 8;
     const int64_t nyz = (int64_t)m.ny * m.nz;
-    const bool pairs = nyz % 2 == 0 && ((uintptr_t)nuc % 16) == 0 && ((uintptr_t)mag % 16) == 0;
-    const int64_t per_wg = (int64_t)kProjThreads * (pairs ? 2 : 1);
-    const int64_t n_proj = (4 * nyz + per_wg - 1) / per_wg;
+    const int64_t n_proj = (4 * nyz + kProjThreads - 1) / kProjThreads;
     const bool pad_s = m.ny16 != m.ny || m.nzk != m.nz;
     const int64_t n_elem = (tw ? (int64_t)m.n0p * m.nyk + (int64_t)m.nzk * m.n1p : 0) +
                            (pad_s ? (int64_t)sets * sstride : 0);
     const int64_t n_tw = (n_elem + 255) / 256;
-    const dim3 grid((unsigned)(n_proj * nb + n_tw));
-    if (pairs)
-        hipLaunchKernelGGL(sep_prepare_kernel<2>, grid, dim3(256), 0, s, d, g, m, nuc, mag, (int)n_proj, (int)nb,
-                           tw ? 1 : 0, pad_s ? 1 : 0, S, ey, ez);
-    else
-        hipLaunchKernelGGL(sep_prepare_kernel<1>, grid, dim3(256), 0, s, d, g, m, nuc, mag, (int)n_proj, (int)nb,
-                           tw ? 1 : 0, pad_s ? 1 : 0, S, ey, ez);
+    hipLaunchKernelGGL(sep_prepare_kernel, dim3((unsigned)(n_proj * nb + n_tw)), dim3(256), 0, s, d, g, m, nuc, mag,
+                       (int)n_proj, (int)nb, tw ? 1 : 0, pad_s ? 1 : 0, S, ey, ez);
     NUMAG_HIP_CHECK(hipGetLastError());
     // first contraction: 32 x 64 or 16 x 64 outputs per wave when that still makes
     // a few workgroups per CU, else 16 x 16
@@ -796,17 +767,10 @@ int launch_separable(const double *nuc, const double *mag, const numag_regular &
     double2 *T = f64 ? (double2 *)(base + L.ey + L.ez + L.s) : nullptr;
     if (!f64) {
         const int sets = (int)(4 * n_snap);
-        const bool pairs = nyz % 2 == 0 && ((uintptr_t)nuc % 16) == 0 && ((uintptr_t)mag % 16) == 0;
-        const int64_t per_wg = (int64_t)kProjThreads * (pairs ? 2 : 1);
-        const int64_t n_proj = (4 * nyz + per_wg - 1) / per_wg;
+        const int64_t n_proj = (4 * nyz + kProjThreads - 1) / kProjThreads;
         const int64_t n_tw = ((pad_s ? (int64_t)sets * m.ny16 * m.nzk : 0) + 255) / 256;
-        const dim3 grid((unsigned)(n_proj * n_snap + n_tw));
-        if (pairs)
-            hipLaunchKernelGGL(sep_prepare_kernel<2>, grid, dim3(256), 0, s, d, g, m, nuc, mag, (int)n_proj,
-                               (int)n_snap, 0, pad_s ? 1 : 0, S, nullptr, nullptr);
-        else
-            hipLaunchKernelGGL(sep_prepare_kernel<1>, grid, dim3(256), 0, s, d, g, m, nuc, mag, (int)n_proj,
-                               (int)n_snap, 0, pad_s ? 1 : 0, S, nullptr, nullptr);
+        hipLaunchKernelGGL(sep_prepare_kernel, dim3((unsigned)(n_proj * n_snap + n_tw)), dim3(256), 0, s, d, g, m, nuc,
+                           mag, (int)n_proj, (int)n_snap, 0, pad_s ? 1 : 0, S, nullptr, nullptr);
         NUMAG_HIP_CHECK(hipGetLastError());
         const BfLayout B = bf_layout(m, path, n_snap);
         char *bbase = base + L.s;
