@@ -485,6 +485,44 @@ def traffic_per_launch(kernel, shape=None):
         return None
 
 
+def gated_rel_err(x, ref, exclude=None):
+    """max over the gated pixels of |x - ref| / |ref|; gated: |ref| >= 1e-6 max|ref|
+    (complex sums by their modulus), `exclude` masks pixels out (q = 0)."""
+    mag = np.abs(ref)
+    ok = np.ones(ref.shape, dtype=bool) if exclude is None else ~exclude
+    if not np.any(mag[ok] > 0):
+        return float(np.max(np.abs(x - ref))) if x.size else 0.0
+    gate = ok & (mag >= 1e-6 * mag[ok].max())
+    return float(np.max(np.abs(x - ref)[gate] / mag[gate]))
+
+
+def step_accuracy(oracle, numag, ref, g, idx, amp, amp_sep, xs):
+    """Gated relative errors of the step's direct sums, separable sums and 13 cross
+    sections at the sampled pixels, against the oracle's sums `ref` [n, 4] there."""
+    qy, qz, qhat = oracle.pixels(g["kind"], g["n0"], g["n1"], g["qmax"])
+    zq = (qy[idx] == 0) & (qz[idx] == 0)
+
+    def sums_err(a):
+        h = a[0].cpu().numpy()
+        c = (h[..., 0] + 1j * h[..., 1])[idx]
+        return max(gated_rel_err(c[:, ch], ref[:, ch]) for ch in range(4) if np.any(ref[:, ch] != 0))
+
+    oref = oracle.cross_sections(ref, qhat[idx])
+    x = xs[0].cpu().numpy()[:, idx]
+    obs = {name: gated_rel_err(x[i], oref[name], zq) for i, name in enumerate(numag.OBSERVABLES)}
+    res = {"pixels": int(idx.size), "direct_sums": sums_err(amp),
+           "separable_sums": sums_err(amp_sep) if amp_sep is not None else None,
+           "observables": {k: float(f"{v:.2e}") for k, v in obs.items()}}
+    res["worst"] = max([res["direct_sums"], max(obs.values())] +
+                       ([res["separable_sums"]] if amp_sep is not None else []))
+    res["direct_sums"] = float(f"{res['direct_sums']:.2e}")
+    if amp_sep is not None:
+        res["separable_sums"] = float(f"{res['separable_sums']:.2e}")
+    res["worst"] = float(f"{res['worst']:.2e}")
+    res["gate"] = 1e-5
+    return res
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -782,9 +820,10 @@ def main():
         qy, qz, _ = oracle.pixels(g["kind"], g["n0"], g["n1"], g["qmax"])
         idx = rng.choice(P, args.cpu_pixels, replace=False)
         t0 = time.perf_counter()
-        oracle.amplitudes(cfg["pos"], cfg["nuc"], cfg["mag"], qy[idx], qz[idx])
+        ref = oracle.amplitudes(cfg["pos"], cfg["nuc"], cfg["mag"], qy[idx], qz[idx])
         dt = time.perf_counter() - t0
         one = one_core_oracle_rate(cfg, qy[idx[:args.cpu_pixels_1core]], qz[idx[:args.cpu_pixels_1core]])
+        accuracy = step_accuracy(oracle, numag, ref, g, idx, amp, amp_sep if have_sep else None, xs)
         out["cpu_baseline"] = {
             "value": round(W * idx.size / dt / 1e9, 5),
             "unit": "Gterm/s",
@@ -794,6 +833,9 @@ def main():
                       f"of the 256x256 detector ({W * idx.size:.3g} terms, {dt:.1f} s)",
             "cpu_model": cpu_model(),
             "one_core": one,
+            # the timed step's last results against the same oracle sums (the metric's
+            # accuracy condition), gated relative error as in the parity tests
+            "gpu_vs_oracle": accuracy,
         }
     print(json.dumps(out))
 
