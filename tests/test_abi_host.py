@@ -277,3 +277,45 @@ def test_noalloc_entry_rejects_before_any_gpu_work():
     assert "static scratch" in numag.last_error()
     text = open(HEADER).read()
     assert "#define NUMAG_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)" in text
+
+
+def test_separable_hermitian_path_validates():
+    """NUMAG_PATH_SEPARABLE_F64_HERMITIAN follows the separable paths' rules (a regular
+    grid, one unrotated object, a Cartesian detector, coherent mode) and only the
+    entry points that run separable paths accept it; path values end there.  Every
+    case returns before any GPU work."""
+    lib = numag._lib
+    H64 = numag.PATH_SEPARABLE_F64_HERMITIAN
+    grid = numag.qgrid(0, 8, 8, 1.0)
+    pol = numag.qgrid(1, 8, 8, 1.0)
+    s = _cpu_sample()
+    assert _call_amp(s, grid, path=H64, ws=0x3000, nws=1 << 30) == numag.E_INVALID
+    assert "regular" in numag.last_error()
+    assert _call_amp(s, grid, path=H64 + 1, ws=0x3000, nws=1 << 30) == numag.E_INVALID
+    assert "unknown path" in numag.last_error()
+    reg = numag.regular_grid((4, 5, 6), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0))
+    sr = _cpu_sample(W=120)
+    sr.pos = None
+    sr.nuc = ctypes.c_void_p(0x1000)
+    sr.regular = ctypes.cast(ctypes.pointer(reg), ctypes.c_void_p)
+    assert lib.numag_workspace_size(ctypes.byref(sr), 1, ctypes.byref(grid), H64, 0) == \
+        lib.numag_workspace_size(ctypes.byref(sr), 1, ctypes.byref(grid), numag.PATH_SEPARABLE_F64, 0) > 0
+    assert _call_amp(sr, pol, path=H64, ws=0x3000, nws=1 << 30) == numag.E_INVALID
+    assert "Cartesian" in numag.last_error()
+    assert _call_amp(sr, grid, path=H64, mode=numag.MODE_DILUTE, amp=None, spec=0x4000, ws=0x3000,
+                     nws=1 << 30) == numag.E_INVALID
+    rot2 = np.stack([np.eye(3).reshape(9)] * 2)
+    assert _call_amp(sr, grid, rot=rot2, n_rot=2, path=H64, ws=0x3000, nws=1 << 30) == numag.E_INVALID
+    # the direct-only entry points refuse it
+    c = numag.consts()
+    fake = ctypes.c_void_p(0x5000)
+    assert lib.numag_grad_path(ctypes.byref(s), None, ctypes.byref(grid), H64, ctypes.byref(c), None, fake, fake,
+                               fake, fake, fake, fake, 1 << 30, None) == numag.E_INVALID
+    assert "path" in numag.last_error()
+    assert lib.numag_amplitudes_noalloc(ctypes.byref(s), 1, None, ctypes.byref(grid), H64,
+                                        ctypes.c_void_p(0x2000), None) == numag.E_INVALID
+    off = np.array([0, 4, 10], dtype=np.int64)
+    so = _cpu_sample(W=10, K=2, offsets=off)
+    h = ctypes.c_void_p()
+    assert lib.numag_plan_create(ctypes.byref(so), 1, None, ctypes.byref(grid), H64, numag.MODE_DILUTE, 1,
+                                 ctypes.byref(h)) == numag.E_INVALID
