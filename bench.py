@@ -271,10 +271,13 @@ def measure_snapshots(torch, numag, synth, n_snap=64):
     grid = numag.qgrid(0, 256, 256, 2.0)
     points = numag.regular_grid(reg["n"], reg["origin"], reg["step"])
     out = torch.empty((n_snap, grid.n_pixels, 4, 2), dtype=torch.float64, device=dev)
-    numag.amplitudes_snapshots(points, grid, nuc=nucs, mag=mt, out=out, device=dev)
-    torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = 5
+    # the engine clock settles after some tens of ms of this load: warm up with about
+    # 60 ms of the same calls before each timed series
+    warm, reps = 200, 20
+    for _ in range(warm):
+        numag.amplitudes_snapshots(points, grid, nuc=nucs, mag=mt, out=out, device=dev)
+    torch.cuda.synchronize()
     e0.record()
     for _ in range(reps):
         numag.amplitudes_snapshots(points, grid, nuc=nucs, mag=mt, out=out, device=dev)
@@ -297,7 +300,8 @@ def measure_snapshots(torch, numag, synth, n_snap=64):
     t_bf = {}
     for name, path in (("hermitian", numag.PATH_SEPARABLE_F64_HERMITIAN), ("bf16x3", numag.PATH_SEPARABLE_BF16X3),
                        ("bf16x6", numag.PATH_SEPARABLE_BF16X6)):
-        numag.amplitudes_snapshots(points, grid, nuc=nucs, mag=mt, path=path, out=out, device=dev)
+        for _ in range(warm):
+            numag.amplitudes_snapshots(points, grid, nuc=nucs, mag=mt, path=path, out=out, device=dev)
         torch.cuda.synchronize()
         e0.record()
         for _ in range(reps):
