@@ -121,7 +121,7 @@ def tuned_vs_default(torch, numag, kernel, kid, sample, grid, fn, rot=None, max_
             "tuned_kernel_ms": round(t_tuned, 4), "tuning_s": round(t_tune, 2)}
 
 
-def polar_only(torch, numag, synth, launches=5, warmup=3):
+def polar_only(torch, numag, synth, launches=5, warmup=8):
     """Direct sums of the 64^3 vortex on a 256 x 256 polar detector (|q| <= 2 nm^-1),
     then the loss gradient's adjoint sum on the same detector.  The warm-up launches
     let the engine clock settle before the timed ones."""
