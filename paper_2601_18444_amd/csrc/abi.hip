@@ -964,11 +964,27 @@ int numag_autotune(const numag_sample *sample, int64_t n_rot, const double *rot,
                                grad_workspace_bytes(dfull, ts.n_points), st, herm);
         };
         // one trial run to size the repetitions: about 0.3 s of timed work per candidate
-        const double t1 = time_runs(run, st, 1);
+        double t1 = time_runs(run, st, 1);
         if (t1 < 0.0) {
             restore();
             if (numag_last_error()[0] == 0) set_error("numag_autotune: a trial run failed");
             return NUMAG_E_HIP;
+        }
+        if (i == 0) {
+            // the engine clock settles after some tens of ms of load: run the first
+            // candidate for about 40 ms before any candidate is timed
+            const int warm = (int)std::min(200.0, std::ceil(40.0 / std::max(t1, 1e-3)));
+            for (int w = 0; w < warm; ++w)
+                if ((rc = run()) != NUMAG_OK) {
+                    restore();
+                    return rc;
+                }
+            t1 = time_runs(run, st, 1);
+            if (t1 < 0.0) {
+                restore();
+                if (numag_last_error()[0] == 0) set_error("numag_autotune: a trial run failed");
+                return NUMAG_E_HIP;
+            }
         }
         const int reps = (int)std::max(1.0, std::min(5.0, 300.0 / std::max(t1, 1e-3)));
         const double t = reps > 1 ? std::min(t1, time_runs(run, st, reps)) : t1;
