@@ -492,7 +492,7 @@ size_t numag_workspace_size(const numag_sample *sample, int64_t n_rot, const num
         // numag_grad: points + amplitudes (when not given) + direct partials + adjoint scratch
         const int64_t P = (int64_t)grid->n0 * grid->n1;
         grad = direct_layout(sample, d).total + align_up((size_t)P * 8 * sizeof(double)) +
-               align_up(grad_workspace_bytes(d, sample->n_points));
+               align_up(grad_workspace_bytes(d, sample->n_points, path == NUMAG_PATH_DIRECT_HERMITIAN));
     }
     return std::max(amp, grad);
 }
@@ -766,8 +766,8 @@ int numag_grad_path(const numag_sample *sample, const double *rot, const numag_q
     Detector d = make_detector(*grid);
     const int64_t P = (int64_t)grid->n0 * grid->n1;
     DirectLayout L = direct_layout(sample, d);
-    const size_t need = L.total + align_up((size_t)P * 8 * sizeof(double)) +
-                        align_up(grad_workspace_bytes(d, sample->n_points));
+    const size_t gbytes = grad_workspace_bytes(d, sample->n_points, hermitian);
+    const size_t need = L.total + align_up((size_t)P * 8 * sizeof(double)) + align_up(gbytes);
     if (ws_bytes < need || workspace == nullptr) {
         set_error("numag_grad: workspace too small (need " + std::to_string(need) + " bytes)");
         return NUMAG_E_WORKSPACE;
@@ -776,7 +776,7 @@ int numag_grad_path(const numag_sample *sample, const double *rot, const numag_q
     Carve cv(workspace);
     char *direct_ws = (char *)cv.take(L.total);
     double *amp = (double *)cv.take((size_t)P * 8 * sizeof(double));
-    void *gws = cv.take(grad_workspace_bytes(d, sample->n_points));
+    void *gws = cv.take(gbytes);
     const Rot R = rot_of(rot, 0);
     if (amp_in == nullptr) {
         rc = run_direct(sample, R, d, amp, direct_ws, st, hermitian);
@@ -791,7 +791,7 @@ int numag_grad_path(const numag_sample *sample, const double *rot, const numag_q
     }
     const PointRec *pts = (const PointRec *)direct_ws;
     return launch_grad(pts, sample->n_points, d, *consts, amp_in, target, weight, loss_out, dnuc_out, dmag_out,
-                       R, gws, grad_workspace_bytes(d, sample->n_points), st, hermitian);
+                       R, gws, gbytes, st, hermitian);
 }
 
 int numag_tune_get(int32_t kernel, const numag_qgrid *grid, int32_t path, int64_t n_points,
@@ -917,7 +917,7 @@ int numag_autotune(const numag_sample *sample, int64_t n_rot, const double *rot,
         } else {
             const Detector &dd = dfull;
             need = direct_layout(&ts, dd).total + align_up((size_t)P * 8 * sizeof(double)) +
-                   align_up(grad_workspace_bytes(dd, ts.n_points));
+                   align_up(grad_workspace_bytes(dd, ts.n_points, path == NUMAG_PATH_DIRECT_HERMITIAN));
         }
         ws_need = std::max(ws_need, align_up(need));
     }
@@ -961,7 +961,7 @@ int numag_autotune(const numag_sample *sample, int64_t n_rot, const double *rot,
             numag_consts k{1.0, 1.0, 1.0, {0.0, 0.0, 1.0}};
             return launch_grad((const PointRec *)base, ts.n_points, dfull, k, amp, target, weight, loss, dn, dm, R,
                                base + L.total + align_up((size_t)P * 8 * sizeof(double)),
-                               grad_workspace_bytes(dfull, ts.n_points), st, herm);
+                               grad_workspace_bytes(dfull, ts.n_points, herm), st, herm);
         };
         // one trial run to size the repetitions: about 0.3 s of timed work per candidate
         double t1 = time_runs(run, st, 1);

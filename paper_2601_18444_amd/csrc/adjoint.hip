@@ -385,11 +385,29 @@ static int adjoint_row_splits(const Detector &d, int64_t W)
     return (int)want;
 }
 
-size_t grad_workspace_bytes(const Detector &d, int64_t W)
+// The part of the detector the adjoint sums: the whole detector, or the half of the
+// Hermitian path (Cartesian rows [0, ceil(n0 / 2)), polar columns [0, n_theta / 2);
+// d.n_theta stays that of the whole detector).
+static Detector adjoint_detector(const Detector &d_full, bool hermitian)
 {
-    const int64_t P = (int64_t)d.n0 * d.n1;
+    Detector d = d_full;
+    if (hermitian) {
+        if (d.kind == NUMAG_GRID_CARTESIAN)
+            d.n0 = (d.n0 + 1) / 2;
+        else
+            d.n1 = d.n1 / 2;
+    }
+    return d;
+}
+
+// Scratch of launch_grad: the residual weights and loss partials of the whole
+// detector, and the gradient partials of the row splits of the part the adjoint
+// sums (its launch shape, hence its split count, is looked up for that part).
+size_t grad_workspace_bytes(const Detector &d_full, int64_t W, bool hermitian)
+{
+    const int64_t P = (int64_t)d_full.n0 * d_full.n1;
     const int64_t nres = (P + kResThreads - 1) / kResThreads;
-    const int splits = adjoint_row_splits(d, W);
+    const int splits = adjoint_row_splits(adjoint_detector(d_full, hermitian), W);
     size_t b = 0;
     b += (size_t)P * 8 * sizeof(double);          // residual weights
     b += (size_t)(nres + 1) * sizeof(double);      // loss partials
@@ -423,15 +441,10 @@ int launch_grad(const PointRec *pts, int64_t W, const Detector &d_full, const nu
     const Detector &dr = d_full;  // the residual and the loss cover the whole detector
     const int64_t P = (int64_t)dr.n0 * dr.n1;
     const int64_t nres = (P + kResThreads - 1) / kResThreads;
-    // the adjoint sums the whole detector, or half of it with folded weights
-    Detector d = d_full;
-    if (hermitian) {
-        if (d.kind == NUMAG_GRID_CARTESIAN)
-            d.n0 = (d.n0 + 1) / 2;
-        else
-            d.n1 = d.n1 / 2;  // theta_m, m < n_theta / 2 (d.n_theta unchanged)
-    }
-    const int splits = adjoint_row_splits(d, W);  // at most those of the whole detector
+    // the adjoint sums the whole detector, or half of it with folded weights; the
+    // split count is the one grad_workspace_bytes sized the scratch for
+    const Detector d = adjoint_detector(d_full, hermitian);
+    const int splits = adjoint_row_splits(d, W);
     char *base = (char *)ws;
     auto take = [&](size_t bytes) {
         char *r = base;

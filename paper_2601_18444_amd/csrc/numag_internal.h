@@ -198,7 +198,8 @@ int launch_grad(const PointRec *pts, int64_t W, const Detector &d, const numag_c
                 const double *amp, const double *target, const double *weight, double *loss,
                 double *dnuc, double *dmag, const Rot &R, void *ws, size_t ws_bytes, hipStream_t s,
                 bool hermitian = false);
-size_t grad_workspace_bytes(const Detector &d, int64_t W);
+// Workspace bytes of launch_grad on detector d (whole), for the path it will run.
+size_t grad_workspace_bytes(const Detector &d, int64_t W, bool hermitian);
 
 // 2D correlation function (eq. crav2d) from data on detector d onto real-space grid rd.
 size_t correlation_2d_workspace_bytes(const Detector &d, const Detector &rd);
