@@ -11,6 +11,9 @@
   over h and h/2 removes: the reference is exact up to rounding.  Tolerance:
   |g - g_FD| <= 1e-4 |g_FD| on components with |g_FD| >= 1e-3 max|g_FD|, else
   <= 1e-7 max|g_FD|.
+* The benchmark's launch configuration: the same vortex sums and gradient under the
+  shapes the autotuner picks on the machine, against the oracle (sums, sampled) and
+  the default shapes (to rounding).
 * Orientational averages (64 particles of 1,331-173,157 points, 1,000 rotations,
   128 x 128 detector; Sec. 3.3 dilute limit): every particle's averaged spectral
   matrix against the oracle over all 1,000 rotations on sampled pixels (this
@@ -29,7 +32,7 @@ if not torch.cuda.is_available():  # pragma: no cover - CPU container
     pytest.skip("needs a GPU", allow_module_level=True)
 
 from paper_2601_18444_amd import numag, synth  # noqa: E402
-from tests.helpers import gated_rel_err, max_norm_err  # noqa: E402
+from tests.helpers import amp_to_complex, gated_rel_err, max_norm_err  # noqa: E402
 
 DEV = "cuda:0"
 TOL = 1e-5
@@ -151,3 +154,45 @@ def test_orientational_average_every_particle_full_rotation_set(orc):
     # the summed average equals the sum of the per-particle ones
     _, tot = numag.amplitudes(s, grid, rot=rots4, mode=numag.MODE_DILUTE, spec_per_object=False)
     assert max_norm_err(tot[0].cpu().numpy(), spec4.sum(axis=0)) <= 1e-12
+
+
+def test_benchmark_launch_configuration_full_size(orc):
+    """The benchmark step's configuration: the 64^3 vortex on the 256 x 256 detector
+    with the launch shapes the autotuner picks on this machine (as bench.py does before
+    it times).  Direct sums against the oracle on 128 sampled pixels (and against the
+    library-default shapes to rounding); the loss gradient under the tuned adjoint
+    shape against the default-shape gradient, which the finite-difference test above
+    checks against the oracle."""
+    cfg = synth.vortex_grid_gradient()
+    g = cfg["grid"]
+    grid = numag.qgrid(g["kind"], g["n0"], g["n1"], g["qmax"])
+    W = cfg["pos"].shape[0]
+    s = numag.Sample(pos=cfg["pos"], nuc=cfg["nuc"], mag=cfg["mag"], device=DEV)
+    k = numag.consts(V=1.0, bH=1.0, scale=1.0, P=(0.0, 0.0, 1.0))
+    tf = cfg["target_field"]
+    ts = numag.Sample(pos=tf["pos"], nuc=tf["nuc"], mag=tf["mag"], device=DEV)
+    numag.tune_clear()
+    try:
+        tamp, _ = numag.amplitudes(ts, grid)
+        T = numag.cross_section(grid, amp=tamp, c=k, obs=("UNPOL",))[0, 0].clone()
+        w = (1.0 / (T + 1e-3 * T.max()) ** 2).contiguous()
+        a_def, _ = numag.amplitudes(s, grid)
+        a_def = a_def.clone()
+        g_def = [t.clone() for t in numag.grad(s, grid, k, weight=w, target=T, amp=a_def[0])]
+        print("tuned shapes:", numag.autotune(s, grid, numag.TUNE_DIRECT),
+              numag.autotune(s, grid, numag.TUNE_ADJOINT), flush=True)
+        a_tun, _ = numag.amplitudes(s, grid)
+        g_tun = numag.grad(s, grid, k, weight=w, target=T, amp=a_tun[0])
+        torch.cuda.synchronize()
+    finally:
+        numag.tune_clear()
+    gpu = amp_to_complex(a_tun[0])
+    assert max_norm_err(gpu, amp_to_complex(a_def[0])) <= 1e-12
+    qy, qz, _ = orc.pixels(g["kind"], g["n0"], g["n1"], g["qmax"])
+    idx = np.sort(np.random.default_rng(96).choice(qy.size, 128, replace=False))
+    ref = orc.amplitudes(cfg["pos"], cfg["nuc"], cfg["mag"], qy[idx], qz[idx])
+    for c in range(4):
+        assert gated_rel_err(gpu[idx, c], ref[:, c]) <= TOL, c
+    assert abs(float(g_tun[0]) - float(g_def[0])) <= 1e-12 * abs(float(g_def[0]))
+    for a, b in zip(g_tun[1:], g_def[1:]):
+        assert float((a - b).abs().max()) <= 1e-10 * float(b.abs().max())
