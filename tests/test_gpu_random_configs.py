@@ -3,7 +3,9 @@ size (odd and even, 1 to 69 rows and columns), q_max, object counts and sizes
 (including empty objects and samples), channel subsets, rotations, object mode
 (coherent, dilute with several rotations, split) and path (direct or half
 detector), each against the FP64 oracle; coherent cases also check the loss and
-gradient.  Every case has its own seed, so a failure names a reproducible case."""
+gradient.  A second sweep of 16 seeded regular-grid cases runs the separable
+matrix-core paths (FP64 and its half-detector variant) in batches of snapshots.
+Every case has its own seed, so a failure names a reproducible case."""
 import numpy as np
 import pytest
 
@@ -87,3 +89,47 @@ def test_random_configuration(orc, case):
         F = orc.amplitudes(pos, on, om, qy, qz, R=rots[0], obj_offsets=offs, obj_pos=obj_pos, per_object=True)
         assert max_norm_err(amp_to_complex(amp[0]), A) <= 1e-9
         assert max_norm_err(spec[0].cpu().numpy(), orc.spectral(F)) <= 1e-9
+
+
+@pytest.mark.parametrize("case", range(16))
+def test_random_separable_configuration(orc, case):
+    """Seeded random regular grids (1 to 40 cells per axis, random steps and origins),
+    Cartesian detectors (1 to 90 rows and columns), q_max, channel subsets and
+    snapshot counts (up to 240, so that large batches take the four-channel-set
+    tiles) on the FP64 separable path or its Hermitian variant: two snapshots
+    against the oracle on sampled pixels, and each equal to its single call."""
+    rng = np.random.default_rng(2000 + case)
+    n = tuple(int(v) for v in rng.integers(1, 41, 3))
+    while n[0] * n[1] * n[2] > 20000:
+        n = (max(1, n[0] // 2), n[1], n[2])
+    step = tuple(float(v) for v in rng.uniform(0.3, 2.0, 3))
+    origin = tuple(float(v) for v in rng.uniform(-30, 5, 3))
+    W = n[0] * n[1] * n[2]
+    n0, n1 = int(rng.integers(1, 91)), int(rng.integers(1, 91))
+    qmax = float(rng.uniform(0.2, 2.5))
+    B = int(rng.integers(1, 13)) if case % 4 else int(rng.integers(100, 241))
+    chan = case % 3  # 0 all channels, 1 nuclear only, 2 magnetic only
+    path = numag.PATH_SEPARABLE_F64_HERMITIAN if case % 2 else numag.PATH_SEPARABLE_F64
+    nuc = rng.standard_normal((B, W)) if chan != 2 else None
+    mag = rng.standard_normal((B, W, 3)) if chan != 1 else None
+    grid = numag.qgrid(0, n0, n1, qmax)
+    points = numag.regular_grid(n, origin, step)
+    amp = numag.amplitudes_snapshots(points, grid, nuc=nuc, mag=mag, path=path, device=DEV)
+    pos = synth.box_lattice(n, step, origin)
+    qy, qz, _ = orc.pixels(0, n0, n1, qmax)
+    idx = np.sort(rng.choice(qy.size, min(qy.size, 48), replace=False))
+    reg = {"n": n, "origin": origin, "step": step}
+    for b in sorted({0, B - 1}):
+        nb = nuc[b] if nuc is not None else None
+        mb = mag[b] if mag is not None else None
+        ref = orc.amplitudes(pos, nb if nb is not None else np.zeros(W), mb if mb is not None else np.zeros((W, 3)),
+                             qy[idx], qz[idx])
+        gpu = amp_to_complex(amp[b])[idx]
+        for c in range(4):
+            if np.max(np.abs(ref[:, c])) == 0:
+                assert np.max(np.abs(gpu[:, c])) == 0, (b, c)
+            else:
+                assert gated_rel_err(gpu[:, c], ref[:, c]) <= 1e-9, (b, c)
+        single = numag.Sample(nuc=nb, mag=mb, regular=reg, n_points=W, device=DEV)
+        one, _ = numag.amplitudes(single, grid, path=path)
+        assert torch.equal(amp[b], one[0]), f"snapshot {b} differs from its single call"
