@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--polar", action="store_true",
                     help="only time the direct sums and the loss gradient of the same points on a "
                          "256 q x 256 theta polar detector (a short run for the polar kernels' profiles)")
+    ap.add_argument("--polar-objects", action="store_true",
+                    help="only run the polar orientational-average measurement (64 particles x 50 rotations)")
     ap.add_argument("--snapshots", action="store_true",
                     help="only run the loop-mode snapshot measurement (64 snapshots, separable path)")
     ap.add_argument("--batched", action="store_true",
@@ -223,23 +225,7 @@ def measure_batched(torch, numag, synth):
     torch.cuda.synchronize()
     t_plain = e0.elapsed_time(e1) * 1e-3
     plain_terms = W * len(sample_rots) * grid.n_pixels
-    # the same particles and average on a polar detector of the same size, first 50
-    # rotations: rotation groups on the polar direct kernel
-    pgrid = numag.qgrid(1, g["n0"], g["n1"], g["qmax"])
-    prots = rots[:50]
-    polar_tuning = tuned_vs_default(
-        torch, numag, numag.TUNE_OBJECTS, numag.KERNEL_OBJECTS, s, pgrid,
-        lambda: numag.amplitudes(s, pgrid, rot=prots[:16], mode=numag.MODE_DILUTE, spec_per_object=True),
-        rot=prots[:16], n=2)
-    polar_tuning["sample"] = "first 16 rotations, dilute per-particle average, polar detector"
-    numag.amplitudes(s, pgrid, rot=prots[:2], mode=numag.MODE_DILUTE, spec_per_object=True)  # warm-up
-    torch.cuda.synchronize()
-    e0.record()
-    numag.amplitudes(s, pgrid, rot=prots, mode=numag.MODE_DILUTE, spec_per_object=True)
-    e1.record()
-    torch.cuda.synchronize()
-    t_polar = e0.elapsed_time(e1) * 1e-3
-    polar_terms = W * len(prots) * pgrid.n_pixels
+    polar = measure_polar_objects(torch, numag, synth, cfg=cfg, sample=s)
     return {
         "workload": "64 particles (1331-173157 points, 2298012 total) x 1000 rotations, 128x128 detector, "
                     "dilute per-particle orientational average (spectral matrix), persistent launch + HIP graph",
@@ -250,13 +236,59 @@ def measure_batched(torch, numag, synth):
         "batched_hermitian_max_diff": herm_diff,
         "plain_direct_per_orientation_Gterm_s": round(plain_terms / t_plain / 1e9, 2),
         "plain_direct_sample": "same particles, first 8 rotations, one coherent direct call per (particle, rotation)",
-        "polar_dilute_s": round(t_polar, 4),
-        "polar_dilute_Gterm_s": round(polar_terms / t_polar / 1e9, 2),
-        "polar_dilute_frac": round(FLOPS_PER_TERM * polar_terms / t_polar / PEAK_FP64_VALU, 4),
+        "polar_dilute_s": polar["call_s"],
+        "polar_dilute_Gterm_s": polar["Gterm_s"],
+        "polar_dilute_frac": polar["frac"],
         "polar_dilute_sample": "same particles, first 50 rotations, 128 q x 128 theta polar detector, dilute "
                                "per-particle average (persistent polar object kernel)",
         "tuning": tuning,
-        "polar_tuning": polar_tuning,
+        "polar_tuning": polar["tuning"],
+    }
+
+
+def measure_polar_objects(torch, numag, synth, cfg=None, sample=None):
+    """The 64 particles of the orientational average, first 50 of their rotations, on a
+    128 q x 128 theta polar detector: dilute per-particle average in one persistent
+    launch of the polar object kernel (launch shape tuned first).  The call (plan,
+    upload, kernel, reductions) and the kernel alone, timed after a warm-up."""
+    dev = "cuda:0"
+    cfg = cfg if cfg is not None else synth.particles_rotations(n_rot=50)
+    g = cfg["grid"]
+    s = sample if sample is not None else numag.Sample(pos=cfg["pos"], nuc=cfg["nuc"], mag=cfg["mag"],
+                                                       obj_offsets=cfg["obj_offsets"], device=dev)
+    W = cfg["pos"].shape[0]
+    pgrid = numag.qgrid(1, g["n0"], g["n1"], g["qmax"])
+    prots = cfg["rotations"][:50]
+    tuning = tuned_vs_default(
+        torch, numag, numag.TUNE_OBJECTS, numag.KERNEL_OBJECTS, s, pgrid,
+        lambda: numag.amplitudes(s, pgrid, rot=prots[:16], mode=numag.MODE_DILUTE, spec_per_object=True),
+        rot=prots[:16], n=2)
+    tuning["sample"] = "first 16 rotations, dilute per-particle average, polar detector"
+    numag.amplitudes(s, pgrid, rot=prots[:2], mode=numag.MODE_DILUTE, spec_per_object=True)  # warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    numag.kernel_timer(True)
+    e0.record()
+    numag.amplitudes(s, pgrid, rot=prots, mode=numag.MODE_DILUTE, spec_per_object=True)
+    e1.record()
+    torch.cuda.synchronize()
+    t_kernel, n = numag.kernel_timer_read(numag.KERNEL_OBJECTS)
+    numag.kernel_timer(False)
+    t_call = e0.elapsed_time(e1) * 1e-3
+    terms = W * len(prots) * pgrid.n_pixels
+    k_s = t_kernel * 1e-3 / max(n, 1)
+    return {
+        "workload": "64 particles (2298012 points) x 50 rotations, 128 q x 128 theta polar detector, dilute "
+                    "per-particle orientational average, persistent polar object kernel",
+        "call_s": round(t_call, 4),
+        "Gterm_s": round(terms / t_call / 1e9, 2),
+        "frac": round(FLOPS_PER_TERM * terms / t_call / PEAK_FP64_VALU, 4),
+        "objects_kernel_s": round(k_s, 4),
+        "roofline": {"kernel": "objects_polar_kernel", "bound": "alu",
+                     "achieved": round(FLOPS_PER_TERM * terms / k_s / 1e12, 3),
+                     "peak": round(PEAK_FP64_VALU / 1e12, 3), "unit": "TFLOP/s",
+                     "frac": round(FLOPS_PER_TERM * terms / k_s / PEAK_FP64_VALU, 4)},
+        "tuning": tuning,
     }
 
 
@@ -595,6 +627,9 @@ def main():
         return
     if args.snapshots:
         print(json.dumps(measure_snapshots(torch, numag, synth)))
+        return
+    if args.polar_objects:
+        print(json.dumps(measure_polar_objects(torch, numag, synth)))
         return
     if args.batched:
         print(json.dumps(measure_batched(torch, numag, synth)))
