@@ -174,3 +174,62 @@ def test_hermitian_gradient_workspace_follows_the_half_detector_shape():
     torch.cuda.synchronize()
     for a, b in zip(full[1:], ref[1:]):
         assert float((a - b).abs().max()) <= 1e-10 * float(b.abs().max())
+
+
+def _pin_random_shapes(rng, grid, W, kind, n0):
+    """Random valid table entries for every kernel on the whole and the half detector."""
+    for path in (numag.PATH_DIRECT, numag.PATH_DIRECT_HERMITIAN):
+        if kind == 1 and path == numag.PATH_DIRECT_HERMITIAN and grid.n1 % 2:
+            continue
+        polar_shapes = [0, 2, 3, 4] + ([1] if n0 <= 32 else [])
+        sh = int(rng.choice([8, 16, 32, 64])) if kind == 0 else int(rng.choice(polar_shapes))
+        numag.tune_set(numag.TUNE_DIRECT, grid, W, shape=(sh, int(rng.choice([64, 1024, 8192]))), path=path)
+        numag.tune_set(numag.TUNE_ADJOINT, grid, W, shape=(0, int(rng.choice([16, 512, 16384]))), path=path)
+        sh = int(rng.choice([8, 16, 32, 64])) if kind == 0 else int(rng.choice(polar_shapes))
+        numag.tune_set(numag.TUNE_OBJECTS, grid, W, shape=(sh, int(rng.choice([32, 2048, 8192]))), path=path)
+
+
+@pytest.mark.parametrize("case", range(10))
+def test_random_pinned_shapes_size_their_workspaces(orc, case):
+    """Every workspace (sums, allocation-free sums, gradient, dilute objects) is sized
+    for the launch shape its kernels take, whatever shapes the table holds for the
+    whole and the half detector: random entries for every kernel, then every entry
+    point against the oracle on both paths."""
+    rng = np.random.default_rng(70000 + case)
+    kind = int(rng.integers(0, 2))
+    n0, n1 = int(rng.integers(1, 90)), int(rng.integers(1, 90))
+    if kind == 1:
+        n1 += n1 % 2
+    qmax = float(rng.uniform(0.2, 2.5))
+    K = int(rng.integers(2, 5))
+    sizes = rng.integers(1, 4000 // K + 1, K)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    W = int(off[-1])
+    pos = rng.uniform(-10, 10, (W, 3))
+    nuc, mag = rng.standard_normal(W), rng.standard_normal((W, 3))
+    grid = numag.qgrid(kind, n0, n1, qmax)
+    _pin_random_shapes(rng, grid, W, kind, n0)
+    numag.clear_workspace_cache()
+    qy, qz, qhat = orc.pixels(kind, n0, n1, qmax)
+    R = synth.uniform_rotations(2, rng)
+    s1 = numag.Sample(pos=pos, nuc=nuc, mag=mag, device=DEV)
+    sK = numag.Sample(pos=pos, nuc=nuc, mag=mag, obj_offsets=off, device=DEV)
+    A = orc.amplitudes(pos, nuc, mag, qy, qz, R=R[0])
+    T, w = rng.uniform(0, 5, qy.size), rng.uniform(0.5, 1.5, qy.size)
+    L, dn, dm = orc.loss_grad(pos, nuc, mag, qy, qz, qhat, T, w, R=R[0])
+    for path in (numag.PATH_DIRECT, numag.PATH_DIRECT_HERMITIAN):
+        amp, _ = numag.amplitudes(s1, grid, rot=R[0], path=path)
+        for c in range(4):
+            assert gated_rel_err(amp_to_complex(amp[0])[:, c], A[:, c]) <= 1e-9, (path, c)
+        na = numag.amplitudes_noalloc(s1, grid, rot=R[0], path=path)
+        assert max_norm_err(amp_to_complex(na[0]), amp_to_complex(amp[0])) <= 1e-11
+        loss, gdn, gdm = numag.grad(s1, grid, numag.consts(), weight=torch.as_tensor(w, device=DEV),
+                                    target=torch.as_tensor(T, device=DEV), rot=R[0], path=path)
+        assert abs(loss.item() - L) <= 1e-9 * abs(L)
+        assert max_norm_err(gdn.cpu().numpy(), dn) <= 1e-8 and max_norm_err(gdm.cpu().numpy(), dm) <= 1e-8
+        _, spec = numag.amplitudes(sK, grid, rot=R, path=path, mode=numag.MODE_DILUTE, spec_per_object=True)
+        spec = spec.cpu().numpy()
+        for k in range(K):
+            sl = slice(off[k], off[k + 1])
+            Fs = [orc.amplitudes(pos[sl], nuc[sl], mag[sl], qy, qz, R=Rr) for Rr in R]
+            assert max_norm_err(spec[k], orc.spectral(np.stack(Fs)) / len(R)) <= 1e-9, (path, k)
