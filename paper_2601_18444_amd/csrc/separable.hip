@@ -777,11 +777,12 @@ int launch_separable(const double *nuc, const double *mag, const numag_regular &
         return B.np == 3 ? launch_bf16_path<3>(m, B, d, g, S, sets, bbase, amp, s)
                          : launch_bf16_path<2>(m, B, d, g, S, sets, bbase, amp, s);
     }
-    // One launch sequence for the whole batch.  Splitting the batch into four chunks
-    // on two streams, so that the projection (HBM-bound) of a chunk runs beside the
-    // second contraction of the previous one, was measured slower for 64 snapshots
-    // (0.42 against 0.34 ms): the two kernels slowed each other down (the
-    // contraction 51 -> 82 us per chunk, the projection 22 -> 70 us).
+    // One launch sequence for the whole batch.  Splitting the batch into chunks on two
+    // streams, so that the projection (HBM-bound) of a chunk runs beside the second
+    // contraction of the previous one, was measured slower for 64 snapshots: 0.30, 0.32
+    // and 0.37 ms for 2, 4 and 8 chunks against 0.27-0.29 ms for one sequence (0.27
+    // against 0.20 ms on the Hermitian half); the two kernels slow each other down more
+    // than the overlap saves.
     return launch_f64_chunk(nuc, mag, g, d, m, 0, n_snap, true, herm, ey, ez, S, T, amp, s);
 }
 
