@@ -16,7 +16,7 @@ if not torch.cuda.is_available():  # pragma: no cover - CPU container
     pytest.skip("needs a GPU", allow_module_level=True)
 
 from paper_2601_18444_amd import numag, synth  # noqa: E402
-from tests.helpers import amp_to_complex, gated_rel_err, zero_q_mask  # noqa: E402
+from tests.helpers import gated_rel_err, zero_q_mask  # noqa: E402
 
 DEV = "cuda:0"
 PATHS = (("direct", numag.PATH_DIRECT), ("direct_hermitian", numag.PATH_DIRECT_HERMITIAN),

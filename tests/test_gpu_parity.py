@@ -4,7 +4,6 @@ Tolerance: the accuracy gate, relative error <= 1e-5 per observable at the
 pixels whose reference magnitude is >= 1e-6 of its maximum (q = 0 excluded);
 integer outputs (bin counts) are compared bit-exactly.
 """
-import math
 
 import numpy as np
 import pytest

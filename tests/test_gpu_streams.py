@@ -1,7 +1,6 @@
 """Calls enqueued on different streams may overlap; the binding gives each stream its
 own workspace.  Sums and gradients computed on two streams at once equal the same
 calls made one after the other on one stream, bit for bit."""
-import numpy as np
 import pytest
 
 pytestmark = pytest.mark.gpu

@@ -11,7 +11,6 @@ import math
 import os
 
 import numpy as np
-import pytest
 
 from paper_2601_18444_amd import synth
 
