@@ -326,6 +326,7 @@ int numag_spectral_matrix(const numag_qgrid *grid, int64_t n_sets, const double 
  * Polar detector: the periodic trapezoidal rule over theta of every q row;
  *   n_bins must equal n_q and qmax_avg is ignored.
  *   I_out     [n_f][n_bins];  count_out [n_bins] int64 or NULL.
+ * With n_f = 0 nothing is written, count_out included.
  */
 int numag_azimuthal_average(const numag_qgrid *grid, const double *f, int32_t n_f, int32_t n_bins,
                             double qmax_avg, double *I_out, int64_t *count_out, void *stream);

@@ -712,7 +712,7 @@ int numag_azimuthal_average(const numag_qgrid *grid, const double *f, int32_t n_
     if (n_f < 0 || n_bins < 1) return invalid("numag_azimuthal_average: need n_f >= 0 and n_bins >= 1");
     if (n_f > 65535 || n_bins > (1 << 24)) return invalid("numag_azimuthal_average: n_f or n_bins too large");
     if (f == nullptr && n_f > 0) return invalid("numag_azimuthal_average: f is NULL");
-    if (I_out == nullptr) return invalid("numag_azimuthal_average: I_out is NULL");
+    if (I_out == nullptr && n_f > 0) return invalid("numag_azimuthal_average: I_out is NULL");
     if (grid->kind == NUMAG_GRID_POLAR) {
         if (n_bins != grid->n0) return invalid("numag_azimuthal_average: polar detector needs n_bins == n_q");
     } else if (!(qmax_avg > 0.0) || !is_finite(qmax_avg)) {

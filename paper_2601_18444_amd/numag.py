@@ -333,8 +333,17 @@ def amplitudes_snapshots(points: Regular, grid: QGrid, nuc=None, mag=None, path=
     regular grid `points`; returns amp [B, P, 4, 2]."""
     dev = torch.device(device)
     W = int(points.n[0]) * int(points.n[1]) * int(points.n[2])
-    nt = _dev(nuc, dev, (-1, W)) if nuc is not None else None
-    mt = _dev(mag, dev, (-1, W, 3)) if mag is not None else None
+
+    def batch(x, per):
+        # [B, W] / [B, W, 3] or flat; B = 0 passes through (the library refuses it)
+        t = _dev(x, dev)
+        n = W * per
+        if n <= 0 or t.numel() % n != 0:
+            raise ValueError("amplitudes_snapshots: weights do not match the grid size")
+        return t.reshape((t.numel() // n, W) + ((3,) if per == 3 else ()))
+
+    nt = batch(nuc, 1) if nuc is not None else None
+    mt = batch(mag, 3) if mag is not None else None
     if nt is None and mt is None:
         raise ValueError("amplitudes_snapshots: nuc or mag is required")
     B = (nt if nt is not None else mt).shape[0]

@@ -112,6 +112,12 @@ def test_other_entry_points_validate():
     assert lib.numag_azimuthal_average(ctypes.byref(pol), ctypes.c_void_p(8), 1, 7, 1.0, ctypes.c_void_p(8),
                                        None, None) == numag.E_INVALID
     assert lib.numag_correlation(None, None, 3, 1, None, 2, 1.0, None, None, None) == numag.E_INVALID
+    # no data sets: valid with NULL data and outputs, nothing launched
+    assert lib.numag_azimuthal_average(ctypes.byref(grid), None, 0, 4, 1.0, None, None, None) == numag.OK
+    assert lib.numag_azimuthal_average(ctypes.byref(grid), None, 1, 4, 1.0, ctypes.c_void_p(8),
+                                       None, None) == numag.E_INVALID
+    assert lib.numag_azimuthal_average(ctypes.byref(grid), ctypes.c_void_p(8), 1, 4, 1.0, None,
+                                       None, None) == numag.E_INVALID
     s = _cpu_sample()
     assert lib.numag_grad(ctypes.byref(s), None, ctypes.byref(grid), ctypes.byref(c), None, None, None, None,
                           None, None, None, 0, None) == numag.E_INVALID
