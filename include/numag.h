@@ -300,6 +300,7 @@ int numag_amplitudes_snapshots(const numag_regular *points, int64_t n_snap, cons
  *             writes them), or NULL; exactly one of amp/spec is given.
  *   obs_mask  NUMAG_OBS_* bits; rows of `out` follow increasing bit order.
  *   out       [n_sets][popcount(obs_mask)][P] doubles.
+ * With n_sets = 0 nothing is written and amp, spec and out may all be NULL.
  */
 int numag_cross_section(const numag_qgrid *grid, int64_t n_sets, const double *amp,
                         const double *spec, const numag_consts *consts, uint32_t obs_mask,

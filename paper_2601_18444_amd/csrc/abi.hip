@@ -689,7 +689,8 @@ int numag_cross_section(const numag_qgrid *grid, int64_t n_sets, const double *a
     int rc;
     if ((rc = check_grid(grid, "numag_cross_section")) != NUMAG_OK) return rc;
     if (n_sets < 0) return invalid("numag_cross_section: n_sets < 0");
-    if ((amp == nullptr) == (spec == nullptr))
+    if (amp != nullptr && spec != nullptr) return invalid("numag_cross_section: give exactly one of amp and spec");
+    if (n_sets > 0 && amp == nullptr && spec == nullptr)
         return invalid("numag_cross_section: give exactly one of amp and spec");
     if (consts == nullptr) return invalid("numag_cross_section: consts is NULL");
     if (!(consts->V > 0.0) || !is_finite(consts->V)) return invalid("numag_cross_section: V must be > 0");
@@ -698,7 +699,7 @@ int numag_cross_section(const numag_qgrid *grid, int64_t n_sets, const double *a
         if (!is_finite(consts->P[a])) return invalid("numag_cross_section: P not finite");
     if (obs_mask == 0 || (obs_mask & ~NUMAG_OBS_ALL) != 0)
         return invalid("numag_cross_section: obs_mask empty or has unknown bits");
-    if (out == nullptr) return invalid("numag_cross_section: out is NULL");
+    if (out == nullptr && n_sets > 0) return invalid("numag_cross_section: out is NULL");
     return launch_cross_section(make_detector(*grid), n_sets, amp, spec, *consts, obs_mask, out,
                                 (hipStream_t)stream);
 }

@@ -113,6 +113,11 @@ def test_other_entry_points_validate():
                                        None, None) == numag.E_INVALID
     assert lib.numag_correlation(None, None, 3, 1, None, 2, 1.0, None, None, None) == numag.E_INVALID
     # no data sets: valid with NULL data and outputs, nothing launched
+    assert lib.numag_cross_section(ctypes.byref(grid), 0, None, None, ctypes.byref(c), 1, None, None) == numag.OK
+    assert lib.numag_cross_section(ctypes.byref(grid), 0, ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.byref(c),
+                                   1, None, None) == numag.E_INVALID
+    assert lib.numag_cross_section(ctypes.byref(grid), 1, ctypes.c_void_p(8), None, ctypes.byref(c), 1, None,
+                                   None) == numag.E_INVALID
     assert lib.numag_azimuthal_average(ctypes.byref(grid), None, 0, 4, 1.0, None, None, None) == numag.OK
     assert lib.numag_azimuthal_average(ctypes.byref(grid), None, 1, 4, 1.0, ctypes.c_void_p(8),
                                        None, None) == numag.E_INVALID

@@ -80,3 +80,14 @@ def test_empty_snapshot_batch_is_refused():
     grid = numag.qgrid(numag.GRID_CARTESIAN, 8, 8, 1.0)
     with pytest.raises(numag.NumagError):
         numag.amplitudes_snapshots(points, grid, nuc=np.zeros((0, 64)), mag=np.zeros((0, 64, 3)), device=DEV)
+
+
+def test_no_amplitude_sets():
+    grid = numag.qgrid(numag.GRID_CARTESIAN, 8, 10, 1.0)
+    amp = torch.empty((0, grid.n_pixels, 4, 2), dtype=torch.float64, device=DEV)
+    xs = numag.cross_section(grid, amp=amp, obs=numag.OBSERVABLES)
+    spec = numag.spectral_matrix(grid, amp)
+    xs2 = numag.cross_section(grid, spec=spec, obs=("UNPOL", "SF"))
+    torch.cuda.synchronize()
+    assert xs.shape == (0, len(numag.OBSERVABLES), grid.n_pixels)
+    assert spec.shape == (0, grid.n_pixels, 16) and xs2.shape == (0, 2, grid.n_pixels)
