@@ -82,6 +82,9 @@ def parse():
                     help="only run the orientation-batch measurement (64 particles x 1000 rotations)")
     ap.add_argument("--ensemble", action="store_true",
                     help="only run the 512-sphere split-mode measurement (512 x 512 detector)")
+    ap.add_argument("--paper-scale", action="store_true",
+                    help="only run the 512-sphere ensemble on the 1000 x 1000 polar detector (sums, half-detector "
+                         "sums, split mode, cross section and 2D correlation)")
     return ap.parse_args()
 
 
@@ -623,6 +626,9 @@ def main():
         return
     if args.ensemble:
         print(json.dumps(measure_ensemble_split(torch, numag, synth)))
+        return
+    if args.paper_scale:
+        print(json.dumps(measure_paper_scale(torch, numag, synth)))
         return
     if args.snapshots:
         print(json.dumps(measure_snapshots(torch, numag, synth)))

@@ -10,15 +10,20 @@
 // "points" are the pixels, placed at -q_p so that the sums' exp(-i ...) becomes
 // exp(+i q.r), with real weights wq_p f_p; the real-space grid plays the role of
 // the detector.  It therefore runs on the same Cartesian / polar direct-sum
-// kernels, and the four weight channels carry four data sets at once.
+// kernels, and their weight channels carry up to four data sets at once: one set
+// runs alone in channel 0 (the kernels' one-channel form, 4.5 instead of 10.5
+// instructions per term), two or three in channels 1-3, four in all four.
+#include <algorithm>
+
 #include "numag_internal.h"
 #include "phasor.h"
 
 namespace numag {
 
 
-// Pixels of detector d as points: Y = -q_y, Z = -q_z, weights wq * f_(set0 + c).
-__global__ void corr2d_points_kernel(Detector d, const double *__restrict__ f, int n_f, int set0,
+// Pixels of detector d as points: Y = -q_y, Z = -q_z, weight channel c0 + c =
+// wq * f_(set0 + c), the other channels zero.
+__global__ void corr2d_points_kernel(Detector d, const double *__restrict__ f, int n_f, int set0, int c0,
                                      PointRec *__restrict__ out)
 {
     const int64_t P = (int64_t)d.n0 * d.n1;
@@ -46,23 +51,26 @@ __global__ void corr2d_points_kernel(Detector d, const double *__restrict__ f, i
     PointRec r;
     r.Y = -qy;
     r.Z = -qz;
-    for (int c = 0; c < 4; ++c) r.w[c] = (set0 + c < n_f) ? wq * f[(int64_t)(set0 + c) * P + p] : 0.0;
+    for (int c = 0; c < 4; ++c) {
+        const int set = set0 + c - c0;
+        r.w[c] = (c >= c0 && set < n_f) ? wq * f[(int64_t)set * P + p] : 0.0;
+    }
     r.pad[0] = r.pad[1] = 0.0;
     out[p] = r;
 }
 
-// C_out[set0 + c][t] = channel c of amp[t]
-__global__ void corr2d_scatter_kernel(const double *__restrict__ amp, int64_t R, int n_f, int set0,
+// C_out[set0 + c][t] = channel c0 + c of amp[t]
+__global__ void corr2d_scatter_kernel(const double *__restrict__ amp, int64_t R, int n_f, int set0, int c0,
                                       double *__restrict__ out)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= R * 4) return;
     const int64_t t = i / 4;
     const int c = (int)(i % 4);
-    if (set0 + c >= n_f) return;
+    if (set0 + c >= n_f || c0 + c >= 4) return;
     double *o = out + ((int64_t)(set0 + c) * R + t) * 2;
-    o[0] = amp[t * 8 + 2 * c];
-    o[1] = amp[t * 8 + 2 * c + 1];
+    o[0] = amp[t * 8 + 2 * (c0 + c)];
+    o[1] = amp[t * 8 + 2 * (c0 + c) + 1];
 }
 
 static size_t al2(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -104,14 +112,19 @@ int launch_correlation_2d(const Detector &d, const double *f, int n_f, const Det
     }
     const Detector rh = half_grid(rd);
     const int64_t Rh = (int64_t)rh.n0 * rh.n1;
-    const DirectPlan plan = corr2d_plan(rh, P);
+    const DirectPlan plan4 = corr2d_plan(rh, P);
     char *base = (char *)ws;
     PointRec *pts = (PointRec *)base;
     double *part = (double *)(base + al2((size_t)P * sizeof(PointRec)));
-    double *amp = (double *)(base + al2((size_t)P * sizeof(PointRec)) + al2(direct_partial_bytes(plan, rh)));
+    double *amp = (double *)(base + al2((size_t)P * sizeof(PointRec)) + al2(direct_partial_bytes(plan4, rh)));
     for (int set0 = 0; set0 < n_f; set0 += 4) {
+        // the sum kernels' channel set for this group: 1 (channel 0), 3 (channels 1-3) or 4
+        const int m = std::min(4, n_f - set0);
+        DirectPlan plan = plan4;
+        plan.channels = m == 1 ? 1 : (m == 4 ? 4 : 3);
+        const int c0 = plan.channels == 3 ? 1 : 0;
         hipLaunchKernelGGL(corr2d_points_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, d, f, n_f, set0,
-                           pts);
+                           c0, pts);
         NUMAG_HIP_CHECK(hipGetLastError());
         int rc;
         if (rd.kind == NUMAG_GRID_CARTESIAN) {
@@ -126,7 +139,7 @@ int launch_correlation_2d(const Detector &d, const double *f, int n_f, const Det
         }
         if (rc != NUMAG_OK) return rc;
         hipLaunchKernelGGL(corr2d_scatter_kernel, dim3((unsigned)((R * 4 + 255) / 256)), dim3(256), 0, s, amp, R, n_f,
-                           set0, C);
+                           set0, c0, C);
         NUMAG_HIP_CHECK(hipGetLastError());
     }
     return NUMAG_OK;

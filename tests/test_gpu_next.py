@@ -33,6 +33,22 @@ def test_correlation_2d_vs_oracle(orc, kind, n0, n1, rkind, r0, r1):
     assert max_norm_err(C, ref) <= 1e-10
 
 
+@pytest.mark.parametrize("n_f", [1, 3, 5, 7])
+@pytest.mark.parametrize("kind,n0,n1,rkind,r0,r1", [(1, 24, 40, 1, 9, 16), (0, 27, 31, 0, 13, 11)])
+def test_correlation_2d_every_channel_grouping(orc, kind, n0, n1, rkind, r0, r1, n_f):
+    """Groups of one data set (one weight channel), of two or three (channels 1-3) and
+    of four, alone and after a full group, against the oracle."""
+    rng = np.random.default_rng(70 + n_f + n0)
+    f = rng.standard_normal((n_f, n0 * n1))
+    qmax, rmax = 1.1, 20.0
+    grid = numag.qgrid(kind, n0, n1, qmax)
+    rgrid = numag.qgrid(rkind, r0, r1, rmax)
+    C = numag.correlation_2d(grid, torch.as_tensor(f, device=DEV), rgrid).cpu().numpy()
+    ref = orc.correlation_2d(kind, n0, n1, qmax, f, rkind, r0, r1, rmax)
+    assert C.shape == (n_f, r0 * r1, 2)
+    assert max_norm_err(C[..., 0] + 1j * C[..., 1], ref) <= 1e-10
+
+
 def test_correlation_2d_of_sphere_cross_section(orc):
     """C of the unpolarized sphere cross section on a polar detector (the use of
     Sec. 4.1, Fig. 6d): the GPU pipeline sums -> cross section -> correlation
