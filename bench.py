@@ -32,6 +32,7 @@ if ROOT not in sys.path:
 PEAK_FP64_VALU = 256 * 2.4e9 * 64 * 2  # 78.6 TFLOP/s: 256 CUs x 64 FP64 FMA lanes x 2 flops x 2.4 GHz
 PEAK_FP32_VALU = 157.3e12              # packed FP32 vector peak (datasheet)
 PEAK_FP64_MFMA = 78.6e12               # FP64 dense matrix peak (datasheet)
+PEAK_HBM = 8.0e12                      # HBM3E bytes/s (datasheet)
 # algorithmic work of one (point, pixel) term: the phase q.X (2 FMA) and the
 # four channel sums, real and imaginary parts (8 FMA); the sine and cosine are
 # not counted
@@ -345,6 +346,10 @@ def measure_snapshots(torch, numag, synth, n_snap=64):
         t_bf[name] = e0.elapsed_time(e1) / reps
     flops = n_snap * 4 * (64 * 64 * 256 * 4 + 256 * 64 * 256 * 8)  # both contractions, four channels
     flops_h = n_snap * 4 * (64 * 64 * 256 * 4 + 128 * 64 * 256 * 8)  # the Hermitian variant's executed flops
+    # the call's kernels run one after the other, so its bound is the projection's HBM time
+    # (the weights read once, the projections written) plus the contractions' matrix-core time
+    hbm_bytes = n_snap * W * 32 + n_snap * 4 * 64 * 64 * 8
+    bound_s = hbm_bytes / PEAK_HBM + flops / PEAK_FP64_MFMA
     return {
         "workload": f"{n_snap} field-sweep snapshots of the 64^3 vortex grid, 256x256 detector, FP64 MFMA separable "
                     "path, one batched call",
@@ -362,6 +367,10 @@ def measure_snapshots(torch, numag, synth, n_snap=64):
         "roofline": {"bound": "mfma", "achieved": round(flops / t_batch / 1e12, 3),
                      "peak": round(PEAK_FP64_MFMA / 1e12, 1), "unit": "TFLOP/s",
                      "frac": round(flops / t_batch / PEAK_FP64_MFMA, 4), "flops_per_call": flops},
+        "sequential_bound": {"hbm_bytes": hbm_bytes, "flops": flops, "bound_ms": round(bound_s * 1e3, 4),
+                             "frac": round(bound_s / t_batch, 4),
+                             "definition": "projection bytes / 8 TB/s + contraction flops / 78.6 TFLOP/s, "
+                                           "over the call's time"},
     }
 
 
