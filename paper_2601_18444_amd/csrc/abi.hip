@@ -484,6 +484,10 @@ size_t numag_workspace_size(const numag_sample *sample, int64_t n_rot, const num
         set_error("numag_workspace_size: n_rot must be >= 1");
         return 0;
     }
+    if (path == NUMAG_PATH_DIRECT_HERMITIAN && grid->kind == NUMAG_GRID_POLAR && grid->n1 % 2 != 0) {
+        set_error("numag_workspace_size: the Hermitian path needs an even n_theta on a polar detector");
+        return 0;
+    }
     Detector d = make_detector(*grid);
     // object modes: enough for both spectral layouts (per object or summed)
     size_t amp = std::max(amplitudes_ws(sample, n_rot, d, path, mode, 0), amplitudes_ws(sample, n_rot, d, path, mode, 1));

@@ -348,7 +348,7 @@ Tables make_tables(const Detector &d, const std::vector<int64_t> &off, int64_t K
     p.row_blocks = (d.n0 + rows - 1) / rows;
     const int64_t nblocks = (int64_t)p.col_blocks * p.row_blocks;
     // slot groups wanted (each spans all pixel blocks)
-    const int64_t want = std::max<int64_t>(1, (ts.target + nblocks - 1) / nblocks);
+    const int64_t want = std::max<int64_t>(1, (ts.target + nblocks - 1) / std::max<int64_t>(nblocks, 1));
     // object groups: single objects, or contiguous groups of roughly equal point counts
     std::vector<int2> groups;
     if (spec_per_object) {

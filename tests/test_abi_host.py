@@ -112,6 +112,14 @@ def test_other_entry_points_validate():
     assert lib.numag_azimuthal_average(ctypes.byref(pol), ctypes.c_void_p(8), 1, 7, 1.0, ctypes.c_void_p(8),
                                        None, None) == numag.E_INVALID
     assert lib.numag_correlation(None, None, 3, 1, None, 2, 1.0, None, None, None) == numag.E_INVALID
+    # the half-detector path on a polar detector needs an even n_theta: the size query
+    # refuses an odd one like the calls do (n_theta = 1 leaves no column to sum)
+    pol1 = numag.qgrid(1, 8, 1, 1.0)
+    s1 = _cpu_sample(W=10)
+    for mode in (0, 1, 2):
+        assert lib.numag_workspace_size(ctypes.byref(s1), 1, ctypes.byref(pol1), numag.PATH_DIRECT_HERMITIAN,
+                                        mode) == 0
+        assert "even n_theta" in numag.last_error()
     # no data sets: valid with NULL data and outputs, nothing launched
     assert lib.numag_cross_section(ctypes.byref(grid), 0, None, None, ctypes.byref(c), 1, None, None) == numag.OK
     assert lib.numag_cross_section(ctypes.byref(grid), 0, ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.byref(c),
